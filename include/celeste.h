@@ -1,0 +1,233 @@
+/*
+ * celeste.h - C ABI of the MI355X FP64 ELBO library (libceleste.so).
+ *
+ * The library evaluates, on one AMD Instinct MI355X (gfx950), the variational lower
+ * bound of the Celeste astronomical-catalog model (Regier et al. 2018, Section III,
+ * Eq. (1)) per light source, its gradient (a hand-written adjoint), its per-source
+ * Hessian-vector product (the tangent of that adjoint), batched Newton trust-region
+ * steps for many sources at once (Section IV-D) and block-coordinate-ascent sweeps
+ * over conflict-free batches of sources (Section IV-D).
+ *
+ * Model, per image n (band b_n, sky level eps_n, calibration iota_n, 3-component
+ * Gaussian PSF) and pixel m (centre (x = col, y = row) in the image frame, which is
+ * the world frame minus the image origin):
+ *   E_s(m)   = iota_n [q a_star f_star(m) + (1-q) a_gal f_gal(m)]
+ *   Var_s(m) = iota_n^2 [q b_star f_star^2 + (1-q) b_gal f_gal^2] - E_s(m)^2
+ *   E(m) = eps_n + sum_t E_t(m),  V(m) = sum_t Var_t(m)   over sources t whose box
+ *   in image n contains m;  a = E[flux_b], b = E[flux_b^2] of the log-normal band flux;
+ *   pixel term  l(m) = x_m (log E - V / (2 E^2)) - E   (second-order expansion of
+ *   E[log F] about E[F]);  ELBO_s = sum over s's own boxes of l(m) - KL_s.
+ * f_star is the PSF; f_gal mixes an exponential and a de Vaucouleurs profile (each a
+ * Gaussian mixture given in the problem description) sheared by the galaxy shape
+ * radius^2 R(angle) diag(1, ratio^2) R(angle)^T and convolved with the PSF.
+ *
+ * Parameters: theta is a device array [n_src][32] of float64, one row per source:
+ *   0 u_x, 1 u_y (world pixels), 2 frac_dev in [0,1], 3 axis ratio in (0,1],
+ *   4 angle (rad, counter-clockwise from +x to the major axis), 5 half-light radius
+ *   (px, > 0), 6 q = probability of a star in (0,1),
+ *   7..16 star: r_mu, r_var, c_mu[4], c_var[4];  17..26 galaxy: same;  27..31 unused.
+ *   r is the log reference-band (r) flux, c_k = log(flux_{k+1}/flux_k) over u,g,r,i,z;
+ *   *_var are variances (> 0).  Gradients are taken with respect to these entries.
+ *
+ * Conventions for every call:
+ *  - Pointers documented "device" must be device memory of the current HIP device;
+ *    "host" pointers are read during the call only.  The caller owns all of them.
+ *  - Calls are stream-ordered and asynchronous unless documented otherwise.  Domain
+ *    checks of theta run on the device; a failure leaves the outputs of that call
+ *    untouched and is reported by celeste_plan_status().
+ *  - Return value: CELESTE_OK or a negative CELESTE_E* code.  Nothing is thrown.
+ *  - A plan is used from one host thread and one stream at a time; distinct plans
+ *    are independent.  Calls on one plan must not overlap.
+ */
+#ifndef CELESTE_H
+#define CELESTE_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CELESTE_ABI_VERSION 1
+
+enum celeste_status {
+    CELESTE_OK = 0,
+    CELESTE_EINVAL = -1,     /* bad size, pointer, geometry or parameter */
+    CELESTE_ECONFLICT = -2,  /* two members of one batch share a pixel */
+    CELESTE_EHIP = -3,       /* a HIP runtime call failed (detail: celeste_last_hip_error) */
+    CELESTE_ENOMEM = -4,     /* device allocation failed */
+    CELESTE_EDOMAIN = -5     /* theta (or a trust-region trial) left the parameter domain */
+};
+
+enum celeste_mode {
+    CELESTE_PLAIN = 0,    /* one launch per source, overlapping sources evaluated on the fly */
+    CELESTE_BATCHED = 1   /* all sources: render pass + one persistent fused adjoint launch */
+};
+
+enum celeste_flags {
+    CELESTE_INCLUDE_KL = 1,       /* subtract KL(q || prior) from each ELBO_s */
+    CELESTE_INCLUDE_LGAMMA = 2    /* include the -log(x!) constant in every pixel term */
+};
+
+/* One image: header of a row-major H x W plane of float64 counts inside x. */
+typedef struct celeste_image {
+    int32_t band;         /* 0..4 = u, g, r, i, z */
+    int32_t H, W;
+    int32_t reserved;
+    int64_t pix_offset;   /* offset of pixel (0, 0) in x */
+    double sky;           /* eps_n > 0, expected sky counts per pixel */
+    double iota;          /* iota_n > 0, counts per unit flux */
+    double origin_x, origin_y;   /* world coordinates of pixel (row 0, col 0) */
+    double psf[3][6];     /* per component: weight > 0, mean offset x, y, covariance xx, xy, yy */
+} celeste_image;
+
+/* A source's patch ("active pixels") in one image: rows r0..r0+h-1, cols c0..c0+w-1. */
+typedef struct celeste_box {
+    int32_t img, r0, c0, h, w;
+} celeste_box;
+
+typedef struct celeste_problem_desc {
+    int32_t n_img;
+    int32_t n_src;
+    const celeste_image* images;   /* host [n_img] */
+    const double* x;               /* device [n_pix]; NaN marks a masked pixel */
+    int64_t n_pix;
+    const int32_t* patch_ptr;      /* host [n_src + 1], CSR into boxes */
+    const celeste_box* boxes;      /* host [patch_ptr[n_src]]; at most one box per (source, image) */
+    double exp_alpha[6], exp_nu[6];    /* exponential profile: weights (sum 1) and variances */
+    double dev_alpha[8], dev_nu[8];    /* de Vaucouleurs profile */
+    double prior_phi;              /* prior probability of a star, (0, 1) */
+    double prior_r[2][2];          /* [star, galaxy][mean, variance] of log r-band flux */
+    double prior_c[2][2][4];       /* [star, galaxy][mean, variance][colour k] */
+    uint32_t flags;                /* celeste_flags */
+    int32_t reserved;
+} celeste_problem_desc;
+
+/* Trust-region constants (Nocedal & Wright, Ch. 4) for celeste_newton / celeste_sweep. */
+typedef struct celeste_tr_params {
+    double radius0;        /* initial radius (unconstrained coordinates), e.g. 1 */
+    double radius_max;     /* e.g. 1e3 */
+    double eta_accept;     /* accept the step if actual/predicted > eta_accept, e.g. 0.1 */
+    double gtol;           /* a source stops once max |grad| in unconstrained space < gtol */
+    int32_t newton_steps;  /* Newton iterations per source per batch visit (celeste_sweep) */
+    int32_t reserved;
+} celeste_tr_params;
+
+typedef struct celeste_plan_info {
+    int64_t n_visits;      /* sum over boxes of h*w: (source, pixel) pairs of one evaluation */
+    int64_t n_pairs;       /* boxes */
+    int64_t n_items;       /* work items of the fused adjoint launch */
+    int64_t n_tiles;       /* render tiles touched by at least one box */
+    int64_t n_nbr;         /* entries of the box-overlap lists used by the plain form */
+    int32_t chunk;         /* pixels per adjoint work item */
+    int32_t waves_per_block;
+    int32_t grid_blocks;   /* persistent grid size of the fused adjoint launch */
+    int32_t tile_h, tile_w;
+    int32_t dynamic_queue; /* 1: items popped from a device counter; 0: static round robin */
+    int64_t workspace_bytes;
+} celeste_plan_info;
+
+typedef struct celeste_plan celeste_plan;
+
+/* Validates the geometry (Section III model: boxes inside images, positive PSF
+ * covariances and weights, sky and iota > 0, mixture variances > 0, one box per
+ * (source, image)), bins boxes into render tiles and work items, and allocates the
+ * plan-owned device workspace.  The only call that allocates.  Synchronous.
+ * Returns CELESTE_EINVAL (nothing allocated) or CELESTE_ENOMEM on failure. */
+int celeste_plan_create(const celeste_problem_desc* desc, celeste_plan** out);
+
+/* Frees the plan's own memory (never the caller's).  NULL is a no-op. */
+void celeste_plan_destroy(celeste_plan* plan);
+
+int celeste_plan_get_info(const celeste_plan* plan, celeste_plan_info* info);
+
+/* Per-source ELBO_s (Eq. (1) restricted to s's boxes, other sources fixed) into
+ * elbo[n_src] (device).  active: device [n_src] bytes, nonzero = evaluate, or NULL
+ * for all; entries of inactive sources are left untouched.  mode: celeste_mode. */
+int celeste_elbo(celeste_plan* plan, const double* theta, const uint8_t* active, int mode,
+                 double* elbo, hipStream_t stream);
+
+/* ELBO_s and its gradient with respect to theta[s][0..26] (device grad[n_src][32],
+ * entries 27..31 set to 0), from the hand-written adjoint; pixel intermediates are
+ * recomputed, not stored. */
+int celeste_elbo_grad(celeste_plan* plan, const double* theta, const uint8_t* active, int mode,
+                      double* elbo, double* grad, hipStream_t stream);
+
+/* Block-diagonal Hessian-vector product: hv[s] = (d^2 ELBO_s / d theta_s^2) v[s]
+ * (device [n_src][32]; entries 27..31 of v ignored, of hv set to 0).  Computed as the
+ * forward-mode tangent of the adjoint.  grad (device [n_src][32] or NULL) receives the
+ * gradient as a by-product.  All sources, batched form. */
+int celeste_hvp(celeste_plan* plan, const double* theta, const double* v, double* hv,
+                double* grad, hipStream_t stream);
+
+/* Dense per-source Hessians hess[k][27][27] (device, row-major) of the n listed
+ * sources src[k] (host list), from 27 tangent-adjoint passes. */
+int celeste_hessian(celeste_plan* plan, const double* theta, const int32_t* src, int n,
+                    double* hess, hipStream_t stream);
+
+/* Newton trust-region iterations (Section IV-D) for the n sources src[] (host list,
+ * distinct).  Each listed source is optimised with every other source held at its
+ * value in theta at entry.  Per iteration: gradient, dense 27x27 Hessian, exact
+ * trust-region subproblem in unconstrained coordinates (logit of q, frac_dev, axis
+ * ratio; log of radius and variances) by a Jacobi eigendecomposition and a secular
+ * equation, trial evaluation, accept/reject and radius update - all on the device.
+ * theta_inout (device [n_src][32]) is updated in place; radius (device [n_src]) is
+ * read and written (initialise with params->radius0); elbo_out (device [n_src] or
+ * NULL) receives the final ELBO_s of the listed sources. */
+int celeste_newton(celeste_plan* plan, double* theta_inout, const int32_t* src, int n,
+                   int n_steps, const celeste_tr_params* params, double* radius,
+                   double* elbo_out, hipStream_t stream);
+
+/* Total ELBO of the field (each covered pixel counted once, minus every KL) into
+ * out[0] (device). */
+int celeste_total_elbo(celeste_plan* plan, const double* theta, double* out, hipStream_t stream);
+
+/* Greedy colouring of the box-overlap graph in a seeded random order: every batch is
+ * a set of sources no two of which share a pixel of any image (the conflict-free
+ * schedule of Section IV-D).  Host call.  batch_ptr (host [n_src + 1]) and
+ * batch_src (host [n_src]) receive the CSR schedule, *n_batches its length. */
+int celeste_color_batches(const celeste_plan* plan, uint64_t seed, int32_t* batch_ptr,
+                          int32_t* batch_src, int32_t* n_batches);
+
+/* Block coordinate ascent: n_sweeps passes over the batches (host CSR batch_ptr,
+ * batch_src), each batch optimised by params->newton_steps Newton trust-region
+ * iterations with all other sources fixed.  Batches must be conflict-free
+ * (CELESTE_ECONFLICT otherwise, nothing run).  elbo_trace (device [n_sweeps + 1])
+ * receives the total ELBO before the first sweep and after each sweep. */
+int celeste_sweep(celeste_plan* plan, double* theta_inout, const int32_t* batch_ptr,
+                  const int32_t* batch_src, int n_batches, int n_sweeps,
+                  const celeste_tr_params* params, double* elbo_trace, hipStream_t stream);
+
+/* Launch configuration of the fused adjoint: pixels per item (multiple of 64, at most
+ * 1024), waves per block (1, 2 or 4), persistent grid size (blocks, >= 1),
+ * dynamic_queue (0/1), render tile (tile_h * tile_w == 64).  Rebuilds work items
+ * (synchronous; no allocation beyond the plan's item buffer, reallocated if it grows). */
+int celeste_plan_set_launch(celeste_plan* plan, int chunk, int waves_per_block, int grid_blocks,
+                            int dynamic_queue, int tile_h, int tile_w);
+
+/* Times candidate launch configurations of celeste_elbo_grad (batched) on theta with
+ * HIP events (median of `reps` runs each) and keeps the fastest.  Synchronous.
+ * best_ms (host, or NULL) receives its time. */
+int celeste_autotune(celeste_plan* plan, const double* theta, int reps, double* best_ms,
+                     hipStream_t stream);
+
+/* Capture the batched celeste_elbo_grad sequence for these exact pointers in a HIP
+ * graph on first use and replay it afterwards (0 = off, the default). */
+int celeste_plan_use_graph(celeste_plan* plan, int enable);
+
+/* Synchronises `stream` and returns the domain status of the last call on this plan
+ * (CELESTE_OK or CELESTE_EDOMAIN), then clears it. */
+int celeste_plan_status(celeste_plan* plan, hipStream_t stream);
+
+/* HIP error string of the last CELESTE_EHIP on this thread. */
+const char* celeste_last_hip_error(void);
+
+const char* celeste_status_string(int status);
+int celeste_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CELESTE_H */

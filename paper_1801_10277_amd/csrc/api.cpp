@@ -1,0 +1,1057 @@
+// Host side of libceleste: plan construction (validation, box binning, work items,
+// overlap lists), the C entry points, HIP graph capture of the batched evaluation, the
+// launch-configuration autotuner, conflict-free batching and the sweep driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "celeste.h"
+#include "internal.h"
+
+using namespace cel;
+
+namespace {
+
+thread_local std::string g_hip_error;
+
+int hip_fail(hipError_t e, const char* what) {
+    g_hip_error = std::string(what) + ": " + hipGetErrorString(e);
+    return CELESTE_EHIP;
+}
+
+#define HIPCHK(call)                                            \
+    do {                                                        \
+        hipError_t e_ = (call);                                 \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);       \
+    } while (0)
+
+template <class T>
+int dalloc(T** p, size_t n, size_t& total) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    const size_t bytes = n * sizeof(T);
+    if (hipMalloc((void**)p, bytes) != hipSuccess) {
+        *p = nullptr;
+        return CELESTE_ENOMEM;
+    }
+    total += bytes;
+    return CELESTE_OK;
+}
+
+bool finite(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+struct celeste_plan {
+    int device = 0;
+    int n_img = 0, n_src = 0;
+    int64_t n_pix = 0, n_visits = 0;
+    std::vector<celeste_image> images;
+    std::vector<int32_t> patch_ptr;
+    std::vector<PairDev> pairs;
+    std::vector<Item> items;
+    std::vector<int32_t> nbr;
+    std::vector<TileDev> tiles;
+    std::vector<int32_t> tile_list;
+    Consts consts{};
+    const double* d_x = nullptr;
+    int n_cu = 256;
+
+    // launch configuration
+    int chunk = 256, wpb = 4, grid = 0, dynamic = 0, tile_h = 8, tile_w = 8;
+    bool use_graph = false;
+
+    // device memory
+    celeste_image* d_images = nullptr;
+    PairDev* d_pairs = nullptr;
+    Item* d_items = nullptr;
+    size_t cap_items = 0;
+    int32_t* d_nbr = nullptr;
+    TileDev* d_tiles = nullptr;
+    size_t cap_tiles = 0;
+    int32_t* d_tile_list = nullptr;
+    size_t cap_tile_list = 0;
+    int32_t* d_patch_ptr = nullptr;
+    double* d_tab1 = nullptr;    // double tables
+    double* d_coef1 = nullptr;
+    double* d_tab2 = nullptr;    // dual tables
+    double* d_coef2 = nullptr;
+    double* d_partials = nullptr;
+    double* d_E = nullptr;
+    double* d_V = nullptr;
+    double* d_bg = nullptr;
+    double* d_tile_sums = nullptr;
+    int* d_status = nullptr;
+    int* d_counter = nullptr;
+    double* d_grad = nullptr;
+    double* d_hess = nullptr;
+    double* d_theta_trial = nullptr;
+    double* d_pred = nullptr;
+    double* d_elbo_cur = nullptr;
+    double* d_elbo_trial = nullptr;
+    double* d_radius = nullptr;
+    uint8_t* d_done = nullptr;
+    int32_t* d_list_src = nullptr;   // [n_src]
+    int32_t* d_list_pair = nullptr;  // [n_pairs]
+    int32_t* d_list_item = nullptr;  // [cap_items]
+    size_t cap_list_item = 0;
+    size_t workspace = 0;
+
+    // graph cache of the batched elbo_grad sequence
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const void* gkey[4] = {nullptr, nullptr, nullptr, nullptr};
+    int gkey_cfg = -1;
+
+    Geometry geom() const {
+        Geometry g;
+        g.images = d_images;
+        g.pairs = d_pairs;
+        g.items = d_items;
+        g.nbr = d_nbr;
+        g.x = d_x;
+        g.consts = consts;
+        return g;
+    }
+    int64_t n_pairs() const { return (int64_t)pairs.size(); }
+    int persistent_grid() const { return grid > 0 ? grid : 8 * n_cu; }
+};
+
+namespace {
+
+// ---------------------------------------------------------------- geometry builders
+
+void build_items(celeste_plan* p) {
+    p->items.clear();
+    for (size_t i = 0; i < p->pairs.size(); ++i) {
+        PairDev& pd = p->pairs[i];
+        const int area = pd.h * pd.w;
+        pd.item_begin = (int32_t)p->items.size();
+        for (int s = 0; s < area; s += p->chunk) {
+            Item it;
+            it.pair = (int32_t)i;
+            it.start = s;
+            it.count = std::min(p->chunk, area - s);
+            it.pad = 0;
+            p->items.push_back(it);
+        }
+        pd.item_end = (int32_t)p->items.size();
+    }
+}
+
+void build_tiles(celeste_plan* p) {
+    const int th = p->tile_h, tw = p->tile_w;
+    std::vector<std::vector<int32_t>> per_img_pairs(p->n_img);
+    for (size_t i = 0; i < p->pairs.size(); ++i) per_img_pairs[p->pairs[i].img].push_back((int32_t)i);
+    p->tiles.clear();
+    p->tile_list.clear();
+    for (int n = 0; n < p->n_img; ++n) {
+        const celeste_image& im = p->images[n];
+        const int ntr = (im.H + th - 1) / th, ntc = (im.W + tw - 1) / tw;
+        std::vector<int32_t> cnt((size_t)ntr * ntc, 0);
+        for (int32_t pi : per_img_pairs[n]) {
+            const PairDev& pd = p->pairs[pi];
+            for (int tr = pd.r0 / th; tr <= (pd.r0 + pd.h - 1) / th; ++tr)
+                for (int tc = pd.c0 / tw; tc <= (pd.c0 + pd.w - 1) / tw; ++tc) cnt[(size_t)tr * ntc + tc]++;
+        }
+        std::vector<int64_t> start(cnt.size(), -1);
+        const size_t base_tile = p->tiles.size();
+        int64_t off = (int64_t)p->tile_list.size();
+        for (size_t t = 0; t < cnt.size(); ++t) {
+            if (!cnt[t]) continue;
+            TileDev td;
+            td.img = n;
+            td.r0 = (int)(t / ntc) * th;
+            td.c0 = (int)(t % ntc) * tw;
+            td.list_begin = (int32_t)off;
+            td.list_end = (int32_t)(off + cnt[t]);
+            td.pad = 0;
+            start[t] = (int64_t)(p->tiles.size() - base_tile);
+            p->tiles.push_back(td);
+            off += cnt[t];
+        }
+        p->tile_list.resize(off);
+        std::vector<int32_t> fill(p->tiles.size() - base_tile, 0);
+        for (int32_t pi : per_img_pairs[n]) {   // ascending pair order inside every tile
+            const PairDev& pd = p->pairs[pi];
+            for (int tr = pd.r0 / th; tr <= (pd.r0 + pd.h - 1) / th; ++tr)
+                for (int tc = pd.c0 / tw; tc <= (pd.c0 + pd.w - 1) / tw; ++tc) {
+                    const int64_t k = start[(size_t)tr * ntc + tc];
+                    TileDev& td = p->tiles[base_tile + k];
+                    p->tile_list[td.list_begin + fill[k]++] = pi;
+                }
+        }
+    }
+}
+
+bool boxes_intersect(const PairDev& a, const PairDev& b) {
+    return a.r0 < b.r0 + b.h && b.r0 < a.r0 + a.h && a.c0 < b.c0 + b.w && b.c0 < a.c0 + a.w;
+}
+
+void build_nbr(celeste_plan* p) {
+    const int cell = 128;
+    p->nbr.clear();
+    std::vector<std::vector<int32_t>> per_img(p->n_img);
+    for (size_t i = 0; i < p->pairs.size(); ++i) per_img[p->pairs[i].img].push_back((int32_t)i);
+    std::vector<std::vector<int32_t>> lists(p->pairs.size());
+    for (int n = 0; n < p->n_img; ++n) {
+        const celeste_image& im = p->images[n];
+        const int nr = (im.H + cell - 1) / cell, nc = (im.W + cell - 1) / cell;
+        std::vector<std::vector<int32_t>> cells((size_t)nr * nc);
+        for (int32_t pi : per_img[n]) {
+            const PairDev& pd = p->pairs[pi];
+            for (int r = pd.r0 / cell; r <= (pd.r0 + pd.h - 1) / cell; ++r)
+                for (int c = pd.c0 / cell; c <= (pd.c0 + pd.w - 1) / cell; ++c)
+                    cells[(size_t)r * nc + c].push_back(pi);
+        }
+        for (int32_t pi : per_img[n]) {
+            const PairDev& pd = p->pairs[pi];
+            std::vector<int32_t>& L = lists[pi];
+            for (int r = pd.r0 / cell; r <= (pd.r0 + pd.h - 1) / cell; ++r)
+                for (int c = pd.c0 / cell; c <= (pd.c0 + pd.w - 1) / cell; ++c)
+                    for (int32_t qi : cells[(size_t)r * nc + c])
+                        if (qi != pi && boxes_intersect(pd, p->pairs[qi])) L.push_back(qi);
+            std::sort(L.begin(), L.end());
+            L.erase(std::unique(L.begin(), L.end()), L.end());
+        }
+    }
+    for (size_t i = 0; i < p->pairs.size(); ++i) {
+        p->pairs[i].nbr_begin = (int32_t)p->nbr.size();
+        p->nbr.insert(p->nbr.end(), lists[i].begin(), lists[i].end());
+        p->pairs[i].nbr_end = (int32_t)p->nbr.size();
+    }
+}
+
+int upload_geometry(celeste_plan* p) {
+    HIPCHK(hipMemcpy(p->d_pairs, p->pairs.data(), p->pairs.size() * sizeof(PairDev), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(p->d_items, p->items.data(), p->items.size() * sizeof(Item), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(p->d_tiles, p->tiles.data(), p->tiles.size() * sizeof(TileDev), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(p->d_tile_list, p->tile_list.data(), p->tile_list.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice));
+    return CELESTE_OK;
+}
+
+void drop_graph(celeste_plan* p) {
+    if (p->gexec) {
+        (void)hipGraphExecDestroy(p->gexec);
+        p->gexec = nullptr;
+    }
+    p->gkey_cfg = -1;
+}
+
+// ---------------------------------------------------------------- validation
+int validate_desc(const celeste_problem_desc* d) {
+    if (!d || d->n_img <= 0 || d->n_src <= 0 || !d->images || !d->x || !d->patch_ptr || d->n_pix <= 0)
+        return CELESTE_EINVAL;
+    if (d->flags & ~(uint32_t)(CELESTE_INCLUDE_KL | CELESTE_INCLUDE_LGAMMA)) return CELESTE_EINVAL;
+    for (int n = 0; n < d->n_img; ++n) {
+        const celeste_image& im = d->images[n];
+        if (im.band < 0 || im.band > 4 || im.H <= 0 || im.W <= 0 || im.pix_offset < 0) return CELESTE_EINVAL;
+        if (im.pix_offset + (int64_t)im.H * im.W > d->n_pix) return CELESTE_EINVAL;
+        if (!(im.sky > 0.0) || !finite(im.sky) || !(im.iota > 0.0) || !finite(im.iota)) return CELESTE_EINVAL;
+        if (!finite(im.origin_x) || !finite(im.origin_y)) return CELESTE_EINVAL;
+        for (int k = 0; k < NPSF; ++k) {
+            const double* ps = im.psf[k];
+            for (int f = 0; f < 6; ++f)
+                if (!finite(ps[f])) return CELESTE_EINVAL;
+            if (!(ps[0] > 0.0) || !(ps[3] > 0.0) || !(ps[5] > 0.0) || !(ps[3] * ps[5] - ps[4] * ps[4] > 0.0))
+                return CELESTE_EINVAL;
+        }
+    }
+    if (d->patch_ptr[0] != 0) return CELESTE_EINVAL;
+    for (int s = 0; s < d->n_src; ++s)
+        if (d->patch_ptr[s + 1] < d->patch_ptr[s]) return CELESTE_EINVAL;
+    const int nb = d->patch_ptr[d->n_src];
+    if (nb > 0 && !d->boxes) return CELESTE_EINVAL;
+    for (int s = 0; s < d->n_src; ++s) {
+        for (int b = d->patch_ptr[s]; b < d->patch_ptr[s + 1]; ++b) {
+            const celeste_box& bx = d->boxes[b];
+            if (bx.img < 0 || bx.img >= d->n_img) return CELESTE_EINVAL;
+            const celeste_image& im = d->images[bx.img];
+            if (bx.h <= 0 || bx.w <= 0 || bx.r0 < 0 || bx.c0 < 0 || bx.r0 + bx.h > im.H || bx.c0 + bx.w > im.W)
+                return CELESTE_EINVAL;
+            for (int b2 = d->patch_ptr[s]; b2 < b; ++b2)
+                if (d->boxes[b2].img == bx.img) return CELESTE_EINVAL;
+        }
+    }
+    for (int j = 0; j < NEXP; ++j)
+        if (!(d->exp_alpha[j] > 0.0) || !(d->exp_nu[j] > 0.0) || !finite(d->exp_nu[j])) return CELESTE_EINVAL;
+    for (int j = 0; j < NDEV; ++j)
+        if (!(d->dev_alpha[j] > 0.0) || !(d->dev_nu[j] > 0.0) || !finite(d->dev_nu[j])) return CELESTE_EINVAL;
+    if (!(d->prior_phi > 0.0 && d->prior_phi < 1.0)) return CELESTE_EINVAL;
+    for (int t = 0; t < 2; ++t) {
+        if (!finite(d->prior_r[t][0]) || !(d->prior_r[t][1] > 0.0)) return CELESTE_EINVAL;
+        for (int k = 0; k < 4; ++k)
+            if (!finite(d->prior_c[t][0][k]) || !(d->prior_c[t][1][k] > 0.0)) return CELESTE_EINVAL;
+    }
+    return CELESTE_OK;
+}
+
+// ---------------------------------------------------------------- launch helpers
+struct Scope {
+    Sel src, pair, item;
+};
+
+Scope scope_all(const celeste_plan* p) {
+    Scope s;
+    s.src = Sel{nullptr, 0, p->n_src};
+    s.pair = Sel{nullptr, 0, (int32_t)p->pairs.size()};
+    s.item = Sel{nullptr, 0, (int32_t)p->items.size()};
+    return s;
+}
+
+Scope scope_source(const celeste_plan* p, int s) {
+    Scope sc;
+    const int pb = p->patch_ptr[s], pe = p->patch_ptr[s + 1];
+    sc.src = Sel{nullptr, s, 1};
+    sc.pair = Sel{nullptr, pb, pe - pb};
+    const int ib = pb < pe ? p->pairs[pb].item_begin : 0;
+    const int ie = pb < pe ? p->pairs[pe - 1].item_end : 0;
+    sc.item = Sel{nullptr, ib, ie - ib};
+    return sc;
+}
+
+int prep(celeste_plan* p, const double* theta, const Sel& pairs, bool tangent, int dir_mode,
+         const double* dir, int dir_unit, hipStream_t st) {
+    PrepArgs a{};
+    a.g = p->geom();
+    a.theta = theta;
+    a.dir = dir;
+    a.dir_mode = dir_mode;
+    a.dir_unit = dir_unit;
+    a.pairs = pairs;
+    a.tab = tangent ? p->d_tab2 : p->d_tab1;
+    a.coef = tangent ? p->d_coef2 : p->d_coef1;
+    a.status = p->d_status;
+    HIPCHK(launch_prep(a, tangent, st));
+    return CELESTE_OK;
+}
+
+int render(celeste_plan* p, bool sums, hipStream_t st) {
+    RenderArgs a{};
+    a.g = p->geom();
+    a.tiles = p->d_tiles;
+    a.tile_list = p->d_tile_list;
+    a.n_tiles = (int32_t)p->tiles.size();
+    a.tile_h = p->tile_h;
+    a.tile_w = p->tile_w;
+    a.tab = p->d_tab1;
+    a.coef = p->d_coef1;
+    a.E = p->d_E;
+    a.V = p->d_V;
+    a.tile_sums = sums ? p->d_tile_sums : nullptr;
+    a.status = p->d_status;
+    HIPCHK(launch_render(a, 4, st));
+    return CELESTE_OK;
+}
+
+int adjoint(celeste_plan* p, const Sel& items, const uint8_t* active, bool tangent, int base, bool deriv,
+            hipStream_t st, int grid_override = 0) {
+    AdjArgs a{};
+    a.g = p->geom();
+    a.items = items;
+    a.active = active;
+    a.tab = tangent ? p->d_tab2 : p->d_tab1;
+    a.coef = tangent ? p->d_coef2 : p->d_coef1;
+    a.tab_val = p->d_tab1;
+    a.coef_val = p->d_coef1;
+    a.tab_val_stride = 1;
+    a.dynamic = p->dynamic;
+    a.counter = p->d_counter;
+    a.E = p->d_E;
+    a.V = p->d_V;
+    a.bg = p->d_bg;
+    a.partials = p->d_partials;
+    a.status = p->d_status;
+    const int grid = grid_override > 0 ? grid_override : p->persistent_grid();
+    HIPCHK(launch_adjoint(a, tangent, base, deriv, grid, p->wpb, st));
+    return CELESTE_OK;
+}
+
+int finalize(celeste_plan* p, const double* theta, const Sel& srcs, const uint8_t* active, bool tangent,
+             int dir_mode, const double* dir, int dir_unit, bool deriv, double* elbo, double* grad,
+             double* tan_out, int64_t tan_stride, bool tan_by_list, hipStream_t st) {
+    const bool pad = tan_out && tan_stride == ROW;
+    FinArgs a{};
+    a.g = p->geom();
+    a.srcs = srcs;
+    a.active = active;
+    a.theta = theta;
+    a.dir = dir;
+    a.dir_mode = dir_mode;
+    a.dir_unit = dir_unit;
+    a.patch_ptr = p->d_patch_ptr;
+    a.partials = p->d_partials;
+    a.deriv = deriv ? 1 : 0;
+    a.elbo = elbo;
+    a.grad = grad;
+    a.tangent = tan_out;
+    a.tangent_stride = tan_stride;
+    a.tangent_by_list = tan_by_list ? 1 : 0;
+    a.tangent_pad = pad ? 1 : 0;
+    a.status = p->d_status;
+    HIPCHK(launch_finalize(a, tangent, st));
+    return CELESTE_OK;
+}
+
+int background(celeste_plan* p, const Sel& items, hipStream_t st) {
+    BgArgs a{};
+    a.g = p->geom();
+    a.items = items;
+    a.tab_val = p->d_tab1;
+    a.coef_val = p->d_coef1;
+    a.bg = p->d_bg;
+    a.status = p->d_status;
+    HIPCHK(launch_background(a, p->persistent_grid(), p->wpb, st));
+    return CELESTE_OK;
+}
+
+#define CHK(x)                              \
+    do {                                    \
+        int r_ = (x);                       \
+        if (r_ != CELESTE_OK) return r_;    \
+    } while (0)
+
+int validate_theta(celeste_plan* p, const double* theta, const uint8_t* active, const int32_t* d_list, int n,
+                   hipStream_t st) {
+    HIPCHK(launch_validate(theta, active, d_list, n, p->n_src, p->d_status, st));
+    return CELESTE_OK;
+}
+
+// Batched evaluation: validate, tables, render, fused adjoint, finalize.
+int batched_sequence(celeste_plan* p, const double* theta, const uint8_t* active, bool deriv, double* elbo,
+                     double* grad, hipStream_t st) {
+    const Scope sc = scope_all(p);
+    CHK(validate_theta(p, theta, active, nullptr, p->n_src, st));
+    CHK(prep(p, theta, sc.pair, false, DIR_NONE, nullptr, 0, st));
+    CHK(render(p, false, st));
+    CHK(adjoint(p, sc.item, active, false, BASE_PLANES, deriv, st));
+    CHK(finalize(p, theta, sc.src, active, false, DIR_NONE, nullptr, 0, deriv, elbo, grad, nullptr, 0, false, st));
+    return CELESTE_OK;
+}
+
+int plain_sequence(celeste_plan* p, const double* theta, const uint8_t* active, bool deriv, double* elbo,
+                   double* grad, hipStream_t st) {
+    const Scope all = scope_all(p);
+    CHK(validate_theta(p, theta, active, nullptr, p->n_src, st));
+    CHK(prep(p, theta, all.pair, false, DIR_NONE, nullptr, 0, st));
+    for (int s = 0; s < p->n_src; ++s) {
+        const Scope sc = scope_source(p, s);
+        CHK(adjoint(p, sc.item, active, false, BASE_NBR, deriv, st));
+        CHK(finalize(p, theta, sc.src, active, false, DIR_NONE, nullptr, 0, deriv, elbo, grad, nullptr, 0, false,
+                     st));
+    }
+    return CELESTE_OK;
+}
+
+int config_code(const celeste_plan* p) {
+    return ((p->chunk * 8 + p->wpb) * 2 + p->dynamic) * 1000003 + p->persistent_grid() * 131 + p->tile_h;
+}
+
+// Lists of boxes and items of a set of sources (host), uploaded into the plan's list buffers
+// at the given offsets.
+struct HostScope {
+    std::vector<int32_t> src, pair, item;
+};
+
+void scope_lists(const celeste_plan* p, const int32_t* src, int n, HostScope& hs) {
+    for (int j = 0; j < n; ++j) {
+        const int s = src[j];
+        hs.src.push_back(s);
+        for (int pi = p->patch_ptr[s]; pi < p->patch_ptr[s + 1]; ++pi) {
+            hs.pair.push_back(pi);
+            for (int it = p->pairs[pi].item_begin; it < p->pairs[pi].item_end; ++it) hs.item.push_back(it);
+        }
+    }
+}
+
+int fill_u8(uint8_t* d, const Sel& srcs, uint8_t v, hipStream_t st) {
+    HIPCHK(launch_fill_u8_sel(d, srcs, v, st));
+    return CELESTE_OK;
+}
+
+int fill_f64(double* d, const Sel& srcs, double v, hipStream_t st) {
+    HIPCHK(launch_fill_f64_sel(d, srcs, v, st));
+    return CELESTE_OK;
+}
+
+// Newton trust-region iterations for one source set; lists already on the device.
+int newton_run(celeste_plan* p, double* theta, const Sel& src, const Sel& pair, const Sel& item, int n_steps,
+               const celeste_tr_params* prm, double* radius, hipStream_t st) {
+    const Scope all = scope_all(p);
+    // background of every listed visit with all sources at their entry values
+    CHK(prep(p, theta, all.pair, false, DIR_NONE, nullptr, 0, st));
+    CHK(background(p, item, st));
+    TrArgs tr{};
+    tr.srcs = src;
+    tr.theta = theta;
+    tr.grad = p->d_grad;
+    tr.hess = p->d_hess;
+    tr.radius = radius;
+    tr.theta_trial = p->d_theta_trial;
+    tr.pred = p->d_pred;
+    tr.elbo_cur = p->d_elbo_cur;
+    tr.elbo_trial = p->d_elbo_trial;
+    tr.done = p->d_done;
+    tr.eta_accept = prm->eta_accept;
+    tr.radius_max = prm->radius_max;
+    tr.gtol = prm->gtol;
+    tr.status = p->d_status;
+    for (int it = 0; it < n_steps; ++it) {
+        CHK(prep(p, theta, pair, false, DIR_NONE, nullptr, 0, st));
+        CHK(adjoint(p, item, nullptr, false, BASE_BG, true, st));
+        CHK(finalize(p, theta, src, nullptr, false, DIR_NONE, nullptr, 0, true, p->d_elbo_cur, p->d_grad, nullptr,
+                     0, false, st));
+        for (int i = 0; i < NP; ++i) {
+            CHK(prep(p, theta, pair, true, DIR_UNIT, nullptr, i, st));
+            CHK(adjoint(p, item, nullptr, true, BASE_BG, true, st));
+            CHK(finalize(p, theta, src, nullptr, true, DIR_UNIT, nullptr, i, true, nullptr, nullptr,
+                         p->d_hess + (size_t)i * NP, (int64_t)NP * NP, true, st));
+        }
+        HIPCHK(launch_tr_solve(tr, st));
+        CHK(prep(p, p->d_theta_trial, pair, false, DIR_NONE, nullptr, 0, st));
+        CHK(adjoint(p, item, nullptr, false, BASE_BG, false, st));
+        CHK(finalize(p, p->d_theta_trial, src, nullptr, false, DIR_NONE, nullptr, 0, false, p->d_elbo_trial, nullptr,
+                     nullptr, 0, false, st));
+        HIPCHK(launch_tr_update(tr, st));
+    }
+    return CELESTE_OK;
+}
+
+}  // namespace
+
+// ================================================================ C entry points
+extern "C" {
+
+int celeste_version(void) { return CELESTE_ABI_VERSION; }
+
+const char* celeste_last_hip_error(void) { return g_hip_error.c_str(); }
+
+const char* celeste_status_string(int s) {
+    switch (s) {
+        case CELESTE_OK: return "ok";
+        case CELESTE_EINVAL: return "invalid argument, size or geometry";
+        case CELESTE_ECONFLICT: return "batch members share pixels";
+        case CELESTE_EHIP: return "HIP runtime error";
+        case CELESTE_ENOMEM: return "device allocation failed";
+        case CELESTE_EDOMAIN: return "parameters outside their domain";
+        default: return "unknown status";
+    }
+}
+
+void celeste_plan_destroy(celeste_plan* p) {
+    if (!p) return;
+    drop_graph(p);
+    void* bufs[] = {p->d_images, p->d_pairs, p->d_items, p->d_nbr, p->d_tiles, p->d_tile_list, p->d_patch_ptr,
+                    p->d_tab1, p->d_coef1, p->d_tab2, p->d_coef2, p->d_partials, p->d_E, p->d_V, p->d_bg,
+                    p->d_tile_sums, p->d_status, p->d_counter, p->d_grad, p->d_hess, p->d_theta_trial,
+                    p->d_pred, p->d_elbo_cur, p->d_elbo_trial, p->d_radius, p->d_done, p->d_list_src,
+                    p->d_list_pair, p->d_list_item};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    delete p;
+}
+
+int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
+    if (!out) return CELESTE_EINVAL;
+    *out = nullptr;
+    const int v = validate_desc(d);
+    if (v != CELESTE_OK) return v;
+    celeste_plan* p = new celeste_plan();
+    HIPCHK(hipGetDevice(&p->device));
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess && prop.multiProcessorCount > 0)
+        p->n_cu = prop.multiProcessorCount;
+    p->n_img = d->n_img;
+    p->n_src = d->n_src;
+    p->n_pix = d->n_pix;
+    p->d_x = d->x;
+    p->images.assign(d->images, d->images + d->n_img);
+    p->patch_ptr.assign(d->patch_ptr, d->patch_ptr + d->n_src + 1);
+    std::memcpy(p->consts.exp_alpha, d->exp_alpha, sizeof(d->exp_alpha));
+    std::memcpy(p->consts.exp_nu, d->exp_nu, sizeof(d->exp_nu));
+    std::memcpy(p->consts.dev_alpha, d->dev_alpha, sizeof(d->dev_alpha));
+    std::memcpy(p->consts.dev_nu, d->dev_nu, sizeof(d->dev_nu));
+    p->consts.prior_phi = d->prior_phi;
+    std::memcpy(p->consts.prior_r, d->prior_r, sizeof(d->prior_r));
+    std::memcpy(p->consts.prior_c, d->prior_c, sizeof(d->prior_c));
+    p->consts.flags = d->flags;
+    const int nb = d->patch_ptr[d->n_src];
+    p->pairs.resize(nb);
+    int64_t voff = 0;
+    for (int s = 0; s < d->n_src; ++s)
+        for (int b = d->patch_ptr[s]; b < d->patch_ptr[s + 1]; ++b) {
+            const celeste_box& bx = d->boxes[b];
+            PairDev& pd = p->pairs[b];
+            pd.src = s;
+            pd.img = bx.img;
+            pd.r0 = bx.r0;
+            pd.c0 = bx.c0;
+            pd.h = bx.h;
+            pd.w = bx.w;
+            pd.visit_off = voff;
+            voff += (int64_t)bx.h * bx.w;
+        }
+    p->n_visits = voff;
+    build_items(p);
+    build_nbr(p);
+    build_tiles(p);
+    // capacity of per-item buffers: the smallest chunk (64 pixels) gives the most items
+    size_t max_items = 0;
+    for (const PairDev& pd : p->pairs) max_items += (size_t)((int64_t)pd.h * pd.w + 63) / 64;
+    const size_t np = std::max<size_t>(p->pairs.size(), 1);
+    size_t& W = p->workspace;
+    int r = CELESTE_OK;
+    auto A = [&](int rc) { if (rc != CELESTE_OK && r == CELESTE_OK) r = rc; };
+    A(dalloc(&p->d_images, p->n_img, W));
+    A(dalloc(&p->d_pairs, np, W));
+    A(dalloc(&p->d_items, max_items, W));
+    p->cap_items = max_items;
+    A(dalloc(&p->d_nbr, std::max<size_t>(p->nbr.size(), 1), W));
+    A(dalloc(&p->d_tiles, p->tiles.size(), W));
+    p->cap_tiles = p->tiles.size();
+    A(dalloc(&p->d_tile_list, p->tile_list.size(), W));
+    p->cap_tile_list = p->tile_list.size();
+    A(dalloc(&p->d_patch_ptr, (size_t)p->n_src + 1, W));
+    A(dalloc(&p->d_tab1, np * NCOMP * CST, W));
+    A(dalloc(&p->d_coef1, np * NCOEF, W));
+    A(dalloc(&p->d_tab2, np * NCOMP * CST * 2, W));
+    A(dalloc(&p->d_coef2, np * NCOEF * 2, W));
+    A(dalloc(&p->d_partials, max_items * NACC * 2, W));
+    A(dalloc(&p->d_E, (size_t)p->n_pix, W));
+    A(dalloc(&p->d_V, (size_t)p->n_pix, W));
+    A(dalloc(&p->d_bg, (size_t)p->n_visits * 2, W));
+    A(dalloc(&p->d_tile_sums, std::max<size_t>(p->tiles.size(), 1), W));
+    A(dalloc(&p->d_status, 1, W));
+    A(dalloc(&p->d_counter, 1, W));
+    const size_t S = (size_t)p->n_src;
+    A(dalloc(&p->d_grad, S * ROW, W));
+    A(dalloc(&p->d_hess, S * NP * NP, W));
+    A(dalloc(&p->d_theta_trial, S * ROW, W));
+    A(dalloc(&p->d_pred, S * 2, W));
+    A(dalloc(&p->d_elbo_cur, S, W));
+    A(dalloc(&p->d_elbo_trial, S, W));
+    A(dalloc(&p->d_radius, S, W));
+    A(dalloc(&p->d_done, S, W));
+    A(dalloc(&p->d_list_src, S, W));
+    A(dalloc(&p->d_list_pair, np, W));
+    A(dalloc(&p->d_list_item, max_items, W));
+    p->cap_list_item = max_items;
+    if (r != CELESTE_OK) {
+        celeste_plan_destroy(p);
+        return r;
+    }
+    int rc = upload_geometry(p);
+    if (rc == CELESTE_OK) {
+        if (hipMemcpy(p->d_images, p->images.data(), p->images.size() * sizeof(celeste_image),
+                      hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(p->d_nbr, p->nbr.data(), p->nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(p->d_patch_ptr, p->patch_ptr.data(), p->patch_ptr.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemset(p->d_status, 0, sizeof(int)) != hipSuccess ||
+            hipMemset(p->d_counter, 0, sizeof(int)) != hipSuccess ||
+            hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            rc = hip_fail(hipGetLastError(), "plan upload");
+    }
+    if (rc != CELESTE_OK) {
+        celeste_plan_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return CELESTE_OK;
+}
+
+int celeste_plan_get_info(const celeste_plan* p, celeste_plan_info* info) {
+    if (!p || !info) return CELESTE_EINVAL;
+    info->n_visits = p->n_visits;
+    info->n_pairs = (int64_t)p->pairs.size();
+    info->n_items = (int64_t)p->items.size();
+    info->n_tiles = (int64_t)p->tiles.size();
+    info->n_nbr = (int64_t)p->nbr.size();
+    info->chunk = p->chunk;
+    info->waves_per_block = p->wpb;
+    info->grid_blocks = p->persistent_grid();
+    info->tile_h = p->tile_h;
+    info->tile_w = p->tile_w;
+    info->dynamic_queue = p->dynamic;
+    info->workspace_bytes = (int64_t)p->workspace;
+    return CELESTE_OK;
+}
+
+int celeste_plan_set_launch(celeste_plan* p, int chunk, int wpb, int grid, int dynamic, int tile_h, int tile_w) {
+    if (!p || chunk < 64 || chunk > 1024 || chunk % 64 || (wpb != 1 && wpb != 2 && wpb != 4) || grid < 1 ||
+        (dynamic != 0 && dynamic != 1) || tile_h < 1 || tile_w < 1 || tile_h * tile_w != 64)
+        return CELESTE_EINVAL;
+    HIPCHK(hipDeviceSynchronize());
+    drop_graph(p);
+    p->chunk = chunk;
+    p->wpb = wpb;
+    p->grid = grid;
+    p->dynamic = dynamic;
+    if (tile_h != p->tile_h || tile_w != p->tile_w) {
+        p->tile_h = tile_h;
+        p->tile_w = tile_w;
+        build_tiles(p);
+        if (p->tiles.size() > p->cap_tiles) {
+            (void)hipFree(p->d_tiles);
+            (void)hipFree(p->d_tile_sums);
+            if (hipMalloc((void**)&p->d_tiles, p->tiles.size() * sizeof(TileDev)) != hipSuccess ||
+                hipMalloc((void**)&p->d_tile_sums, p->tiles.size() * sizeof(double)) != hipSuccess)
+                return CELESTE_ENOMEM;
+            p->cap_tiles = p->tiles.size();
+        }
+        if (p->tile_list.size() > p->cap_tile_list) {
+            (void)hipFree(p->d_tile_list);
+            if (hipMalloc((void**)&p->d_tile_list, p->tile_list.size() * sizeof(int32_t)) != hipSuccess)
+                return CELESTE_ENOMEM;
+            p->cap_tile_list = p->tile_list.size();
+        }
+    }
+    build_items(p);
+    return upload_geometry(p);
+}
+
+int celeste_plan_use_graph(celeste_plan* p, int enable) {
+    if (!p) return CELESTE_EINVAL;
+    p->use_graph = enable != 0;
+    if (!p->use_graph) drop_graph(p);
+    return CELESTE_OK;
+}
+
+int celeste_plan_status(celeste_plan* p, hipStream_t st) {
+    if (!p) return CELESTE_EINVAL;
+    HIPCHK(hipStreamSynchronize(st));
+    int s = 0;
+    HIPCHK(hipMemcpy(&s, p->d_status, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemset(p->d_status, 0, sizeof(int)));
+    return s;
+}
+
+int celeste_elbo(celeste_plan* p, const double* theta, const uint8_t* active, int mode, double* elbo,
+                 hipStream_t st) {
+    if (!p || !theta || !elbo || (mode != CELESTE_PLAIN && mode != CELESTE_BATCHED)) return CELESTE_EINVAL;
+    if (mode == CELESTE_BATCHED) return batched_sequence(p, theta, active, false, elbo, nullptr, st);
+    return plain_sequence(p, theta, active, false, elbo, nullptr, st);
+}
+
+int celeste_elbo_grad(celeste_plan* p, const double* theta, const uint8_t* active, int mode, double* elbo,
+                      double* grad, hipStream_t st) {
+    if (!p || !theta || !elbo || !grad || (mode != CELESTE_PLAIN && mode != CELESTE_BATCHED))
+        return CELESTE_EINVAL;
+    if (mode == CELESTE_PLAIN) return plain_sequence(p, theta, active, true, elbo, grad, st);
+    if (!p->use_graph) return batched_sequence(p, theta, active, true, elbo, grad, st);
+    const void* key[4] = {theta, active, elbo, grad};
+    const int cfg = config_code(p);
+    if (!p->gexec || std::memcmp(key, p->gkey, sizeof(key)) != 0 || cfg != p->gkey_cfg) {
+        drop_graph(p);
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+        const int rc = batched_sequence(p, theta, active, true, elbo, grad, p->cap_stream);
+        const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+        if (rc != CELESTE_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        const hipError_t e2 = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e2 != hipSuccess) {
+            p->gexec = nullptr;
+            return hip_fail(e2, "hipGraphInstantiate");
+        }
+        std::memcpy(p->gkey, key, sizeof(key));
+        p->gkey_cfg = cfg;
+    }
+    HIPCHK(hipGraphLaunch(p->gexec, st));
+    return CELESTE_OK;
+}
+
+int celeste_hvp(celeste_plan* p, const double* theta, const double* v, double* hv, double* grad, hipStream_t st) {
+    if (!p || !theta || !v || !hv) return CELESTE_EINVAL;
+    const Scope sc = scope_all(p);
+    CHK(validate_theta(p, theta, nullptr, nullptr, p->n_src, st));
+    CHK(prep(p, theta, sc.pair, false, DIR_NONE, nullptr, 0, st));
+    CHK(render(p, false, st));
+    CHK(prep(p, theta, sc.pair, true, DIR_VEC, v, 0, st));
+    CHK(adjoint(p, sc.item, nullptr, true, BASE_PLANES, true, st));
+    CHK(finalize(p, theta, sc.src, nullptr, true, DIR_VEC, v, 0, true, nullptr, grad, hv, ROW, false, st));
+    return CELESTE_OK;
+}
+
+int celeste_hessian(celeste_plan* p, const double* theta, const int32_t* src, int n, double* hess,
+                    hipStream_t st) {
+    if (!p || !theta || !src || n <= 0 || n > p->n_src || !hess) return CELESTE_EINVAL;
+    std::vector<char> seen(p->n_src, 0);
+    for (int j = 0; j < n; ++j) {
+        if (src[j] < 0 || src[j] >= p->n_src || seen[src[j]]) return CELESTE_EINVAL;
+        seen[src[j]] = 1;
+    }
+    HostScope hs;
+    scope_lists(p, src, n, hs);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(p->d_list_src, hs.src.data(), hs.src.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(p->d_list_pair, hs.pair.data(), hs.pair.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(p->d_list_item, hs.item.data(), hs.item.size() * 4, hipMemcpyHostToDevice));
+    const Sel ss{p->d_list_src, 0, (int32_t)hs.src.size()};
+    const Sel sp{p->d_list_pair, 0, (int32_t)hs.pair.size()};
+    const Sel si{p->d_list_item, 0, (int32_t)hs.item.size()};
+    const Scope all = scope_all(p);
+    CHK(validate_theta(p, theta, nullptr, nullptr, p->n_src, st));
+    CHK(prep(p, theta, all.pair, false, DIR_NONE, nullptr, 0, st));
+    CHK(render(p, false, st));
+    for (int i = 0; i < NP; ++i) {
+        CHK(prep(p, theta, sp, true, DIR_UNIT, nullptr, i, st));
+        CHK(adjoint(p, si, nullptr, true, BASE_PLANES, true, st));
+        CHK(finalize(p, theta, ss, nullptr, true, DIR_UNIT, nullptr, i, true, nullptr, nullptr, hess + (size_t)i * NP,
+                     (int64_t)NP * NP, true, st));
+    }
+    return CELESTE_OK;
+}
+
+int celeste_total_elbo(celeste_plan* p, const double* theta, double* out, hipStream_t st) {
+    if (!p || !theta || !out) return CELESTE_EINVAL;
+    const Scope sc = scope_all(p);
+    CHK(validate_theta(p, theta, nullptr, nullptr, p->n_src, st));
+    CHK(prep(p, theta, sc.pair, false, DIR_NONE, nullptr, 0, st));
+    CHK(render(p, true, st));
+    HIPCHK(launch_tile_total(p->d_tile_sums, (int)p->tiles.size(), theta, p->consts, p->n_src, out, p->d_status, st));
+    return CELESTE_OK;
+}
+
+int celeste_newton(celeste_plan* p, double* theta, const int32_t* src, int n, int n_steps,
+                   const celeste_tr_params* prm, double* radius, double* elbo_out, hipStream_t st) {
+    if (!p || !theta || !src || n <= 0 || n > p->n_src || n_steps < 0 || !prm || !radius) return CELESTE_EINVAL;
+    if (!(prm->radius0 > 0.0) || !(prm->radius_max >= prm->radius0) || !(prm->eta_accept >= 0.0) ||
+        !(prm->eta_accept < 0.25) || !(prm->gtol >= 0.0))
+        return CELESTE_EINVAL;
+    std::vector<char> seen(p->n_src, 0);
+    for (int j = 0; j < n; ++j) {
+        if (src[j] < 0 || src[j] >= p->n_src || seen[src[j]]) return CELESTE_EINVAL;
+        seen[src[j]] = 1;
+    }
+    HostScope hs;
+    scope_lists(p, src, n, hs);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(p->d_list_src, hs.src.data(), hs.src.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(p->d_list_pair, hs.pair.data(), std::max<size_t>(hs.pair.size(), 1) * 4, hipMemcpyHostToDevice));
+    if (!hs.item.empty())
+        HIPCHK(hipMemcpy(p->d_list_item, hs.item.data(), hs.item.size() * 4, hipMemcpyHostToDevice));
+    const Sel ss{p->d_list_src, 0, (int32_t)hs.src.size()};
+    const Sel sp{p->d_list_pair, 0, (int32_t)hs.pair.size()};
+    const Sel si{p->d_list_item, 0, (int32_t)hs.item.size()};
+    CHK(validate_theta(p, theta, nullptr, p->d_list_src, n, st));
+    CHK(fill_u8(p->d_done, ss, 0, st));
+    CHK(newton_run(p, theta, ss, sp, si, n_steps, prm, radius, st));
+    if (elbo_out) {
+        // final ELBO_s at the returned point
+        CHK(prep(p, theta, sp, false, DIR_NONE, nullptr, 0, st));
+        CHK(adjoint(p, si, nullptr, false, BASE_BG, false, st));
+        CHK(finalize(p, theta, ss, nullptr, false, DIR_NONE, nullptr, 0, false, elbo_out, nullptr, nullptr, 0, false,
+                     st));
+    }
+    return CELESTE_OK;
+}
+
+int celeste_color_batches(const celeste_plan* p, uint64_t seed, int32_t* batch_ptr, int32_t* batch_src,
+                          int32_t* n_batches) {
+    if (!p || !batch_ptr || !batch_src || !n_batches) return CELESTE_EINVAL;
+    const int S = p->n_src;
+    std::vector<std::vector<int32_t>> adj(S);
+    for (const PairDev& pd : p->pairs)
+        for (int k = pd.nbr_begin; k < pd.nbr_end; ++k) {
+            const int t = p->pairs[p->nbr[k]].src;
+            if (t != pd.src) adj[pd.src].push_back(t);
+        }
+    std::vector<int32_t> order(S);
+    std::iota(order.begin(), order.end(), 0);
+    std::mt19937_64 rng(seed);
+    for (int i = S - 1; i > 0; --i) {   // Fisher-Yates with the engine's raw output
+        const int j = (int)(rng() % (uint64_t)(i + 1));
+        std::swap(order[i], order[j]);
+    }
+    std::vector<int32_t> color(S, -1);
+    int n_col = 0;
+    std::vector<int32_t> mark;
+    for (int s : order) {
+        for (int t : adj[s])
+            if (color[t] >= 0) {
+                if ((int)mark.size() <= color[t]) mark.resize(color[t] + 1, -1);
+                mark[color[t]] = s;
+            }
+        int c = 0;
+        while (c < (int)mark.size() && mark[c] == s) ++c;
+        color[s] = c;
+        n_col = std::max(n_col, c + 1);
+    }
+    std::vector<int32_t> cnt(n_col + 1, 0);
+    for (int s = 0; s < S; ++s) cnt[color[s] + 1]++;
+    for (int c = 0; c < n_col; ++c) cnt[c + 1] += cnt[c];
+    for (int c = 0; c <= n_col; ++c) batch_ptr[c] = cnt[c];
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int s = 0; s < S; ++s) batch_src[fill[color[s]]++] = s;
+    *n_batches = n_col;
+    return CELESTE_OK;
+}
+
+int celeste_sweep(celeste_plan* p, double* theta, const int32_t* batch_ptr, const int32_t* batch_src, int n_batches,
+                  int n_sweeps, const celeste_tr_params* prm, double* elbo_trace, hipStream_t st) {
+    if (!p || !theta || !batch_ptr || !batch_src || n_batches <= 0 || n_sweeps < 0 || !prm || !elbo_trace)
+        return CELESTE_EINVAL;
+    if (!(prm->radius0 > 0.0) || !(prm->radius_max >= prm->radius0) || !(prm->eta_accept >= 0.0) ||
+        !(prm->eta_accept < 0.25) || !(prm->gtol >= 0.0) || prm->newton_steps < 0)
+        return CELESTE_EINVAL;
+    if (batch_ptr[0] != 0) return CELESTE_EINVAL;
+    for (int b = 0; b < n_batches; ++b)
+        if (batch_ptr[b + 1] < batch_ptr[b]) return CELESTE_EINVAL;
+    const int total = batch_ptr[n_batches];
+    for (int k = 0; k < total; ++k)
+        if (batch_src[k] < 0 || batch_src[k] >= p->n_src) return CELESTE_EINVAL;
+    // conflict check: no two members of a batch share a pixel; no source twice in a batch
+    std::vector<int32_t> in_batch(p->n_src, -1);
+    for (int b = 0; b < n_batches; ++b) {
+        for (int k = batch_ptr[b]; k < batch_ptr[b + 1]; ++k) {
+            if (in_batch[batch_src[k]] == b) return CELESTE_EINVAL;
+            in_batch[batch_src[k]] = b;
+        }
+        for (int k = batch_ptr[b]; k < batch_ptr[b + 1]; ++k) {
+            const int s = batch_src[k];
+            for (int pi = p->patch_ptr[s]; pi < p->patch_ptr[s + 1]; ++pi)
+                for (int q = p->pairs[pi].nbr_begin; q < p->pairs[pi].nbr_end; ++q) {
+                    const int t = p->pairs[p->nbr[q]].src;
+                    if (t != s && in_batch[t] == b) return CELESTE_ECONFLICT;
+                }
+        }
+    }
+    // all batches' lists, concatenated
+    HostScope hs;
+    std::vector<int32_t> off_src(n_batches + 1), off_pair(n_batches + 1), off_item(n_batches + 1);
+    for (int b = 0; b < n_batches; ++b) {
+        off_src[b] = (int32_t)hs.src.size();
+        off_pair[b] = (int32_t)hs.pair.size();
+        off_item[b] = (int32_t)hs.item.size();
+        scope_lists(p, batch_src + batch_ptr[b], batch_ptr[b + 1] - batch_ptr[b], hs);
+    }
+    off_src[n_batches] = (int32_t)hs.src.size();
+    off_pair[n_batches] = (int32_t)hs.pair.size();
+    off_item[n_batches] = (int32_t)hs.item.size();
+    // list buffers sized for one appearance of each source; grow if a schedule repeats sources
+    HIPCHK(hipStreamSynchronize(st));
+    int32_t *dl_src = p->d_list_src, *dl_pair = p->d_list_pair, *dl_item = p->d_list_item;
+    std::vector<void*> temp;
+    if (hs.src.size() > (size_t)p->n_src || hs.pair.size() > p->pairs.size() || hs.item.size() > p->cap_list_item) {
+        if (hipMalloc((void**)&dl_src, hs.src.size() * 4) != hipSuccess) return CELESTE_ENOMEM;
+        temp.push_back(dl_src);
+        if (hipMalloc((void**)&dl_pair, std::max<size_t>(hs.pair.size(), 1) * 4) != hipSuccess) return CELESTE_ENOMEM;
+        temp.push_back(dl_pair);
+        if (hipMalloc((void**)&dl_item, std::max<size_t>(hs.item.size(), 1) * 4) != hipSuccess) return CELESTE_ENOMEM;
+        temp.push_back(dl_item);
+    }
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);
+        for (void* t : temp) (void)hipFree(t);
+    };
+    if (hipMemcpy(dl_src, hs.src.data(), hs.src.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        (!hs.pair.empty() &&
+         hipMemcpy(dl_pair, hs.pair.data(), hs.pair.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+        (!hs.item.empty() &&
+         hipMemcpy(dl_item, hs.item.data(), hs.item.size() * 4, hipMemcpyHostToDevice) != hipSuccess)) {
+        cleanup();
+        return hip_fail(hipGetLastError(), "sweep list upload");
+    }
+    int rc = CELESTE_OK;
+    do {
+        rc = celeste_total_elbo(p, theta, elbo_trace, st);
+        if (rc != CELESTE_OK) break;
+        for (int sw = 0; sw < n_sweeps && rc == CELESTE_OK; ++sw) {
+            for (int b = 0; b < n_batches && rc == CELESTE_OK; ++b) {
+                const Sel ss{dl_src + off_src[b], 0, off_src[b + 1] - off_src[b]};
+                const Sel sp{dl_pair + off_pair[b], 0, off_pair[b + 1] - off_pair[b]};
+                const Sel si{dl_item + off_item[b], 0, off_item[b + 1] - off_item[b]};
+                if (ss.n == 0) continue;
+                rc = fill_u8(p->d_done, ss, 0, st);
+                if (rc != CELESTE_OK) break;
+                // fresh trust region for every visit of a batch
+                rc = fill_f64(p->d_radius, ss, prm->radius0, st);
+                if (rc != CELESTE_OK) break;
+                rc = newton_run(p, theta, ss, sp, si, prm->newton_steps, prm, p->d_radius, st);
+            }
+            if (rc == CELESTE_OK) rc = celeste_total_elbo(p, theta, elbo_trace + sw + 1, st);
+        }
+    } while (0);
+    cleanup();
+    return rc;
+}
+
+int celeste_autotune(celeste_plan* p, const double* theta, int reps, double* best_ms, hipStream_t st) {
+    if (!p || !theta || reps < 1) return CELESTE_EINVAL;
+    double* d_elbo = nullptr;
+    double* d_grad = nullptr;
+    if (hipMalloc((void**)&d_elbo, (size_t)p->n_src * 8) != hipSuccess) return CELESTE_ENOMEM;
+    if (hipMalloc((void**)&d_grad, (size_t)p->n_src * ROW * 8) != hipSuccess) {
+        (void)hipFree(d_elbo);
+        return CELESTE_ENOMEM;
+    }
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const bool graph = p->use_graph;
+    p->use_graph = false;
+    auto time_cfg = [&](double& ms) -> int {
+        std::vector<double> t;
+        for (int r = 0; r < reps + 1; ++r) {
+            HIPCHK(hipEventRecord(e0, st));
+            CHK(batched_sequence(p, theta, nullptr, true, d_elbo, d_grad, st));
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float f = 0.f;
+            HIPCHK(hipEventElapsedTime(&f, e0, e1));
+            if (r > 0) t.push_back(f);
+        }
+        std::sort(t.begin(), t.end());
+        ms = t[t.size() / 2];
+        return CELESTE_OK;
+    };
+    struct Cfg { int chunk, wpb, grid, dyn, th, tw; };
+    Cfg best{p->chunk, p->wpb, p->persistent_grid(), p->dynamic, p->tile_h, p->tile_w};
+    double best_t = 1e300;
+    int rc = celeste_plan_set_launch(p, best.chunk, best.wpb, best.grid, best.dyn, best.th, best.tw);
+    if (rc == CELESTE_OK) rc = time_cfg(best_t);
+    auto trial = [&](Cfg c) {
+        if (rc != CELESTE_OK) return;
+        rc = celeste_plan_set_launch(p, c.chunk, c.wpb, c.grid, c.dyn, c.th, c.tw);
+        if (rc != CELESTE_OK) return;
+        double t = 0;
+        rc = time_cfg(t);
+        if (rc == CELESTE_OK && t < best_t) {
+            best_t = t;
+            best = c;
+        }
+    };
+    const int tiles[3][2] = {{8, 8}, {4, 16}, {16, 4}};
+    for (auto& tl : tiles) trial(Cfg{best.chunk, best.wpb, best.grid, best.dyn, tl[0], tl[1]});
+    for (int ch : {64, 128, 256, 512, 1024}) trial(Cfg{ch, best.wpb, best.grid, best.dyn, best.th, best.tw});
+    for (int w : {1, 2, 4}) trial(Cfg{best.chunk, w, best.grid, best.dyn, best.th, best.tw});
+    for (int g : {p->n_cu, 2 * p->n_cu, 4 * p->n_cu, 8 * p->n_cu, 16 * p->n_cu, 64 * p->n_cu})
+        trial(Cfg{best.chunk, best.wpb, g, best.dyn, best.th, best.tw});
+    for (int d : {0, 1}) trial(Cfg{best.chunk, best.wpb, best.grid, d, best.th, best.tw});
+    if (rc == CELESTE_OK) rc = celeste_plan_set_launch(p, best.chunk, best.wpb, best.grid, best.dyn, best.th, best.tw);
+    p->use_graph = graph;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(d_elbo);
+    (void)hipFree(d_grad);
+    if (best_ms) *best_ms = best_t;
+    return rc;
+}
+
+}  // extern "C"

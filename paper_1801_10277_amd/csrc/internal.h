@@ -1,0 +1,198 @@
+// Internal layouts shared by the HIP kernels and the host side of libceleste.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "celeste.h"
+#include "dual.h"
+
+namespace cel {
+
+constexpr int NPSF = 3;
+constexpr int NDEV = 8;
+constexpr int NEXP = 6;
+constexpr int NGAL_PER_PSF = NDEV + NEXP;                 // 14
+constexpr int NCOMP = NPSF * (1 + NGAL_PER_PSF);           // 45 Gaussians per (source, image)
+constexpr int CST = 10;                                    // fields per component entry
+constexpr int NP = 27;                                     // parameters per source
+constexpr int ROW = 32;                                    // padded row of theta / grad
+constexpr int NCOEF = 4;                                   // per-(source, image) brightness factors
+
+// Fields of one component entry of a (source, image) table.  For the Gaussian
+// N(p; mean, S) scaled by a weight w: log_w = log(w / (2 pi sqrt(det S))), P = S^-1.
+enum CompField {
+    F_CX = 0, F_CY, F_PXX, F_PXY, F_PYY, F_LOGW,
+    F_WT,    // galaxy: frac_dev (de Vaucouleurs) or 1 - frac_dev (exponential); star: 1
+    F_WNU,   // galaxy: F_WT * nu_j (the component covariance is nu_j Sigma_shape + PSF)
+    F_SGN,   // +1 de Vaucouleurs, -1 exponential, 0 star
+    F_PAD
+};
+
+// Per-(source, image) brightness factors: the source's expected light is
+// k1 f_star + k2 f_gal and its second moment k3 f_star^2 + k4 f_gal^2 with
+// k1 = iota q E[flux|star], k2 = iota (1-q) E[flux|gal],
+// k3 = iota^2 q E[flux^2|star], k4 = iota^2 (1-q) E[flux^2|gal].
+enum Coef { C_K1 = 0, C_K2, C_K3, C_K4 };
+
+// Accumulators of one work item (sums over its pixels of the pixel term and of its
+// derivatives with respect to the intermediate quantities of the own source).
+enum AccField {
+    A_VAL = 0,        // sum of pixel terms
+    A_K1, A_K2, A_K3, A_K4,   // d/dk1..k4
+    A_UX, A_UY,       // d/d position
+    A_FDEV,           // d/d frac_dev
+    A_SXX, A_SXY, A_SYY,      // 2 d/dSxx, d/dSxy, 2 d/dSyy of the galaxy shape covariance
+    NACC
+};
+
+struct PairDev {              // one box (source, image)
+    int32_t src, img, r0, c0, h, w;
+    int64_t visit_off;        // first visit of the box in the global visit numbering
+    int32_t item_begin, item_end;   // work items of this box in the full item list
+    int32_t nbr_begin, nbr_end;     // other boxes of the same image that intersect it
+};
+
+struct Item {                 // a chunk of a box's pixels (row-major inside the box)
+    int32_t pair, start, count, pad;
+};
+
+struct TileDev {              // a tile_h x tile_w render tile and its box list
+    int32_t img, r0, c0, list_begin, list_end, pad;
+};
+
+struct Consts {
+    double exp_alpha[NEXP], exp_nu[NEXP], dev_alpha[NDEV], dev_nu[NDEV];
+    double prior_phi, prior_r[2][2], prior_c[2][2][4];
+    uint32_t flags;
+    int32_t pad;
+};
+
+// A subset of sources / boxes / items: entry j is ids[j] if ids is set, else base + j.
+struct Sel {
+    const int32_t* ids;
+    int32_t base, n;
+};
+__host__ __device__ inline int32_t sel_at(const Sel& s, int32_t j) { return s.ids ? s.ids[j] : s.base + j; }
+
+enum BaseMode {
+    BASE_PLANES = 0,   // E, V planes of all sources (own included)
+    BASE_BG = 1,       // per-visit background excluding the own source
+    BASE_NBR = 2       // background evaluated on the fly from the overlapping boxes
+};
+
+// Direction seeding of the tangent pass.
+enum DirMode { DIR_NONE = 0, DIR_VEC = 1, DIR_UNIT = 2 };
+
+struct Geometry {
+    const celeste_image* images;
+    const PairDev* pairs;
+    const Item* items;
+    const int32_t* nbr;
+    const double* x;
+    Consts consts;
+};
+
+struct PrepArgs {
+    Geometry g;
+    const double* theta;       // [S][32]
+    const double* dir;         // [S][32] when dir_mode == DIR_VEC
+    int32_t dir_mode, dir_unit;
+    Sel pairs;
+    double* tab;               // [n_pairs][NCOMP][CST] of T
+    double* coef;              // [n_pairs][NCOEF] of T
+    const int* status;
+};
+
+struct RenderArgs {
+    Geometry g;
+    const TileDev* tiles;
+    const int32_t* tile_list;
+    int32_t n_tiles, tile_h, tile_w, pad;
+    const double* tab;         // double tables
+    const double* coef;
+    double* E;
+    double* V;
+    double* tile_sums;         // [n_tiles] pixel-term sums of covered pixels, or null
+    const int* status;
+};
+
+struct AdjArgs {
+    Geometry g;
+    Sel items;
+    const uint8_t* active;     // [S] or null
+    const double* tab;         // T tables
+    const double* coef;
+    const double* tab_val;     // double-valued tables used for overlapping boxes (BASE_NBR)
+    const double* coef_val;
+    int32_t tab_val_stride;    // 1 if tab_val holds doubles, 2 if it holds duals
+    int32_t dynamic;
+    int* counter;
+    const double* E;
+    const double* V;
+    const double* bg;          // [n_visits][2]
+    double* partials;          // [n_items_total][NACC] of T
+    const int* status;
+};
+
+struct BgArgs {
+    Geometry g;
+    Sel items;
+    const double* tab_val;
+    const double* coef_val;
+    double* bg;
+    const int* status;
+};
+
+struct FinArgs {
+    Geometry g;
+    Sel srcs;
+    const uint8_t* active;
+    const double* theta;
+    const double* dir;
+    int32_t dir_mode, dir_unit;
+    const int32_t* patch_ptr;  // device [S+1]
+    const double* partials;
+    int32_t deriv;             // 0: value only
+    double* elbo;              // [S] or null
+    double* grad;              // [S][32] or null: value parts of the gradient
+    double* tangent;           // [S][32] or null: tangent parts (Hessian-vector product)
+    int64_t tangent_stride;    // row stride of `tangent` in doubles
+    int32_t tangent_by_list;   // 1: row j of `tangent` is list entry j (not source id)
+    int32_t tangent_pad;       // 1: also zero entries 27..31 of each row
+    const int* status;
+};
+
+// Kernel launchers (kernels.hip)
+hipError_t launch_validate(const double* theta, const uint8_t* active, const int32_t* list, int n,
+                           int S, int* status, hipStream_t st);
+hipError_t launch_prep(const PrepArgs& a, bool tangent, hipStream_t st);
+hipError_t launch_render(const RenderArgs& a, int waves_per_block, hipStream_t st);
+hipError_t launch_adjoint(const AdjArgs& a, bool tangent, int base_mode, bool deriv, int grid,
+                          int waves_per_block, hipStream_t st);
+hipError_t launch_background(const BgArgs& a, int grid, int waves_per_block, hipStream_t st);
+hipError_t launch_finalize(const FinArgs& a, bool tangent, hipStream_t st);
+hipError_t launch_tile_total(const double* tile_sums, int n_tiles, const double* theta, const Consts& c,
+                             int S, double* out, const int* status, hipStream_t st);
+hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st);
+hipError_t launch_fill_u8_sel(uint8_t* p, const Sel& s, uint8_t v, hipStream_t st);
+hipError_t launch_fill_f64_sel(double* p, const Sel& s, double v, hipStream_t st);
+
+// Trust region (tr.hip)
+struct TrArgs {
+    Sel srcs;
+    double* theta;             // [S][32] current point, updated by tr_update
+    const double* grad;        // [S][32] natural-space gradient at theta
+    const double* hess;        // [n][27][27] by list position
+    double* radius;            // [S]
+    double* theta_trial;       // [S][32]
+    double* pred;              // [S] predicted increase
+    double* elbo_cur;          // [S]
+    const double* elbo_trial;  // [S]
+    uint8_t* done;             // [S]
+    double eta_accept, radius_max, gtol;
+    int* status;
+};
+hipError_t launch_tr_solve(const TrArgs& a, hipStream_t st);
+hipError_t launch_tr_update(const TrArgs& a, hipStream_t st);
+
+}  // namespace cel

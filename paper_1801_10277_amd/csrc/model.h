@@ -1,0 +1,300 @@
+// Device-side model arithmetic, templated on the scalar type T (double for values and
+// gradients, dual for Hessian-vector products).  Regier et al. 2018, Section III and
+// Eq. (1); the pixel-level details follow the model the paper cites and are listed with
+// the library's header.
+#pragma once
+#include "internal.h"
+
+namespace cel {
+
+// log flux_b = log r + sum_k BSIGN[b][k] c_k with c_k = log(flux_{k+1} / flux_k),
+// reference band r = 2.
+__device__ __constant__ static const signed char BSIGN[5][4] = {
+    {-1, -1, 0, 0}, {0, -1, 0, 0}, {0, 0, 0, 0}, {0, 0, 1, 0}, {0, 0, 1, 1}};
+
+constexpr double LOG_2PI = 1.8378770664093454836;
+
+template <class T>
+__device__ inline T seed(const double* theta, const double* dir, int dir_mode, int dir_unit,
+                         int s, int i) {
+    double t = 0.0;
+    if (dir_mode == DIR_VEC) t = dir[(size_t)s * ROW + i];
+    else if (dir_mode == DIR_UNIT) t = (i == dir_unit) ? 1.0 : 0.0;
+    return scalar_traits<T>::make(theta[(size_t)s * ROW + i], t);
+}
+
+// Log-normal band-flux moments of both types: a = E[flux_b], b = E[flux_b^2].
+template <class T>
+__device__ inline void flux_moments(const T* p, int band, T* a, T* b) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int base = 7 + 10 * t;
+        T m = p[base];
+        T v = p[base + 1];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int sg = BSIGN[band][k];
+            if (sg != 0) {
+                m = m + (double)sg * p[base + 2 + k];
+                v = v + p[base + 6 + k];
+            }
+        }
+        a[t] = exp(m + 0.5 * v);
+        b[t] = exp(2.0 * m + 2.0 * v);
+    }
+}
+
+// Galaxy shape covariance radius^2 R(angle) diag(1, ratio^2) R(angle)^T.
+template <class T>
+__device__ inline void shape_cov(const T* p, T& sxx, T& sxy, T& syy) {
+    const T c = cos(p[4]), s = sin(p[4]);
+    const T r2 = p[5] * p[5], q2 = p[3] * p[3];
+    sxx = r2 * (c * c + q2 * s * s);
+    sxy = r2 * (c * s) * (1.0 - q2);
+    syy = r2 * (s * s + q2 * c * c);
+}
+
+template <class T>
+__device__ inline void write_comp(T* e, T cx, T cy, T sxx, T sxy, T syy, double logw0, T wt, T wnu,
+                                  double sgn) {
+    const T det = sxx * syy - sxy * sxy;
+    const T inv = 1.0 / det;
+    e[F_CX] = cx;
+    e[F_CY] = cy;
+    e[F_PXX] = syy * inv;
+    e[F_PXY] = -(sxy * inv);
+    e[F_PYY] = sxx * inv;
+    e[F_LOGW] = logw0 - LOG_2PI - 0.5 * log(det);
+    e[F_WT] = wt;
+    e[F_WNU] = wnu;
+    e[F_SGN] = scalar_traits<T>::make(sgn, 0.0);
+    e[F_PAD] = scalar_traits<T>::make(0.0, 0.0);
+}
+
+// Table of the 45 Gaussians of source parameters p in image im (components: 3 star,
+// then per PSF component 8 de Vaucouleurs and 6 exponential) and the k1..k4 factors.
+template <class T>
+__device__ inline void build_pair(const T* p, const celeste_image& im, const Consts& K, T* tab, T* coef) {
+    T a[2], b[2];
+    flux_moments(p, im.band, a, b);
+    const T q = p[6];
+    const double io = im.iota;
+    coef[C_K1] = io * (q * a[0]);
+    coef[C_K2] = io * ((1.0 - q) * a[1]);
+    coef[C_K3] = (io * io) * (q * b[0]);
+    coef[C_K4] = (io * io) * ((1.0 - q) * b[1]);
+    T sxx, sxy, syy;
+    shape_cov(p, sxx, sxy, syy);
+    const T ux = p[0] - im.origin_x, uy = p[1] - im.origin_y;
+    const T fdev = p[2];
+    const T fexp = 1.0 - fdev;
+    const T one = scalar_traits<T>::make(1.0, 0.0);
+    const T zero = scalar_traits<T>::make(0.0, 0.0);
+    for (int k = 0; k < NPSF; ++k) {
+        const double* ps = im.psf[k];
+        const T cx = ux + ps[1], cy = uy + ps[2];
+        write_comp(tab + k * CST, cx, cy, scalar_traits<T>::make(ps[3], 0.0),
+                   scalar_traits<T>::make(ps[4], 0.0), scalar_traits<T>::make(ps[5], 0.0),
+                   log(ps[0]), one, zero, 0.0);
+        T* g = tab + (NPSF + k * NGAL_PER_PSF) * CST;
+        for (int j = 0; j < NDEV; ++j) {
+            const double nu = K.dev_nu[j];
+            write_comp(g + j * CST, cx, cy, nu * sxx + ps[3], nu * sxy + ps[4], nu * syy + ps[5],
+                       log(ps[0] * K.dev_alpha[j]), fdev, nu * fdev, 1.0);
+        }
+        for (int j = 0; j < NEXP; ++j) {
+            const double nu = K.exp_nu[j];
+            write_comp(g + (NDEV + j) * CST, cx, cy, nu * sxx + ps[3], nu * sxy + ps[4],
+                       nu * syy + ps[5], log(ps[0] * K.exp_alpha[j]), fexp, nu * fexp, -1.0);
+        }
+    }
+}
+
+// Own-source profile sums at one pixel and their derivatives with respect to the
+// position, frac_dev and the shape covariance.
+template <class T>
+struct Own {
+    T fs, fsx, fsy;            // f_star and d f_star / d u
+    T fg, D, gx, gy;           // f_gal, d f_gal / d frac_dev, d f_gal / d u
+    T sxx, sxy, syy;           // 2 d f_gal / d Sxx, d f_gal / d Sxy, 2 d f_gal / d Syy
+};
+
+template <class T, bool DERIV>
+__device__ __forceinline__ void eval_own(const T* __restrict__ tab, double px, double py, Own<T>& o) {
+    const T zero = scalar_traits<T>::make(0.0, 0.0);
+    o.fs = o.fsx = o.fsy = o.fg = o.D = o.gx = o.gy = o.sxx = o.sxy = o.syy = zero;
+#pragma unroll
+    for (int c = 0; c < NPSF; ++c) {
+        const T* e = tab + c * CST;
+        const T dx = px - e[F_CX], dy = py - e[F_CY];
+        const T pdx = e[F_PXX] * dx + e[F_PXY] * dy;
+        const T pdy = e[F_PXY] * dx + e[F_PYY] * dy;
+        const T n = exp(e[F_LOGW] - 0.5 * (dx * pdx + dy * pdy));
+        o.fs += n;
+        if (DERIV) {
+            o.fsx += n * pdx;
+            o.fsy += n * pdy;
+        }
+    }
+#pragma unroll 2
+    for (int c = NPSF; c < NCOMP; ++c) {
+        const T* e = tab + c * CST;
+        const T dx = px - e[F_CX], dy = py - e[F_CY];
+        const T pdx = e[F_PXX] * dx + e[F_PXY] * dy;
+        const T pdy = e[F_PXY] * dx + e[F_PYY] * dy;
+        const T n = exp(e[F_LOGW] - 0.5 * (dx * pdx + dy * pdy));
+        const T nw = n * e[F_WT];
+        o.fg += nw;
+        if (DERIV) {
+            o.D += e[F_SGN] * n;
+            o.gx += nw * pdx;
+            o.gy += nw * pdy;
+            const T nwnu = n * e[F_WNU];
+            o.sxx += nwnu * (pdx * pdx - e[F_PXX]);
+            o.sxy += nwnu * (pdx * pdy - e[F_PXY]);
+            o.syy += nwnu * (pdy * pdy - e[F_PYY]);
+        }
+    }
+}
+
+// Value-only profile sums from a table whose entries are `stride` doubles apart
+// (stride 2 reads the value parts of a dual table).
+__device__ __forceinline__ void eval_value(const double* __restrict__ tab, int stride, double px,
+                                           double py, double& fs, double& fg) {
+    fs = 0.0;
+    fg = 0.0;
+#pragma unroll
+    for (int c = 0; c < NPSF; ++c) {
+        const double* e = tab + c * CST * stride;
+        const double dx = px - e[F_CX * stride], dy = py - e[F_CY * stride];
+        const double pdx = e[F_PXX * stride] * dx + e[F_PXY * stride] * dy;
+        const double pdy = e[F_PXY * stride] * dx + e[F_PYY * stride] * dy;
+        fs += exp(e[F_LOGW * stride] - 0.5 * (dx * pdx + dy * pdy));
+    }
+#pragma unroll 2
+    for (int c = NPSF; c < NCOMP; ++c) {
+        const double* e = tab + c * CST * stride;
+        const double dx = px - e[F_CX * stride], dy = py - e[F_CY * stride];
+        const double pdx = e[F_PXX * stride] * dx + e[F_PXY * stride] * dy;
+        const double pdy = e[F_PXY * stride] * dx + e[F_PYY * stride] * dy;
+        fg += exp(e[F_LOGW * stride] - 0.5 * (dx * pdx + dy * pdy)) * e[F_WT * stride];
+    }
+}
+
+// Pixel term and its derivatives, accumulated into acc[NACC].  E and V are the
+// totals at the pixel, Es the own source's mean light, k the own factors.
+template <class T, bool DERIV>
+__device__ __forceinline__ void pixel_accumulate(double x, T E, T V, T Es, const Own<T>& o, const T* k,
+                                                 T* acc, bool lgam) {
+    const T inv = 1.0 / E;
+    const T r = V * inv * inv;
+    T l = x * (log(E) - 0.5 * r) - E;
+    if (lgam) l = l - lgamma(x + 1.0);
+    acc[A_VAL] += l;
+    if (DERIV) {
+        const T lE = x * inv * (1.0 + r) - 1.0;     // d l / d E
+        const T lV = -0.5 * x * (inv * inv);        // d l / d V
+        const T A = lE - 2.0 * Es * lV;             // d l / d E_s through E and through Var_s
+        acc[A_K1] += A * o.fs;
+        acc[A_K2] += A * o.fg;
+        acc[A_K3] += lV * (o.fs * o.fs);
+        acc[A_K4] += lV * (o.fg * o.fg);
+        const T Gs = A * k[C_K1] + 2.0 * lV * (k[C_K3] * o.fs);   // d l / d f_star
+        const T Gg = A * k[C_K2] + 2.0 * lV * (k[C_K4] * o.fg);   // d l / d f_gal
+        acc[A_UX] += Gs * o.fsx + Gg * o.gx;
+        acc[A_UY] += Gs * o.fsy + Gg * o.gy;
+        acc[A_FDEV] += Gg * o.D;
+        acc[A_SXX] += Gg * o.sxx;
+        acc[A_SXY] += Gg * o.sxy;
+        acc[A_SYY] += Gg * o.syy;
+    }
+}
+
+// Chain rule from one box's accumulated sums z[NACC] to d/d theta (27 entries).
+template <class T>
+__device__ inline void chain_pair(const T* p, const celeste_image& im, const T* z, T* g) {
+    T a[2], b[2];
+    flux_moments(p, im.band, a, b);
+    const double io = im.iota, io2 = io * io;
+    const T q = p[6];
+    const T k1 = io * (q * a[0]), k2 = io * ((1.0 - q) * a[1]);
+    const T k3 = io2 * (q * b[0]), k4 = io2 * ((1.0 - q) * b[1]);
+    g[6] += z[A_K1] * (io * a[0]) - z[A_K2] * (io * a[1]) + z[A_K3] * (io2 * b[0]) -
+            z[A_K4] * (io2 * b[1]);
+    // d k / d m = k (first moment) or 2k (second); d k / d v = k/2 or 2k
+    const T dm[2] = {z[A_K1] * k1 + 2.0 * (z[A_K3] * k3), z[A_K2] * k2 + 2.0 * (z[A_K4] * k4)};
+    const T dv[2] = {0.5 * (z[A_K1] * k1) + 2.0 * (z[A_K3] * k3),
+                     0.5 * (z[A_K2] * k2) + 2.0 * (z[A_K4] * k4)};
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int base = 7 + 10 * t;
+        g[base] += dm[t];
+        g[base + 1] += dv[t];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int sg = BSIGN[im.band][k];
+            if (sg != 0) {
+                g[base + 2 + k] += (double)sg * dm[t];
+                g[base + 6 + k] += dv[t];
+            }
+        }
+    }
+    g[0] += z[A_UX];
+    g[1] += z[A_UY];
+    g[2] += z[A_FDEV];
+    const T Gxx = 0.5 * z[A_SXX], Gxy = z[A_SXY], Gyy = 0.5 * z[A_SYY];
+    const T c = cos(p[4]), s = sin(p[4]);
+    const T re = p[5], r2 = re * re, rho = p[3], q2 = rho * rho;
+    const T cs = c * s, c2 = c * c, s2 = s * s, om = 1.0 - q2;
+    // d Sigma / d axis ratio
+    g[3] += (2.0 * r2 * rho) * (Gxx * s2 - Gxy * cs + Gyy * c2);
+    // d Sigma / d angle
+    g[4] += r2 * om * (2.0 * cs * (Gyy - Gxx) + Gxy * (c2 - s2));
+    // d Sigma / d radius
+    g[5] += (2.0 * re) * (Gxx * (c2 + q2 * s2) + Gxy * (cs * om) + Gyy * (s2 + q2 * c2));
+}
+
+template <class T>
+__device__ inline T kl_normal(T m, T v, double m0, double v0) {
+    const T d = m - m0;
+    return 0.5 * (log(v0) - log(v) + (v + d * d) / v0 - 1.0);
+}
+
+// KL(q || prior) of one source; subtracts its gradient from g.
+template <class T>
+__device__ inline T kl_source(const T* p, const Consts& K, T* g) {
+    const T q = p[6];
+    const double phi = K.prior_phi;
+    const T lq = log(q / phi), lnq = log((1.0 - q) / (1.0 - phi));
+    T kl = q * lq + (1.0 - q) * lnq;
+    T dq = lq - lnq;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int base = 7 + 10 * t;
+        const T w = (t == 0) ? q : 1.0 - q;
+        const double m0 = K.prior_r[t][0], v0 = K.prior_r[t][1];
+        T kt = kl_normal(p[base], p[base + 1], m0, v0);
+        g[base] -= w * ((p[base] - m0) / v0);
+        g[base + 1] -= w * (0.5 * (1.0 / v0 - 1.0 / p[base + 1]));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double cm = K.prior_c[t][0][k], cv = K.prior_c[t][1][k];
+            kt += kl_normal(p[base + 2 + k], p[base + 6 + k], cm, cv);
+            g[base + 2 + k] -= w * ((p[base + 2 + k] - cm) / cv);
+            g[base + 6 + k] -= w * (0.5 * (1.0 / cv - 1.0 / p[base + 6 + k]));
+        }
+        kl += w * kt;
+        dq += (t == 0) ? kt : -kt;
+    }
+    g[6] -= dq;
+    return kl;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline dual wave_sum(dual v) { return mkd(wave_sum(v.v), wave_sum(v.t)); }
+
+}  // namespace cel
