@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark of the FP64 ELBO + gradient hot path on one MI355X.
+
+Workload: the SDSS-shaped field (5 bands of 2048 x 1489 px, 2000 sources, 40% stars,
+patch side log-uniform in [21, 101] px, r-band flux log-normal in [50, 1e5] e-), all
+sources evaluated per step by the batched path (table build, tile-binned render, one
+persistent fused adjoint launch, finalize) replayed as a HIP graph.  One step = one
+ELBO + gradient of every source; the metric counts (source, pixel) visits per second.
+
+Also reported: the plain per-source form on the same field (one launch per source,
+overlapping sources evaluated on the fly), per-phase device times from HIP events, the
+roofline of the dominant kernel (the fused adjoint, FP64 ALU bound) and the FP64 CPU
+oracle timed on a bounded sample of the same sources on this host's cores, with the
+parity of the GPU result on that sample.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "source-pixel ELBO+grad evals/s (FP64), % FP64 peak; batched vs plain at 1e-9"
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector peak (vendor figure)
+
+# Algorithmic FP64 operations, counted from the formulas the kernels evaluate (add, sub,
+# mul, div = 1 each; exp = 27 and log = 78: the FP64 operations of one call of the ROCm
+# device library's exp and log on gfx950, read from this build's ISA).
+EXP_FLOPS = 27
+LOG_FLOPS = 78
+N_STAR, N_GAL = 3, 42                   # Gaussians per (source, image): 3 star, 3 x (8 + 6) galaxy
+
+# Strip algorithm (what runs): per strip of L rows and per Gaussian, the value and the
+# first row ratio at the top row (2 exps + 16), then per row 2 multiplies for the
+# recurrence plus the accumulation; the adjoint pass repeats the seed and adds 3 moment
+# accumulations per row and a fold per strip.
+SEED = 16 + 2 * EXP_FLOPS               # d, P d, d'Pd, exponents (16) + 2 exp
+RENDER_PER_STRIP = (N_STAR + N_GAL) * SEED
+RENDER_PER_VISIT = N_STAR * 3 + N_GAL * 4 + 11
+ADJ_PER_STRIP = 2 * (N_STAR + N_GAL) * SEED + N_STAR * 12 + N_GAL * 46
+ADJ_PER_VISIT = (N_STAR * 3 + N_GAL * 4) + (N_STAR * 6 + N_GAL * 8) + (46 + LOG_FLOPS)
+
+# Direct evaluation of the same quantities (one exp per Gaussian per visit), for context.
+GAUSS_VALUE = 13 + EXP_FLOPS
+DIRECT_ADJ_PER_VISIT = N_STAR * (GAUSS_VALUE + 5) + N_GAL * (GAUSS_VALUE + 21) + 62 + LOG_FLOPS
+DIRECT_RENDER_PER_VISIT = N_STAR * (GAUSS_VALUE + 1) + N_GAL * (GAUSS_VALUE + 2) + 12
+ADJOINT_BYTES_PER_VISIT = 24            # x, E, V read once (float64)
+
+
+def strip_count(f, L):
+    import numpy as np
+    b = f.boxes.astype(np.int64)
+    return int(np.sum(b[:, 4] * ((b[:, 3] + L - 1) // L)))
+
+
+LAUNCH_KEYS = ("chunk", "waves_per_block", "grid_blocks", "dynamic_queue", "strip_rows", "render_mode",
+               "n_classes", "tile_h", "tile_w")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(f, theta_gpu_grad, elbo_gpu, seconds):
+    """The oracle as it stands, OpenMP over sources on this host, on a bounded sample."""
+    import numpy as np
+    from oracle import oracle as O
+    O.build()
+    P = O.Problem(f)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    batch = max(cores, 8)
+    done, visits, t0 = 0, 0, time.perf_counter()
+    rel_e, rel_g = 0.0, 0.0
+    while time.perf_counter() - t0 < seconds and done < f.n_src:
+        srcs = np.arange(done, min(done + batch, f.n_src))
+        val, g = O.grad_many(P, srcs)
+        b = f.boxes[f.patch_ptr[srcs[0]]:f.patch_ptr[srcs[-1] + 1]]
+        visits += int((b[:, 3].astype(np.int64) * b[:, 4]).sum())
+        for k, s in enumerate(srcs):
+            ref = val[k, 0] + val[k, 1]
+            rel_e = max(rel_e, abs(elbo_gpu[s] - ref) / abs(ref))
+            gi = g[k]
+            rel_g = max(rel_g, float(np.max(np.abs(theta_gpu_grad[s, :27] - gi)) / np.abs(gi).max()))
+        done = srcs[-1] + 1
+    dt = time.perf_counter() - t0
+    return {"value": visits / dt, "unit": "source-pixel ELBO+grad evals/s", "cores": cores, "kind": "oracle",
+            "sample": "first %d of %d sources of the same field (%d visits, %.1f s), FP64 dual-number "
+                      "gradient, OpenMP over sources" % (done, f.n_src, visits, dt)}, rel_e, rel_g, done
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--sources", type=int, default=2000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1801_10277_amd import binding as B, synth
+
+    log("generating the field ...")
+    t = time.perf_counter()
+    f = synth.sdss_field(args.sources)
+    log("field ready in %.1f s: %d sources, %d boxes, %d visits" % (time.perf_counter() - t, f.n_src,
+                                                                    len(f.boxes), f.visits()))
+    dev = torch.device("cuda:0")
+    theta = torch.tensor(f.theta, dtype=torch.float64, device=dev)
+    plan = B.Plan(f, check_status=False)
+    info = plan.info()
+    visits = info["n_visits"]
+    elbo = torch.zeros(f.n_src, dtype=torch.float64, device=dev)
+    grad = torch.zeros(f.n_src, 32, dtype=torch.float64, device=dev)
+
+    if not args.no_tune:
+        ms = plan.autotune(theta, reps=3)
+        info = plan.info()
+        log("autotuned: %s (%.3f ms)" % ({k: info[k] for k in LAUNCH_KEYS}, ms))
+
+    # correctness of this configuration before timing
+    plan.check_status = True
+    plan.elbo_grad(theta, mode=B.CELESTE_BATCHED, elbo=elbo, grad=grad)
+    plan.check_status = False
+
+    plan.use_graph(True)
+    for _ in range(args.warmup):
+        plan.elbo_grad(theta, elbo=elbo, grad=grad)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.elbo_grad(theta, elbo=elbo, grad=grad)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = 1e3 * dt / args.steps
+    value = visits * args.steps / dt
+    log("batched: %.3f ms/step, %.3e visits/s" % (ms_step, value))
+
+    # per-phase device time with HIP events on the launch stream (outside the graph)
+    plan.use_graph(False)
+    plan.profile(True, reset=True)
+    n_prof = max(5, min(args.steps, 20))
+    for _ in range(n_prof):
+        plan.elbo_grad(theta, elbo=elbo, grad=grad)
+    phase_ms, calls = plan.profile(False, reset=True)
+    phase = [m / calls for m in phase_ms]
+    log("phases (ms): tables %.3f render %.3f adjoint %.3f finalize %.3f" % tuple(phase))
+    adj_ms = phase[2]
+    L = info["strip_rows"]
+    strips = strip_count(f, L)
+    adj_flops = strips * ADJ_PER_STRIP + visits * ADJ_PER_VISIT
+    render_flops = strips * RENDER_PER_STRIP + visits * RENDER_PER_VISIT
+    achieved = adj_flops / (adj_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "k_adjoint_strips<double, planes, grad, L=%d> (fused own-source forward + adjoint)" % L,
+                "flops_per_launch": adj_flops, "flops_per_visit": round(adj_flops / visits, 1),
+                "visits_per_launch": visits, "strips_per_launch": strips, "avg_launch_ms": round(adj_ms, 4)}
+    whole = (adj_flops + render_flops) / visits * value / 1e12
+    direct_equiv = (DIRECT_ADJ_PER_VISIT + DIRECT_RENDER_PER_VISIT) * value / 1e12
+
+    plain = None
+    if not args.no_plain:
+        plan.elbo_grad(theta, mode=B.CELESTE_PLAIN, elbo=elbo, grad=grad)
+        torch.cuda.synchronize()
+        n_plain = 3
+        t0 = time.perf_counter()
+        for _ in range(n_plain):
+            plan.elbo_grad(theta, mode=B.CELESTE_PLAIN, elbo=elbo, grad=grad)
+        torch.cuda.synchronize()
+        pdt = (time.perf_counter() - t0) / n_plain
+        plain = {"visits_per_s": visits / pdt, "ms_per_step": 1e3 * pdt}
+        log("plain: %.3f ms/step, %.3e visits/s" % (1e3 * pdt, visits / pdt))
+
+    # batched result for the parity sample
+    plan.elbo_grad(theta, mode=B.CELESTE_BATCHED, elbo=elbo, grad=grad)
+    torch.cuda.synchronize()
+    cpu, parity = None, None
+    if not args.no_cpu:
+        cpu, rel_e, rel_g, n_checked = cpu_baseline(f, grad.cpu().numpy(), elbo.cpu().numpy(), args.cpu_seconds)
+        parity = {"sources_checked": int(n_checked), "max_rel_err_elbo": rel_e, "max_rel_err_grad": rel_g}
+        log("cpu oracle: %.3e visits/s on %d cores" % (cpu["value"], cpu["cores"]))
+
+    out = {"metric": METRIC, "value": value, "unit": "source-pixel ELBO+grad evals/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "SDSS-shaped field, %d sources, 5 bands x 2048x1489 px, batched "
+                                  "fused launch replayed as a HIP graph" % f.n_src,
+                      "sources": f.n_src, "visits_per_step": visits, "form": "batched",
+                      "launch": {k: info[k] for k in LAUNCH_KEYS},
+                      "phase_ms": [round(v, 4) for v in phase],
+                      "path_flops_per_visit": round((adj_flops + render_flops) / visits, 1),
+                      "path_tflops": round(whole, 3),
+                      "path_frac_fp64_peak": round(whole / FP64_PEAK_TFLOPS, 4),
+                      "direct_formula_flops_per_visit": DIRECT_ADJ_PER_VISIT + DIRECT_RENDER_PER_VISIT,
+                      "direct_formula_equivalent_tflops": round(direct_equiv, 3),
+                      "plain": plain,
+                      "batched_vs_plain": (value / plain["visits_per_s"]) if plain else None,
+                      "parity_vs_oracle": parity},
+           "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

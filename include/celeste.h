@@ -120,11 +120,15 @@ typedef struct celeste_plan_info {
     int64_t n_items;       /* work items of the fused adjoint launch */
     int64_t n_tiles;       /* render tiles touched by at least one box */
     int64_t n_nbr;         /* entries of the box-overlap lists used by the plain form */
-    int32_t chunk;         /* pixels per adjoint work item */
+    int32_t chunk;         /* strips per adjoint work item */
     int32_t waves_per_block;
     int32_t grid_blocks;   /* persistent grid size of the fused adjoint launch */
     int32_t tile_h, tile_w;
     int32_t dynamic_queue; /* 1: items popped from a device counter; 0: static round robin */
+    int32_t strip_rows;    /* pixels per strip: a lane walks one column of a box this many rows */
+    int32_t render_mode;   /* 0: strips per conflict-free class of boxes; 1: binned tiles */
+    int32_t n_classes;     /* conflict-free classes of boxes (render launches) */
+    int32_t reserved;
     int64_t workspace_bytes;
 } celeste_plan_info;
 
@@ -199,12 +203,14 @@ int celeste_sweep(celeste_plan* plan, double* theta_inout, const int32_t* batch_
                   const int32_t* batch_src, int n_batches, int n_sweeps,
                   const celeste_tr_params* params, double* elbo_trace, hipStream_t stream);
 
-/* Launch configuration of the fused adjoint: pixels per item (multiple of 64, at most
- * 1024), waves per block (1, 2 or 4), persistent grid size (blocks, >= 1),
- * dynamic_queue (0/1), render tile (tile_h * tile_w == 64).  Rebuilds work items
- * (synchronous; no allocation beyond the plan's item buffer, reallocated if it grows). */
+/* Launch configuration: strips per work item (multiple of 64, at most 1024), waves per
+ * block (1, 2 or 4), persistent grid size (blocks, >= 1), dynamic_queue (0/1), render
+ * tile tile_h x tile_w of the tile render (tile_w divides 64; tile_h * tile_w = 64, 128
+ * or 256), strip_rows (4, 8 or 16 pixels per strip) and render_mode (0: strips per
+ * conflict-free class, 1: binned tiles).  Rebuilds work items and render tiles
+ * (synchronous; the tile buffers are reallocated if they grow). */
 int celeste_plan_set_launch(celeste_plan* plan, int chunk, int waves_per_block, int grid_blocks,
-                            int dynamic_queue, int tile_h, int tile_w);
+                            int dynamic_queue, int tile_h, int tile_w, int strip_rows, int render_mode);
 
 /* Times candidate launch configurations of celeste_elbo_grad (batched) on theta with
  * HIP events (median of `reps` runs each) and keeps the fastest.  Synchronous.
@@ -215,6 +221,13 @@ int celeste_autotune(celeste_plan* plan, const double* theta, int reps, double* 
 /* Capture the batched celeste_elbo_grad sequence for these exact pointers in a HIP
  * graph on first use and replay it afterwards (0 = off, the default). */
 int celeste_plan_use_graph(celeste_plan* plan, int enable);
+
+/* Per-phase device time of the batched evaluation (celeste_elbo / celeste_elbo_grad,
+ * batched, outside a graph), measured with HIP events on the caller's stream while
+ * enabled; each instrumented call then synchronises its stream.  ms (host [4], or
+ * NULL) receives the summed milliseconds of (tables, render, fused adjoint, finalize)
+ * since the last reset and *calls their count; reset != 0 clears both afterwards. */
+int celeste_plan_profile(celeste_plan* plan, int enable, double* ms, int64_t* calls, int reset);
 
 /* Synchronises `stream` and returns the domain status of the last call on this plan
  * (CELESTE_OK or CELESTE_EDOMAIN), then clears it. */

@@ -26,7 +26,7 @@ CELESTE_INCLUDE_LGAMMA = 2
 EXPORTS = ["celeste_plan_create", "celeste_plan_destroy", "celeste_plan_get_info", "celeste_elbo",
            "celeste_elbo_grad", "celeste_hvp", "celeste_hessian", "celeste_newton", "celeste_total_elbo",
            "celeste_color_batches", "celeste_sweep", "celeste_plan_set_launch", "celeste_autotune",
-           "celeste_plan_use_graph", "celeste_plan_status", "celeste_last_hip_error",
+           "celeste_plan_use_graph", "celeste_plan_profile", "celeste_plan_status", "celeste_last_hip_error",
            "celeste_status_string", "celeste_version"]
 
 
@@ -60,7 +60,9 @@ class celeste_plan_info(C.Structure):
     _fields_ = [("n_visits", C.c_int64), ("n_pairs", C.c_int64), ("n_items", C.c_int64),
                 ("n_tiles", C.c_int64), ("n_nbr", C.c_int64), ("chunk", C.c_int32),
                 ("waves_per_block", C.c_int32), ("grid_blocks", C.c_int32), ("tile_h", C.c_int32),
-                ("tile_w", C.c_int32), ("dynamic_queue", C.c_int32), ("workspace_bytes", C.c_int64)]
+                ("tile_w", C.c_int32), ("dynamic_queue", C.c_int32), ("strip_rows", C.c_int32),
+                ("render_mode", C.c_int32), ("n_classes", C.c_int32), ("reserved", C.c_int32),
+                ("workspace_bytes", C.c_int64)]
 
 
 _lib = None
@@ -88,9 +90,10 @@ def lib():
     L.celeste_total_elbo.argtypes = [vp, dp, dp, vp]
     L.celeste_color_batches.argtypes = [vp, C.c_uint64, ip, ip, ip]
     L.celeste_sweep.argtypes = [vp, dp, ip, ip, C.c_int, C.c_int, C.POINTER(celeste_tr_params), dp, vp]
-    L.celeste_plan_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
+    L.celeste_plan_set_launch.argtypes = [vp] + [C.c_int] * 8
     L.celeste_autotune.argtypes = [vp, dp, C.c_int, C.POINTER(C.c_double), vp]
     L.celeste_plan_use_graph.argtypes = [vp, C.c_int]
+    L.celeste_plan_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
     L.celeste_plan_status.argtypes = [vp, vp]
     L.celeste_last_hip_error.restype = C.c_char_p
     L.celeste_status_string.argtypes = [C.c_int]
@@ -281,15 +284,24 @@ class Plan:
         self._status("celeste_sweep")
         return trace
 
-    def set_launch(self, chunk=256, waves_per_block=4, grid_blocks=2048, dynamic=0, tile_h=8, tile_w=8):
+    def set_launch(self, chunk=256, waves_per_block=4, grid_blocks=2048, dynamic=0, tile_h=8, tile_w=8,
+                   strip_rows=8, render_mode=0):
         check(lib().celeste_plan_set_launch(self.h, chunk, waves_per_block, grid_blocks, dynamic, tile_h,
-                                            tile_w), "celeste_plan_set_launch")
+                                            tile_w, strip_rows, render_mode), "celeste_plan_set_launch")
 
     def autotune(self, theta, reps=5):
         ms = C.c_double()
         check(lib().celeste_autotune(self.h, _ptr(self._theta(theta)), reps, C.byref(ms), _stream()),
               "celeste_autotune")
         return ms.value
+
+    def profile(self, enable=True, reset=True):
+        """Enable/disable phase timing; returns (ms[4] summed since last reset, calls)."""
+        ms = (C.c_double * 4)()
+        n = C.c_int64()
+        check(lib().celeste_plan_profile(self.h, 1 if enable else 0, ms, C.byref(n), 1 if reset else 0),
+              "celeste_plan_profile")
+        return list(ms), n.value
 
     def use_graph(self, enable=True):
         check(lib().celeste_plan_use_graph(self.h, 1 if enable else 0), "celeste_plan_use_graph")

@@ -66,7 +66,8 @@ struct celeste_plan {
     int n_cu = 256;
 
     // launch configuration
-    int chunk = 256, wpb = 4, grid = 0, dynamic = 0, tile_h = 8, tile_w = 8;
+    int chunk = 256, wpb = 4, grid = 0, dynamic = 0, tile_h = 8, tile_w = 8, rows = 8;
+    int render_mode = 0;   // 0: strips per conflict-free class, 1: binned tiles
     bool use_graph = false;
 
     // device memory
@@ -89,6 +90,7 @@ struct celeste_plan {
     double* d_V = nullptr;
     double* d_bg = nullptr;
     double* d_tile_sums = nullptr;
+    double* d_pair_lgamma = nullptr;
     int* d_status = nullptr;
     int* d_counter = nullptr;
     double* d_grad = nullptr;
@@ -103,7 +105,19 @@ struct celeste_plan {
     int32_t* d_list_pair = nullptr;  // [n_pairs]
     int32_t* d_list_item = nullptr;  // [cap_items]
     size_t cap_list_item = 0;
+    // conflict-free classes of boxes (no two boxes of a class share a pixel) and their items
+    std::vector<int32_t> pair_class;
+    int n_class = 0;
+    std::vector<int32_t> cls_ptr, cls_items;
+    int32_t* d_cls_items = nullptr;
+    int max_pix = 0;
     size_t workspace = 0;
+
+    // phase timing of the batched sequence
+    bool profiling = false;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    double phase_ms[4] = {0, 0, 0, 0};
+    int64_t phase_calls = 0;
 
     // graph cache of the batched elbo_grad sequence
     hipStream_t cap_stream = nullptr;
@@ -129,22 +143,66 @@ namespace {
 
 // ---------------------------------------------------------------- geometry builders
 
+// Work items: runs of up to `chunk` strips (a strip = `rows` consecutive pixels of one
+// column of a box), in box order.
+int64_t strips_of(const PairDev& pd, int rows) { return (int64_t)pd.w * ((pd.h + rows - 1) / rows); }
+
 void build_items(celeste_plan* p) {
     p->items.clear();
     for (size_t i = 0; i < p->pairs.size(); ++i) {
         PairDev& pd = p->pairs[i];
-        const int area = pd.h * pd.w;
+        const int n = (int)strips_of(pd, p->rows);
         pd.item_begin = (int32_t)p->items.size();
-        for (int s = 0; s < area; s += p->chunk) {
+        for (int s = 0; s < n; s += p->chunk) {
             Item it;
             it.pair = (int32_t)i;
             it.start = s;
-            it.count = std::min(p->chunk, area - s);
+            it.count = std::min(p->chunk, n - s);
             it.pad = 0;
             p->items.push_back(it);
         }
         pd.item_end = (int32_t)p->items.size();
     }
+}
+
+// Greedy colouring of the box-overlap graph (largest boxes first): boxes of one class
+// never share a pixel, so a class can add its light to the planes without atomics.
+void build_pair_classes(celeste_plan* p) {
+    const size_t n = p->pairs.size();
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (int64_t)p->pairs[a].h * p->pairs[a].w > (int64_t)p->pairs[b].h * p->pairs[b].w;
+    });
+    p->pair_class.assign(n, -1);
+    p->n_class = 0;
+    std::vector<int32_t> mark;
+    for (int32_t i : order) {
+        const PairDev& pd = p->pairs[i];
+        for (int k = pd.nbr_begin; k < pd.nbr_end; ++k) {
+            const int c = p->pair_class[p->nbr[k]];
+            if (c >= 0) {
+                if ((int)mark.size() <= c) mark.resize(c + 1, -1);
+                mark[c] = i;
+            }
+        }
+        int c = 0;
+        while (c < (int)mark.size() && mark[c] == i) ++c;
+        p->pair_class[i] = c;
+        p->n_class = std::max(p->n_class, c + 1);
+    }
+}
+
+void build_class_items(celeste_plan* p) {
+    p->cls_ptr.assign(p->n_class + 1, 0);
+    for (size_t i = 0; i < p->pairs.size(); ++i)
+        p->cls_ptr[p->pair_class[i] + 1] += p->pairs[i].item_end - p->pairs[i].item_begin;
+    for (int c = 0; c < p->n_class; ++c) p->cls_ptr[c + 1] += p->cls_ptr[c];
+    p->cls_items.assign(p->items.size(), 0);
+    std::vector<int32_t> fill(p->cls_ptr.begin(), p->cls_ptr.end() - 1);
+    for (size_t i = 0; i < p->pairs.size(); ++i)
+        for (int it = p->pairs[i].item_begin; it < p->pairs[i].item_end; ++it)
+            p->cls_items[fill[p->pair_class[i]]++] = it;
 }
 
 void build_tiles(celeste_plan* p) {
@@ -233,6 +291,9 @@ void build_nbr(celeste_plan* p) {
 int upload_geometry(celeste_plan* p) {
     HIPCHK(hipMemcpy(p->d_pairs, p->pairs.data(), p->pairs.size() * sizeof(PairDev), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(p->d_items, p->items.data(), p->items.size() * sizeof(Item), hipMemcpyHostToDevice));
+    if (!p->cls_items.empty())
+        HIPCHK(hipMemcpy(p->d_cls_items, p->cls_items.data(), p->cls_items.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(p->d_tiles, p->tiles.data(), p->tiles.size() * sizeof(TileDev), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(p->d_tile_list, p->tile_list.data(), p->tile_list.size() * sizeof(int32_t),
                      hipMemcpyHostToDevice));
@@ -264,6 +325,9 @@ int validate_desc(const celeste_problem_desc* d) {
                 if (!finite(ps[f])) return CELESTE_EINVAL;
             if (!(ps[0] > 0.0) || !(ps[3] > 0.0) || !(ps[5] > 0.0) || !(ps[3] * ps[5] - ps[4] * ps[4] > 0.0))
                 return CELESTE_EINVAL;
+            // smallest eigenvalue of the PSF covariance >= 0.01 px^2 (sigma >= 0.1 px)
+            const double tr = ps[3] + ps[5], df = ps[3] - ps[5];
+            if (!(0.5 * (tr - std::sqrt(df * df + 4.0 * ps[4] * ps[4])) >= 0.01)) return CELESTE_EINVAL;
         }
     }
     if (d->patch_ptr[0] != 0) return CELESTE_EINVAL;
@@ -335,7 +399,7 @@ int prep(celeste_plan* p, const double* theta, const Sel& pairs, bool tangent, i
     return CELESTE_OK;
 }
 
-int render(celeste_plan* p, bool sums, hipStream_t st) {
+int render_tiles(celeste_plan* p, bool sums, hipStream_t st) {
     RenderArgs a{};
     a.g = p->geom();
     a.tiles = p->d_tiles;
@@ -353,6 +417,19 @@ int render(celeste_plan* p, bool sums, hipStream_t st) {
     return CELESTE_OK;
 }
 
+// E and V planes of all sources: sky fill, then one strip launch per conflict-free class.
+int render(celeste_plan* p, hipStream_t st) {
+    if (p->render_mode == 1) return render_tiles(p, false, st);
+    HIPCHK(launch_fill_planes(p->d_images, p->n_img, p->max_pix, p->d_E, p->d_V, p->d_status, st));
+    const Geometry g = p->geom();
+    for (int c = 0; c < p->n_class; ++c) {
+        const Sel sel{p->d_cls_items + p->cls_ptr[c], 0, p->cls_ptr[c + 1] - p->cls_ptr[c]};
+        HIPCHK(launch_render_strips(sel, g, p->d_tab1, p->d_coef1, p->d_E, p->d_V, p->rows, p->persistent_grid(),
+                                    p->wpb, p->d_status, st));
+    }
+    return CELESTE_OK;
+}
+
 int adjoint(celeste_plan* p, const Sel& items, const uint8_t* active, bool tangent, int base, bool deriv,
             hipStream_t st, int grid_override = 0) {
     AdjArgs a{};
@@ -363,7 +440,6 @@ int adjoint(celeste_plan* p, const Sel& items, const uint8_t* active, bool tange
     a.coef = tangent ? p->d_coef2 : p->d_coef1;
     a.tab_val = p->d_tab1;
     a.coef_val = p->d_coef1;
-    a.tab_val_stride = 1;
     a.dynamic = p->dynamic;
     a.counter = p->d_counter;
     a.E = p->d_E;
@@ -372,7 +448,7 @@ int adjoint(celeste_plan* p, const Sel& items, const uint8_t* active, bool tange
     a.partials = p->d_partials;
     a.status = p->d_status;
     const int grid = grid_override > 0 ? grid_override : p->persistent_grid();
-    HIPCHK(launch_adjoint(a, tangent, base, deriv, grid, p->wpb, st));
+    HIPCHK(launch_adjoint(a, tangent, base, deriv, grid, p->wpb, p->rows, st));
     return CELESTE_OK;
 }
 
@@ -389,6 +465,7 @@ int finalize(celeste_plan* p, const double* theta, const Sel& srcs, const uint8_
     a.dir_mode = dir_mode;
     a.dir_unit = dir_unit;
     a.patch_ptr = p->d_patch_ptr;
+    a.pair_lgamma = (p->consts.flags & CELESTE_INCLUDE_LGAMMA) ? p->d_pair_lgamma : nullptr;
     a.partials = p->d_partials;
     a.deriv = deriv ? 1 : 0;
     a.elbo = elbo;
@@ -410,7 +487,7 @@ int background(celeste_plan* p, const Sel& items, hipStream_t st) {
     a.coef_val = p->d_coef1;
     a.bg = p->d_bg;
     a.status = p->d_status;
-    HIPCHK(launch_background(a, p->persistent_grid(), p->wpb, st));
+    HIPCHK(launch_background(a, p->persistent_grid(), p->wpb, p->rows, st));
     return CELESTE_OK;
 }
 
@@ -428,13 +505,28 @@ int validate_theta(celeste_plan* p, const double* theta, const uint8_t* active, 
 
 // Batched evaluation: validate, tables, render, fused adjoint, finalize.
 int batched_sequence(celeste_plan* p, const double* theta, const uint8_t* active, bool deriv, double* elbo,
-                     double* grad, hipStream_t st) {
+                     double* grad, hipStream_t st, bool capturing = false) {
     const Scope sc = scope_all(p);
+    const bool prof = p->profiling && !capturing;
+    if (prof) HIPCHK(hipEventRecord(p->ev[0], st));
     CHK(validate_theta(p, theta, active, nullptr, p->n_src, st));
     CHK(prep(p, theta, sc.pair, false, DIR_NONE, nullptr, 0, st));
-    CHK(render(p, false, st));
+    if (prof) HIPCHK(hipEventRecord(p->ev[1], st));
+    CHK(render(p, st));
+    if (prof) HIPCHK(hipEventRecord(p->ev[2], st));
     CHK(adjoint(p, sc.item, active, false, BASE_PLANES, deriv, st));
+    if (prof) HIPCHK(hipEventRecord(p->ev[3], st));
     CHK(finalize(p, theta, sc.src, active, false, DIR_NONE, nullptr, 0, deriv, elbo, grad, nullptr, 0, false, st));
+    if (prof) {
+        HIPCHK(hipEventRecord(p->ev[4], st));
+        HIPCHK(hipEventSynchronize(p->ev[4]));
+        for (int k = 0; k < 4; ++k) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, p->ev[k], p->ev[k + 1]));
+            p->phase_ms[k] += ms;
+        }
+        p->phase_calls++;
+    }
     return CELESTE_OK;
 }
 
@@ -453,7 +545,8 @@ int plain_sequence(celeste_plan* p, const double* theta, const uint8_t* active, 
 }
 
 int config_code(const celeste_plan* p) {
-    return ((p->chunk * 8 + p->wpb) * 2 + p->dynamic) * 1000003 + p->persistent_grid() * 131 + p->tile_h;
+    return ((((p->chunk * 8 + p->wpb) * 2 + p->dynamic) * 32 + p->rows) * 2 + p->render_mode) * 1000003 +
+           p->persistent_grid() * 131 + p->tile_h * 7 + p->tile_w;
 }
 
 // Lists of boxes and items of a set of sources (host), uploaded into the plan's list buffers
@@ -554,10 +647,12 @@ void celeste_plan_destroy(celeste_plan* p) {
                     p->d_tab1, p->d_coef1, p->d_tab2, p->d_coef2, p->d_partials, p->d_E, p->d_V, p->d_bg,
                     p->d_tile_sums, p->d_status, p->d_counter, p->d_grad, p->d_hess, p->d_theta_trial,
                     p->d_pred, p->d_elbo_cur, p->d_elbo_trial, p->d_radius, p->d_done, p->d_list_src,
-                    p->d_list_pair, p->d_list_item};
+                    p->d_list_pair, p->d_list_item, p->d_cls_items, p->d_pair_lgamma};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    for (hipEvent_t& e : p->ev)
+        if (e) (void)hipEventDestroy(e);
     delete p;
 }
 
@@ -602,12 +697,15 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
             voff += (int64_t)bx.h * bx.w;
         }
     p->n_visits = voff;
+    for (const celeste_image& im : p->images) p->max_pix = std::max<int64_t>(p->max_pix, (int64_t)im.H * im.W);
     build_items(p);
     build_nbr(p);
+    build_pair_classes(p);
+    build_class_items(p);
     build_tiles(p);
-    // capacity of per-item buffers: the smallest chunk (64 pixels) gives the most items
+    // capacity of per-item buffers: the shortest strips (4 rows) and smallest chunk (64)
     size_t max_items = 0;
-    for (const PairDev& pd : p->pairs) max_items += (size_t)((int64_t)pd.h * pd.w + 63) / 64;
+    for (const PairDev& pd : p->pairs) max_items += (size_t)((strips_of(pd, 4) + 63) / 64);
     const size_t np = std::max<size_t>(p->pairs.size(), 1);
     size_t& W = p->workspace;
     int r = CELESTE_OK;
@@ -631,6 +729,7 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     A(dalloc(&p->d_V, (size_t)p->n_pix, W));
     A(dalloc(&p->d_bg, (size_t)p->n_visits * 2, W));
     A(dalloc(&p->d_tile_sums, std::max<size_t>(p->tiles.size(), 1), W));
+    A(dalloc(&p->d_pair_lgamma, np, W));
     A(dalloc(&p->d_status, 1, W));
     A(dalloc(&p->d_counter, 1, W));
     const size_t S = (size_t)p->n_src;
@@ -645,6 +744,7 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     A(dalloc(&p->d_list_src, S, W));
     A(dalloc(&p->d_list_pair, np, W));
     A(dalloc(&p->d_list_item, max_items, W));
+    A(dalloc(&p->d_cls_items, max_items, W));
     p->cap_list_item = max_items;
     if (r != CELESTE_OK) {
         celeste_plan_destroy(p);
@@ -662,6 +762,10 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
             hipMemset(p->d_counter, 0, sizeof(int)) != hipSuccess ||
             hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
             rc = hip_fail(hipGetLastError(), "plan upload");
+    }
+    if (rc == CELESTE_OK && (p->consts.flags & CELESTE_INCLUDE_LGAMMA)) {
+        const hipError_t e = launch_pair_lgamma(p->geom(), (int)p->pairs.size(), p->d_pair_lgamma, nullptr);
+        if (e != hipSuccess || hipDeviceSynchronize() != hipSuccess) rc = hip_fail(hipGetLastError(), "log(x!) sums");
     }
     if (rc != CELESTE_OK) {
         celeste_plan_destroy(p);
@@ -684,16 +788,24 @@ int celeste_plan_get_info(const celeste_plan* p, celeste_plan_info* info) {
     info->tile_h = p->tile_h;
     info->tile_w = p->tile_w;
     info->dynamic_queue = p->dynamic;
+    info->strip_rows = p->rows;
+    info->render_mode = p->render_mode;
+    info->n_classes = p->n_class;
     info->workspace_bytes = (int64_t)p->workspace;
     return CELESTE_OK;
 }
 
-int celeste_plan_set_launch(celeste_plan* p, int chunk, int wpb, int grid, int dynamic, int tile_h, int tile_w) {
+int celeste_plan_set_launch(celeste_plan* p, int chunk, int wpb, int grid, int dynamic, int tile_h, int tile_w,
+                            int strip_rows, int render_mode) {
     if (!p || chunk < 64 || chunk > 1024 || chunk % 64 || (wpb != 1 && wpb != 2 && wpb != 4) || grid < 1 ||
-        (dynamic != 0 && dynamic != 1) || tile_h < 1 || tile_w < 1 || tile_h * tile_w != 64)
+        (dynamic != 0 && dynamic != 1) || tile_w < 1 || tile_w > 64 || 64 % tile_w || tile_h < 1 ||
+        (tile_h * tile_w != 64 && tile_h * tile_w != 128 && tile_h * tile_w != 256) ||
+        (strip_rows != 4 && strip_rows != 8 && strip_rows != 16) || (render_mode != 0 && render_mode != 1))
         return CELESTE_EINVAL;
     HIPCHK(hipDeviceSynchronize());
     drop_graph(p);
+    p->rows = strip_rows;
+    p->render_mode = render_mode;
     p->chunk = chunk;
     p->wpb = wpb;
     p->grid = grid;
@@ -718,7 +830,23 @@ int celeste_plan_set_launch(celeste_plan* p, int chunk, int wpb, int grid, int d
         }
     }
     build_items(p);
+    build_class_items(p);
     return upload_geometry(p);
+}
+
+int celeste_plan_profile(celeste_plan* p, int enable, double* ms, int64_t* calls, int reset) {
+    if (!p) return CELESTE_EINVAL;
+    if (enable && !p->ev[0])
+        for (hipEvent_t& e : p->ev) HIPCHK(hipEventCreate(&e));
+    p->profiling = enable != 0;
+    if (ms)
+        for (int k = 0; k < 4; ++k) ms[k] = p->phase_ms[k];
+    if (calls) *calls = p->phase_calls;
+    if (reset) {
+        for (double& v : p->phase_ms) v = 0.0;
+        p->phase_calls = 0;
+    }
+    return CELESTE_OK;
 }
 
 int celeste_plan_use_graph(celeste_plan* p, int enable) {
@@ -756,7 +884,7 @@ int celeste_elbo_grad(celeste_plan* p, const double* theta, const uint8_t* activ
         drop_graph(p);
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-        const int rc = batched_sequence(p, theta, active, true, elbo, grad, p->cap_stream);
+        const int rc = batched_sequence(p, theta, active, true, elbo, grad, p->cap_stream, true);
         const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
         if (rc != CELESTE_OK) {
             if (g) (void)hipGraphDestroy(g);
@@ -781,7 +909,7 @@ int celeste_hvp(celeste_plan* p, const double* theta, const double* v, double* h
     const Scope sc = scope_all(p);
     CHK(validate_theta(p, theta, nullptr, nullptr, p->n_src, st));
     CHK(prep(p, theta, sc.pair, false, DIR_NONE, nullptr, 0, st));
-    CHK(render(p, false, st));
+    CHK(render(p, st));
     CHK(prep(p, theta, sc.pair, true, DIR_VEC, v, 0, st));
     CHK(adjoint(p, sc.item, nullptr, true, BASE_PLANES, true, st));
     CHK(finalize(p, theta, sc.src, nullptr, true, DIR_VEC, v, 0, true, nullptr, grad, hv, ROW, false, st));
@@ -808,7 +936,7 @@ int celeste_hessian(celeste_plan* p, const double* theta, const int32_t* src, in
     const Scope all = scope_all(p);
     CHK(validate_theta(p, theta, nullptr, nullptr, p->n_src, st));
     CHK(prep(p, theta, all.pair, false, DIR_NONE, nullptr, 0, st));
-    CHK(render(p, false, st));
+    CHK(render(p, st));
     for (int i = 0; i < NP; ++i) {
         CHK(prep(p, theta, sp, true, DIR_UNIT, nullptr, i, st));
         CHK(adjoint(p, si, nullptr, true, BASE_PLANES, true, st));
@@ -823,7 +951,7 @@ int celeste_total_elbo(celeste_plan* p, const double* theta, double* out, hipStr
     const Scope sc = scope_all(p);
     CHK(validate_theta(p, theta, nullptr, nullptr, p->n_src, st));
     CHK(prep(p, theta, sc.pair, false, DIR_NONE, nullptr, 0, st));
-    CHK(render(p, true, st));
+    CHK(render_tiles(p, true, st));
     HIPCHK(launch_tile_total(p->d_tile_sums, (int)p->tiles.size(), theta, p->consts, p->n_src, out, p->d_status, st));
     return CELESTE_OK;
 }
@@ -1021,14 +1149,15 @@ int celeste_autotune(celeste_plan* p, const double* theta, int reps, double* bes
         ms = t[t.size() / 2];
         return CELESTE_OK;
     };
-    struct Cfg { int chunk, wpb, grid, dyn, th, tw; };
-    Cfg best{p->chunk, p->wpb, p->persistent_grid(), p->dynamic, p->tile_h, p->tile_w};
+    struct Cfg { int chunk, wpb, grid, dyn, th, tw, rows, rmode; };
+    Cfg best{p->chunk, p->wpb, p->persistent_grid(), p->dynamic, p->tile_h, p->tile_w, p->rows, p->render_mode};
     double best_t = 1e300;
-    int rc = celeste_plan_set_launch(p, best.chunk, best.wpb, best.grid, best.dyn, best.th, best.tw);
+    int rc = celeste_plan_set_launch(p, best.chunk, best.wpb, best.grid, best.dyn, best.th, best.tw, best.rows,
+                                     best.rmode);
     if (rc == CELESTE_OK) rc = time_cfg(best_t);
     auto trial = [&](Cfg c) {
         if (rc != CELESTE_OK) return;
-        rc = celeste_plan_set_launch(p, c.chunk, c.wpb, c.grid, c.dyn, c.th, c.tw);
+        rc = celeste_plan_set_launch(p, c.chunk, c.wpb, c.grid, c.dyn, c.th, c.tw, c.rows, c.rmode);
         if (rc != CELESTE_OK) return;
         double t = 0;
         rc = time_cfg(t);
@@ -1037,14 +1166,21 @@ int celeste_autotune(celeste_plan* p, const double* theta, int reps, double* bes
             best = c;
         }
     };
-    const int tiles[3][2] = {{8, 8}, {4, 16}, {16, 4}};
-    for (auto& tl : tiles) trial(Cfg{best.chunk, best.wpb, best.grid, best.dyn, tl[0], tl[1]});
-    for (int ch : {64, 128, 256, 512, 1024}) trial(Cfg{ch, best.wpb, best.grid, best.dyn, best.th, best.tw});
-    for (int w : {1, 2, 4}) trial(Cfg{best.chunk, w, best.grid, best.dyn, best.th, best.tw});
-    for (int g : {p->n_cu, 2 * p->n_cu, 4 * p->n_cu, 8 * p->n_cu, 16 * p->n_cu, 64 * p->n_cu})
-        trial(Cfg{best.chunk, best.wpb, g, best.dyn, best.th, best.tw});
-    for (int d : {0, 1}) trial(Cfg{best.chunk, best.wpb, best.grid, d, best.th, best.tw});
-    if (rc == CELESTE_OK) rc = celeste_plan_set_launch(p, best.chunk, best.wpb, best.grid, best.dyn, best.th, best.tw);
+    Cfg c = best;
+    for (int r : {4, 8, 16}) { c = best; c.rows = r; trial(c); }
+    for (int ch : {64, 128, 256, 512, 1024}) { c = best; c.chunk = ch; trial(c); }
+    for (int w : {1, 2, 4}) { c = best; c.wpb = w; trial(c); }
+    for (int g : {p->n_cu, 2 * p->n_cu, 4 * p->n_cu, 8 * p->n_cu, 16 * p->n_cu, 64 * p->n_cu}) {
+        c = best;
+        c.grid = g;
+        trial(c);
+    }
+    for (int d : {0, 1}) { c = best; c.dyn = d; trial(c); }
+    const int tiles[4][2] = {{8, 8}, {4, 16}, {16, 8}, {16, 16}};
+    for (auto& tl : tiles) { c = best; c.rmode = 1; c.th = tl[0]; c.tw = tl[1]; trial(c); }
+    if (rc == CELESTE_OK)
+        rc = celeste_plan_set_launch(p, best.chunk, best.wpb, best.grid, best.dyn, best.th, best.tw, best.rows,
+                                     best.rmode);
     p->use_graph = graph;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

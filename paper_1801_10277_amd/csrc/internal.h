@@ -25,7 +25,7 @@ enum CompField {
     F_WT,    // galaxy: frac_dev (de Vaucouleurs) or 1 - frac_dev (exponential); star: 1
     F_WNU,   // galaxy: F_WT * nu_j (the component covariance is nu_j Sigma_shape + PSF)
     F_SGN,   // +1 de Vaucouleurs, -1 exponential, 0 star
-    F_PAD
+    F_RDY    // exp(-P_yy): ratio of successive row-to-row factors down a column
 };
 
 // Per-(source, image) brightness factors: the source's expected light is
@@ -52,7 +52,7 @@ struct PairDev {              // one box (source, image)
     int32_t nbr_begin, nbr_end;     // other boxes of the same image that intersect it
 };
 
-struct Item {                 // a chunk of a box's pixels (row-major inside the box)
+struct Item {                 // a run of strips of one box: strips start .. start + count - 1
     int32_t pair, start, count, pad;
 };
 
@@ -122,9 +122,8 @@ struct AdjArgs {
     const uint8_t* active;     // [S] or null
     const double* tab;         // T tables
     const double* coef;
-    const double* tab_val;     // double-valued tables used for overlapping boxes (BASE_NBR)
+    const double* tab_val;     // double tables used for overlapping boxes (BASE_NBR)
     const double* coef_val;
-    int32_t tab_val_stride;    // 1 if tab_val holds doubles, 2 if it holds duals
     int32_t dynamic;
     int* counter;
     const double* E;
@@ -151,6 +150,7 @@ struct FinArgs {
     const double* dir;
     int32_t dir_mode, dir_unit;
     const int32_t* patch_ptr;  // device [S+1]
+    const double* pair_lgamma; // [n_pairs] sum of log(x!) over each box, or null
     const double* partials;
     int32_t deriv;             // 0: value only
     double* elbo;              // [S] or null
@@ -167,9 +167,16 @@ hipError_t launch_validate(const double* theta, const uint8_t* active, const int
                            int S, int* status, hipStream_t st);
 hipError_t launch_prep(const PrepArgs& a, bool tangent, hipStream_t st);
 hipError_t launch_render(const RenderArgs& a, int waves_per_block, hipStream_t st);
+// strips.hip
 hipError_t launch_adjoint(const AdjArgs& a, bool tangent, int base_mode, bool deriv, int grid,
-                          int waves_per_block, hipStream_t st);
-hipError_t launch_background(const BgArgs& a, int grid, int waves_per_block, hipStream_t st);
+                          int waves_per_block, int strip_rows, hipStream_t st);
+hipError_t launch_background(const BgArgs& a, int grid, int waves_per_block, int strip_rows, hipStream_t st);
+hipError_t launch_pair_lgamma(const Geometry& g, int n_pairs, double* out, hipStream_t st);
+hipError_t launch_fill_planes(const celeste_image* images, int n_img, int max_pix, double* E, double* V,
+                              const int* status, hipStream_t st);
+hipError_t launch_render_strips(const Sel& items, const Geometry& g, const double* tab, const double* coef,
+                                double* E, double* V, int strip_rows, int grid, int waves_per_block,
+                                const int* status, hipStream_t st);
 hipError_t launch_finalize(const FinArgs& a, bool tangent, hipStream_t st);
 hipError_t launch_tile_total(const double* tile_sums, int n_tiles, const double* theta, const Consts& c,
                              int S, double* out, const int* status, hipStream_t st);

@@ -3,17 +3,17 @@
 // Work decomposition:
 //  * k_prep:      one thread per (source, image) box builds the box's 45-Gaussian table
 //                 and brightness factors (value, or value + tangent).
-//  * k_render:    one wave per 64-pixel tile sums E[F] and Var[F] of every box that
-//                 covers each pixel, in box order (deterministic, no atomics).
-//  * k_adjoint:   persistent waves pop work items (a chunk of one box's pixels); each lane
-//                 walks pixels of the chunk, recomputes the own source's Gaussians, forms
-//                 the pixel term and its adjoint, and the wave reduces its 11 sums with
-//                 cross-lane shuffles into one per-item slot.
+//  * k_render:    one wave per render tile sums E[F] and Var[F] of every box that
+//                 covers each pixel, in box order (deterministic, no atomics), and
+//                 optionally the pixel terms of covered pixels (total ELBO).
+//  * the fused adjoint and the strip render live in strips.hip.
 //  * k_finalize:  one thread per source sums its items in a fixed order and applies the
 //                 chain rule to the 27 parameters, plus the KL term.
 // Table entries are addressed with wave-uniform indices so the compiler serves them
 // through scalar loads; pixel data is read coalesced along box rows.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "internal.h"
 #include "model.h"
@@ -73,168 +73,80 @@ __global__ void __launch_bounds__(128) k_prep(PrepArgs a) {
 }
 
 // ----------------------------------------------------------------------- render
-__global__ void __launch_bounds__(256) k_render(RenderArgs a) {
+// Tile = (64 / tile_w * RP) rows x tile_w cols; lane l owns rows (l / tile_w) + k * (64 / tile_w),
+// k < RP, of column l % tile_w.
+template <int RP>
+__global__ void __launch_bounds__(256) k_render(RenderArgs a, const TileDev* __restrict__ tiles,
+                                                const int32_t* __restrict__ tile_list,
+                                                const PairDev* __restrict__ pairs,
+                                                const celeste_image* __restrict__ images,
+                                                const double* __restrict__ tab, const double* __restrict__ coef,
+                                                const double* __restrict__ xs, double* __restrict__ Eout,
+                                                double* __restrict__ Vout, double* __restrict__ tile_sums) {
     if (*a.status) return;
     const int lane = threadIdx.x & 63;
     const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (t >= a.n_tiles) return;
-    const TileDev td = a.tiles[t];
-    const celeste_image& im = a.g.images[td.img];
-    const int r = td.r0 + lane / a.tile_w;
+    const TileDev td = tiles[t];
+    const celeste_image& im = images[td.img];
+    const int rows_per_pass = 64 / a.tile_w;
     const int c = td.c0 + lane % a.tile_w;
-    const bool inside = r < im.H && c < im.W;
-    double E = im.sky, V = 0.0;
-    bool covered = false;
-    for (int k = td.list_begin; k < td.list_end; ++k) {
-        const int pi = __builtin_amdgcn_readfirstlane(a.tile_list[k]);
-        const PairDev o = a.g.pairs[pi];
-        if (!inside || r < o.r0 || r >= o.r0 + o.h || c < o.c0 || c >= o.c0 + o.w) continue;
-        covered = true;
-        double fs, fg;
-        eval_value(a.tab + (size_t)pi * NCOMP * CST, 1, (double)c, (double)r, fs, fg);
-        const double* k4 = a.coef + (size_t)pi * NCOEF;
-        const double Et = k4[C_K1] * fs + k4[C_K2] * fg;
-        E += Et;
-        V += k4[C_K3] * fs * fs + k4[C_K4] * fg * fg - Et * Et;
+    int r[RP];
+    bool inside[RP], covered[RP];
+    double E[RP], V[RP], px[RP], py[RP];
+#pragma unroll
+    for (int k = 0; k < RP; ++k) {
+        r[k] = td.r0 + lane / a.tile_w + k * rows_per_pass;
+        inside[k] = r[k] < im.H && c < im.W;
+        covered[k] = false;
+        E[k] = im.sky;
+        V[k] = 0.0;
+        px[k] = (double)c;
+        py[k] = (double)r[k];
     }
-    const size_t gi = (size_t)im.pix_offset + (size_t)r * im.W + c;
-    if (inside) {
-        a.E[gi] = E;
-        a.V[gi] = V;
+    for (int j = td.list_begin; j < td.list_end; ++j) {
+        const int pi = __builtin_amdgcn_readfirstlane(tile_list[j]);
+        const PairDev o = pairs[pi];
+        bool in[RP];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < RP; ++k) {
+            in[k] = inside[k] && r[k] >= o.r0 && r[k] < o.r0 + o.h && c >= o.c0 && c < o.c0 + o.w;
+            any |= in[k];
+        }
+        if (!any) continue;
+        double fs[RP], fg[RP];
+        eval_value<RP>(tab + (size_t)pi * NCOMP * CST, px, py, fs, fg);
+        const double* k4 = coef + (size_t)pi * NCOEF;
+        const double k1 = k4[C_K1], k2 = k4[C_K2], k3 = k4[C_K3], kk4 = k4[C_K4];
+#pragma unroll
+        for (int k = 0; k < RP; ++k) {
+            if (!in[k]) continue;
+            covered[k] = true;
+            const double Et = k1 * fs[k] + k2 * fg[k];
+            E[k] += Et;
+            V[k] += k3 * fs[k] * fs[k] + kk4 * fg[k] * fg[k] - Et * Et;
+        }
     }
-    if (a.tile_sums) {
-        double l = 0.0;
-        if (covered) {
-            const double x = a.g.x[gi];
+    double l = 0.0;
+#pragma unroll
+    for (int k = 0; k < RP; ++k) {
+        if (!inside[k]) continue;
+        const size_t gi = (size_t)im.pix_offset + (size_t)r[k] * im.W + c;
+        Eout[gi] = E[k];
+        Vout[gi] = V[k];
+        if (tile_sums && covered[k]) {
+            const double x = xs[gi];
             if (x == x) {
-                l = x * (log(E) - 0.5 * V / (E * E)) - E;
-                if (a.g.consts.flags & CELESTE_INCLUDE_LGAMMA) l -= lgamma(x + 1.0);
+                double lk = x * (log(E[k]) - 0.5 * V[k] / (E[k] * E[k])) - E[k];
+                if (a.g.consts.flags & CELESTE_INCLUDE_LGAMMA) lk -= lgamma(x + 1.0);
+                l += lk;
             }
         }
+    }
+    if (tile_sums) {
         l = wave_sum(l);
-        if (lane == 0) a.tile_sums[t] = l;
-    }
-}
-
-// ----------------------------------------------------------------------- adjoint
-__device__ inline void nbr_background(const Geometry& g, const PairDev& p, const double* tab_val,
-                                      const double* coef_val, int stride, double sky, int r, int c,
-                                      double& Eb, double& Vb) {
-    Eb = sky;
-    Vb = 0.0;
-    for (int q = p.nbr_begin; q < p.nbr_end; ++q) {
-        const int pi = __builtin_amdgcn_readfirstlane(g.nbr[q]);
-        const PairDev o = g.pairs[pi];
-        if (r < o.r0 || r >= o.r0 + o.h || c < o.c0 || c >= o.c0 + o.w) continue;
-        double fs, fg;
-        eval_value(tab_val + (size_t)pi * NCOMP * CST * stride, stride, (double)c, (double)r, fs, fg);
-        const double* k = coef_val + (size_t)pi * NCOEF * stride;
-        const double Et = k[C_K1 * stride] * fs + k[C_K2 * stride] * fg;
-        Eb += Et;
-        Vb += k[C_K3 * stride] * fs * fs + k[C_K4 * stride] * fg * fg - Et * Et;
-    }
-}
-
-__device__ inline int next_item(int* counter, int lane) {
-    int v = 0;
-    if (lane == 0) v = atomicAdd(counter, 1);
-    return __shfl(v, 0, 64);
-}
-
-template <class T, int BASE, bool DERIV>
-__global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
-    if (*a.status) return;
-    const int lane = threadIdx.x & 63;
-    const int wpb = blockDim.x >> 6;
-    const int nw = gridDim.x * wpb;
-    const bool lgam = (a.g.consts.flags & CELESTE_INCLUDE_LGAMMA) != 0;
-    int j = a.dynamic ? next_item(a.counter, lane) : blockIdx.x * wpb + (threadIdx.x >> 6);
-    while (j < a.items.n) {
-        const int ii = __builtin_amdgcn_readfirstlane(sel_at(a.items, j));
-        const Item it = a.g.items[ii];
-        const PairDev p = a.g.pairs[it.pair];
-        if (!a.active || a.active[p.src]) {
-            const celeste_image& im = a.g.images[p.img];
-            const T* tab = reinterpret_cast<const T*>(a.tab) + (size_t)it.pair * NCOMP * CST;
-            const T* kp = reinterpret_cast<const T*>(a.coef) + (size_t)it.pair * NCOEF;
-            const T k[NCOEF] = {kp[0], kp[1], kp[2], kp[3]};
-            T acc[NACC];
-#pragma unroll
-            for (int f = 0; f < NACC; ++f) acc[f] = scalar_traits<T>::make(0.0, 0.0);
-            for (int q = lane; q < it.count; q += 64) {
-                const int idx = it.start + q;
-                const int rr = idx / p.w;
-                const int r = p.r0 + rr;
-                const int c = p.c0 + (idx - rr * p.w);
-                const size_t gi = (size_t)im.pix_offset + (size_t)r * im.W + c;
-                const double x = a.g.x[gi];
-                if (x != x) continue;   // masked pixel
-                double Eb, Vb;
-                if (BASE == BASE_PLANES) {
-                    Eb = a.E[gi];
-                    Vb = a.V[gi];
-                } else if (BASE == BASE_BG) {
-                    const size_t vi = (size_t)(p.visit_off + idx);
-                    Eb = a.bg[2 * vi];
-                    Vb = a.bg[2 * vi + 1];
-                } else {
-                    nbr_background(a.g, p, a.tab_val, a.coef_val, a.tab_val_stride, im.sky, r, c, Eb, Vb);
-                }
-                if (BASE == BASE_PLANES && !DERIV) {
-                    // value only: the planes already hold the totals
-                    Own<T> o;
-                    pixel_accumulate<T, false>(x, scalar_traits<T>::make(Eb, 0.0),
-                                               scalar_traits<T>::make(Vb, 0.0),
-                                               scalar_traits<T>::make(0.0, 0.0), o, k, acc, lgam);
-                    continue;
-                }
-                Own<T> o;
-                eval_own<T, DERIV>(tab, (double)c, (double)r, o);
-                const T Es = k[C_K1] * o.fs + k[C_K2] * o.fg;
-                const T Vs = k[C_K3] * (o.fs * o.fs) + k[C_K4] * (o.fg * o.fg) - Es * Es;
-                T E, V;
-                if (BASE == BASE_PLANES) {
-                    E = value_with_tangent(Eb, Es);
-                    V = value_with_tangent(Vb, Vs);
-                } else {
-                    E = Eb + Es;
-                    V = Vb + Vs;
-                }
-                pixel_accumulate<T, DERIV>(x, E, V, Es, o, k, acc, lgam);
-            }
-            T* out = reinterpret_cast<T*>(a.partials) + (size_t)ii * NACC;
-#pragma unroll
-            for (int f = 0; f < NACC; ++f) {
-                const T s = wave_sum(acc[f]);
-                if (lane == 0) out[f] = s;
-            }
-        }
-        j = a.dynamic ? next_item(a.counter, lane) : j + nw;
-    }
-}
-
-// Per-visit background (sky + every other overlapping box) of the selected items.
-__global__ void __launch_bounds__(256) k_background(BgArgs a) {
-    if (*a.status) return;
-    const int lane = threadIdx.x & 63;
-    const int wpb = blockDim.x >> 6;
-    const int nw = gridDim.x * wpb;
-    for (int j = blockIdx.x * wpb + (threadIdx.x >> 6); j < a.items.n; j += nw) {
-        const int ii = __builtin_amdgcn_readfirstlane(sel_at(a.items, j));
-        const Item it = a.g.items[ii];
-        const PairDev p = a.g.pairs[it.pair];
-        const celeste_image& im = a.g.images[p.img];
-        for (int q = lane; q < it.count; q += 64) {
-            const int idx = it.start + q;
-            const int rr = idx / p.w;
-            const int r = p.r0 + rr;
-            const int c = p.c0 + (idx - rr * p.w);
-            double Eb, Vb;
-            nbr_background(a.g, p, a.tab_val, a.coef_val, 1, im.sky, r, c, Eb, Vb);
-            const size_t vi = (size_t)(p.visit_off + idx);
-            a.bg[2 * vi] = Eb;
-            a.bg[2 * vi + 1] = Vb;
-        }
+        if (lane == 0) tile_sums[t] = l;
     }
 }
 
@@ -266,6 +178,7 @@ __global__ void __launch_bounds__(128) k_finalize(FinArgs a) {
             }
         }
         val += z[A_VAL];
+        if (a.pair_lgamma) val = val - a.pair_lgamma[pi];
         if (a.deriv) chain_pair<T>(p, a.g.images[pd.img], z, g);
     }
     if (a.g.consts.flags & CELESTE_INCLUDE_KL) {
@@ -346,48 +259,14 @@ hipError_t launch_prep(const PrepArgs& a, bool tangent, hipStream_t st) {
 hipError_t launch_render(const RenderArgs& a, int wpb, hipStream_t st) {
     if (a.n_tiles <= 0) return hipSuccess;
     const dim3 grid((a.n_tiles + wpb - 1) / wpb);
-    hipLaunchKernelGGL(k_render, grid, dim3(64 * wpb), 0, st, a);
-    return hipGetLastError();
-}
-
-template <class T, int BASE, bool DERIV>
-static void adj(const AdjArgs& a, int grid, int wpb, hipStream_t st) {
-    hipLaunchKernelGGL((k_adjoint<T, BASE, DERIV>), dim3(grid), dim3(64 * wpb), 0, st, a);
-}
-
-hipError_t launch_adjoint(const AdjArgs& a, bool tangent, int base, bool deriv, int grid, int wpb,
-                          hipStream_t st) {
-    if (a.items.n <= 0) return hipSuccess;
-    if (a.dynamic) {
-        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, a.counter, 0, 1);
-    } else {
-        const int need = (a.items.n + wpb - 1) / wpb;
-        if (grid > need) grid = need;
-    }
-    if (grid < 1) grid = 1;
-    if (tangent) {
-        if (base == BASE_PLANES) deriv ? adj<dual, BASE_PLANES, true>(a, grid, wpb, st)
-                                       : adj<dual, BASE_PLANES, false>(a, grid, wpb, st);
-        else if (base == BASE_BG) deriv ? adj<dual, BASE_BG, true>(a, grid, wpb, st)
-                                        : adj<dual, BASE_BG, false>(a, grid, wpb, st);
-        else deriv ? adj<dual, BASE_NBR, true>(a, grid, wpb, st) : adj<dual, BASE_NBR, false>(a, grid, wpb, st);
-    } else {
-        if (base == BASE_PLANES) deriv ? adj<double, BASE_PLANES, true>(a, grid, wpb, st)
-                                       : adj<double, BASE_PLANES, false>(a, grid, wpb, st);
-        else if (base == BASE_BG) deriv ? adj<double, BASE_BG, true>(a, grid, wpb, st)
-                                        : adj<double, BASE_BG, false>(a, grid, wpb, st);
-        else deriv ? adj<double, BASE_NBR, true>(a, grid, wpb, st)
-                   : adj<double, BASE_NBR, false>(a, grid, wpb, st);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_background(const BgArgs& a, int grid, int wpb, hipStream_t st) {
-    if (a.items.n <= 0) return hipSuccess;
-    const int need = (a.items.n + wpb - 1) / wpb;
-    if (grid > need) grid = need;
-    if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_background, dim3(grid), dim3(64 * wpb), 0, st, a);
+    const int rp = a.tile_h * a.tile_w / 64;
+    const Geometry& g = a.g;
+#define RENDER_ARGS a, a.tiles, a.tile_list, g.pairs, g.images, a.tab, a.coef, g.x, a.E, a.V, a.tile_sums
+    if (rp == 1) hipLaunchKernelGGL(k_render<1>, grid, dim3(64 * wpb), 0, st, RENDER_ARGS);
+    else if (rp == 2) hipLaunchKernelGGL(k_render<2>, grid, dim3(64 * wpb), 0, st, RENDER_ARGS);
+    else if (rp == 4) hipLaunchKernelGGL(k_render<4>, grid, dim3(64 * wpb), 0, st, RENDER_ARGS);
+    else return hipErrorInvalidValue;
+#undef RENDER_ARGS
     return hipGetLastError();
 }
 

@@ -5,6 +5,10 @@
 #pragma once
 #include "internal.h"
 
+#ifndef CELESTE_GAL_UNROLL
+#define CELESTE_GAL_UNROLL 1
+#endif
+
 namespace cel {
 
 // log flux_b = log r + sum_k BSIGN[b][k] c_k with c_k = log(flux_{k+1} / flux_k),
@@ -68,7 +72,7 @@ __device__ inline void write_comp(T* e, T cx, T cy, T sxx, T sxy, T syy, double 
     e[F_WT] = wt;
     e[F_WNU] = wnu;
     e[F_SGN] = scalar_traits<T>::make(sgn, 0.0);
-    e[F_PAD] = scalar_traits<T>::make(0.0, 0.0);
+    e[F_RDY] = exp(-(sxx * inv));
 }
 
 // Table of the 45 Gaussians of source parameters p in image im (components: 3 star,
@@ -110,103 +114,39 @@ __device__ inline void build_pair(const T* p, const celeste_image& im, const Con
     }
 }
 
-// Own-source profile sums at one pixel and their derivatives with respect to the
-// position, frac_dev and the shape covariance.
-template <class T>
-struct Own {
-    T fs, fsx, fsy;            // f_star and d f_star / d u
-    T fg, D, gx, gy;           // f_gal, d f_gal / d frac_dev, d f_gal / d u
-    T sxx, sxy, syy;           // 2 d f_gal / d Sxx, d f_gal / d Sxy, 2 d f_gal / d Syy
-};
-
-template <class T, bool DERIV>
-__device__ __forceinline__ void eval_own(const T* __restrict__ tab, double px, double py, Own<T>& o) {
-    const T zero = scalar_traits<T>::make(0.0, 0.0);
-    o.fs = o.fsx = o.fsy = o.fg = o.D = o.gx = o.gy = o.sxx = o.sxy = o.syy = zero;
+// Value-only profile sums of NPIX pixels from a double table.
+template <int NPIX>
+__device__ __forceinline__ void eval_value(const double* __restrict__ tab, const double* px, const double* py,
+                                           double* fs, double* fg) {
+#pragma unroll
+    for (int k = 0; k < NPIX; ++k) {
+        fs[k] = 0.0;
+        fg[k] = 0.0;
+    }
 #pragma unroll
     for (int c = 0; c < NPSF; ++c) {
-        const T* e = tab + c * CST;
-        const T dx = px - e[F_CX], dy = py - e[F_CY];
-        const T pdx = e[F_PXX] * dx + e[F_PXY] * dy;
-        const T pdy = e[F_PXY] * dx + e[F_PYY] * dy;
-        const T n = exp(e[F_LOGW] - 0.5 * (dx * pdx + dy * pdy));
-        o.fs += n;
-        if (DERIV) {
-            o.fsx += n * pdx;
-            o.fsy += n * pdy;
-        }
-    }
-#pragma unroll 2
-    for (int c = NPSF; c < NCOMP; ++c) {
-        const T* e = tab + c * CST;
-        const T dx = px - e[F_CX], dy = py - e[F_CY];
-        const T pdx = e[F_PXX] * dx + e[F_PXY] * dy;
-        const T pdy = e[F_PXY] * dx + e[F_PYY] * dy;
-        const T n = exp(e[F_LOGW] - 0.5 * (dx * pdx + dy * pdy));
-        const T nw = n * e[F_WT];
-        o.fg += nw;
-        if (DERIV) {
-            o.D += e[F_SGN] * n;
-            o.gx += nw * pdx;
-            o.gy += nw * pdy;
-            const T nwnu = n * e[F_WNU];
-            o.sxx += nwnu * (pdx * pdx - e[F_PXX]);
-            o.sxy += nwnu * (pdx * pdy - e[F_PXY]);
-            o.syy += nwnu * (pdy * pdy - e[F_PYY]);
-        }
-    }
-}
-
-// Value-only profile sums from a table whose entries are `stride` doubles apart
-// (stride 2 reads the value parts of a dual table).
-__device__ __forceinline__ void eval_value(const double* __restrict__ tab, int stride, double px,
-                                           double py, double& fs, double& fg) {
-    fs = 0.0;
-    fg = 0.0;
+        const double* e = tab + c * CST;
+        const double cx = e[F_CX], cy = e[F_CY], a = e[F_PXX], b = e[F_PXY], d = e[F_PYY], lw = e[F_LOGW];
 #pragma unroll
-    for (int c = 0; c < NPSF; ++c) {
-        const double* e = tab + c * CST * stride;
-        const double dx = px - e[F_CX * stride], dy = py - e[F_CY * stride];
-        const double pdx = e[F_PXX * stride] * dx + e[F_PXY * stride] * dy;
-        const double pdy = e[F_PXY * stride] * dx + e[F_PYY * stride] * dy;
-        fs += exp(e[F_LOGW * stride] - 0.5 * (dx * pdx + dy * pdy));
+        for (int k = 0; k < NPIX; ++k) {
+            const double dx = px[k] - cx, dy = py[k] - cy;
+            const double pdx = a * dx + b * dy;
+            const double pdy = b * dx + d * dy;
+            fs[k] += exp(lw - 0.5 * (dx * pdx + dy * pdy));
+        }
     }
-#pragma unroll 2
+#pragma unroll CELESTE_GAL_UNROLL
     for (int c = NPSF; c < NCOMP; ++c) {
-        const double* e = tab + c * CST * stride;
-        const double dx = px - e[F_CX * stride], dy = py - e[F_CY * stride];
-        const double pdx = e[F_PXX * stride] * dx + e[F_PXY * stride] * dy;
-        const double pdy = e[F_PXY * stride] * dx + e[F_PYY * stride] * dy;
-        fg += exp(e[F_LOGW * stride] - 0.5 * (dx * pdx + dy * pdy)) * e[F_WT * stride];
-    }
-}
-
-// Pixel term and its derivatives, accumulated into acc[NACC].  E and V are the
-// totals at the pixel, Es the own source's mean light, k the own factors.
-template <class T, bool DERIV>
-__device__ __forceinline__ void pixel_accumulate(double x, T E, T V, T Es, const Own<T>& o, const T* k,
-                                                 T* acc, bool lgam) {
-    const T inv = 1.0 / E;
-    const T r = V * inv * inv;
-    T l = x * (log(E) - 0.5 * r) - E;
-    if (lgam) l = l - lgamma(x + 1.0);
-    acc[A_VAL] += l;
-    if (DERIV) {
-        const T lE = x * inv * (1.0 + r) - 1.0;     // d l / d E
-        const T lV = -0.5 * x * (inv * inv);        // d l / d V
-        const T A = lE - 2.0 * Es * lV;             // d l / d E_s through E and through Var_s
-        acc[A_K1] += A * o.fs;
-        acc[A_K2] += A * o.fg;
-        acc[A_K3] += lV * (o.fs * o.fs);
-        acc[A_K4] += lV * (o.fg * o.fg);
-        const T Gs = A * k[C_K1] + 2.0 * lV * (k[C_K3] * o.fs);   // d l / d f_star
-        const T Gg = A * k[C_K2] + 2.0 * lV * (k[C_K4] * o.fg);   // d l / d f_gal
-        acc[A_UX] += Gs * o.fsx + Gg * o.gx;
-        acc[A_UY] += Gs * o.fsy + Gg * o.gy;
-        acc[A_FDEV] += Gg * o.D;
-        acc[A_SXX] += Gg * o.sxx;
-        acc[A_SXY] += Gg * o.sxy;
-        acc[A_SYY] += Gg * o.syy;
+        const double* e = tab + c * CST;
+        const double cx = e[F_CX], cy = e[F_CY], a = e[F_PXX], b = e[F_PXY], d = e[F_PYY], lw = e[F_LOGW];
+        const double wt = e[F_WT];
+#pragma unroll
+        for (int k = 0; k < NPIX; ++k) {
+            const double dx = px[k] - cx, dy = py[k] - cy;
+            const double pdx = a * dx + b * dy;
+            const double pdy = b * dx + d * dy;
+            fg[k] += exp(lw - 0.5 * (dx * pdx + dy * pdy)) * wt;
+        }
     }
 }
 

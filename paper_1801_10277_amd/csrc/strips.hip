@@ -1,0 +1,506 @@
+// Strip kernels: the batched render, the fused forward + adjoint and the per-visit
+// background, all walking vertical strips of L pixels.
+//
+// Along a column the exponent of a Gaussian is a quadratic in the row offset, so the
+// value at the next row is the current one times a ratio that itself shrinks by the
+// constant factor exp(-P_yy) per row.  A lane therefore pays two exps per Gaussian per
+// strip (value and first ratio at the strip's top row) and two multiplies per further
+// row, instead of one exp per Gaussian per pixel; the result equals the direct
+// evaluation up to a few ulps per row.  In the adjoint the per-row derivative terms are
+// polynomials of degree <= 2 in the row offset, so each Gaussian contributes through
+// three moments sum_k g_k, sum_k g_k k, sum_k g_k k^2 of its weighted values.
+//
+// Work item = a run of up to `chunk` strips of one box (strip s of a box of width w:
+// column s mod w, rows L (s / w) ... L (s / w) + L - 1 clipped to the box).  Lane j of a
+// wave takes strips start + j, start + j + 64, ...; consecutive lanes hold consecutive
+// columns, so pixel loads of one row are contiguous.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "model.h"
+
+namespace cel {
+
+__device__ __forceinline__ double clamp_arg(double v) { return v < 700.0 ? v : 700.0; }
+__device__ __forceinline__ dual clamp_arg(dual v) { return v.v < 700.0 ? v : mkd(700.0, 0.0); }
+
+__device__ __forceinline__ void strip_geometry(const PairDev& p, int s, int L, int& c, int& r0, int& nrow) {
+    const int rb = s / p.w;
+    c = p.c0 + (s - rb * p.w);
+    r0 = p.r0 + rb * L;
+    nrow = min(L, p.h - rb * L);
+}
+
+// Value and first row ratio of component e at column px, top row py0.
+template <class T>
+__device__ __forceinline__ void strip_seed(const T* e, double px, double py0, T& n, T& rt, T& pdx0, T& pdy0) {
+    const T dx = px - e[F_CX], dy = py0 - e[F_CY];
+    pdx0 = e[F_PXX] * dx + e[F_PXY] * dy;
+    pdy0 = e[F_PXY] * dx + e[F_PYY] * dy;
+    n = exp(e[F_LOGW] - 0.5 * (dx * pdx0 + dy * pdy0));
+    rt = exp(clamp_arg(-(pdy0 + 0.5 * e[F_PYY])));
+}
+
+// Pass A: star and galaxy profile values down the strip.
+template <class T, int L>
+__device__ __forceinline__ void strip_values(const T* __restrict__ tab, double px, double py0, T* fs, T* fg) {
+    const T zero = scalar_traits<T>::make(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < L; ++k) fs[k] = fg[k] = zero;
+#pragma unroll
+    for (int c = 0; c < NPSF; ++c) {
+        const T* e = tab + c * CST;
+        T n, rt, pdx0, pdy0;
+        strip_seed(e, px, py0, n, rt, pdx0, pdy0);
+        const T rdy = e[F_RDY];
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            fs[k] += n;
+            if (k + 1 < L) {
+                n = n * rt;
+                rt = rt * rdy;
+            }
+        }
+    }
+#pragma unroll CELESTE_GAL_UNROLL
+    for (int c = NPSF; c < NCOMP; ++c) {
+        const T* e = tab + c * CST;
+        T n, rt, pdx0, pdy0;
+        strip_seed(e, px, py0, n, rt, pdx0, pdy0);
+        const T rdy = e[F_RDY], wt = e[F_WT];
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            fg[k] += n * wt;
+            if (k + 1 < L) {
+                n = n * rt;
+                rt = rt * rdy;
+            }
+        }
+    }
+}
+
+// Pass B: d/d(position, frac_dev, shape covariance) accumulated with per-row weights
+// Gs (star) and Gg (galaxy).
+template <class T, int L>
+__device__ __forceinline__ void strip_adjoint(const T* __restrict__ tab, double px, double py0, const T* Gs,
+                                              const T* Gg, T* acc) {
+    constexpr double KC = 0.5 * (L - 1);
+    const T zero = scalar_traits<T>::make(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < NPSF; ++c) {
+        const T* e = tab + c * CST;
+        T n, rt, pdx0, pdy0;
+        strip_seed(e, px, py0, n, rt, pdx0, pdy0);
+        const T rdy = e[F_RDY];
+        T m0 = zero, m1 = zero;
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            const T g = Gs[k] * n;
+            m0 += g;
+            m1 += g * (k - KC);
+            if (k + 1 < L) {
+                n = n * rt;
+                rt = rt * rdy;
+            }
+        }
+        const T pdxc = pdx0 + e[F_PXY] * KC, pdyc = pdy0 + e[F_PYY] * KC;
+        acc[A_UX] += pdxc * m0 + e[F_PXY] * m1;
+        acc[A_UY] += pdyc * m0 + e[F_PYY] * m1;
+    }
+#pragma unroll CELESTE_GAL_UNROLL
+    for (int c = NPSF; c < NCOMP; ++c) {
+        const T* e = tab + c * CST;
+        T n, rt, pdx0, pdy0;
+        strip_seed(e, px, py0, n, rt, pdx0, pdy0);
+        const T rdy = e[F_RDY];
+        T m0 = zero, m1 = zero, m2 = zero;
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            const T g = Gg[k] * n;
+            m0 += g;
+            m1 += g * (k - KC);
+            m2 += g * ((k - KC) * (k - KC));
+            if (k + 1 < L) {
+                n = n * rt;
+                rt = rt * rdy;
+            }
+        }
+        const T a = e[F_PXX], b = e[F_PXY], d = e[F_PYY];
+        const T pdxc = pdx0 + b * KC, pdyc = pdy0 + d * KC;
+        const T wt = e[F_WT], wnu = e[F_WNU];
+        acc[A_FDEV] += e[F_SGN] * m0;
+        acc[A_UX] += wt * (pdxc * m0 + b * m1);
+        acc[A_UY] += wt * (pdyc * m0 + d * m1);
+        acc[A_SXX] += wnu * ((pdxc * pdxc - a) * m0 + 2.0 * (pdxc * b) * m1 + (b * b) * m2);
+        acc[A_SXY] += wnu * ((pdxc * pdyc - b) * m0 + (pdxc * d + pdyc * b) * m1 + (b * d) * m2);
+        acc[A_SYY] += wnu * ((pdyc * pdyc - d) * m0 + 2.0 * (pdyc * d) * m1 + (d * d) * m2);
+    }
+}
+
+// Pixel term of one row: accumulates the value and d/dk1..k4 and returns the row
+// weights d l / d f_star and d l / d f_gal.
+// (The -log(x!) constant is not added here: each box's sum of it is precomputed once.)
+template <class T, bool DERIV>
+__device__ __forceinline__ void strip_pixel(double x, T E, T V, T fs, T fg, const T* k, T* acc, T& Gs, T& Gg) {
+    const T Es = k[C_K1] * fs + k[C_K2] * fg;
+    const T inv = 1.0 / E;
+    const T r = V * inv * inv;
+    acc[A_VAL] += x * (log(E) - 0.5 * r) - E;
+    if (DERIV) {
+        const T lE = x * inv * (1.0 + r) - 1.0;
+        const T lV = -0.5 * x * (inv * inv);
+        const T A = lE - 2.0 * Es * lV;
+        acc[A_K1] += A * fs;
+        acc[A_K2] += A * fg;
+        acc[A_K3] += lV * (fs * fs);
+        acc[A_K4] += lV * (fg * fg);
+        Gs = A * k[C_K1] + 2.0 * lV * (k[C_K3] * fs);
+        Gg = A * k[C_K2] + 2.0 * lV * (k[C_K4] * fg);
+    }
+}
+
+// Sky plus the light of every other box of the image that covers each row of the strip.
+template <int L>
+__device__ __forceinline__ void strip_background(const PairDev& p, const PairDev* __restrict__ pairs,
+                                                 const int32_t* __restrict__ nbr, const double* __restrict__ tabv,
+                                                 const double* __restrict__ coefv, double sky, int c, int r0,
+                                                 double* Eb, double* Vb) {
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        Eb[k] = sky;
+        Vb[k] = 0.0;
+    }
+    for (int q = p.nbr_begin; q < p.nbr_end; ++q) {
+        const int pi = __builtin_amdgcn_readfirstlane(nbr[q]);
+        const PairDev o = pairs[pi];
+        if (c < o.c0 || c >= o.c0 + o.w || r0 + L <= o.r0 || r0 >= o.r0 + o.h) continue;
+        double fs[L], fg[L];
+        strip_values<double, L>(tabv + (size_t)pi * NCOMP * CST, (double)c, (double)r0, fs, fg);
+        const double* kk = coefv + (size_t)pi * NCOEF;
+        const double k1 = kk[C_K1], k2 = kk[C_K2], k3 = kk[C_K3], k4 = kk[C_K4];
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            const int r = r0 + k;
+            if (r < o.r0 || r >= o.r0 + o.h) continue;
+            const double Et = k1 * fs[k] + k2 * fg[k];
+            Eb[k] += Et;
+            Vb[k] += k3 * fs[k] * fs[k] + k4 * fg[k] * fg[k] - Et * Et;
+        }
+    }
+}
+
+__device__ inline int next_item_s(int* counter, int lane) {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(counter, 1);
+    return __shfl(v, 0, 64);
+}
+
+// ----------------------------------------------------------------------- planes
+__global__ void __launch_bounds__(256) k_fill_planes(const celeste_image* __restrict__ images,
+                                                     double* __restrict__ E, double* __restrict__ V,
+                                                     const int* status) {
+    if (*status) return;
+    const celeste_image& im = images[blockIdx.y];
+    const int64_t npix = (int64_t)im.H * im.W;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += (int64_t)gridDim.x * blockDim.x) {
+        E[im.pix_offset + i] = im.sky;
+        V[im.pix_offset + i] = 0.0;
+    }
+}
+
+// Adds the light of the boxes of one conflict-free class to the planes (no two boxes of a
+// class share a pixel, so the read-modify-write needs no atomics; classes run in order).
+template <int L>
+__global__ void __launch_bounds__(256) k_render_strips(Sel sel, const Item* __restrict__ items,
+                                                       const PairDev* __restrict__ pairs,
+                                                       const celeste_image* __restrict__ images,
+                                                       const double* __restrict__ tab,
+                                                       const double* __restrict__ coef, double* __restrict__ E,
+                                                       double* __restrict__ V, const int* status) {
+    if (*status) return;
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int nw = gridDim.x * wpb;
+    for (int j = blockIdx.x * wpb + (threadIdx.x >> 6); j < sel.n; j += nw) {
+        const int ii = __builtin_amdgcn_readfirstlane(sel_at(sel, j));
+        const Item it = items[ii];
+        const PairDev p = pairs[it.pair];
+        const celeste_image& im = images[p.img];
+        const double* tb = tab + (size_t)it.pair * NCOMP * CST;
+        const double* kp = coef + (size_t)it.pair * NCOEF;
+        const double k1 = kp[C_K1], k2 = kp[C_K2], k3 = kp[C_K3], k4 = kp[C_K4];
+        for (int q = lane; q < it.count; q += 64) {
+            int c, r0, nrow;
+            strip_geometry(p, it.start + q, L, c, r0, nrow);
+            double fs[L], fg[L];
+            strip_values<double, L>(tb, (double)c, (double)r0, fs, fg);
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                if (k >= nrow) break;
+                const size_t gi = (size_t)im.pix_offset + (size_t)(r0 + k) * im.W + c;
+                const double Et = k1 * fs[k] + k2 * fg[k];
+                E[gi] += Et;
+                V[gi] += k3 * fs[k] * fs[k] + k4 * fg[k] * fg[k] - Et * Et;
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------- adjoint
+template <class T, int BASE, bool DERIV, int L>
+__global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* __restrict__ items,
+                                                        const PairDev* __restrict__ pairs,
+                                                        const celeste_image* __restrict__ images,
+                                                        const int32_t* __restrict__ nbr,
+                                                        const double* __restrict__ xs, const double* __restrict__ Ep,
+                                                        const double* __restrict__ Vp, const double* __restrict__ bg,
+                                                        const double* __restrict__ tabp,
+                                                        const double* __restrict__ coefp,
+                                                        const double* __restrict__ tabv,
+                                                        const double* __restrict__ coefv,
+                                                        const uint8_t* __restrict__ active,
+                                                        double* __restrict__ partials) {
+    if (*a.status) return;
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int nw = gridDim.x * wpb;
+    const T zero = scalar_traits<T>::make(0.0, 0.0);
+    int j = a.dynamic ? next_item_s(a.counter, lane) : blockIdx.x * wpb + (threadIdx.x >> 6);
+    while (j < a.items.n) {
+        const int ii = __builtin_amdgcn_readfirstlane(sel_at(a.items, j));
+        const Item it = items[ii];
+        const PairDev p = pairs[it.pair];
+        if (!active || active[p.src]) {
+            const celeste_image& im = images[p.img];
+            const T* tab = reinterpret_cast<const T*>(tabp) + (size_t)it.pair * NCOMP * CST;
+            const T* kp = reinterpret_cast<const T*>(coefp) + (size_t)it.pair * NCOEF;
+            const T k[NCOEF] = {kp[0], kp[1], kp[2], kp[3]};
+            T acc[NACC];
+#pragma unroll
+            for (int f = 0; f < NACC; ++f) acc[f] = zero;
+            for (int q = lane; q < it.count; q += 64) {
+                int c, r0, nrow;
+                strip_geometry(p, it.start + q, L, c, r0, nrow);
+                const double px = (double)c, py0 = (double)r0;
+                double x[L], Eb[L], Vb[L];
+                if (BASE == BASE_NBR) {
+                    strip_background<L>(p, pairs, nbr, tabv, coefv, im.sky, c, r0, Eb, Vb);
+                }
+#pragma unroll
+                for (int kk = 0; kk < L; ++kk) {
+                    const int rr = kk < nrow ? kk : 0;   // rows past the box reuse row 0 (masked below)
+                    const size_t gi = (size_t)im.pix_offset + (size_t)(r0 + rr) * im.W + c;
+                    x[kk] = kk < nrow ? xs[gi] : __builtin_nan("");
+                    if (BASE == BASE_PLANES) {
+                        Eb[kk] = Ep[gi];
+                        Vb[kk] = Vp[gi];
+                    } else if (BASE == BASE_BG) {
+                        const size_t vi = (size_t)p.visit_off + (size_t)(r0 + rr - p.r0) * p.w + (c - p.c0);
+                        Eb[kk] = bg[2 * vi];
+                        Vb[kk] = bg[2 * vi + 1];
+                    }
+                }
+                if (BASE == BASE_PLANES && !DERIV) {
+                    // value only: the planes already hold the totals
+#pragma unroll
+                    for (int kk = 0; kk < L; ++kk) {
+                        if (!(x[kk] == x[kk])) continue;
+                        T gs, gg;
+                        strip_pixel<T, false>(x[kk], scalar_traits<T>::make(Eb[kk], 0.0),
+                                              scalar_traits<T>::make(Vb[kk], 0.0), zero, zero, k, acc, gs, gg);
+                    }
+                    continue;
+                }
+                T fs[L], fg[L];
+                strip_values<T, L>(tab, px, py0, fs, fg);
+                // fs, fg become the row weights of pass B
+#pragma unroll
+                for (int kk = 0; kk < L; ++kk) {
+                    T gs = zero, gg = zero;
+                    if (x[kk] == x[kk]) {
+                        const T Es = k[C_K1] * fs[kk] + k[C_K2] * fg[kk];
+                        const T Vs = k[C_K3] * (fs[kk] * fs[kk]) + k[C_K4] * (fg[kk] * fg[kk]) - Es * Es;
+                        T E, V;
+                        if (BASE == BASE_PLANES) {
+                            E = value_with_tangent(Eb[kk], Es);
+                            V = value_with_tangent(Vb[kk], Vs);
+                        } else {
+                            E = Eb[kk] + Es;
+                            V = Vb[kk] + Vs;
+                        }
+                        strip_pixel<T, DERIV>(x[kk], E, V, fs[kk], fg[kk], k, acc, gs, gg);
+                    }
+                    fs[kk] = gs;
+                    fg[kk] = gg;
+                    // one row at a time: interleaving the rows' log/division chains would
+                    // multiply the live registers without adding useful parallelism
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                if (DERIV) strip_adjoint<T, L>(tab, px, py0, fs, fg, acc);
+            }
+            T* out = reinterpret_cast<T*>(partials) + (size_t)ii * NACC;
+#pragma unroll
+            for (int f = 0; f < NACC; ++f) {
+                const T s = wave_sum(acc[f]);
+                if (lane == 0) out[f] = s;
+            }
+        }
+        j = a.dynamic ? next_item_s(a.counter, lane) : j + nw;
+    }
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) k_background_strips(BgArgs a, const Item* __restrict__ items,
+                                                           const PairDev* __restrict__ pairs,
+                                                           const celeste_image* __restrict__ images,
+                                                           const int32_t* __restrict__ nbr,
+                                                           const double* __restrict__ tabv,
+                                                           const double* __restrict__ coefv,
+                                                           double* __restrict__ bg) {
+    if (*a.status) return;
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int nw = gridDim.x * wpb;
+    for (int j = blockIdx.x * wpb + (threadIdx.x >> 6); j < a.items.n; j += nw) {
+        const int ii = __builtin_amdgcn_readfirstlane(sel_at(a.items, j));
+        const Item it = items[ii];
+        const PairDev p = pairs[it.pair];
+        const celeste_image& im = images[p.img];
+        for (int q = lane; q < it.count; q += 64) {
+            int c, r0, nrow;
+            strip_geometry(p, it.start + q, L, c, r0, nrow);
+            double Eb[L], Vb[L];
+            strip_background<L>(p, pairs, nbr, tabv, coefv, im.sky, c, r0, Eb, Vb);
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                if (k >= nrow) break;
+                const size_t vi = (size_t)p.visit_off + (size_t)(r0 + k - p.r0) * p.w + (c - p.c0);
+                bg[2 * vi] = Eb[k];
+                bg[2 * vi + 1] = Vb[k];
+            }
+        }
+    }
+}
+
+// Sum over each box of log(x!) (masked pixels excluded): a constant of the pixel terms,
+// computed once per plan, one wave per box, fixed-order reduction.
+__global__ void __launch_bounds__(256) k_pair_lgamma(const PairDev* __restrict__ pairs, int n_pairs,
+                                                     const celeste_image* __restrict__ images,
+                                                     const double* __restrict__ xs, double* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (w >= n_pairs) return;
+    const PairDev p = pairs[w];
+    const celeste_image& im = images[p.img];
+    double acc = 0.0;
+    for (int i = lane; i < p.h * p.w; i += 64) {
+        const int rr = i / p.w;
+        const double x = xs[(size_t)im.pix_offset + (size_t)(p.r0 + rr) * im.W + p.c0 + (i - rr * p.w)];
+        if (x == x) acc += lgamma(x + 1.0);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) out[w] = acc;
+}
+
+// ----------------------------------------------------------------------- launchers
+hipError_t launch_pair_lgamma(const Geometry& g, int n_pairs, double* out, hipStream_t st) {
+    if (n_pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pair_lgamma, dim3((n_pairs + 3) / 4), dim3(256), 0, st, g.pairs, n_pairs, g.images, g.x, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_planes(const celeste_image* images, int n_img, int max_pix, double* E, double* V,
+                              const int* status, hipStream_t st) {
+    if (n_img <= 0) return hipSuccess;
+    int bx = (max_pix + 255) / 256;
+    if (bx > 4096) bx = 4096;
+    hipLaunchKernelGGL(k_fill_planes, dim3(bx, n_img), dim3(256), 0, st, images, E, V, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_strips(const Sel& sel, const Geometry& g, const double* tab, const double* coef, double* E,
+                                double* V, int L, int grid, int wpb, const int* status, hipStream_t st) {
+    if (sel.n <= 0) return hipSuccess;
+    const int need = (sel.n + wpb - 1) / wpb;
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    if (L == 8)
+        hipLaunchKernelGGL(k_render_strips<8>, dim3(grid), dim3(64 * wpb), 0, st, sel, g.items, g.pairs, g.images, tab,
+                           coef, E, V, status);
+    else if (L == 4)
+        hipLaunchKernelGGL(k_render_strips<4>, dim3(grid), dim3(64 * wpb), 0, st, sel, g.items, g.pairs, g.images, tab,
+                           coef, E, V, status);
+    else if (L == 16)
+        hipLaunchKernelGGL(k_render_strips<16>, dim3(grid), dim3(64 * wpb), 0, st, sel, g.items, g.pairs, g.images,
+                           tab, coef, E, V, status);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <class T, int BASE, bool DERIV, int L>
+static void adjs(const AdjArgs& a, int grid, int wpb, hipStream_t st) {
+    const Geometry& g = a.g;
+    hipLaunchKernelGGL((k_adjoint_strips<T, BASE, DERIV, L>), dim3(grid), dim3(64 * wpb), 0, st, a, g.items, g.pairs,
+                       g.images, g.nbr, g.x, a.E, a.V, a.bg, a.tab, a.coef, a.tab_val, a.coef_val, a.active,
+                       a.partials);
+}
+
+template <class T, int BASE, bool DERIV>
+static hipError_t adjs_L(const AdjArgs& a, int grid, int wpb, int L, hipStream_t st) {
+    if (L == 8) adjs<T, BASE, DERIV, 8>(a, grid, wpb, st);
+    else if (L == 4) adjs<T, BASE, DERIV, 4>(a, grid, wpb, st);
+    else if (L == 16 && std::is_same<T, double>::value && BASE != BASE_NBR) adjs<T, BASE, DERIV, 16>(a, grid, wpb, st);
+    else return hipErrorInvalidValue;
+    return hipSuccess;
+}
+
+hipError_t launch_adjoint(const AdjArgs& a, bool tangent, int base, bool deriv, int grid, int wpb, int L,
+                          hipStream_t st) {
+    if (a.items.n <= 0) return hipSuccess;
+    if (a.dynamic) {
+        hipError_t e = launch_fill_int(a.counter, 0, 1, st);
+        if (e != hipSuccess) return e;
+    } else {
+        const int need = (a.items.n + wpb - 1) / wpb;
+        if (grid > need) grid = need;
+    }
+    if (grid < 1) grid = 1;
+    hipError_t e;
+    if (tangent) {
+        if (base == BASE_PLANES) e = deriv ? adjs_L<dual, BASE_PLANES, true>(a, grid, wpb, L, st)
+                                           : adjs_L<dual, BASE_PLANES, false>(a, grid, wpb, L, st);
+        else if (base == BASE_BG) e = deriv ? adjs_L<dual, BASE_BG, true>(a, grid, wpb, L, st)
+                                            : adjs_L<dual, BASE_BG, false>(a, grid, wpb, L, st);
+        else e = deriv ? adjs_L<dual, BASE_NBR, true>(a, grid, wpb, L, st)
+                       : adjs_L<dual, BASE_NBR, false>(a, grid, wpb, L, st);
+    } else {
+        if (base == BASE_PLANES) e = deriv ? adjs_L<double, BASE_PLANES, true>(a, grid, wpb, L, st)
+                                           : adjs_L<double, BASE_PLANES, false>(a, grid, wpb, L, st);
+        else if (base == BASE_BG) e = deriv ? adjs_L<double, BASE_BG, true>(a, grid, wpb, L, st)
+                                            : adjs_L<double, BASE_BG, false>(a, grid, wpb, L, st);
+        else e = deriv ? adjs_L<double, BASE_NBR, true>(a, grid, wpb, L, st)
+                       : adjs_L<double, BASE_NBR, false>(a, grid, wpb, L, st);
+    }
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_background(const BgArgs& a, int grid, int wpb, int L, hipStream_t st) {
+    if (a.items.n <= 0) return hipSuccess;
+    const int need = (a.items.n + wpb - 1) / wpb;
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    const Geometry& g = a.g;
+    if (L == 8)
+        hipLaunchKernelGGL(k_background_strips<8>, dim3(grid), dim3(64 * wpb), 0, st, a, g.items, g.pairs, g.images,
+                           g.nbr, a.tab_val, a.coef_val, a.bg);
+    else if (L == 4)
+        hipLaunchKernelGGL(k_background_strips<4>, dim3(grid), dim3(64 * wpb), 0, st, a, g.items, g.pairs, g.images,
+                           g.nbr, a.tab_val, a.coef_val, a.bg);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace cel
