@@ -1,0 +1,154 @@
+"""Oracle Newton trust-region step for one source (TEST INFRASTRUCTURE ONLY).
+
+Regier et al. 2018, Section IV-D: each source's parameters are optimised by Newton's
+method with exact Hessians, step sizes controlled by a trust region (Nocedal & Wright);
+Section VI-B: the trust-region subproblem is solved through an eigendecomposition.
+
+Reading of the unstated details (shared with the device implementation as a reading,
+not as code):
+  * the step is taken in unconstrained coordinates: logit of q, frac_dev and the axis
+    ratio; log of the radius and of every variance; identity for the rest;
+  * the model minimised is f = -ELBO_s with gradient g and Hessian B in those
+    coordinates (B includes the diagonal term g_theta * theta''(eta));
+  * subproblem min g'p + p'Bp/2, |p| <= radius: the interior Newton step when B is
+    positive definite and the step fits, else |p(mu)| = radius with
+    p(mu) = -(B + mu I)^-1 g, mu > max(0, -lambda_min) (secular equation), and the hard
+    case (g orthogonal to the lowest eigenspace) completed along that eigenvector;
+  * ratio rho = actual / predicted increase: rho < 1/4 shrinks the radius by 4;
+    rho > 3/4 with a boundary step doubles it (capped); the step is accepted when
+    rho > eta_accept; a non-finite trial is rejected and shrinks the radius.
+Gradient and Hessian come from the oracle's dual numbers; the eigendecomposition is
+numpy's.
+"""
+import numpy as np
+
+from . import oracle as O
+
+LOGIT = {2, 3, 6}
+LOG = {5} | {7 + 10 * t + o for t in (0, 1) for o in (1, 6, 7, 8, 9)}
+
+
+def to_unconstrained(th):
+    eta, d1, d2 = np.empty(27), np.empty(27), np.empty(27)
+    for i in range(27):
+        t = th[i]
+        if i in LOGIT:
+            eta[i] = np.log(t) - np.log1p(-t)
+            d1[i] = t * (1 - t)
+            d2[i] = d1[i] * (1 - 2 * t)
+        elif i in LOG:
+            eta[i] = np.log(t)
+            d1[i] = t
+            d2[i] = t
+        else:
+            eta[i], d1[i], d2[i] = t, 1.0, 0.0
+    return eta, d1, d2
+
+
+def from_unconstrained(eta):
+    th = np.empty(27)
+    for i in range(27):
+        if i in LOGIT:
+            th[i] = 1.0 / (1.0 + np.exp(-eta[i]))
+        elif i in LOG:
+            th[i] = np.exp(eta[i])
+        else:
+            th[i] = eta[i]
+    return th
+
+
+def subproblem(g, B, R):
+    """Exact trust-region subproblem via the eigendecomposition of B."""
+    lam, Q = np.linalg.eigh(0.5 * (B + B.T))
+    gh = Q.T @ g
+    lmin = lam.min()
+    if lmin > 0:
+        p = -gh / lam
+        if p @ p <= R * R:
+            return Q @ p, lam, gh, p
+    lo0 = max(0.0, -lmin)
+    tol = 1e-12 * max(np.abs(lam).max(), 1e-300)
+    low = lam <= lmin + tol
+    gmin2 = np.sum(gh[low] ** 2)
+    rest = np.where(low, 0.0, gh / np.where(low, 1.0, lam + lo0))
+    if lo0 > 0 and gmin2 <= 1e-28 * max(gh @ gh, 1e-300) and rest @ rest <= R * R:
+        ph = -rest
+        ph[np.argmin(lam)] = np.sqrt(max(R * R - rest @ rest, 0.0))
+        return Q @ ph, lam, gh, ph
+
+    def norm(mu):
+        return np.linalg.norm(gh / (lam + mu))
+
+    lo, hi = lo0, lo0 + np.linalg.norm(gh) / R
+    mu = hi
+    for _ in range(200):
+        v = gh / (lam + mu)
+        n2 = v @ v
+        d3 = np.sum(v * v / (lam + mu))
+        nrm = np.sqrt(n2)
+        if abs(nrm - R) <= 1e-13 * R:
+            break
+        if nrm > R:
+            lo = mu
+        else:
+            hi = mu
+        nmu = mu + (nrm - R) / R * (n2 / d3)
+        if not (lo < nmu < hi):
+            nmu = 0.5 * (lo + hi)
+        if nmu == mu:
+            break
+        mu = nmu
+    ph = -gh / (lam + mu)
+    return Q @ ph, lam, gh, ph
+
+
+def source_fixed_elbo(f, theta_all, s, row):
+    th = theta_all.copy()
+    th[s, :27] = row
+    return O.source_elbo(O.Problem(f, th), s)
+
+
+def newton_steps(f, theta_in, s, n_steps, radius0=1.0, radius_max=1e3, eta_accept=0.1, gtol=1e-8,
+                 record=None):
+    """n_steps trust-region iterations on source s, every other source fixed at theta_in.
+    Returns (theta row [27], ELBO_s, radius)."""
+    row = theta_in[s, :27].copy()
+    R = radius0
+    done = False
+    f0 = None
+    for _ in range(n_steps):
+        if done:
+            break
+        th = theta_in.copy()
+        th[s, :27] = row
+        P = O.Problem(f, th)
+        val, g, _ = O.source_grad(P, s)
+        f0 = val[0] + val[1]
+        H = O.source_hessian(P, s)
+        eta, d1, d2 = to_unconstrained(row)
+        gm = -d1 * g
+        B = -(d1[:, None] * (0.5 * (H + H.T)) * d1[None, :]) - np.diag(d2 * g)
+        if not np.max(np.abs(gm)) >= gtol:
+            done = True
+            break
+        p, lam, gh, ph = subproblem(gm, B, R)
+        pred = -np.sum(gh * ph + 0.5 * lam * ph * ph)
+        pn = np.linalg.norm(ph)
+        trial = from_unconstrained(eta + p)
+        f1 = source_fixed_elbo(f, theta_in, s, trial)
+        finite = np.isfinite(f1)
+        rho = (f1 - f0) / pred if (finite and pred > 0) else -1.0
+        Rold = R
+        if not finite or rho < 0.25:
+            R = 0.25 * R
+        elif rho > 0.75 and pn >= 0.99 * Rold:
+            R = min(2 * R, radius_max)
+        if record is not None:
+            record.append({"f0": f0, "f1": f1, "pred": pred, "rho": rho, "radius": Rold})
+        f_before = f0
+        if finite and rho > eta_accept:
+            row = trial
+            f0 = f1
+        if not (pred > 1e-15 * abs(f_before)) or R < 1e-12:
+            done = True
+    return row, f0, R

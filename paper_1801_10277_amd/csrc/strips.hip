@@ -450,7 +450,7 @@ template <class T, int BASE, bool DERIV>
 static hipError_t adjs_L(const AdjArgs& a, int grid, int wpb, int L, hipStream_t st) {
     if (L == 8) adjs<T, BASE, DERIV, 8>(a, grid, wpb, st);
     else if (L == 4) adjs<T, BASE, DERIV, 4>(a, grid, wpb, st);
-    else if (L == 16 && std::is_same<T, double>::value && BASE != BASE_NBR) adjs<T, BASE, DERIV, 16>(a, grid, wpb, st);
+    else if (L == 16) adjs<T, BASE, DERIV, 16>(a, grid, wpb, st);
     else return hipErrorInvalidValue;
     return hipSuccess;
 }
@@ -497,6 +497,9 @@ hipError_t launch_background(const BgArgs& a, int grid, int wpb, int L, hipStrea
                            g.nbr, a.tab_val, a.coef_val, a.bg);
     else if (L == 4)
         hipLaunchKernelGGL(k_background_strips<4>, dim3(grid), dim3(64 * wpb), 0, st, a, g.items, g.pairs, g.images,
+                           g.nbr, a.tab_val, a.coef_val, a.bg);
+    else if (L == 16)
+        hipLaunchKernelGGL(k_background_strips<16>, dim3(grid), dim3(64 * wpb), 0, st, a, g.items, g.pairs, g.images,
                            g.nbr, a.tab_val, a.coef_val, a.bg);
     else
         return hipErrorInvalidValue;

@@ -46,6 +46,7 @@ def oracle_source(O, f, s):
 
 
 def check_field(B, O, f, sources, modes=(1, 0), name=""):
+    """ELBO and gradient of the listed sources, batched (1) and plain (0), vs the oracle."""
     theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
     plan = B.Plan(f)
     for mode in modes:
@@ -134,3 +135,100 @@ def test_total_elbo(B, O, synth):
     say("case total elbo")
     t = plan.total_elbo(theta).cpu().numpy()[0]
     np.testing.assert_allclose(t, O.total_elbo(O.Problem(f)), rtol=1e-11)
+
+
+LAUNCHES = [dict(chunk=64, waves_per_block=1, grid_blocks=256, dynamic=0, strip_rows=4, render_mode=0),
+            dict(chunk=128, waves_per_block=2, grid_blocks=4096, dynamic=1, strip_rows=8, render_mode=1,
+                 tile_h=16, tile_w=8),
+            dict(chunk=1024, waves_per_block=4, grid_blocks=1024, dynamic=0, strip_rows=16, render_mode=0),
+            dict(chunk=256, waves_per_block=4, grid_blocks=2048, dynamic=1, strip_rows=8, render_mode=1,
+                 tile_h=16, tile_w=16)]
+
+
+def test_launch_configurations_agree(B, synth):
+    f = synth.tiny(S=5, n_bands=3, size=40, side=23, seed=101)
+    plan = B.Plan(f)
+    theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+    e0, g0 = plan.elbo_grad(theta)
+    e0, g0 = e0.cpu().numpy(), g0.cpu().numpy()
+    gmax = np.abs(g0).max(axis=1, keepdims=True)
+    for cfg in LAUNCHES:
+        say("case launch", cfg)
+        plan.set_launch(**cfg)
+        e, g = plan.elbo_grad(theta)
+        e, g = e.cpu().numpy(), g.cpu().numpy()
+        np.testing.assert_allclose(e, e0, rtol=1e-12)
+        assert np.all(np.abs(g - g0) <= 1e-11 * gmax)
+        v = np.zeros((5, 32))
+        v[:, :27] = 1.0
+        hv = plan.hvp(theta, torch.tensor(v, device="cuda")).cpu().numpy()
+        if cfg is LAUNCHES[0]:
+            hv0 = hv
+        else:
+            assert np.all(np.abs(hv - hv0) <= 1e-11 * np.abs(hv0).max(axis=1, keepdims=True))
+
+
+def test_graph_replays_match_eager(B, synth):
+    f = synth.tiny(S=4, n_bands=2, size=30, side=15, seed=111)
+    plan = B.Plan(f)
+    theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+    e0, g0 = plan.elbo_grad(theta)
+    e0, g0 = e0.clone(), g0.clone()
+    plan.use_graph(True)
+    elbo = torch.zeros_like(e0)
+    grad = torch.zeros_like(g0)
+    for rep in range(4):
+        say("case graph replay", rep)
+        elbo.fill_(0.0)
+        grad.fill_(0.0)
+        plan.elbo_grad(theta, elbo=elbo, grad=grad)
+        torch.cuda.synchronize()
+        assert torch.equal(elbo, e0) and torch.equal(grad, g0)
+        x = torch.randn(1000, device="cuda").sum()      # unrelated eager work between replays
+        torch.cuda.synchronize()
+    plan.use_graph(False)
+
+
+def test_two_runs_bitwise_equal(B, synth):
+    f = synth.tiny(S=6, n_bands=2, size=40, side=21, seed=121)
+    plan = B.Plan(f)
+    theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+    a = [t.clone() for t in plan.elbo_grad(theta)]
+    b = plan.elbo_grad(theta)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_source_without_boxes_and_ragged_boxes(B, O, synth):
+    f = synth.tiny(S=3, n_bands=2, size=23, side=13, seed=131)
+    # source 2 keeps no box: its ELBO is -KL only
+    nb = int(f.patch_ptr[2])
+    f.boxes = f.boxes[:nb]
+    f.patch_ptr[3] = nb
+    # ragged heights and widths
+    f.boxes[0, 3] = 11
+    f.boxes[1, 4] = 7
+    check_field(B, O, f, range(3), name="ragged")
+
+
+def test_masked_pixels(B, O, synth):
+    f = synth.tiny(S=2, n_bands=2, size=19, side=13, seed=141)
+    rng = np.random.default_rng(5)
+    f.x[rng.choice(f.x.size, 20, replace=False)] = np.nan
+    check_field(B, O, f, range(2), name="masked")
+
+
+def test_config2_full_size_sampled(B, O, synth):
+    """Full field at the autotuned launch configuration used by the benchmark."""
+    f = synth.make_config(2)
+    plan = B.Plan(f)
+    theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+    plan.autotune(theta, reps=1)
+    plan.use_graph(True)
+    say("case config2 full", plan.info())
+    e, g = plan.elbo_grad(theta)
+    e, g = e.cpu().numpy(), g.cpu().numpy()
+    P = O.Problem(f)
+    for s in [0, 517, 1999]:
+        val, gref, gabs = O.source_grad(P, s)
+        within(np.array([e[s]]), np.array([val[0] + val[1]]), np.array([abs(val[2]) + abs(val[1])]), "c2 elbo")
+        within(g[s, :27], gref, gabs, "c2 grad s=%d" % s)

@@ -1,0 +1,69 @@
+"""Pins of the oracle trust-region step: optimality conditions of the subproblem
+(Nocedal & Wright, Thm. 4.1), the coordinate transforms against finite differences,
+and monotone ascent of the iterations."""
+import numpy as np
+import pytest
+
+from oracle import newton as N
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_subproblem_satisfies_optimality_conditions(seed):
+    rng = np.random.default_rng(seed)
+    n = 27
+    A = rng.standard_normal((n, n))
+    B = 0.5 * (A + A.T)
+    if seed % 2 == 0:
+        B = B @ B.T / n + 0.1 * np.eye(n)       # positive definite
+    g = rng.standard_normal(n)
+    for R in (0.05, 1.0, 100.0):
+        p, lam, gh, ph = N.subproblem(g, B, R)
+        nrm = np.linalg.norm(p)
+        assert nrm <= R * (1 + 1e-10)
+        # (B + mu I) p = -g for some mu >= 0 with mu (R - |p|) = 0 and B + mu I PSD
+        r = -g - B @ p
+        mu = (r @ p) / (p @ p)
+        assert mu >= -1e-9
+        np.testing.assert_allclose(B @ p + mu * p, -g, atol=1e-8 * max(1.0, np.abs(g).max()))
+        assert np.linalg.eigvalsh(B + mu * np.eye(n)).min() >= -1e-8
+        if mu > 1e-8:
+            assert abs(nrm - R) <= 1e-10 * R
+        # no feasible point on a random sample does better
+        m = lambda q: g @ q + 0.5 * q @ B @ q
+        for _ in range(50):
+            q = rng.standard_normal(n)
+            q *= R * rng.random() / np.linalg.norm(q)
+            assert m(q) >= m(p) - 1e-9 * max(1.0, abs(m(p)))
+
+
+def test_transforms_round_trip_and_derivatives():
+    rng = np.random.default_rng(0)
+    th = np.abs(rng.uniform(0.1, 0.9, 27))
+    th[[0, 1, 4]] = [3.0, -2.0, 0.7]
+    eta, d1, d2 = N.to_unconstrained(th)
+    np.testing.assert_allclose(N.from_unconstrained(eta), th, rtol=1e-14)
+    h = 1e-5
+    for i in range(27):
+        e1, e2 = eta.copy(), eta.copy()
+        e1[i] += h
+        e2[i] -= h
+        fd1 = (N.from_unconstrained(e1)[i] - N.from_unconstrained(e2)[i]) / (2 * h)
+        fd2 = (N.from_unconstrained(e1)[i] - 2 * th[i] + N.from_unconstrained(e2)[i]) / h ** 2
+        np.testing.assert_allclose(d1[i], fd1, rtol=1e-8, atol=1e-12)
+        np.testing.assert_allclose(d2[i], fd2, rtol=1e-4, atol=1e-6)
+
+
+def test_iterations_ascend(synth, O):
+    f = synth.tiny(S=2, n_bands=2, size=17, side=11, seed=8)
+    rec = []
+    row, fend, R = N.newton_steps(f, f.theta, 0, 8, record=rec)
+    start = O.source_elbo(O.Problem(f), 0)
+    assert fend >= start
+    cur = start
+    for r in rec:
+        if r["rho"] > 0.1:
+            assert r["f1"] > cur
+            cur = r["f1"]
+    th = f.theta.copy()
+    th[0, :27] = row
+    np.testing.assert_allclose(O.source_elbo(O.Problem(f, th), 0), fend, rtol=1e-13)
