@@ -51,6 +51,24 @@ DIRECT_RENDER_PER_VISIT = N_STAR * (GAUSS_VALUE + 1) + N_GAL * (GAUSS_VALUE + 2)
 ADJOINT_BYTES_PER_VISIT = 24            # x, E, V read once (float64)
 
 
+def measured_traffic(kernel_launch):
+    """HBM bytes per launch of the fused adjoint from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources and launch; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "fused_adjoint_sdss_field_2000src.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        prof = json.load(fh)
+    h = hashlib.sha256()
+    for fn in ("strips.hip", "model.h", "internal.h", "dual.h"):
+        with open(os.path.join(ROOT, "paper_1801_10277_amd", "csrc", fn), "rb") as fh:
+            h.update(fh.read())
+    if prof.get("source_sha256") != h.hexdigest() or prof.get("launch") != kernel_launch:
+        return None
+    return prof["bytes_per_launch"]
+
+
 def strip_count(f, L):
     import numpy as np
     b = f.boxes.astype(np.int64)
@@ -102,6 +120,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--sources", type=int, default=2000)
+    ap.add_argument("--launch", type=str, default=None,
+                    help="fixed launch chunk,waves_per_block,grid,dynamic,strip_rows,render_mode (skips autotune)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 512 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -125,7 +147,12 @@ def main():
     elbo = torch.zeros(f.n_src, dtype=torch.float64, device=dev)
     grad = torch.zeros(f.n_src, 32, dtype=torch.float64, device=dev)
 
-    if not args.no_tune:
+    if args.launch:
+        ch, wpb, grid, dyn, rows, rmode = (int(v) for v in args.launch.split(","))
+        plan.set_launch(chunk=ch, waves_per_block=wpb, grid_blocks=grid, dynamic=dyn, strip_rows=rows,
+                        render_mode=rmode)
+        info = plan.info()
+    elif not args.no_tune:
         ms = plan.autotune(theta, reps=3)
         info = plan.info()
         log("autotuned: %s (%.3f ms)" % ({k: info[k] for k in LAUNCH_KEYS}, ms))
@@ -163,8 +190,13 @@ def main():
     adj_flops = strips * ADJ_PER_STRIP + visits * ADJ_PER_VISIT
     render_flops = strips * RENDER_PER_STRIP + visits * RENDER_PER_VISIT
     achieved = adj_flops / (adj_ms * 1e-3) / 1e12
+    launch_str = "%d,%d,%d,%d,%d,%d" % (info["chunk"], info["waves_per_block"], info["grid_blocks"],
+                                        info["dynamic_queue"], info["strip_rows"], info["render_mode"])
+    traffic = measured_traffic(launch_str)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "traffic_algorithmic": ADJOINT_BYTES_PER_VISIT * visits,
                 "kernel": "k_adjoint_strips<double, planes, grad, L=%d> (fused own-source forward + adjoint)" % L,
                 "flops_per_launch": adj_flops, "flops_per_visit": round(adj_flops / visits, 1),
                 "visits_per_launch": visits, "strips_per_launch": strips, "avg_launch_ms": round(adj_ms, 4)}
@@ -183,6 +215,14 @@ def main():
         pdt = (time.perf_counter() - t0) / n_plain
         plain = {"visits_per_s": visits / pdt, "ms_per_step": 1e3 * pdt}
         log("plain: %.3f ms/step, %.3e visits/s" % (1e3 * pdt, visits / pdt))
+
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # batched result for the parity sample
     plan.elbo_grad(theta, mode=B.CELESTE_BATCHED, elbo=elbo, grad=grad)
