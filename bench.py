@@ -28,21 +28,29 @@ METRIC = "source-pixel ELBO+grad evals/s (FP64), % FP64 peak; batched vs plain a
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector peak (vendor figure)
 
 # Algorithmic FP64 operations, counted from the formulas the kernels evaluate (add, sub,
-# mul, div = 1 each; exp = 27 and log = 78: the FP64 operations of one call of the ROCm
-# device library's exp and log on gfx950, read from this build's ISA).
+# mul, div = 1 each).  exp in the strip seeds is the table-driven exp (64/ln2 scaling,
+# two-part reduction, degree-5 polynomial, table product: 16 FLOPs); elsewhere exp = 27
+# and log = 78, the FP64 operations of one call of the ROCm device library's exp and log on
+# gfx950 (read from this build's ISA).
 EXP_FLOPS = 27
+FEXP_FLOPS = 16
 LOG_FLOPS = 78
 N_STAR, N_GAL = 3, 42                   # Gaussians per (source, image): 3 star, 3 x (8 + 6) galaxy
 
 # Strip algorithm (what runs): per strip of L rows and per Gaussian, the value and the
-# first row ratio at the top row (2 exps + 16), then per row 2 multiplies for the
-# recurrence plus the accumulation; the adjoint pass repeats the seed and adds 3 moment
-# accumulations per row and a fold per strip.
-SEED = 16 + 2 * EXP_FLOPS               # d, P d, d'Pd, exponents (16) + 2 exp
-RENDER_PER_STRIP = (N_STAR + N_GAL) * SEED
-RENDER_PER_VISIT = N_STAR * 3 + N_GAL * 4 + 11
-ADJ_PER_STRIP = 2 * (N_STAR + N_GAL) * SEED + N_STAR * 12 + N_GAL * 46
-ADJ_PER_VISIT = (N_STAR * 3 + N_GAL * 4) + (N_STAR * 6 + N_GAL * 8) + (46 + LOG_FLOPS)
+# first row ratio at the top row (2 exps + 16 FLOPs), then per row 2 multiplies for the
+# recurrence plus the accumulation.  Pass A (profile values) runs in the render's strip
+# pass and its values are stored; the fused adjoint runs the pixel terms and pass B
+# (seed again, 3 moment accumulations per row, a fold per strip).
+SEED = 16 + 2 * FEXP_FLOPS
+PASS_A_PER_STRIP = (N_STAR + N_GAL) * SEED
+PASS_A_PER_VISIT = N_STAR * 3 + N_GAL * 4
+PASS_B_PER_STRIP = (N_STAR + N_GAL) * SEED + N_STAR * 12 + N_GAL * 46
+PASS_B_PER_VISIT = N_STAR * 6 + N_GAL * 8
+PIXEL_PER_VISIT = 46 + LOG_FLOPS
+GATHER_PER_VISIT = 11
+RENDER_PER_STRIP, RENDER_PER_VISIT = PASS_A_PER_STRIP, PASS_A_PER_VISIT + GATHER_PER_VISIT
+ADJ_PER_STRIP, ADJ_PER_VISIT = PASS_B_PER_STRIP, PASS_B_PER_VISIT + PIXEL_PER_VISIT
 
 # Direct evaluation of the same quantities (one exp per Gaussian per visit), for context.
 GAUSS_VALUE = 13 + EXP_FLOPS

@@ -126,7 +126,9 @@ typedef struct celeste_plan_info {
     int32_t tile_h, tile_w;
     int32_t dynamic_queue; /* 1: items popped from a device counter; 0: static round robin */
     int32_t strip_rows;    /* pixels per strip: a lane walks one column of a box this many rows */
-    int32_t render_mode;   /* 0: strips per conflict-free class of boxes; 1: binned tiles */
+    int32_t render_mode;   /* 0: strips per conflict-free class of boxes; 1: binned tiles evaluating
+                              the Gaussians; 2: one strip pass storing each visit's own profile
+                              values, then a binned-tile gather (the fused adjoint reuses them) */
     int32_t n_classes;     /* conflict-free classes of boxes (render launches) */
     int32_t reserved;
     int64_t workspace_bytes;
@@ -205,10 +207,10 @@ int celeste_sweep(celeste_plan* plan, double* theta_inout, const int32_t* batch_
 
 /* Launch configuration: strips per work item (multiple of 64, at most 1024), waves per
  * block (1, 2 or 4), persistent grid size (blocks, >= 1), dynamic_queue (0/1), render
- * tile tile_h x tile_w of the tile render (tile_w divides 64; tile_h * tile_w = 64, 128
- * or 256), strip_rows (4, 8 or 16 pixels per strip) and render_mode (0: strips per
- * conflict-free class, 1: binned tiles).  Rebuilds work items and render tiles
- * (synchronous; the tile buffers are reallocated if they grow). */
+ * tile tile_h x tile_w (tile_w divides 64; tile_h * tile_w = 64, 128 or 256),
+ * strip_rows (4, 8 or 16 pixels per strip) and render_mode (see celeste_plan_info; the
+ * default is 2).  Rebuilds work items and render tiles (synchronous; the tile buffers
+ * are reallocated if they grow). */
 int celeste_plan_set_launch(celeste_plan* plan, int chunk, int waves_per_block, int grid_blocks,
                             int dynamic_queue, int tile_h, int tile_w, int strip_rows, int render_mode);
 
@@ -235,6 +237,11 @@ int celeste_plan_status(celeste_plan* plan, hipStream_t stream);
 
 /* HIP error string of the last CELESTE_EHIP on this thread. */
 const char* celeste_last_hip_error(void);
+
+/* Diagnostic: y[i] = exp(x[i]) (device arrays of n) by the table-driven exponential the
+ * strip kernels use (Tang's method: 64-entry 2^(j/64) table, |r| <= ln2/128, degree-5
+ * polynomial), for comparison with the device library.  x[i] <= 709, not NaN. */
+int celeste_debug_exp(const double* x, double* y, int n, hipStream_t stream);
 
 const char* celeste_status_string(int status);
 int celeste_version(void);

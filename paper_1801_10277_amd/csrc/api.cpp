@@ -67,7 +67,7 @@ struct celeste_plan {
 
     // launch configuration
     int chunk = 256, wpb = 4, grid = 0, dynamic = 0, tile_h = 8, tile_w = 8, rows = 8;
-    int render_mode = 0;   // 0: strips per conflict-free class, 1: binned tiles
+    int render_mode = 2;   // 0: strips per conflict-free class, 1: binned tiles, 2: stored values + gather
     bool use_graph = false;
 
     // device memory
@@ -89,6 +89,8 @@ struct celeste_plan {
     double* d_E = nullptr;
     double* d_V = nullptr;
     double* d_bg = nullptr;
+    double* d_fg = nullptr;      // [n_visits][2] own profile values (render mode 2)
+    bool fg_valid = false;       // d_fg holds the values of the last render
     double* d_tile_sums = nullptr;
     double* d_pair_lgamma = nullptr;
     int* d_status = nullptr;
@@ -417,9 +419,31 @@ int render_tiles(celeste_plan* p, bool sums, hipStream_t st) {
     return CELESTE_OK;
 }
 
-// E and V planes of all sources: sky fill, then one strip launch per conflict-free class.
+// E and V planes of all sources.  Mode 2: every box's own profile values (one parallel
+// strip pass), then a tile gather; mode 1: tiles evaluate the Gaussians; mode 0: sky fill,
+// then one strip launch per conflict-free class.
 int render(celeste_plan* p, hipStream_t st) {
+    p->fg_valid = false;
     if (p->render_mode == 1) return render_tiles(p, false, st);
+    if (p->render_mode == 2) {
+        const Geometry g = p->geom();
+        const Sel all{nullptr, 0, (int32_t)p->items.size()};
+        HIPCHK(launch_strip_fg(all, g, p->d_tab1, p->d_fg, p->rows, p->persistent_grid(), p->wpb, p->d_status, st));
+        RenderArgs a{};
+        a.g = g;
+        a.tiles = p->d_tiles;
+        a.tile_list = p->d_tile_list;
+        a.n_tiles = (int32_t)p->tiles.size();
+        a.tile_h = p->tile_h;
+        a.tile_w = p->tile_w;
+        a.coef = p->d_coef1;
+        a.E = p->d_E;
+        a.V = p->d_V;
+        a.status = p->d_status;
+        HIPCHK(launch_gather_planes(a, p->d_fg, 4, st));
+        p->fg_valid = true;
+        return CELESTE_OK;
+    }
     HIPCHK(launch_fill_planes(p->d_images, p->n_img, p->max_pix, p->d_E, p->d_V, p->d_status, st));
     const Geometry g = p->geom();
     for (int c = 0; c < p->n_class; ++c) {
@@ -445,6 +469,7 @@ int adjoint(celeste_plan* p, const Sel& items, const uint8_t* active, bool tange
     a.E = p->d_E;
     a.V = p->d_V;
     a.bg = p->d_bg;
+    a.fg = (base == BASE_PLANES && !tangent && p->fg_valid) ? p->d_fg : nullptr;
     a.partials = p->d_partials;
     a.status = p->d_status;
     const int grid = grid_override > 0 ? grid_override : p->persistent_grid();
@@ -626,6 +651,12 @@ extern "C" {
 
 int celeste_version(void) { return CELESTE_ABI_VERSION; }
 
+int celeste_debug_exp(const double* x, double* y, int n, hipStream_t st) {
+    if (!x || !y || n < 0) return CELESTE_EINVAL;
+    HIPCHK(launch_debug_exp(x, y, n, st));
+    return CELESTE_OK;
+}
+
 const char* celeste_last_hip_error(void) { return g_hip_error.c_str(); }
 
 const char* celeste_status_string(int s) {
@@ -647,7 +678,7 @@ void celeste_plan_destroy(celeste_plan* p) {
                     p->d_tab1, p->d_coef1, p->d_tab2, p->d_coef2, p->d_partials, p->d_E, p->d_V, p->d_bg,
                     p->d_tile_sums, p->d_status, p->d_counter, p->d_grad, p->d_hess, p->d_theta_trial,
                     p->d_pred, p->d_elbo_cur, p->d_elbo_trial, p->d_radius, p->d_done, p->d_list_src,
-                    p->d_list_pair, p->d_list_item, p->d_cls_items, p->d_pair_lgamma};
+                    p->d_list_pair, p->d_list_item, p->d_cls_items, p->d_pair_lgamma, p->d_fg};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -728,6 +759,7 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     A(dalloc(&p->d_E, (size_t)p->n_pix, W));
     A(dalloc(&p->d_V, (size_t)p->n_pix, W));
     A(dalloc(&p->d_bg, (size_t)p->n_visits * 2, W));
+    A(dalloc(&p->d_fg, (size_t)p->n_visits * 2, W));
     A(dalloc(&p->d_tile_sums, std::max<size_t>(p->tiles.size(), 1), W));
     A(dalloc(&p->d_pair_lgamma, np, W));
     A(dalloc(&p->d_status, 1, W));
@@ -800,7 +832,7 @@ int celeste_plan_set_launch(celeste_plan* p, int chunk, int wpb, int grid, int d
     if (!p || chunk < 64 || chunk > 1024 || chunk % 64 || (wpb != 1 && wpb != 2 && wpb != 4) || grid < 1 ||
         (dynamic != 0 && dynamic != 1) || tile_w < 1 || tile_w > 64 || 64 % tile_w || tile_h < 1 ||
         (tile_h * tile_w != 64 && tile_h * tile_w != 128 && tile_h * tile_w != 256) ||
-        (strip_rows != 4 && strip_rows != 8 && strip_rows != 16) || (render_mode != 0 && render_mode != 1))
+        (strip_rows != 4 && strip_rows != 8 && strip_rows != 16) || render_mode < 0 || render_mode > 2)
         return CELESTE_EINVAL;
     HIPCHK(hipDeviceSynchronize());
     drop_graph(p);
@@ -1177,7 +1209,8 @@ int celeste_autotune(celeste_plan* p, const double* theta, int reps, double* bes
     }
     for (int d : {0, 1}) { c = best; c.dyn = d; trial(c); }
     const int tiles[4][2] = {{8, 8}, {4, 16}, {16, 8}, {16, 16}};
-    for (auto& tl : tiles) { c = best; c.rmode = 1; c.th = tl[0]; c.tw = tl[1]; trial(c); }
+    for (auto& tl : tiles) { c = best; c.rmode = 2; c.th = tl[0]; c.tw = tl[1]; trial(c); }
+    for (int m : {0, 1}) { c = best; c.rmode = m; trial(c); }
     if (rc == CELESTE_OK)
         rc = celeste_plan_set_launch(p, best.chunk, best.wpb, best.grid, best.dyn, best.th, best.tw, best.rows,
                                      best.rmode);

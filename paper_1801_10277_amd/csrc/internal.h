@@ -129,6 +129,7 @@ struct AdjArgs {
     const double* E;
     const double* V;
     const double* bg;          // [n_visits][2]
+    const double* fg;          // [n_visits][2] own profile values from the render, or null
     double* partials;          // [n_items_total][NACC] of T
     const int* status;
 };
@@ -171,9 +172,13 @@ hipError_t launch_render(const RenderArgs& a, int waves_per_block, hipStream_t s
 hipError_t launch_adjoint(const AdjArgs& a, bool tangent, int base_mode, bool deriv, int grid,
                           int waves_per_block, int strip_rows, hipStream_t st);
 hipError_t launch_background(const BgArgs& a, int grid, int waves_per_block, int strip_rows, hipStream_t st);
+hipError_t launch_debug_exp(const double* x, double* y, int n, hipStream_t st);
 hipError_t launch_pair_lgamma(const Geometry& g, int n_pairs, double* out, hipStream_t st);
 hipError_t launch_fill_planes(const celeste_image* images, int n_img, int max_pix, double* E, double* V,
                               const int* status, hipStream_t st);
+hipError_t launch_strip_fg(const Sel& items, const Geometry& g, const double* tab, double* fg, int strip_rows, int grid,
+                           int waves_per_block, const int* status, hipStream_t st);
+hipError_t launch_gather_planes(const RenderArgs& a, const double* fg, int waves_per_block, hipStream_t st);
 hipError_t launch_render_strips(const Sel& items, const Geometry& g, const double* tab, const double* coef,
                                 double* E, double* V, int strip_rows, int grid, int waves_per_block,
                                 const int* status, hipStream_t st);

@@ -18,6 +18,39 @@ __device__ __constant__ static const signed char BSIGN[5][4] = {
 
 constexpr double LOG_2PI = 1.8378770664093454836;
 
+// Table-driven exponential (P. T. P. Tang, "Table-driven implementation of the exponential
+// function in IEEE floating-point arithmetic", ACM TOMS 15(2), 1989), with 64 table
+// entries: x = (64 k + j) ln2/64 + r, |r| <= ln2/128, so e^x = 2^k 2^(j/64) e^r and e^r is
+// the degree-5 Taylor polynomial (truncation r^6/720 < 3.5e-17 relative).  The table
+// t2[j] = 2^(j/64) lives in LDS (fill_exp_table).  Accuracy within a few ulps of the
+// correctly rounded result for arguments down to the underflow threshold; arguments must
+// be <= 709 (callers clamp) and not NaN.
+constexpr double INV_LN2_64 = 92.332482616893656877;       // 64 / ln 2
+constexpr double LN2_64_HI = 1.0830424696249145e-02;        // ln 2 / 64, leading part
+constexpr double LN2_64_LO = 3.623510646634843e-19;         // ln 2 / 64 - LN2_64_HI
+
+__device__ __forceinline__ void fill_exp_table(double* t2) {
+    for (int j = threadIdx.x; j < 64; j += blockDim.x) t2[j] = exp2((double)j * (1.0 / 64.0));
+    __syncthreads();
+}
+
+__device__ __forceinline__ double fexp(double x, const double* __restrict__ t2) {
+    const double n = rint(x * INV_LN2_64);
+    const double r = fma(-n, LN2_64_LO, fma(-n, LN2_64_HI, x));
+    const int ni = (int)n;
+    double p = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(t2[ni & 63] * p, ni >> 6);
+}
+
+__device__ __forceinline__ dual fexp(dual x, const double* __restrict__ t2) {
+    const double e = fexp(x.v, t2);
+    return mkd(e, e * x.t);
+}
+
 template <class T>
 __device__ inline T seed(const double* theta, const double* dir, int dir_mode, int dir_unit,
                          int s, int i) {

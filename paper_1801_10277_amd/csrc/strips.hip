@@ -33,17 +33,19 @@ __device__ __forceinline__ void strip_geometry(const PairDev& p, int s, int L, i
 
 // Value and first row ratio of component e at column px, top row py0.
 template <class T>
-__device__ __forceinline__ void strip_seed(const T* e, double px, double py0, T& n, T& rt, T& pdx0, T& pdy0) {
+__device__ __forceinline__ void strip_seed(const T* e, double px, double py0, T& n, T& rt, T& pdx0, T& pdy0,
+                                           const double* __restrict__ t2) {
     const T dx = px - e[F_CX], dy = py0 - e[F_CY];
     pdx0 = e[F_PXX] * dx + e[F_PXY] * dy;
     pdy0 = e[F_PXY] * dx + e[F_PYY] * dy;
-    n = exp(e[F_LOGW] - 0.5 * (dx * pdx0 + dy * pdy0));
-    rt = exp(clamp_arg(-(pdy0 + 0.5 * e[F_PYY])));
+    n = fexp(e[F_LOGW] - 0.5 * (dx * pdx0 + dy * pdy0), t2);
+    rt = fexp(clamp_arg(-(pdy0 + 0.5 * e[F_PYY])), t2);
 }
 
 // Pass A: star and galaxy profile values down the strip.
 template <class T, int L>
-__device__ __forceinline__ void strip_values(const T* __restrict__ tab, double px, double py0, T* fs, T* fg) {
+__device__ __forceinline__ void strip_values(const T* __restrict__ tab, double px, double py0, T* fs, T* fg,
+                                             const double* __restrict__ t2) {
     const T zero = scalar_traits<T>::make(0.0, 0.0);
 #pragma unroll
     for (int k = 0; k < L; ++k) fs[k] = fg[k] = zero;
@@ -51,7 +53,7 @@ __device__ __forceinline__ void strip_values(const T* __restrict__ tab, double p
     for (int c = 0; c < NPSF; ++c) {
         const T* e = tab + c * CST;
         T n, rt, pdx0, pdy0;
-        strip_seed(e, px, py0, n, rt, pdx0, pdy0);
+        strip_seed(e, px, py0, n, rt, pdx0, pdy0, t2);
         const T rdy = e[F_RDY];
 #pragma unroll
         for (int k = 0; k < L; ++k) {
@@ -66,7 +68,7 @@ __device__ __forceinline__ void strip_values(const T* __restrict__ tab, double p
     for (int c = NPSF; c < NCOMP; ++c) {
         const T* e = tab + c * CST;
         T n, rt, pdx0, pdy0;
-        strip_seed(e, px, py0, n, rt, pdx0, pdy0);
+        strip_seed(e, px, py0, n, rt, pdx0, pdy0, t2);
         const T rdy = e[F_RDY], wt = e[F_WT];
 #pragma unroll
         for (int k = 0; k < L; ++k) {
@@ -83,14 +85,14 @@ __device__ __forceinline__ void strip_values(const T* __restrict__ tab, double p
 // Gs (star) and Gg (galaxy).
 template <class T, int L>
 __device__ __forceinline__ void strip_adjoint(const T* __restrict__ tab, double px, double py0, const T* Gs,
-                                              const T* Gg, T* acc) {
+                                              const T* Gg, T* acc, const double* __restrict__ t2) {
     constexpr double KC = 0.5 * (L - 1);
     const T zero = scalar_traits<T>::make(0.0, 0.0);
 #pragma unroll
     for (int c = 0; c < NPSF; ++c) {
         const T* e = tab + c * CST;
         T n, rt, pdx0, pdy0;
-        strip_seed(e, px, py0, n, rt, pdx0, pdy0);
+        strip_seed(e, px, py0, n, rt, pdx0, pdy0, t2);
         const T rdy = e[F_RDY];
         T m0 = zero, m1 = zero;
 #pragma unroll
@@ -111,7 +113,7 @@ __device__ __forceinline__ void strip_adjoint(const T* __restrict__ tab, double 
     for (int c = NPSF; c < NCOMP; ++c) {
         const T* e = tab + c * CST;
         T n, rt, pdx0, pdy0;
-        strip_seed(e, px, py0, n, rt, pdx0, pdy0);
+        strip_seed(e, px, py0, n, rt, pdx0, pdy0, t2);
         const T rdy = e[F_RDY];
         T m0 = zero, m1 = zero, m2 = zero;
 #pragma unroll
@@ -164,7 +166,7 @@ template <int L>
 __device__ __forceinline__ void strip_background(const PairDev& p, const PairDev* __restrict__ pairs,
                                                  const int32_t* __restrict__ nbr, const double* __restrict__ tabv,
                                                  const double* __restrict__ coefv, double sky, int c, int r0,
-                                                 double* Eb, double* Vb) {
+                                                 double* Eb, double* Vb, const double* __restrict__ t2) {
 #pragma unroll
     for (int k = 0; k < L; ++k) {
         Eb[k] = sky;
@@ -175,7 +177,7 @@ __device__ __forceinline__ void strip_background(const PairDev& p, const PairDev
         const PairDev o = pairs[pi];
         if (c < o.c0 || c >= o.c0 + o.w || r0 + L <= o.r0 || r0 >= o.r0 + o.h) continue;
         double fs[L], fg[L];
-        strip_values<double, L>(tabv + (size_t)pi * NCOMP * CST, (double)c, (double)r0, fs, fg);
+        strip_values<double, L>(tabv + (size_t)pi * NCOMP * CST, (double)c, (double)r0, fs, fg, t2);
         const double* kk = coefv + (size_t)pi * NCOEF;
         const double k1 = kk[C_K1], k2 = kk[C_K2], k3 = kk[C_K3], k4 = kk[C_K4];
 #pragma unroll
@@ -218,6 +220,8 @@ __global__ void __launch_bounds__(256) k_render_strips(Sel sel, const Item* __re
                                                        const double* __restrict__ coef, double* __restrict__ E,
                                                        double* __restrict__ V, const int* status) {
     if (*status) return;
+    __shared__ double t2[64];
+    fill_exp_table(t2);
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int nw = gridDim.x * wpb;
@@ -233,7 +237,7 @@ __global__ void __launch_bounds__(256) k_render_strips(Sel sel, const Item* __re
             int c, r0, nrow;
             strip_geometry(p, it.start + q, L, c, r0, nrow);
             double fs[L], fg[L];
-            strip_values<double, L>(tb, (double)c, (double)r0, fs, fg);
+            strip_values<double, L>(tb, (double)c, (double)r0, fs, fg, t2);
 #pragma unroll
             for (int k = 0; k < L; ++k) {
                 if (k >= nrow) break;
@@ -247,7 +251,7 @@ __global__ void __launch_bounds__(256) k_render_strips(Sel sel, const Item* __re
 }
 
 // ----------------------------------------------------------------------- adjoint
-template <class T, int BASE, bool DERIV, int L>
+template <class T, int BASE, bool DERIV, int L, bool FGM>
 __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* __restrict__ items,
                                                         const PairDev* __restrict__ pairs,
                                                         const celeste_image* __restrict__ images,
@@ -259,8 +263,11 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
                                                         const double* __restrict__ tabv,
                                                         const double* __restrict__ coefv,
                                                         const uint8_t* __restrict__ active,
+                                                        const double* __restrict__ fgm,
                                                         double* __restrict__ partials) {
     if (*a.status) return;
+    __shared__ double t2[64];
+    fill_exp_table(t2);
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int nw = gridDim.x * wpb;
@@ -284,7 +291,7 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
                 const double px = (double)c, py0 = (double)r0;
                 double x[L], Eb[L], Vb[L];
                 if (BASE == BASE_NBR) {
-                    strip_background<L>(p, pairs, nbr, tabv, coefv, im.sky, c, r0, Eb, Vb);
+                    strip_background<L>(p, pairs, nbr, tabv, coefv, im.sky, c, r0, Eb, Vb, t2);
                 }
 #pragma unroll
                 for (int kk = 0; kk < L; ++kk) {
@@ -312,7 +319,18 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
                     continue;
                 }
                 T fs[L], fg[L];
-                strip_values<T, L>(tab, px, py0, fs, fg);
+                if (FGM) {
+                    // own profile values stored by the render's strip pass
+#pragma unroll
+                    for (int kk = 0; kk < L; ++kk) {
+                        const int rr = kk < nrow ? kk : 0;
+                        const size_t vi = (size_t)p.visit_off + (size_t)(r0 + rr - p.r0) * p.w + (c - p.c0);
+                        fs[kk] = scalar_traits<T>::make(fgm[2 * vi], 0.0);
+                        fg[kk] = scalar_traits<T>::make(fgm[2 * vi + 1], 0.0);
+                    }
+                } else {
+                    strip_values<T, L>(tab, px, py0, fs, fg, t2);
+                }
                 // fs, fg become the row weights of pass B
 #pragma unroll
                 for (int kk = 0; kk < L; ++kk) {
@@ -336,7 +354,7 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
                     // multiply the live registers without adding useful parallelism
                     __builtin_amdgcn_sched_barrier(0);
                 }
-                if (DERIV) strip_adjoint<T, L>(tab, px, py0, fs, fg, acc);
+                if (DERIV) strip_adjoint<T, L>(tab, px, py0, fs, fg, acc, t2);
             }
             T* out = reinterpret_cast<T*>(partials) + (size_t)ii * NACC;
 #pragma unroll
@@ -358,6 +376,8 @@ __global__ void __launch_bounds__(256) k_background_strips(BgArgs a, const Item*
                                                            const double* __restrict__ coefv,
                                                            double* __restrict__ bg) {
     if (*a.status) return;
+    __shared__ double t2[64];
+    fill_exp_table(t2);
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int nw = gridDim.x * wpb;
@@ -370,7 +390,7 @@ __global__ void __launch_bounds__(256) k_background_strips(BgArgs a, const Item*
             int c, r0, nrow;
             strip_geometry(p, it.start + q, L, c, r0, nrow);
             double Eb[L], Vb[L];
-            strip_background<L>(p, pairs, nbr, tabv, coefv, im.sky, c, r0, Eb, Vb);
+            strip_background<L>(p, pairs, nbr, tabv, coefv, im.sky, c, r0, Eb, Vb, t2);
 #pragma unroll
             for (int k = 0; k < L; ++k) {
                 if (k >= nrow) break;
@@ -402,7 +422,105 @@ __global__ void __launch_bounds__(256) k_pair_lgamma(const PairDev* __restrict__
     if (lane == 0) out[w] = acc;
 }
 
+// Own star and galaxy profile values of every visit of the selected items, stored as
+// [visit][2] (render pass 1; the fused adjoint reads them back instead of recomputing).
+template <int L>
+__global__ void __launch_bounds__(256) k_strip_fg(Sel sel, const Item* __restrict__ items,
+                                                  const PairDev* __restrict__ pairs, const double* __restrict__ tab,
+                                                  double* __restrict__ fgm, const int* status) {
+    if (*status) return;
+    __shared__ double t2[64];
+    fill_exp_table(t2);
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int nw = gridDim.x * wpb;
+    for (int j = blockIdx.x * wpb + (threadIdx.x >> 6); j < sel.n; j += nw) {
+        const int ii = __builtin_amdgcn_readfirstlane(sel_at(sel, j));
+        const Item it = items[ii];
+        const PairDev p = pairs[it.pair];
+        const double* tb = tab + (size_t)it.pair * NCOMP * CST;
+        for (int q = lane; q < it.count; q += 64) {
+            int c, r0, nrow;
+            strip_geometry(p, it.start + q, L, c, r0, nrow);
+            double fs[L], fg[L];
+            strip_values<double, L>(tb, (double)c, (double)r0, fs, fg, t2);
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                if (k >= nrow) break;
+                const size_t vi = (size_t)p.visit_off + (size_t)(r0 + k - p.r0) * p.w + (c - p.c0);
+                fgm[2 * vi] = fs[k];
+                fgm[2 * vi + 1] = fg[k];
+            }
+        }
+    }
+}
+
+// Render pass 2: E and V of every pixel of a tile, summing the stored own values of the
+// tile's boxes in ascending box order (deterministic, no atomics).  Tile = (64 / tile_w * RP)
+// rows x tile_w columns; lane l owns rows l / tile_w + k (64 / tile_w), k < RP.
+template <int RP>
+__global__ void __launch_bounds__(256) k_gather_planes(RenderArgs a, const TileDev* __restrict__ tiles,
+                                                       const int32_t* __restrict__ tile_list,
+                                                       const PairDev* __restrict__ pairs,
+                                                       const celeste_image* __restrict__ images,
+                                                       const double* __restrict__ coef,
+                                                       const double* __restrict__ fgm, double* __restrict__ Eout,
+                                                       double* __restrict__ Vout) {
+    if (*a.status) return;
+    const int lane = threadIdx.x & 63;
+    const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (t >= a.n_tiles) return;
+    const TileDev td = tiles[t];
+    const celeste_image& im = images[td.img];
+    const int rows_per_pass = 64 / a.tile_w;
+    const int c = td.c0 + lane % a.tile_w;
+    int r[RP];
+    double E[RP], V[RP];
+#pragma unroll
+    for (int k = 0; k < RP; ++k) {
+        r[k] = td.r0 + lane / a.tile_w + k * rows_per_pass;
+        E[k] = im.sky;
+        V[k] = 0.0;
+    }
+    for (int j = td.list_begin; j < td.list_end; ++j) {
+        const int pi = __builtin_amdgcn_readfirstlane(tile_list[j]);
+        const PairDev o = pairs[pi];
+        const double* kp = coef + (size_t)pi * NCOEF;
+        const double k1 = kp[C_K1], k2 = kp[C_K2], k3 = kp[C_K3], k4 = kp[C_K4];
+#pragma unroll
+        for (int k = 0; k < RP; ++k) {
+            if (r[k] < o.r0 || r[k] >= o.r0 + o.h || c < o.c0 || c >= o.c0 + o.w) continue;
+            const size_t vi = (size_t)o.visit_off + (size_t)(r[k] - o.r0) * o.w + (c - o.c0);
+            const double fs = fgm[2 * vi], fg = fgm[2 * vi + 1];
+            const double Et = k1 * fs + k2 * fg;
+            E[k] += Et;
+            V[k] += k3 * fs * fs + k4 * fg * fg - Et * Et;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < RP; ++k) {
+        if (r[k] >= im.H || c >= im.W) continue;
+        const size_t gi = (size_t)im.pix_offset + (size_t)r[k] * im.W + c;
+        Eout[gi] = E[k];
+        Vout[gi] = V[k];
+    }
+}
+
+// Elementwise table-driven exp, for testing it against the device library.
+__global__ void __launch_bounds__(256) k_debug_exp(const double* __restrict__ x, double* __restrict__ y, int n) {
+    __shared__ double t2[64];
+    fill_exp_table(t2);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = fexp(x[i], t2);
+}
+
 // ----------------------------------------------------------------------- launchers
+hipError_t launch_debug_exp(const double* x, double* y, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_debug_exp, dim3((n + 255) / 256), dim3(256), 0, st, x, y, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_pair_lgamma(const Geometry& g, int n_pairs, double* out, hipStream_t st) {
     if (n_pairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pair_lgamma, dim3((n_pairs + 3) / 4), dim3(256), 0, st, g.pairs, n_pairs, g.images, g.x, out);
@@ -415,6 +533,37 @@ hipError_t launch_fill_planes(const celeste_image* images, int n_img, int max_pi
     int bx = (max_pix + 255) / 256;
     if (bx > 4096) bx = 4096;
     hipLaunchKernelGGL(k_fill_planes, dim3(bx, n_img), dim3(256), 0, st, images, E, V, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_strip_fg(const Sel& sel, const Geometry& g, const double* tab, double* fg, int L, int grid, int wpb,
+                           const int* status, hipStream_t st) {
+    if (sel.n <= 0) return hipSuccess;
+    const int need = (sel.n + wpb - 1) / wpb;
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    if (L == 8)
+        hipLaunchKernelGGL(k_strip_fg<8>, dim3(grid), dim3(64 * wpb), 0, st, sel, g.items, g.pairs, tab, fg, status);
+    else if (L == 4)
+        hipLaunchKernelGGL(k_strip_fg<4>, dim3(grid), dim3(64 * wpb), 0, st, sel, g.items, g.pairs, tab, fg, status);
+    else if (L == 16)
+        hipLaunchKernelGGL(k_strip_fg<16>, dim3(grid), dim3(64 * wpb), 0, st, sel, g.items, g.pairs, tab, fg, status);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_planes(const RenderArgs& a, const double* fg, int wpb, hipStream_t st) {
+    if (a.n_tiles <= 0) return hipSuccess;
+    const dim3 grid((a.n_tiles + wpb - 1) / wpb);
+    const int rp = a.tile_h * a.tile_w / 64;
+    const Geometry& g = a.g;
+#define GATHER_ARGS a, a.tiles, a.tile_list, g.pairs, g.images, a.coef, fg, a.E, a.V
+    if (rp == 1) hipLaunchKernelGGL(k_gather_planes<1>, grid, dim3(64 * wpb), 0, st, GATHER_ARGS);
+    else if (rp == 2) hipLaunchKernelGGL(k_gather_planes<2>, grid, dim3(64 * wpb), 0, st, GATHER_ARGS);
+    else if (rp == 4) hipLaunchKernelGGL(k_gather_planes<4>, grid, dim3(64 * wpb), 0, st, GATHER_ARGS);
+    else return hipErrorInvalidValue;
+#undef GATHER_ARGS
     return hipGetLastError();
 }
 
@@ -441,9 +590,14 @@ hipError_t launch_render_strips(const Sel& sel, const Geometry& g, const double*
 template <class T, int BASE, bool DERIV, int L>
 static void adjs(const AdjArgs& a, int grid, int wpb, hipStream_t st) {
     const Geometry& g = a.g;
-    hipLaunchKernelGGL((k_adjoint_strips<T, BASE, DERIV, L>), dim3(grid), dim3(64 * wpb), 0, st, a, g.items, g.pairs,
-                       g.images, g.nbr, g.x, a.E, a.V, a.bg, a.tab, a.coef, a.tab_val, a.coef_val, a.active,
-                       a.partials);
+    if (BASE == BASE_PLANES && std::is_same<T, double>::value && a.fg)
+        hipLaunchKernelGGL((k_adjoint_strips<T, BASE, DERIV, L, true>), dim3(grid), dim3(64 * wpb), 0, st, a, g.items,
+                           g.pairs, g.images, g.nbr, g.x, a.E, a.V, a.bg, a.tab, a.coef, a.tab_val, a.coef_val,
+                           a.active, a.fg, a.partials);
+    else
+        hipLaunchKernelGGL((k_adjoint_strips<T, BASE, DERIV, L, false>), dim3(grid), dim3(64 * wpb), 0, st, a,
+                           g.items, g.pairs, g.images, g.nbr, g.x, a.E, a.V, a.bg, a.tab, a.coef, a.tab_val,
+                           a.coef_val, a.active, nullptr, a.partials);
 }
 
 template <class T, int BASE, bool DERIV>

@@ -232,3 +232,19 @@ def test_config2_full_size_sampled(B, O, synth):
         val, gref, gabs = O.source_grad(P, s)
         within(np.array([e[s]]), np.array([val[0] + val[1]]), np.array([abs(val[2]) + abs(val[1])]), "c2 elbo")
         within(g[s, :27], gref, gabs, "c2 grad s=%d" % s)
+
+
+def test_table_exp_accuracy(B):
+    """The strip kernels' table-driven exp against the host libm exp, in ulps."""
+    rng = np.random.default_rng(9)
+    x = np.concatenate([rng.uniform(-745.0, 709.0, 200000), rng.uniform(-40.0, 3.0, 200000),
+                        rng.uniform(-1e-3, 1e-3, 10000), [0.0, -0.0, 1.0, -1.0, 700.0, -700.0, -744.0, 709.0],
+                        np.log(2.0) / 64 * np.arange(-200, 200)])
+    say("case table exp", x.size)
+    y = B.debug_exp(torch.tensor(x, device="cuda")).cpu().numpy()
+    ref = np.exp(x)
+    normal = ref >= 2.2250738585072014e-308
+    ulp = np.spacing(ref[normal])
+    err = np.abs(y[normal] - ref[normal]) / ulp
+    assert err.max() <= 4.0, err.max()
+    assert np.all(np.abs(y[~normal] - ref[~normal]) <= 4 * 5e-324)
