@@ -118,6 +118,79 @@ def cpu_baseline(f, theta_gpu_grad, elbo_gpu, seconds):
                       "gradient, OpenMP over sources" % (done, f.n_src, visits, dt)}, rel_e, rel_g, done
 
 
+def run_newton(args):
+    """Config 3: 1024 sources of the field generator, N trust-region Newton iterations of
+    every source (others held at their entry values), all on the device."""
+    import numpy as np
+    import torch
+    from paper_1801_10277_amd import binding as B, synth
+    f = synth.config3()
+    dev = torch.device("cuda:0")
+    plan = B.Plan(f, check_status=False)
+    theta0 = torch.tensor(f.theta, dtype=torch.float64, device=dev)
+    src = np.arange(f.n_src, dtype=np.int32)
+    params = B.tr_params()
+    e0 = plan.elbo(theta0).cpu().numpy()
+    warm = theta0.clone()
+    plan.newton(warm, src, 1, params)                       # untimed warm-up
+    theta = theta0.clone()
+    radius = torch.full((f.n_src,), params.radius0, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e1, radius = plan.newton(theta, src, args.newton_steps, params, radius)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plan.check_status = True
+    plan._status("celeste_newton")
+    e1 = e1.cpu().numpy()
+    visits = plan.info()["n_visits"]
+    out = {"metric": "Newton trust-region iterations per second (ELBO + gradient + 27x27 Hessian + TR solve per "
+                     "source)", "value": f.n_src * args.newton_steps / dt, "unit": "source-iterations/s",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "1024 sources, 5 bands x 2048x1489 px, %d iterations, others fixed"
+                                  % args.newton_steps, "visits_per_evaluation": visits,
+                      "seconds": dt, "visit_iterations_per_s": visits * args.newton_steps / dt,
+                      "mean_elbo_gain": float(np.mean(e1 - e0)), "min_elbo_gain": float(np.min(e1 - e0)),
+                      "sources_improved": int(np.sum(e1 > e0))}}
+    print(json.dumps(out), flush=True)
+
+
+def run_sweep(args):
+    """Config 4: 16 overlapping fields x 2 epochs x 5 bands (160 images), 20 000 sources,
+    conflict-free batches, block-coordinate-ascent sweeps of Newton steps."""
+    import numpy as np
+    import torch
+    from paper_1801_10277_amd import binding as B, synth
+    log("generating the sky region ...")
+    t = time.perf_counter()
+    f = synth.config4()
+    log("region ready in %.1f s: %d images, %d sources, %d boxes, %d visits" % (
+        time.perf_counter() - t, f.n_img, f.n_src, len(f.boxes), f.visits()))
+    dev = torch.device("cuda:0")
+    plan = B.Plan(f, check_status=False)
+    log("plan: %s" % plan.info())
+    theta = torch.tensor(f.theta, dtype=torch.float64, device=dev)
+    ptr, srcl = plan.color_batches(seed=4)
+    params = B.tr_params(newton_steps=args.newton_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    trace = plan.sweep(theta, ptr, srcl, args.sweeps, params)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plan.check_status = True
+    plan._status("celeste_sweep")
+    trace = trace.cpu().numpy()
+    out = {"metric": "block-coordinate-ascent sweeps per second", "value": args.sweeps / dt, "unit": "sweeps/s",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "16 fields x 2 epochs x 5 bands (160 images of 2048x1489 px), %d sources, "
+                                  "%d conflict-free batches, %d Newton steps per batch visit"
+                                  % (f.n_src, len(ptr) - 1, args.newton_steps),
+                      "seconds": dt, "visits_per_evaluation": plan.info()["n_visits"],
+                      "elbo_trace": [float(v) for v in trace],
+                      "monotone": bool(np.all(np.diff(trace) >= 0))}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,11 +205,20 @@ def main():
                     help="fixed launch chunk,waves_per_block,grid,dynamic,strip_rows,render_mode (skips autotune)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 512 MiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--workload", choices=("elbo_grad", "newton", "sweep"), default="elbo_grad")
+    ap.add_argument("--newton-steps", type=int, default=None)
+    ap.add_argument("--sweeps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "newton":
+        args.newton_steps = args.newton_steps or 20
+        return run_newton(args)
+    if args.workload == "sweep":
+        args.newton_steps = args.newton_steps or 5
+        return run_sweep(args)
 
     import numpy as np
     import torch

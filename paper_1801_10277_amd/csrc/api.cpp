@@ -97,6 +97,8 @@ struct celeste_plan {
     int* d_counter = nullptr;
     double* d_grad = nullptr;
     double* d_hess = nullptr;
+    double* d_gw = nullptr;      // [n_pairs][11] per-box gradient sums
+    double* d_hw = nullptr;      // [n_pairs][10][10] per-box Hessian of the pixel part w.r.t. its intermediates
     double* d_theta_trial = nullptr;
     double* d_pred = nullptr;
     double* d_elbo_cur = nullptr;
@@ -516,6 +518,14 @@ int background(celeste_plan* p, const Sel& items, hipStream_t st) {
     return CELESTE_OK;
 }
 
+// Dense Hessians of the listed sources (d_hess by list position).  Expects the item
+// partials of a double gradient pass over `item` in d_partials.  Ten tangent passes along
+// the boxes' intermediates (brightness factors, position, frac_dev, shape covariance)
+// give each box's 10x10 Hessian of its pixel terms; the chain rule and its tangent
+// assemble the 27x27 blocks.
+int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& src, const Sel& pair, const Sel& item,
+                               int base, hipStream_t st);
+
 #define CHK(x)                              \
     do {                                    \
         int r_ = (x);                       \
@@ -601,6 +611,19 @@ int fill_f64(double* d, const Sel& srcs, double v, hipStream_t st) {
     return CELESTE_OK;
 }
 
+int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& src, const Sel& pair, const Sel& item,
+                               int base, hipStream_t st) {
+    HIPCHK(launch_pair_reduce(pair, p->d_pairs, p->d_partials, false, 0, p->d_gw, p->d_hw, p->d_status, st));
+    for (int i = 0; i < 10; ++i) {
+        CHK(prep(p, theta, pair, true, DIR_W, nullptr, i, st));
+        CHK(adjoint(p, item, nullptr, true, base, true, st));
+        HIPCHK(launch_pair_reduce(pair, p->d_pairs, p->d_partials, true, i, p->d_gw, p->d_hw, p->d_status, st));
+    }
+    HIPCHK(launch_assemble_hessian(src, p->geom(), p->d_patch_ptr, theta, p->d_gw, p->d_hw, p->d_hess, p->d_status,
+                                   st));
+    return CELESTE_OK;
+}
+
 // Newton trust-region iterations for one source set; lists already on the device.
 int newton_run(celeste_plan* p, double* theta, const Sel& src, const Sel& pair, const Sel& item, int n_steps,
                const celeste_tr_params* prm, double* radius, hipStream_t st) {
@@ -628,12 +651,7 @@ int newton_run(celeste_plan* p, double* theta, const Sel& src, const Sel& pair, 
         CHK(adjoint(p, item, nullptr, false, BASE_BG, true, st));
         CHK(finalize(p, theta, src, nullptr, false, DIR_NONE, nullptr, 0, true, p->d_elbo_cur, p->d_grad, nullptr,
                      0, false, st));
-        for (int i = 0; i < NP; ++i) {
-            CHK(prep(p, theta, pair, true, DIR_UNIT, nullptr, i, st));
-            CHK(adjoint(p, item, nullptr, true, BASE_BG, true, st));
-            CHK(finalize(p, theta, src, nullptr, true, DIR_UNIT, nullptr, i, true, nullptr, nullptr,
-                         p->d_hess + (size_t)i * NP, (int64_t)NP * NP, true, st));
-        }
+        CHK(hessian_from_intermediates(p, theta, src, pair, item, BASE_BG, st));
         HIPCHK(launch_tr_solve(tr, st));
         CHK(prep(p, p->d_theta_trial, pair, false, DIR_NONE, nullptr, 0, st));
         CHK(adjoint(p, item, nullptr, false, BASE_BG, false, st));
@@ -678,7 +696,8 @@ void celeste_plan_destroy(celeste_plan* p) {
                     p->d_tab1, p->d_coef1, p->d_tab2, p->d_coef2, p->d_partials, p->d_E, p->d_V, p->d_bg,
                     p->d_tile_sums, p->d_status, p->d_counter, p->d_grad, p->d_hess, p->d_theta_trial,
                     p->d_pred, p->d_elbo_cur, p->d_elbo_trial, p->d_radius, p->d_done, p->d_list_src,
-                    p->d_list_pair, p->d_list_item, p->d_cls_items, p->d_pair_lgamma, p->d_fg};
+                    p->d_list_pair, p->d_list_item, p->d_cls_items, p->d_pair_lgamma, p->d_fg, p->d_gw,
+                    p->d_hw};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -767,6 +786,8 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     const size_t S = (size_t)p->n_src;
     A(dalloc(&p->d_grad, S * ROW, W));
     A(dalloc(&p->d_hess, S * NP * NP, W));
+    A(dalloc(&p->d_gw, np * NACC, W));
+    A(dalloc(&p->d_hw, np * 100, W));
     A(dalloc(&p->d_theta_trial, S * ROW, W));
     A(dalloc(&p->d_pred, S * 2, W));
     A(dalloc(&p->d_elbo_cur, S, W));
@@ -969,12 +990,9 @@ int celeste_hessian(celeste_plan* p, const double* theta, const int32_t* src, in
     CHK(validate_theta(p, theta, nullptr, nullptr, p->n_src, st));
     CHK(prep(p, theta, all.pair, false, DIR_NONE, nullptr, 0, st));
     CHK(render(p, st));
-    for (int i = 0; i < NP; ++i) {
-        CHK(prep(p, theta, sp, true, DIR_UNIT, nullptr, i, st));
-        CHK(adjoint(p, si, nullptr, true, BASE_PLANES, true, st));
-        CHK(finalize(p, theta, ss, nullptr, true, DIR_UNIT, nullptr, i, true, nullptr, nullptr, hess + (size_t)i * NP,
-                     (int64_t)NP * NP, true, st));
-    }
+    CHK(adjoint(p, si, nullptr, false, BASE_PLANES, true, st));
+    CHK(hessian_from_intermediates(p, theta, ss, sp, si, BASE_PLANES, st));
+    HIPCHK(hipMemcpyAsync(hess, p->d_hess, (size_t)n * NP * NP * sizeof(double), hipMemcpyDeviceToDevice, st));
     return CELESTE_OK;
 }
 

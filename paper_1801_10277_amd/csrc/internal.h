@@ -80,8 +80,9 @@ enum BaseMode {
     BASE_NBR = 2       // background evaluated on the fly from the overlapping boxes
 };
 
-// Direction seeding of the tangent pass.
-enum DirMode { DIR_NONE = 0, DIR_VEC = 1, DIR_UNIT = 2 };
+// Direction seeding of the tangent pass: a vector in parameter space, a parameter unit
+// vector, or a unit vector of a pair's intermediates (see WField in model.h).
+enum DirMode { DIR_NONE = 0, DIR_VEC = 1, DIR_UNIT = 2, DIR_W = 3 };
 
 struct Geometry {
     const celeste_image* images;
@@ -188,6 +189,16 @@ hipError_t launch_tile_total(const double* tile_sums, int n_tiles, const double*
 hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st);
 hipError_t launch_fill_u8_sel(uint8_t* p, const Sel& s, uint8_t v, hipStream_t st);
 hipError_t launch_fill_f64_sel(double* p, const Sel& s, double v, hipStream_t st);
+
+// Per-box sums of item partials: value parts into gw[pair][NACC] (double pass) or the
+// tangent parts of accumulators 1..10 into hw[pair][dir][10] (tangent pass along a
+// pair-intermediate direction).
+hipError_t launch_pair_reduce(const Sel& pairs, const PairDev* dpairs, const double* partials, bool tangent, int dir,
+                              double* gw, double* hw, const int* status, hipStream_t st);
+// 27x27 Hessians of the listed sources (hess by list position) from gw, hw and the KL.
+hipError_t launch_assemble_hessian(const Sel& srcs, const Geometry& g, const int32_t* patch_ptr,
+                                   const double* theta, const double* gw, const double* hw, double* hess,
+                                   const int* status, hipStream_t st);
 
 // Trust region (tr.hip)
 struct TrArgs {

@@ -64,11 +64,21 @@ __global__ void __launch_bounds__(128) k_prep(PrepArgs a) {
     if (j >= a.pairs.n) return;
     const int pi = sel_at(a.pairs, j);
     const PairDev pd = a.g.pairs[pi];
-    T p[NP];
-    for (int i = 0; i < NP; ++i) p[i] = seed<T>(a.theta, a.dir, a.dir_mode, a.dir_unit, pd.src, i);
     const celeste_image im = a.g.images[pd.img];
     T* tab = reinterpret_cast<T*>(a.tab) + (size_t)pi * NCOMP * CST;
     T* coef = reinterpret_cast<T*>(a.coef) + (size_t)pi * NCOEF;
+    if (a.dir_mode == DIR_W) {
+        // tangent along one of the pair's intermediates
+        double p[NP], w[NW];
+        for (int i = 0; i < NP; ++i) p[i] = a.theta[(size_t)pd.src * ROW + i];
+        pair_w<double>(p, im, w);
+        T wt[NW];
+        for (int i = 0; i < NW; ++i) wt[i] = scalar_traits<T>::make(w[i], i == a.dir_unit ? 1.0 : 0.0);
+        build_from_w<T>(wt, im, a.g.consts, tab, coef);
+        return;
+    }
+    T p[NP];
+    for (int i = 0; i < NP; ++i) p[i] = seed<T>(a.theta, a.dir, a.dir_mode, a.dir_unit, pd.src, i);
     build_pair<T>(p, im, a.g.consts, tab, coef);
 }
 
@@ -202,6 +212,74 @@ __global__ void __launch_bounds__(128) k_finalize(FinArgs a) {
     }
 }
 
+// Per-box sums of the item partials (fixed order).
+__global__ void __launch_bounds__(128) k_pair_reduce(Sel sel, const PairDev* __restrict__ pairs,
+                                                     const double* __restrict__ partials, int tangent, int dir,
+                                                     double* __restrict__ gw, double* __restrict__ hw,
+                                                     const int* status) {
+    if (*status) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= sel.n) return;
+    const int pi = sel_at(sel, j);
+    const PairDev pd = pairs[pi];
+    double z[NACC];
+    for (int f = 0; f < NACC; ++f) z[f] = 0.0;
+    for (int it = pd.item_begin; it < pd.item_end; ++it) {
+        if (tangent) {
+            const dual* q = reinterpret_cast<const dual*>(partials) + (size_t)it * NACC;
+            for (int f = 0; f < NACC; ++f) z[f] += q[f].t;
+        } else {
+            const double* q = partials + (size_t)it * NACC;
+            for (int f = 0; f < NACC; ++f) z[f] += q[f];
+        }
+    }
+    if (tangent) {
+        double* o = hw + ((size_t)pi * NW + dir) * NW;
+        for (int f = 0; f < NW; ++f) o[f] = z[f + 1];
+    } else {
+        double* o = gw + (size_t)pi * NACC;
+        for (int f = 0; f < NACC; ++f) o[f] = z[f];
+    }
+}
+
+// Hessian of ELBO_s: column d is the tangent, along parameter d, of the chain rule
+// J^T z applied to the pair gradients z (value gw, tangent hw * (dw / dtheta_d)), plus the
+// KL term.  One thread per (listed source, direction).
+__global__ void __launch_bounds__(128) k_assemble_hessian(Sel srcs, Geometry g, const int32_t* __restrict__ patch_ptr,
+                                                          const double* __restrict__ theta,
+                                                          const double* __restrict__ gw,
+                                                          const double* __restrict__ hw,
+                                                          double* __restrict__ hess, const int* status) {
+    if (*status) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= srcs.n * NP) return;
+    const int j = t / NP, d = t - j * NP;
+    const int s = sel_at(srcs, j);
+    dual p[NP], gh[NP];
+    for (int i = 0; i < NP; ++i) {
+        p[i] = mkd(theta[(size_t)s * ROW + i], i == d ? 1.0 : 0.0);
+        gh[i] = mkd(0.0, 0.0);
+    }
+    for (int pi = patch_ptr[s]; pi < patch_ptr[s + 1]; ++pi) {
+        const celeste_image& im = g.images[g.pairs[pi].img];
+        dual w[NW];
+        pair_w<dual>(p, im, w);
+        dual z[NACC];
+        const double* gz = gw + (size_t)pi * NACC;
+        const double* h = hw + (size_t)pi * NW * NW;
+        z[A_VAL] = mkd(gz[A_VAL], 0.0);
+        for (int a = 0; a < NW; ++a) {
+            double tz = 0.0;
+            for (int i = 0; i < NW; ++i) tz += h[i * NW + a] * w[i].t;
+            z[a + 1] = mkd(gz[a + 1], tz);
+        }
+        chain_pair<dual>(p, im, z, gh);
+    }
+    if (g.consts.flags & CELESTE_INCLUDE_KL) kl_source<dual>(p, g.consts, gh);
+    double* o = hess + (size_t)j * NP * NP + (size_t)d * NP;
+    for (int i = 0; i < NP; ++i) o[i] = gh[i].t;
+}
+
 // Total ELBO: fixed-order sum of the per-tile pixel sums minus every source's KL.
 __global__ void __launch_bounds__(256) k_tile_total(const double* tile_sums, int n_tiles,
                                                     const double* theta, Consts K, int S,
@@ -293,6 +371,24 @@ hipError_t launch_fill_u8_sel(uint8_t* p, const Sel& s, uint8_t v, hipStream_t s
 hipError_t launch_fill_f64_sel(double* p, const Sel& s, double v, hipStream_t st) {
     if (s.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_f64_sel, dim3((s.n + 255) / 256), dim3(256), 0, st, p, s, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_reduce(const Sel& sel, const PairDev* dpairs, const double* partials, bool tangent, int dir,
+                              double* gw, double* hw, const int* status, hipStream_t st) {
+    if (sel.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pair_reduce, dim3((sel.n + 127) / 128), dim3(128), 0, st, sel, dpairs, partials,
+                       tangent ? 1 : 0, dir, gw, hw, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_hessian(const Sel& srcs, const Geometry& g, const int32_t* patch_ptr, const double* theta,
+                                   const double* gw, const double* hw, double* hess, const int* status,
+                                   hipStream_t st) {
+    if (srcs.n <= 0) return hipSuccess;
+    const int n = srcs.n * NP;
+    hipLaunchKernelGGL(k_assemble_hessian, dim3((n + 127) / 128), dim3(128), 0, st, srcs, g, patch_ptr, theta, gw,
+                       hw, hess, status);
     return hipGetLastError();
 }
 

@@ -108,22 +108,38 @@ __device__ inline void write_comp(T* e, T cx, T cy, T sxx, T sxy, T syy, double 
     e[F_RDY] = exp(-(sxx * inv));
 }
 
-// Table of the 45 Gaussians of source parameters p in image im (components: 3 star,
-// then per PSF component 8 de Vaucouleurs and 6 exponential) and the k1..k4 factors.
+// Intermediate quantities of one (source, image) pair through which the pixel terms depend
+// on the source's parameters: the brightness factors k1..k4, the position, frac_dev and the
+// galaxy shape covariance.  The order matches the accumulators A_K1..A_SYY (index + 1).
+enum WField { W_K1 = 0, W_K2, W_K3, W_K4, W_UX, W_UY, W_FDEV, W_SXX, W_SXY, W_SYY, NW };
+
 template <class T>
-__device__ inline void build_pair(const T* p, const celeste_image& im, const Consts& K, T* tab, T* coef) {
+__device__ inline void pair_w(const T* p, const celeste_image& im, T* w) {
     T a[2], b[2];
     flux_moments(p, im.band, a, b);
     const T q = p[6];
     const double io = im.iota;
-    coef[C_K1] = io * (q * a[0]);
-    coef[C_K2] = io * ((1.0 - q) * a[1]);
-    coef[C_K3] = (io * io) * (q * b[0]);
-    coef[C_K4] = (io * io) * ((1.0 - q) * b[1]);
-    T sxx, sxy, syy;
-    shape_cov(p, sxx, sxy, syy);
-    const T ux = p[0] - im.origin_x, uy = p[1] - im.origin_y;
-    const T fdev = p[2];
+    w[W_K1] = io * (q * a[0]);
+    w[W_K2] = io * ((1.0 - q) * a[1]);
+    w[W_K3] = (io * io) * (q * b[0]);
+    w[W_K4] = (io * io) * ((1.0 - q) * b[1]);
+    w[W_UX] = p[0];
+    w[W_UY] = p[1];
+    w[W_FDEV] = p[2];
+    shape_cov(p, w[W_SXX], w[W_SXY], w[W_SYY]);
+}
+
+// Table of the 45 Gaussians (components: 3 star, then per PSF component 8 de Vaucouleurs
+// and 6 exponential) and the k1..k4 factors from the intermediates w of a pair.
+template <class T>
+__device__ inline void build_from_w(const T* w, const celeste_image& im, const Consts& K, T* tab, T* coef) {
+    coef[C_K1] = w[W_K1];
+    coef[C_K2] = w[W_K2];
+    coef[C_K3] = w[W_K3];
+    coef[C_K4] = w[W_K4];
+    const T sxx = w[W_SXX], sxy = w[W_SXY], syy = w[W_SYY];
+    const T ux = w[W_UX] - im.origin_x, uy = w[W_UY] - im.origin_y;
+    const T fdev = w[W_FDEV];
     const T fexp = 1.0 - fdev;
     const T one = scalar_traits<T>::make(1.0, 0.0);
     const T zero = scalar_traits<T>::make(0.0, 0.0);
@@ -145,6 +161,13 @@ __device__ inline void build_pair(const T* p, const celeste_image& im, const Con
                        nu * syy + ps[5], log(ps[0] * K.exp_alpha[j]), fexp, nu * fexp, -1.0);
         }
     }
+}
+
+template <class T>
+__device__ inline void build_pair(const T* p, const celeste_image& im, const Consts& K, T* tab, T* coef) {
+    T w[NW];
+    pair_w(p, im, w);
+    build_from_w(w, im, K, tab, coef);
 }
 
 // Value-only profile sums of NPIX pixels from a double table.

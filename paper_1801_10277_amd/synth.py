@@ -98,6 +98,12 @@ class Field:
 # drawing helpers
 
 
+def _workers():
+    env = os.environ.get("SYNTH_WORKERS") or os.environ.get("OMP_NUM_THREADS")
+    n = int(env) if env else (os.cpu_count() or 1)
+    return max(1, min(n, 16))
+
+
 def _psf_draw(rng, n_img):
     """Per image: 3-component isotropic PSF, weights Dirichlet(5,3,2), sigma U[1,3] px."""
     psf = np.zeros((n_img, 3, 6))
@@ -265,14 +271,29 @@ def _assemble(rng, images_meta, pos, kind, flux, colours, shape, box_sides, thet
     img_psf = np.array([m["psf"] for m in images_meta])
     band_flux = _band_fluxes(flux, colours)
     x = np.empty(int(sizes.sum()))
-    for n in range(n_img):
+    # one independent stream per image (spawned from the field's stream), so images can
+    # be drawn concurrently and the result does not depend on the number of workers
+    streams = [np.random.default_rng(s) for s in
+               np.random.SeedSequence(int(rng.integers(2 ** 63))).spawn(n_img)]
+
+    def draw(n):
+        r = streams[n]
         if render:
-            im = _render_image(rng, int(img_H[n]), int(img_W[n]), img_sky[n], img_iota[n],
+            im = _render_image(r, int(img_H[n]), int(img_W[n]), img_sky[n], img_iota[n],
                                img_origin[n], img_psf[n], int(img_band[n]), pos, kind,
                                band_flux, shape, b_exp, b_dev)
         else:
-            im = rng.poisson(img_sky[n], size=(int(img_H[n]), int(img_W[n]))).astype(float)
+            im = r.poisson(img_sky[n], size=(int(img_H[n]), int(img_W[n]))).astype(float)
         x[img_off[n]:img_off[n] + sizes[n]] = im.reshape(-1)
+
+    workers = min(n_img, _workers())
+    if workers > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(draw, range(n_img)))
+    else:
+        for n in range(n_img):
+            draw(n)
     # patch boxes, centred on the starting position
     S = theta.shape[0]
     ptr = [0]
