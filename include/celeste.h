@@ -128,7 +128,9 @@ typedef struct celeste_plan_info {
     int32_t strip_rows;    /* pixels per strip: a lane walks one column of a box this many rows */
     int32_t render_mode;   /* 0: strips per conflict-free class of boxes; 1: binned tiles evaluating
                               the Gaussians; 2: one strip pass storing each visit's own profile
-                              values, then a binned-tile gather (the fused adjoint reuses them) */
+                              values, then a binned-tile gather (the fused adjoint reuses them);
+                              3 (default): the stored values only - the fused adjoint sums each
+                              pixel's background from the overlapping boxes' values, no planes */
     int32_t n_classes;     /* conflict-free classes of boxes (render launches) */
     int32_t reserved;
     int64_t workspace_bytes;
@@ -209,7 +211,7 @@ int celeste_sweep(celeste_plan* plan, double* theta_inout, const int32_t* batch_
  * block (1, 2 or 4), persistent grid size (blocks, >= 1), dynamic_queue (0/1), render
  * tile tile_h x tile_w (tile_w divides 64; tile_h * tile_w = 64, 128 or 256),
  * strip_rows (4, 8 or 16 pixels per strip) and render_mode (see celeste_plan_info; the
- * default is 2).  Rebuilds work items and render tiles (synchronous; the tile buffers
+ * default is 3).  Rebuilds work items and render tiles (synchronous; the tile buffers
  * are reallocated if they grow). */
 int celeste_plan_set_launch(celeste_plan* plan, int chunk, int waves_per_block, int grid_blocks,
                             int dynamic_queue, int tile_h, int tile_w, int strip_rows, int render_mode);

@@ -67,7 +67,9 @@ struct celeste_plan {
 
     // launch configuration
     int chunk = 256, wpb = 4, grid = 0, dynamic = 0, tile_h = 8, tile_w = 8, rows = 8;
-    int render_mode = 2;   // 0: strips per conflict-free class, 1: binned tiles, 2: stored values + gather
+    // 0: strips per conflict-free class, 1: binned tiles, 2: stored values + tile gather,
+    // 3: stored values, background gathered inside the fused adjoint (no planes)
+    int render_mode = 3;
     bool use_graph = false;
 
     // device memory
@@ -427,10 +429,12 @@ int render_tiles(celeste_plan* p, bool sums, hipStream_t st) {
 int render(celeste_plan* p, hipStream_t st) {
     p->fg_valid = false;
     if (p->render_mode == 1) return render_tiles(p, false, st);
-    if (p->render_mode == 2) {
+    if (p->render_mode == 2 || p->render_mode == 3) {
         const Geometry g = p->geom();
         const Sel all{nullptr, 0, (int32_t)p->items.size()};
         HIPCHK(launch_strip_fg(all, g, p->d_tab1, p->d_fg, p->rows, p->persistent_grid(), p->wpb, p->d_status, st));
+        p->fg_valid = true;
+        if (p->render_mode == 3) return CELESTE_OK;   // no planes: the adjoint gathers from stored values
         RenderArgs a{};
         a.g = g;
         a.tiles = p->d_tiles;
@@ -471,7 +475,8 @@ int adjoint(celeste_plan* p, const Sel& items, const uint8_t* active, bool tange
     a.E = p->d_E;
     a.V = p->d_V;
     a.bg = p->d_bg;
-    a.fg = (base == BASE_PLANES && !tangent && p->fg_valid) ? p->d_fg : nullptr;
+    if (base == BASE_PLANES && p->render_mode == 3) base = BASE_FG;
+    a.fg = ((base == BASE_PLANES || base == BASE_FG) && p->fg_valid) ? p->d_fg : nullptr;
     a.partials = p->d_partials;
     a.status = p->d_status;
     const int grid = grid_override > 0 ? grid_override : p->persistent_grid();
@@ -853,7 +858,7 @@ int celeste_plan_set_launch(celeste_plan* p, int chunk, int wpb, int grid, int d
     if (!p || chunk < 64 || chunk > 1024 || chunk % 64 || (wpb != 1 && wpb != 2 && wpb != 4) || grid < 1 ||
         (dynamic != 0 && dynamic != 1) || tile_w < 1 || tile_w > 64 || 64 % tile_w || tile_h < 1 ||
         (tile_h * tile_w != 64 && tile_h * tile_w != 128 && tile_h * tile_w != 256) ||
-        (strip_rows != 4 && strip_rows != 8 && strip_rows != 16) || render_mode < 0 || render_mode > 2)
+        (strip_rows != 4 && strip_rows != 8 && strip_rows != 16) || render_mode < 0 || render_mode > 3)
         return CELESTE_EINVAL;
     HIPCHK(hipDeviceSynchronize());
     drop_graph(p);
@@ -1228,7 +1233,7 @@ int celeste_autotune(celeste_plan* p, const double* theta, int reps, double* bes
     for (int d : {0, 1}) { c = best; c.dyn = d; trial(c); }
     const int tiles[4][2] = {{8, 8}, {4, 16}, {16, 8}, {16, 16}};
     for (auto& tl : tiles) { c = best; c.rmode = 2; c.th = tl[0]; c.tw = tl[1]; trial(c); }
-    for (int m : {0, 1}) { c = best; c.rmode = m; trial(c); }
+    for (int m : {0, 1, 3}) { c = best; c.rmode = m; trial(c); }
     if (rc == CELESTE_OK)
         rc = celeste_plan_set_launch(p, best.chunk, best.wpb, best.grid, best.dyn, best.th, best.tw, best.rows,
                                      best.rmode);

@@ -77,7 +77,8 @@ __host__ __device__ inline int32_t sel_at(const Sel& s, int32_t j) { return s.id
 enum BaseMode {
     BASE_PLANES = 0,   // E, V planes of all sources (own included)
     BASE_BG = 1,       // per-visit background excluding the own source
-    BASE_NBR = 2       // background evaluated on the fly from the overlapping boxes
+    BASE_NBR = 2,      // background evaluated on the fly from the overlapping boxes
+    BASE_FG = 3        // background from the overlapping boxes' stored profile values
 };
 
 // Direction seeding of the tangent pass: a vector in parameter space, a parameter unit

@@ -191,6 +191,38 @@ __device__ __forceinline__ void strip_background(const PairDev& p, const PairDev
     }
 }
 
+// Sky plus the light of every other box of the image covering each row of the strip, from
+// the boxes' stored own profile values (ascending box order).
+template <int L>
+__device__ __forceinline__ void strip_background_fg(const PairDev& p, const PairDev* __restrict__ pairs,
+                                                    const int32_t* __restrict__ nbr,
+                                                    const double* __restrict__ coefv,
+                                                    const double* __restrict__ fgm, double sky, int c, int r0,
+                                                    double* Eb, double* Vb) {
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        Eb[k] = sky;
+        Vb[k] = 0.0;
+    }
+    for (int q = p.nbr_begin; q < p.nbr_end; ++q) {
+        const int pi = __builtin_amdgcn_readfirstlane(nbr[q]);
+        const PairDev o = pairs[pi];
+        if (c < o.c0 || c >= o.c0 + o.w || r0 + L <= o.r0 || r0 >= o.r0 + o.h) continue;
+        const double* kk = coefv + (size_t)pi * NCOEF;
+        const double k1 = kk[C_K1], k2 = kk[C_K2], k3 = kk[C_K3], k4 = kk[C_K4];
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            const int r = r0 + k;
+            if (r < o.r0 || r >= o.r0 + o.h) continue;
+            const size_t vi = (size_t)o.visit_off + (size_t)(r - o.r0) * o.w + (c - o.c0);
+            const double fs = fgm[2 * vi], fg = fgm[2 * vi + 1];
+            const double Et = k1 * fs + k2 * fg;
+            Eb[k] += Et;
+            Vb[k] += k3 * fs * fs + k4 * fg * fg - Et * Et;
+        }
+    }
+}
+
 __device__ inline int next_item_s(int* counter, int lane) {
     int v = 0;
     if (lane == 0) v = atomicAdd(counter, 1);
@@ -292,6 +324,8 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
                 double x[L], Eb[L], Vb[L];
                 if (BASE == BASE_NBR) {
                     strip_background<L>(p, pairs, nbr, tabv, coefv, im.sky, c, r0, Eb, Vb, t2);
+                } else if (BASE == BASE_FG) {
+                    strip_background_fg<L>(p, pairs, nbr, coefv, fgm, im.sky, c, r0, Eb, Vb);
                 }
 #pragma unroll
                 for (int kk = 0; kk < L; ++kk) {
@@ -590,14 +624,19 @@ hipError_t launch_render_strips(const Sel& sel, const Geometry& g, const double*
 template <class T, int BASE, bool DERIV, int L>
 static void adjs(const AdjArgs& a, int grid, int wpb, hipStream_t st) {
     const Geometry& g = a.g;
-    if (BASE == BASE_PLANES && std::is_same<T, double>::value && a.fg)
-        hipLaunchKernelGGL((k_adjoint_strips<T, BASE, DERIV, L, true>), dim3(grid), dim3(64 * wpb), 0, st, a, g.items,
-                           g.pairs, g.images, g.nbr, g.x, a.E, a.V, a.bg, a.tab, a.coef, a.tab_val, a.coef_val,
-                           a.active, a.fg, a.partials);
-    else
-        hipLaunchKernelGGL((k_adjoint_strips<T, BASE, DERIV, L, false>), dim3(grid), dim3(64 * wpb), 0, st, a,
-                           g.items, g.pairs, g.images, g.nbr, g.x, a.E, a.V, a.bg, a.tab, a.coef, a.tab_val,
-                           a.coef_val, a.active, nullptr, a.partials);
+    // own profile values from the render's stored values: double passes over planes or stored values
+    constexpr bool own_fg = std::is_same<T, double>::value && (BASE == BASE_PLANES || BASE == BASE_FG);
+    if constexpr (own_fg) {
+        if (a.fg) {
+            hipLaunchKernelGGL((k_adjoint_strips<T, BASE, DERIV, L, true>), dim3(grid), dim3(64 * wpb), 0, st, a,
+                               g.items, g.pairs, g.images, g.nbr, g.x, a.E, a.V, a.bg, a.tab, a.coef, a.tab_val,
+                               a.coef_val, a.active, a.fg, a.partials);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_adjoint_strips<T, BASE, DERIV, L, false>), dim3(grid), dim3(64 * wpb), 0, st, a, g.items,
+                       g.pairs, g.images, g.nbr, g.x, a.E, a.V, a.bg, a.tab, a.coef, a.tab_val, a.coef_val,
+                       a.active, a.fg, a.partials);
 }
 
 template <class T, int BASE, bool DERIV>
@@ -607,6 +646,22 @@ static hipError_t adjs_L(const AdjArgs& a, int grid, int wpb, int L, hipStream_t
     else if (L == 16) adjs<T, BASE, DERIV, 16>(a, grid, wpb, st);
     else return hipErrorInvalidValue;
     return hipSuccess;
+}
+
+template <class T, int BASE>
+static hipError_t adjs_D(const AdjArgs& a, bool deriv, int grid, int wpb, int L, hipStream_t st) {
+    return deriv ? adjs_L<T, BASE, true>(a, grid, wpb, L, st) : adjs_L<T, BASE, false>(a, grid, wpb, L, st);
+}
+
+template <class T>
+static hipError_t adjs_B(const AdjArgs& a, int base, bool deriv, int grid, int wpb, int L, hipStream_t st) {
+    switch (base) {
+        case BASE_PLANES: return adjs_D<T, BASE_PLANES>(a, deriv, grid, wpb, L, st);
+        case BASE_BG: return adjs_D<T, BASE_BG>(a, deriv, grid, wpb, L, st);
+        case BASE_NBR: return adjs_D<T, BASE_NBR>(a, deriv, grid, wpb, L, st);
+        case BASE_FG: return a.fg ? adjs_D<T, BASE_FG>(a, deriv, grid, wpb, L, st) : hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_adjoint(const AdjArgs& a, bool tangent, int base, bool deriv, int grid, int wpb, int L,
@@ -620,22 +675,8 @@ hipError_t launch_adjoint(const AdjArgs& a, bool tangent, int base, bool deriv, 
         if (grid > need) grid = need;
     }
     if (grid < 1) grid = 1;
-    hipError_t e;
-    if (tangent) {
-        if (base == BASE_PLANES) e = deriv ? adjs_L<dual, BASE_PLANES, true>(a, grid, wpb, L, st)
-                                           : adjs_L<dual, BASE_PLANES, false>(a, grid, wpb, L, st);
-        else if (base == BASE_BG) e = deriv ? adjs_L<dual, BASE_BG, true>(a, grid, wpb, L, st)
-                                            : adjs_L<dual, BASE_BG, false>(a, grid, wpb, L, st);
-        else e = deriv ? adjs_L<dual, BASE_NBR, true>(a, grid, wpb, L, st)
-                       : adjs_L<dual, BASE_NBR, false>(a, grid, wpb, L, st);
-    } else {
-        if (base == BASE_PLANES) e = deriv ? adjs_L<double, BASE_PLANES, true>(a, grid, wpb, L, st)
-                                           : adjs_L<double, BASE_PLANES, false>(a, grid, wpb, L, st);
-        else if (base == BASE_BG) e = deriv ? adjs_L<double, BASE_BG, true>(a, grid, wpb, L, st)
-                                            : adjs_L<double, BASE_BG, false>(a, grid, wpb, L, st);
-        else e = deriv ? adjs_L<double, BASE_NBR, true>(a, grid, wpb, L, st)
-                       : adjs_L<double, BASE_NBR, false>(a, grid, wpb, L, st);
-    }
+    const hipError_t e = tangent ? adjs_B<dual>(a, base, deriv, grid, wpb, L, st)
+                                 : adjs_B<double>(a, base, deriv, grid, wpb, L, st);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
