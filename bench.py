@@ -199,10 +199,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the launch first (default: the plan's default launch, which the "
+                         "committed counter profile was taken at)")
     ap.add_argument("--sources", type=int, default=2000)
     ap.add_argument("--launch", type=str, default=None,
-                    help="fixed launch chunk,waves_per_block,grid,dynamic,strip_rows,render_mode (skips autotune)")
+                    help="fixed launch chunk,waves_per_block,grid,dynamic,strip_rows,render_mode[,tile_h,tile_w] "
+                         "(skips autotune)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 512 MiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--workload", choices=("elbo_grad", "newton", "sweep"), default="elbo_grad")
@@ -238,11 +241,13 @@ def main():
     grad = torch.zeros(f.n_src, 32, dtype=torch.float64, device=dev)
 
     if args.launch:
-        ch, wpb, grid, dyn, rows, rmode = (int(v) for v in args.launch.split(","))
+        vals = [int(v) for v in args.launch.split(",")]
+        ch, wpb, grid, dyn, rows, rmode = vals[:6]
+        th, tw = vals[6:8] if len(vals) >= 8 else (16, 16)
         plan.set_launch(chunk=ch, waves_per_block=wpb, grid_blocks=grid, dynamic=dyn, strip_rows=rows,
-                        render_mode=rmode)
+                        render_mode=rmode, tile_h=th, tile_w=tw)
         info = plan.info()
-    elif not args.no_tune:
+    elif args.tune:
         ms = plan.autotune(theta, reps=3)
         info = plan.info()
         log("autotuned: %s (%.3f ms)" % ({k: info[k] for k in LAUNCH_KEYS}, ms))

@@ -127,9 +127,9 @@ typedef struct celeste_plan_info {
     int32_t dynamic_queue; /* 1: items popped from a device counter; 0: static round robin */
     int32_t strip_rows;    /* pixels per strip: a lane walks one column of a box this many rows */
     int32_t render_mode;   /* 0: strips per conflict-free class of boxes; 1: binned tiles evaluating
-                              the Gaussians; 2: one strip pass storing each visit's own profile
-                              values, then a binned-tile gather (the fused adjoint reuses them);
-                              3 (default): the stored values only - the fused adjoint sums each
+                              the Gaussians; 2 (default): one strip pass storing each visit's own
+                              profile values, then a binned-tile gather (the fused adjoint reuses
+                              them); 3: the stored values only - the fused adjoint sums each
                               pixel's background from the overlapping boxes' values, no planes */
     int32_t n_classes;     /* conflict-free classes of boxes (render launches) */
     int32_t reserved;
@@ -208,11 +208,13 @@ int celeste_sweep(celeste_plan* plan, double* theta_inout, const int32_t* batch_
                   const celeste_tr_params* params, double* elbo_trace, hipStream_t stream);
 
 /* Launch configuration: strips per work item (multiple of 64, at most 1024), waves per
- * block (1, 2 or 4), persistent grid size (blocks, >= 1), dynamic_queue (0/1), render
- * tile tile_h x tile_w (tile_w divides 64; tile_h * tile_w = 64, 128 or 256),
- * strip_rows (4, 8 or 16 pixels per strip) and render_mode (see celeste_plan_info; the
- * default is 3).  Rebuilds work items and render tiles (synchronous; the tile buffers
- * are reallocated if they grow). */
+ * block (1, 2 or 4), persistent grid size (blocks; 0 = 64 per compute unit), dynamic_queue
+ * (0/1), render tile tile_h x tile_w (tile_w divides 64; tile_h * tile_w = 64, 128 or 256),
+ * strip_rows (4, 8 or 16 pixels per strip) and render_mode (see celeste_plan_info).  A new
+ * plan starts at chunk 64, 4 waves per block, grid 0, static queue, 16 x 16 tiles, 16-row
+ * strips, render mode 2.  Rebuilds work items and render tiles (synchronous).  If grown
+ * tile buffers cannot be allocated it returns CELESTE_ENOMEM and the plan keeps its
+ * previous configuration. */
 int celeste_plan_set_launch(celeste_plan* plan, int chunk, int waves_per_block, int grid_blocks,
                             int dynamic_queue, int tile_h, int tile_w, int strip_rows, int render_mode);
 

@@ -293,8 +293,8 @@ class Plan:
         self._status("celeste_sweep")
         return trace
 
-    def set_launch(self, chunk=256, waves_per_block=4, grid_blocks=2048, dynamic=0, tile_h=8, tile_w=8,
-                   strip_rows=8, render_mode=0):
+    def set_launch(self, chunk=64, waves_per_block=4, grid_blocks=0, dynamic=0, tile_h=16, tile_w=16,
+                   strip_rows=16, render_mode=2):
         check(lib().celeste_plan_set_launch(self.h, chunk, waves_per_block, grid_blocks, dynamic, tile_h,
                                             tile_w, strip_rows, render_mode), "celeste_plan_set_launch")
 

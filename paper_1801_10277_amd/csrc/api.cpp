@@ -66,10 +66,10 @@ struct celeste_plan {
     int n_cu = 256;
 
     // launch configuration
-    int chunk = 256, wpb = 4, grid = 0, dynamic = 0, tile_h = 8, tile_w = 8, rows = 8;
+    int chunk = 64, wpb = 4, grid = 0, dynamic = 0, tile_h = 16, tile_w = 16, rows = 16;
     // 0: strips per conflict-free class, 1: binned tiles, 2: stored values + tile gather,
     // 3: stored values, background gathered inside the fused adjoint (no planes)
-    int render_mode = 3;
+    int render_mode = 2;
     bool use_graph = false;
 
     // device memory
@@ -142,7 +142,7 @@ struct celeste_plan {
         return g;
     }
     int64_t n_pairs() const { return (int64_t)pairs.size(); }
-    int persistent_grid() const { return grid > 0 ? grid : 8 * n_cu; }
+    int persistent_grid() const { return grid > 0 ? grid : 64 * n_cu; }
 };
 
 namespace {
@@ -855,38 +855,58 @@ int celeste_plan_get_info(const celeste_plan* p, celeste_plan_info* info) {
 
 int celeste_plan_set_launch(celeste_plan* p, int chunk, int wpb, int grid, int dynamic, int tile_h, int tile_w,
                             int strip_rows, int render_mode) {
-    if (!p || chunk < 64 || chunk > 1024 || chunk % 64 || (wpb != 1 && wpb != 2 && wpb != 4) || grid < 1 ||
+    if (!p || chunk < 64 || chunk > 1024 || chunk % 64 || (wpb != 1 && wpb != 2 && wpb != 4) || grid < 0 ||
         (dynamic != 0 && dynamic != 1) || tile_w < 1 || tile_w > 64 || 64 % tile_w || tile_h < 1 ||
         (tile_h * tile_w != 64 && tile_h * tile_w != 128 && tile_h * tile_w != 256) ||
         (strip_rows != 4 && strip_rows != 8 && strip_rows != 16) || render_mode < 0 || render_mode > 3)
         return CELESTE_EINVAL;
     HIPCHK(hipDeviceSynchronize());
     drop_graph(p);
+    if (tile_h != p->tile_h || tile_w != p->tile_w) {
+        const int old_h = p->tile_h, old_w = p->tile_w;
+        p->tile_h = tile_h;
+        p->tile_w = tile_w;
+        build_tiles(p);
+        // grow the tile buffers: new ones first, so that a failed allocation leaves the plan
+        // working with its previous tiles
+        TileDev* nt = nullptr;
+        double* ns = nullptr;
+        int32_t* nl = nullptr;
+        bool ok = true;
+        if (p->tiles.size() > p->cap_tiles)
+            ok = hipMalloc((void**)&nt, p->tiles.size() * sizeof(TileDev)) == hipSuccess &&
+                 hipMalloc((void**)&ns, p->tiles.size() * sizeof(double)) == hipSuccess;
+        if (ok && p->tile_list.size() > p->cap_tile_list)
+            ok = hipMalloc((void**)&nl, p->tile_list.size() * sizeof(int32_t)) == hipSuccess;
+        if (!ok) {
+            (void)hipFree(nt);
+            (void)hipFree(ns);
+            (void)hipFree(nl);
+            (void)hipGetLastError();
+            p->tile_h = old_h;
+            p->tile_w = old_w;
+            build_tiles(p);
+            return CELESTE_ENOMEM;
+        }
+        if (nt) {
+            (void)hipFree(p->d_tiles);
+            (void)hipFree(p->d_tile_sums);
+            p->d_tiles = nt;
+            p->d_tile_sums = ns;
+            p->cap_tiles = p->tiles.size();
+        }
+        if (nl) {
+            (void)hipFree(p->d_tile_list);
+            p->d_tile_list = nl;
+            p->cap_tile_list = p->tile_list.size();
+        }
+    }
     p->rows = strip_rows;
     p->render_mode = render_mode;
     p->chunk = chunk;
     p->wpb = wpb;
     p->grid = grid;
     p->dynamic = dynamic;
-    if (tile_h != p->tile_h || tile_w != p->tile_w) {
-        p->tile_h = tile_h;
-        p->tile_w = tile_w;
-        build_tiles(p);
-        if (p->tiles.size() > p->cap_tiles) {
-            (void)hipFree(p->d_tiles);
-            (void)hipFree(p->d_tile_sums);
-            if (hipMalloc((void**)&p->d_tiles, p->tiles.size() * sizeof(TileDev)) != hipSuccess ||
-                hipMalloc((void**)&p->d_tile_sums, p->tiles.size() * sizeof(double)) != hipSuccess)
-                return CELESTE_ENOMEM;
-            p->cap_tiles = p->tiles.size();
-        }
-        if (p->tile_list.size() > p->cap_tile_list) {
-            (void)hipFree(p->d_tile_list);
-            if (hipMalloc((void**)&p->d_tile_list, p->tile_list.size() * sizeof(int32_t)) != hipSuccess)
-                return CELESTE_ENOMEM;
-            p->cap_tile_list = p->tile_list.size();
-        }
-    }
     build_items(p);
     build_class_items(p);
     return upload_geometry(p);
@@ -1221,19 +1241,34 @@ int celeste_autotune(celeste_plan* p, const double* theta, int reps, double* bes
             best = c;
         }
     };
+    // render mode and strip height interact (the register footprint of the fused adjoint
+    // depends on both), so they are searched jointly first; then one coordinate pass over the
+    // remaining knobs, and a second joint pass at the chosen launch shape
+    auto mode_rows = [&]() {
+        const Cfg start = best;
+        for (int m : {0, 1, 2, 3})
+            for (int r : {4, 8, 16}) {
+                Cfg c = start;
+                c.rmode = m;
+                c.rows = r;
+                if (c.rmode != start.rmode || c.rows != start.rows) trial(c);
+            }
+    };
+    mode_rows();
     Cfg c = best;
-    for (int r : {4, 8, 16}) { c = best; c.rows = r; trial(c); }
     for (int ch : {64, 128, 256, 512, 1024}) { c = best; c.chunk = ch; trial(c); }
     for (int w : {1, 2, 4}) { c = best; c.wpb = w; trial(c); }
-    for (int g : {p->n_cu, 2 * p->n_cu, 4 * p->n_cu, 8 * p->n_cu, 16 * p->n_cu, 64 * p->n_cu}) {
+    for (int g : {p->n_cu, 4 * p->n_cu, 16 * p->n_cu, 64 * p->n_cu, 128 * p->n_cu}) {
         c = best;
         c.grid = g;
         trial(c);
     }
     for (int d : {0, 1}) { c = best; c.dyn = d; trial(c); }
-    const int tiles[4][2] = {{8, 8}, {4, 16}, {16, 8}, {16, 16}};
-    for (auto& tl : tiles) { c = best; c.rmode = 2; c.th = tl[0]; c.tw = tl[1]; trial(c); }
-    for (int m : {0, 1, 3}) { c = best; c.rmode = m; trial(c); }
+    if (best.rmode == 1 || best.rmode == 2) {
+        const int tiles[5][2] = {{8, 8}, {4, 16}, {16, 8}, {8, 16}, {16, 16}};
+        for (auto& tl : tiles) { c = best; c.th = tl[0]; c.tw = tl[1]; trial(c); }
+    }
+    mode_rows();
     if (rc == CELESTE_OK)
         rc = celeste_plan_set_launch(p, best.chunk, best.wpb, best.grid, best.dyn, best.th, best.tw, best.rows,
                                      best.rmode);

@@ -321,6 +321,58 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
                 int c, r0, nrow;
                 strip_geometry(p, it.start + q, L, c, r0, nrow);
                 const double px = (double)c, py0 = (double)r0;
+                if constexpr (FGM && DERIV && (BASE == BASE_PLANES || BASE == BASE_FG)) {
+                    // Rows streamed one at a time, the next row's loads in flight, so that only
+                    // the row weights (and for BASE_FG the neighbours' background) stay live
+                    // into pass B.
+                    double Eb[L], Vb[L];
+                    if constexpr (BASE == BASE_FG)
+                        strip_background_fg<L>(p, pairs, nbr, coefv, fgm, im.sky, c, r0, Eb, Vb);
+                    auto row_load = [&](int rr, double& x_, double& e_, double& v_, double& s_, double& g_) {
+                        const size_t gi = (size_t)im.pix_offset + (size_t)(r0 + rr) * im.W + c;
+                        const size_t vi = (size_t)p.visit_off + (size_t)(r0 + rr - p.r0) * p.w + (c - p.c0);
+                        x_ = xs[gi];
+                        if constexpr (BASE == BASE_PLANES) {
+                            e_ = Ep[gi];
+                            v_ = Vp[gi];
+                        }
+                        s_ = fgm[2 * vi];
+                        g_ = fgm[2 * vi + 1];
+                    };
+                    T Gs[L], Gg[L];
+                    double cx_, ce_ = 0.0, cv_ = 0.0, cs_, cg_;
+                    row_load(0, cx_, ce_, cv_, cs_, cg_);
+#pragma unroll
+                    for (int kk = 0; kk < L; ++kk) {
+                        double nx_ = 0.0, ne_ = 0.0, nv_ = 0.0, ns_ = 0.0, ng_ = 0.0;
+                        if (kk + 1 < L) row_load(kk + 1 < nrow ? kk + 1 : 0, nx_, ne_, nv_, ns_, ng_);
+                        T gs = zero, gg = zero;
+                        if (kk < nrow && cx_ == cx_) {
+                            const T fsk = scalar_traits<T>::make(cs_, 0.0), fgk = scalar_traits<T>::make(cg_, 0.0);
+                            T E, V;
+                            if constexpr (BASE == BASE_PLANES) {
+                                E = scalar_traits<T>::make(ce_, 0.0);
+                                V = scalar_traits<T>::make(cv_, 0.0);
+                            } else {
+                                const T Es = k[C_K1] * fsk + k[C_K2] * fgk;
+                                const T Vs = k[C_K3] * (fsk * fsk) + k[C_K4] * (fgk * fgk) - Es * Es;
+                                E = Eb[kk] + Es;
+                                V = Vb[kk] + Vs;
+                            }
+                            strip_pixel<T, true>(cx_, E, V, fsk, fgk, k, acc, gs, gg);
+                        }
+                        Gs[kk] = gs;
+                        Gg[kk] = gg;
+                        cx_ = nx_;
+                        ce_ = ne_;
+                        cv_ = nv_;
+                        cs_ = ns_;
+                        cg_ = ng_;
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    strip_adjoint<T, L>(tab, px, py0, Gs, Gg, acc, t2);
+                    continue;
+                }
                 double x[L], Eb[L], Vb[L];
                 if (BASE == BASE_NBR) {
                     strip_background<L>(p, pairs, nbr, tabv, coefv, im.sky, c, r0, Eb, Vb, t2);

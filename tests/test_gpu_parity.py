@@ -142,7 +142,13 @@ LAUNCHES = [dict(chunk=64, waves_per_block=1, grid_blocks=256, dynamic=0, strip_
                  tile_h=16, tile_w=8),
             dict(chunk=1024, waves_per_block=4, grid_blocks=1024, dynamic=0, strip_rows=16, render_mode=0),
             dict(chunk=256, waves_per_block=4, grid_blocks=2048, dynamic=1, strip_rows=8, render_mode=1,
-                 tile_h=16, tile_w=16)]
+                 tile_h=16, tile_w=16),
+            dict(chunk=64, waves_per_block=4, grid_blocks=0, dynamic=0, strip_rows=16, render_mode=2,
+                 tile_h=16, tile_w=16),
+            dict(chunk=128, waves_per_block=2, grid_blocks=512, dynamic=1, strip_rows=4, render_mode=2,
+                 tile_h=4, tile_w=16),
+            dict(chunk=64, waves_per_block=4, grid_blocks=1024, dynamic=0, strip_rows=16, render_mode=3),
+            dict(chunk=192, waves_per_block=1, grid_blocks=300, dynamic=1, strip_rows=8, render_mode=3)]
 
 
 def test_launch_configurations_agree(B, synth):
