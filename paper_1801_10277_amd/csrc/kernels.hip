@@ -1,14 +1,15 @@
 // HIP kernels of the FP64 ELBO path for gfx950 (CDNA4, wave64).
 //
 // Work decomposition:
-//  * k_prep:      one thread per (source, image) box builds the box's 45-Gaussian table
-//                 and brightness factors (value, or value + tangent).
+//  * k_prep:      one wave per (source, image) box, one lane per table entry, builds the
+//                 box's 45-Gaussian table and brightness factors (value, or value + tangent).
 //  * k_render:    one wave per render tile sums E[F] and Var[F] of every box that
 //                 covers each pixel, in box order (deterministic, no atomics), and
 //                 optionally the pixel terms of covered pixels (total ELBO).
 //  * the fused adjoint and the strip render live in strips.hip.
-//  * k_finalize:  one thread per source sums its items in a fixed order and applies the
-//                 chain rule to the 27 parameters, plus the KL term.
+//  * k_finalize:  one wave per source: each lane sums one box's items in order and applies
+//                 the chain rule to the 27 parameters; a fixed butterfly sums the lanes, then
+//                 the KL term is added.
 // Table entries are addressed with wave-uniform indices so the compiler serves them
 // through scalar loads; pixel data is read coalesced along box rows.
 #include <hip/hip_runtime.h>
@@ -22,64 +23,75 @@ namespace cel {
 
 // ----------------------------------------------------------------------- validation
 // Domain of a source row: finite; q in (0,1); frac_dev in [0,1]; axis ratio in (0,1];
-// radius > 0; variances > 0.
-__device__ inline bool row_ok(const double* p) {
-    for (int i = 0; i < NP; ++i)
-        if (!isfinite(p[i])) return false;
-    if (!(p[6] > 0.0 && p[6] < 1.0)) return false;
-    if (!(p[2] >= 0.0 && p[2] <= 1.0)) return false;
-    if (!(p[3] > 0.0 && p[3] <= 1.0)) return false;
-    if (!(p[5] > 0.0)) return false;
+// radius > 0; variances > 0.  Branch-free so that the row's loads issue together.
+__device__ inline bool row_ok(const double* __restrict__ p) {
+    double v[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) v[i] = p[i];
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) ok &= (bool)isfinite(v[i]);
+    ok &= v[6] > 0.0 && v[6] < 1.0;
+    ok &= v[2] >= 0.0 && v[2] <= 1.0;
+    ok &= v[3] > 0.0 && v[3] <= 1.0;
+    ok &= v[5] > 0.0;
+#pragma unroll
     for (int t = 0; t < 2; ++t) {
         const int base = 7 + 10 * t;
-        if (!(p[base + 1] > 0.0)) return false;
-        for (int k = 0; k < 4; ++k)
-            if (!(p[base + 6 + k] > 0.0)) return false;
+        ok &= v[base + 1] > 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ok &= v[base + 6 + k] > 0.0;
     }
-    return true;
+    return ok;
 }
 
+// One thread per listed source; the status word was cleared by the launcher's fill.
 __global__ void __launch_bounds__(256) k_validate(const double* __restrict__ theta, const uint8_t* active,
                                                   const int32_t* list, int n, int S, int* status) {
-    __shared__ int bad;
-    if (threadIdx.x == 0) bad = 0;
-    __syncthreads();
-    int local = 0;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const int s = list ? list[j] : j;
-        if (s < 0 || s >= S) { local = 1; continue; }
-        if (active && !active[s]) continue;
-        if (!row_ok(theta + (size_t)s * ROW)) local = 1;
-    }
-    if (local) atomicOr(&bad, 1);
-    __syncthreads();
-    if (threadIdx.x == 0) status[0] = bad ? CELESTE_EDOMAIN : 0;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int s = list ? list[j] : j;
+    bool bad;
+    if (s < 0 || s >= S) bad = true;
+    else if (active && !active[s]) bad = false;
+    else bad = !row_ok(theta + (size_t)s * ROW);
+    if (bad) atomicOr(status, CELESTE_EDOMAIN);
 }
 
 // ----------------------------------------------------------------------- prep
+// One wave per box: the box's intermediates are computed by every lane (wave-uniform), then
+// lane c writes table entry c and lane NCOMP the four brightness coefficients.
 template <class T>
-__global__ void __launch_bounds__(128) k_prep(PrepArgs a) {
+__global__ void __launch_bounds__(256) k_prep(PrepArgs a) {
     if (*a.status) return;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (j >= a.pairs.n) return;
     const int pi = sel_at(a.pairs, j);
     const PairDev pd = a.g.pairs[pi];
-    const celeste_image im = a.g.images[pd.img];
+    const celeste_image& im = a.g.images[pd.img];
     T* tab = reinterpret_cast<T*>(a.tab) + (size_t)pi * NCOMP * CST;
     T* coef = reinterpret_cast<T*>(a.coef) + (size_t)pi * NCOEF;
+    T w[NW];
     if (a.dir_mode == DIR_W) {
-        // tangent along one of the pair's intermediates
-        double p[NP], w[NW];
+        // tangent along one of the box's intermediates
+        double p[NP], wv[NW];
         for (int i = 0; i < NP; ++i) p[i] = a.theta[(size_t)pd.src * ROW + i];
-        pair_w<double>(p, im, w);
-        T wt[NW];
-        for (int i = 0; i < NW; ++i) wt[i] = scalar_traits<T>::make(w[i], i == a.dir_unit ? 1.0 : 0.0);
-        build_from_w<T>(wt, im, a.g.consts, tab, coef);
-        return;
+        pair_w<double>(p, im, wv);
+        for (int i = 0; i < NW; ++i) w[i] = scalar_traits<T>::make(wv[i], i == a.dir_unit ? 1.0 : 0.0);
+    } else {
+        T p[NP];
+        for (int i = 0; i < NP; ++i) p[i] = seed<T>(a.theta, a.dir, a.dir_mode, a.dir_unit, pd.src, i);
+        pair_w<T>(p, im, w);
     }
-    T p[NP];
-    for (int i = 0; i < NP; ++i) p[i] = seed<T>(a.theta, a.dir, a.dir_mode, a.dir_unit, pd.src, i);
-    build_pair<T>(p, im, a.g.consts, tab, coef);
+    if (lane < NCOMP) {
+        build_comp_from_w<T>(w, im, a.g.consts, lane, tab + lane * CST);
+    } else if (lane == NCOMP) {
+        coef[C_K1] = w[W_K1];
+        coef[C_K2] = w[W_K2];
+        coef[C_K3] = w[W_K3];
+        coef[C_K4] = w[W_K4];
+    }
 }
 
 // ----------------------------------------------------------------------- render
@@ -162,9 +174,10 @@ __global__ void __launch_bounds__(256) k_render(RenderArgs a, const TileDev* __r
 
 // ----------------------------------------------------------------------- finalize
 template <class T>
-__global__ void __launch_bounds__(128) k_finalize(FinArgs a) {
+__global__ void __launch_bounds__(64) k_finalize(FinArgs a) {
     if (*a.status) return;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.x;
+    const int lane = threadIdx.x;
     if (j >= a.srcs.n) return;
     const int s = sel_at(a.srcs, j);
     if (a.active && !a.active[s]) return;
@@ -175,7 +188,8 @@ __global__ void __launch_bounds__(128) k_finalize(FinArgs a) {
     for (int i = 0; i < NP; ++i) g[i] = zero;
     T val = zero;
     const T* part = reinterpret_cast<const T*>(a.partials);
-    for (int pi = a.patch_ptr[s]; pi < a.patch_ptr[s + 1]; ++pi) {
+    // lane l takes the source's boxes l, l + 64, ...; each box's items in order
+    for (int pi = a.patch_ptr[s] + lane; pi < a.patch_ptr[s + 1]; pi += 64) {
         const PairDev pd = a.g.pairs[pi];
         T z[NACC];
         for (int f = 0; f < NACC; ++f) z[f] = zero;
@@ -191,6 +205,12 @@ __global__ void __launch_bounds__(128) k_finalize(FinArgs a) {
         if (a.pair_lgamma) val = val - a.pair_lgamma[pi];
         if (a.deriv) chain_pair<T>(p, a.g.images[pd.img], z, g);
     }
+    // fixed-order butterfly: every lane ends with the same sums
+    val = wave_sum(val);
+    if (a.deriv) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) g[i] = wave_sum(g[i]);
+    }
     if (a.g.consts.flags & CELESTE_INCLUDE_KL) {
         T gk[NP];
         for (int i = 0; i < NP; ++i) gk[i] = zero;
@@ -198,6 +218,7 @@ __global__ void __launch_bounds__(128) k_finalize(FinArgs a) {
         if (a.deriv)
             for (int i = 0; i < NP; ++i) g[i] += gk[i];
     }
+    if (lane != 0) return;
     if (a.elbo) a.elbo[s] = value_of(val);
     if (a.deriv && a.grad) {
         double* o = a.grad + (size_t)s * ROW;
@@ -322,15 +343,17 @@ __global__ void k_fill_f64_sel(double* p, Sel s, double v) {
 // ----------------------------------------------------------------------- launchers
 hipError_t launch_validate(const double* theta, const uint8_t* active, const int32_t* list, int n,
                            int S, int* status, hipStream_t st) {
-    hipLaunchKernelGGL(k_validate, dim3(1), dim3(256), 0, st, theta, active, list, n, S, status);
+    const hipError_t e = launch_fill_int(status, 0, 1, st);
+    if (e != hipSuccess || n <= 0) return e;
+    hipLaunchKernelGGL(k_validate, dim3((n + 255) / 256), dim3(256), 0, st, theta, active, list, n, S, status);
     return hipGetLastError();
 }
 
 hipError_t launch_prep(const PrepArgs& a, bool tangent, hipStream_t st) {
     if (a.pairs.n <= 0) return hipSuccess;
-    const dim3 grid((a.pairs.n + 127) / 128);
-    if (tangent) hipLaunchKernelGGL(k_prep<dual>, grid, dim3(128), 0, st, a);
-    else hipLaunchKernelGGL(k_prep<double>, grid, dim3(128), 0, st, a);
+    const dim3 grid((a.pairs.n + 3) / 4);
+    if (tangent) hipLaunchKernelGGL(k_prep<dual>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_prep<double>, grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -350,9 +373,9 @@ hipError_t launch_render(const RenderArgs& a, int wpb, hipStream_t st) {
 
 hipError_t launch_finalize(const FinArgs& a, bool tangent, hipStream_t st) {
     if (a.srcs.n <= 0) return hipSuccess;
-    const dim3 grid((a.srcs.n + 127) / 128);
-    if (tangent) hipLaunchKernelGGL(k_finalize<dual>, grid, dim3(128), 0, st, a);
-    else hipLaunchKernelGGL(k_finalize<double>, grid, dim3(128), 0, st, a);
+    const dim3 grid(a.srcs.n);
+    if (tangent) hipLaunchKernelGGL(k_finalize<dual>, grid, dim3(64), 0, st, a);
+    else hipLaunchKernelGGL(k_finalize<double>, grid, dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

@@ -131,43 +131,30 @@ __device__ inline void pair_w(const T* p, const celeste_image& im, T* w) {
 
 // Table of the 45 Gaussians (components: 3 star, then per PSF component 8 de Vaucouleurs
 // and 6 exponential) and the k1..k4 factors from the intermediates w of a pair.
+// Table entry c (0 <= c < NCOMP) of one box from its intermediates w.  Layout: the NPSF
+// star components, then per PSF component its NDEV de Vaucouleurs and NEXP exponential
+// components.  One lane per entry builds a box's table.
 template <class T>
-__device__ inline void build_from_w(const T* w, const celeste_image& im, const Consts& K, T* tab, T* coef) {
-    coef[C_K1] = w[W_K1];
-    coef[C_K2] = w[W_K2];
-    coef[C_K3] = w[W_K3];
-    coef[C_K4] = w[W_K4];
+__device__ inline void build_comp_from_w(const T* w, const celeste_image& im, const Consts& K, int c, T* e) {
     const T sxx = w[W_SXX], sxy = w[W_SXY], syy = w[W_SYY];
     const T ux = w[W_UX] - im.origin_x, uy = w[W_UY] - im.origin_y;
     const T fdev = w[W_FDEV];
-    const T fexp = 1.0 - fdev;
-    const T one = scalar_traits<T>::make(1.0, 0.0);
-    const T zero = scalar_traits<T>::make(0.0, 0.0);
-    for (int k = 0; k < NPSF; ++k) {
-        const double* ps = im.psf[k];
-        const T cx = ux + ps[1], cy = uy + ps[2];
-        write_comp(tab + k * CST, cx, cy, scalar_traits<T>::make(ps[3], 0.0),
-                   scalar_traits<T>::make(ps[4], 0.0), scalar_traits<T>::make(ps[5], 0.0),
-                   log(ps[0]), one, zero, 0.0);
-        T* g = tab + (NPSF + k * NGAL_PER_PSF) * CST;
-        for (int j = 0; j < NDEV; ++j) {
-            const double nu = K.dev_nu[j];
-            write_comp(g + j * CST, cx, cy, nu * sxx + ps[3], nu * sxy + ps[4], nu * syy + ps[5],
-                       log(ps[0] * K.dev_alpha[j]), fdev, nu * fdev, 1.0);
-        }
-        for (int j = 0; j < NEXP; ++j) {
-            const double nu = K.exp_nu[j];
-            write_comp(g + (NDEV + j) * CST, cx, cy, nu * sxx + ps[3], nu * sxy + ps[4],
-                       nu * syy + ps[5], log(ps[0] * K.exp_alpha[j]), fexp, nu * fexp, -1.0);
-        }
+    const int k = c < NPSF ? c : (c - NPSF) / NGAL_PER_PSF;
+    const double* ps = im.psf[k];
+    const T cx = ux + ps[1], cy = uy + ps[2];
+    if (c < NPSF) {
+        write_comp(e, cx, cy, scalar_traits<T>::make(ps[3], 0.0), scalar_traits<T>::make(ps[4], 0.0),
+                   scalar_traits<T>::make(ps[5], 0.0), log(ps[0]), scalar_traits<T>::make(1.0, 0.0),
+                   scalar_traits<T>::make(0.0, 0.0), 0.0);
+        return;
     }
-}
-
-template <class T>
-__device__ inline void build_pair(const T* p, const celeste_image& im, const Consts& K, T* tab, T* coef) {
-    T w[NW];
-    pair_w(p, im, w);
-    build_from_w(w, im, K, tab, coef);
+    const int j = (c - NPSF) % NGAL_PER_PSF;
+    const bool dev = j < NDEV;
+    const double nu = dev ? K.dev_nu[j] : K.exp_nu[j - NDEV];
+    const double alpha = dev ? K.dev_alpha[j] : K.exp_alpha[j - NDEV];
+    const T wt = dev ? fdev : 1.0 - fdev;
+    write_comp(e, cx, cy, nu * sxx + ps[3], nu * sxy + ps[4], nu * syy + ps[5], log(ps[0] * alpha), wt, nu * wt,
+               dev ? 1.0 : -1.0);
 }
 
 // Value-only profile sums of NPIX pixels from a double table.
