@@ -56,12 +56,14 @@ ADJ_PER_STRIP, ADJ_PER_VISIT = PASS_B_PER_STRIP, PASS_B_PER_VISIT + PIXEL_PER_VI
 GAUSS_VALUE = 13 + EXP_FLOPS
 DIRECT_ADJ_PER_VISIT = N_STAR * (GAUSS_VALUE + 5) + N_GAL * (GAUSS_VALUE + 21) + 62 + LOG_FLOPS
 DIRECT_RENDER_PER_VISIT = N_STAR * (GAUSS_VALUE + 1) + N_GAL * (GAUSS_VALUE + 2) + 12
-ADJOINT_BYTES_PER_VISIT = 24            # x, E, V read once (float64)
+# Algorithmic HBM bytes per visit of the fused adjoint: x, E, V (float64) read once, plus the
+# visit's own stored star/galaxy profile values (2 x float64) in render modes 2 and 3.
+ADJOINT_BYTES_PER_VISIT = {0: 24, 1: 24, 2: 40, 3: 40}
 
 
-def measured_traffic(kernel_launch):
-    """HBM bytes per launch of the fused adjoint from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources and launch; else None."""
+def measured_profile(kernel_launch):
+    """The committed rocprofv3 counter summary of the fused adjoint, if it was taken on the
+    current kernel sources and launch; else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "fused_adjoint_sdss_field_2000src.json")
     if not os.path.exists(path):
@@ -74,7 +76,7 @@ def measured_traffic(kernel_launch):
             h.update(fh.read())
     if prof.get("source_sha256") != h.hexdigest() or prof.get("launch") != kernel_launch:
         return None
-    return prof["bytes_per_launch"]
+    return prof
 
 
 def strip_count(f, L):
@@ -195,7 +197,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -287,11 +289,14 @@ def main():
     achieved = adj_flops / (adj_ms * 1e-3) / 1e12
     launch_str = "%d,%d,%d,%d,%d,%d" % (info["chunk"], info["waves_per_block"], info["grid_blocks"],
                                         info["dynamic_queue"], info["strip_rows"], info["render_mode"])
-    traffic = measured_traffic(launch_str)
+    prof = measured_profile(launch_str)
+    traffic = None if prof is None else prof["bytes_per_launch"]
+    counted = None if prof is None else prof["counters"][prof["kernel"]].get("fp64_flops_counted")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                 "traffic": None if traffic is None else round(traffic),
-                "traffic_algorithmic": ADJOINT_BYTES_PER_VISIT * visits,
+                "traffic_algorithmic": ADJOINT_BYTES_PER_VISIT[info["render_mode"]] * visits,
+                "counted_fp64_tflops": None if counted is None else round(counted / (adj_ms * 1e-3) / 1e12, 3),
                 "kernel": "k_adjoint_strips<double, planes, grad, L=%d> (fused own-source forward + adjoint)" % L,
                 "flops_per_launch": adj_flops, "flops_per_visit": round(adj_flops / visits, 1),
                 "visits_per_launch": visits, "strips_per_launch": strips, "avg_launch_ms": round(adj_ms, 4)}
