@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define CELESTE_ABI_VERSION 1
+#define CELESTE_ABI_VERSION 2
 
 enum celeste_status {
     CELESTE_OK = 0,
@@ -242,10 +242,14 @@ int celeste_plan_status(celeste_plan* plan, hipStream_t stream);
 /* HIP error string of the last CELESTE_EHIP on this thread. */
 const char* celeste_last_hip_error(void);
 
-/* Diagnostic: y[i] = exp(x[i]) (device arrays of n) by the table-driven exponential the
- * strip kernels use (Tang's method: 64-entry 2^(j/64) table, |r| <= ln2/128, degree-5
- * polynomial), for comparison with the device library.  x[i] <= 709, not NaN. */
-int celeste_debug_exp(const double* x, double* y, int n, hipStream_t stream);
+/* Diagnostic: the elementary functions of the strip kernels applied elementwise to device
+ * arrays of n, for comparison with a reference libm.  fn = CELESTE_FN_EXP: table-driven
+ * exp (Tang's method: 64-entry 2^(j/64) table, |r| <= ln2/128, degree-5 polynomial),
+ * x[i] <= 709 and not NaN; CELESTE_FN_LOG: table-driven log (Tang's method: 128 breakpoints
+ * in [1/2, 1), degree-6 log1p), finite x[i] > 0; CELESTE_FN_RCP: 1/x by the hardware estimate
+ * and two Newton steps, x[i] finite with a normal reciprocal.  Other fn: CELESTE_EINVAL. */
+enum { CELESTE_FN_EXP = 0, CELESTE_FN_LOG = 1, CELESTE_FN_RCP = 2 };
+int celeste_debug_math(int fn, const double* x, double* y, int n, hipStream_t stream);
 
 const char* celeste_status_string(int status);
 int celeste_version(void);

@@ -27,7 +27,7 @@ EXPORTS = ["celeste_plan_create", "celeste_plan_destroy", "celeste_plan_get_info
            "celeste_elbo_grad", "celeste_hvp", "celeste_hessian", "celeste_newton", "celeste_total_elbo",
            "celeste_color_batches", "celeste_sweep", "celeste_plan_set_launch", "celeste_autotune",
            "celeste_plan_use_graph", "celeste_plan_profile", "celeste_plan_status", "celeste_last_hip_error",
-           "celeste_status_string", "celeste_version", "celeste_debug_exp"]
+           "celeste_status_string", "celeste_version", "celeste_debug_math"]
 
 
 class celeste_image(C.Structure):
@@ -96,7 +96,7 @@ def lib():
     L.celeste_plan_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
     L.celeste_plan_status.argtypes = [vp, vp]
     L.celeste_last_hip_error.restype = C.c_char_p
-    L.celeste_debug_exp.argtypes = [dp, dp, C.c_int, vp]
+    L.celeste_debug_math.argtypes = [C.c_int, dp, dp, C.c_int, vp]
     L.celeste_status_string.argtypes = [C.c_int]
     L.celeste_status_string.restype = C.c_char_p
     _lib = L
@@ -133,11 +133,15 @@ def tr_params(radius0=1.0, radius_max=1e3, eta_accept=0.1, gtol=1e-8, newton_ste
     return p
 
 
-def debug_exp(x):
-    """Table-driven exp of the strip kernels on a float64 CUDA tensor."""
+FN_EXP, FN_LOG, FN_RCP = 0, 1, 2
+
+
+def debug_math(fn, x):
+    """The strip kernels' table-driven exp (FN_EXP), table-driven log (FN_LOG) or Newton
+    reciprocal (FN_RCP) on a float64 CUDA tensor."""
     import torch
     y = torch.empty_like(x)
-    check(lib().celeste_debug_exp(_ptr(x), _ptr(y), x.numel(), _stream()), "celeste_debug_exp")
+    check(lib().celeste_debug_math(fn, _ptr(x), _ptr(y), x.numel(), _stream()), "celeste_debug_math")
     return y
 
 

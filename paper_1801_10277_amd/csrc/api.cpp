@@ -674,9 +674,9 @@ extern "C" {
 
 int celeste_version(void) { return CELESTE_ABI_VERSION; }
 
-int celeste_debug_exp(const double* x, double* y, int n, hipStream_t st) {
-    if (!x || !y || n < 0) return CELESTE_EINVAL;
-    HIPCHK(launch_debug_exp(x, y, n, st));
+int celeste_debug_math(int fn, const double* x, double* y, int n, hipStream_t st) {
+    if (!x || !y || n < 0 || fn < CELESTE_FN_EXP || fn > CELESTE_FN_RCP) return CELESTE_EINVAL;
+    HIPCHK(launch_debug_math(fn, x, y, n, st));
     return CELESTE_OK;
 }
 

@@ -174,7 +174,7 @@ hipError_t launch_render(const RenderArgs& a, int waves_per_block, hipStream_t s
 hipError_t launch_adjoint(const AdjArgs& a, bool tangent, int base_mode, bool deriv, int grid,
                           int waves_per_block, int strip_rows, hipStream_t st);
 hipError_t launch_background(const BgArgs& a, int grid, int waves_per_block, int strip_rows, hipStream_t st);
-hipError_t launch_debug_exp(const double* x, double* y, int n, hipStream_t st);
+hipError_t launch_debug_math(int fn, const double* x, double* y, int n, hipStream_t st);
 hipError_t launch_pair_lgamma(const Geometry& g, int n_pairs, double* out, hipStream_t st);
 hipError_t launch_fill_planes(const celeste_image* images, int n_img, int max_pix, double* E, double* V,
                               const int* status, hipStream_t st);

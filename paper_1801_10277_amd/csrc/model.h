@@ -51,6 +51,59 @@ __device__ __forceinline__ dual fexp(dual x, const double* __restrict__ t2) {
     return mkd(e, e * x.t);
 }
 
+// Table-driven natural logarithm (after P. T. P. Tang, "Table-driven implementation of the
+// logarithm function in IEEE floating-point arithmetic", ACM TOMS 16(4), 1990), for finite
+// x > 0: x = 2^m y with y in [1/2, 1); F_j = 1/2 + (j + 1/2)/256 is the nearest of 128
+// breakpoints (j = the top 7 fraction bits of y), f = y - F_j is exact, and
+// log x = m ln2 + log F_j + log1p(f / F_j) with |f / F_j| <= 1/256, log1p by its degree-6
+// Taylor polynomial (truncation < 2.1e-18).  tl[j] = (1 / F_j, log F_j) lives in LDS
+// (fill_log_table).  Relative error a few ulps away from x = 1; near x = 1 the error is a
+// few 1e-16 absolute (the m ln2 and log F_j terms cancel there).
+constexpr double LN2_HI = 6.93147180369123816490e-01;       // ln 2, leading 32 bits
+constexpr double LN2_LO = 1.90821492927058770002e-10;       // ln 2 - LN2_HI
+
+__device__ __forceinline__ void fill_log_table(double2* tl) {
+    for (int j = threadIdx.x; j < 128; j += blockDim.x) {
+        const double F = 0.5 + (j + 0.5) * (1.0 / 256.0);
+        tl[j] = make_double2(1.0 / F, log(F));
+    }
+}
+
+__device__ __forceinline__ double flog(double x, const double2* __restrict__ tl) {
+    const double y = __builtin_amdgcn_frexp_mant(x);
+    const int m = __builtin_amdgcn_frexp_exp(x);
+    const int j = (int)((unsigned)__double2hiint(y) >> 13) & 127;
+    const double F = fma((double)j, 1.0 / 256.0, 0.5 + 1.0 / 512.0);
+    const double2 t = tl[j];
+    const double r = (y - F) * t.x;
+    double p = fma(r, -1.0 / 6.0, 1.0 / 5.0);
+    p = fma(p, r, -0.25);
+    p = fma(p, r, 1.0 / 3.0);
+    p = fma(p, r, -0.5);
+    p = fma(p * r, r, r);
+    const double md = (double)m;
+    return fma(md, LN2_HI, t.y) + fma(md, LN2_LO, p);
+}
+
+// 1 / x for finite x whose reciprocal is a normal number: the hardware estimate refined by
+// two Newton steps (each doubles the correct bits), within an ulp or so of the quotient.
+__device__ __forceinline__ double frcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ dual flog(dual x, const double2* __restrict__ tl) {
+    return mkd(flog(x.v, tl), x.t * frcp(x.v));
+}
+
+__device__ __forceinline__ dual frcp(dual x) {
+    const double r = frcp(x.v);
+    return mkd(r, -x.t * (r * r));
+}
+
 template <class T>
 __device__ inline T seed(const double* theta, const double* dir, int dir_mode, int dir_unit,
                          int s, int i) {

@@ -143,11 +143,12 @@ __device__ __forceinline__ void strip_adjoint(const T* __restrict__ tab, double 
 // weights d l / d f_star and d l / d f_gal.
 // (The -log(x!) constant is not added here: each box's sum of it is precomputed once.)
 template <class T, bool DERIV>
-__device__ __forceinline__ void strip_pixel(double x, T E, T V, T fs, T fg, const T* k, T* acc, T& Gs, T& Gg) {
+__device__ __forceinline__ void strip_pixel(double x, T E, T V, T fs, T fg, const T* k, T* acc, T& Gs, T& Gg,
+                                            const double2* __restrict__ tl) {
     const T Es = k[C_K1] * fs + k[C_K2] * fg;
-    const T inv = 1.0 / E;
+    const T inv = frcp(E);
     const T r = V * inv * inv;
-    acc[A_VAL] += x * (log(E) - 0.5 * r) - E;
+    acc[A_VAL] += x * (flog(E, tl) - 0.5 * r) - E;
     if (DERIV) {
         const T lE = x * inv * (1.0 + r) - 1.0;
         const T lV = -0.5 * x * (inv * inv);
@@ -299,6 +300,8 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
                                                         double* __restrict__ partials) {
     if (*a.status) return;
     __shared__ double t2[64];
+    __shared__ double2 tl[128];
+    fill_log_table(tl);
     fill_exp_table(t2);
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -359,7 +362,7 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
                                 E = Eb[kk] + Es;
                                 V = Vb[kk] + Vs;
                             }
-                            strip_pixel<T, true>(cx_, E, V, fsk, fgk, k, acc, gs, gg);
+                            strip_pixel<T, true>(cx_, E, V, fsk, fgk, k, acc, gs, gg, tl);
                         }
                         Gs[kk] = gs;
                         Gg[kk] = gg;
@@ -371,6 +374,53 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
                         __builtin_amdgcn_sched_barrier(0);
                     }
                     strip_adjoint<T, L>(tab, px, py0, Gs, Gg, acc, t2);
+                    continue;
+                }
+                if constexpr (DERIV && !FGM && (BASE == BASE_PLANES || BASE == BASE_BG)) {
+                    // Own values from pass A, then the pixel rows streamed as above.
+                    T fs[L], fg[L];
+                    strip_values<T, L>(tab, px, py0, fs, fg, t2);
+                    const double* xs_i = xs + im.pix_offset;
+                    auto row_load = [&](int rr, double& x_, double& e_, double& v_) {
+                        const size_t gi = (size_t)(r0 + rr) * im.W + c;
+                        x_ = xs_i[gi];
+                        if constexpr (BASE == BASE_PLANES) {
+                            e_ = Ep[im.pix_offset + gi];
+                            v_ = Vp[im.pix_offset + gi];
+                        } else {
+                            const size_t vi = (size_t)p.visit_off + (size_t)(r0 + rr - p.r0) * p.w + (c - p.c0);
+                            e_ = bg[2 * vi];
+                            v_ = bg[2 * vi + 1];
+                        }
+                    };
+                    double cx_, ce_, cv_;
+                    row_load(0, cx_, ce_, cv_);
+#pragma unroll
+                    for (int kk = 0; kk < L; ++kk) {
+                        double nx_ = 0.0, ne_ = 0.0, nv_ = 0.0;
+                        if (kk + 1 < L) row_load(kk + 1 < nrow ? kk + 1 : 0, nx_, ne_, nv_);
+                        T gs = zero, gg = zero;
+                        if (kk < nrow && cx_ == cx_) {
+                            const T Es = k[C_K1] * fs[kk] + k[C_K2] * fg[kk];
+                            const T Vs = k[C_K3] * (fs[kk] * fs[kk]) + k[C_K4] * (fg[kk] * fg[kk]) - Es * Es;
+                            T E, V;
+                            if constexpr (BASE == BASE_PLANES) {
+                                E = value_with_tangent(ce_, Es);
+                                V = value_with_tangent(cv_, Vs);
+                            } else {
+                                E = ce_ + Es;
+                                V = cv_ + Vs;
+                            }
+                            strip_pixel<T, true>(cx_, E, V, fs[kk], fg[kk], k, acc, gs, gg, tl);
+                        }
+                        fs[kk] = gs;
+                        fg[kk] = gg;
+                        cx_ = nx_;
+                        ce_ = ne_;
+                        cv_ = nv_;
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    strip_adjoint<T, L>(tab, px, py0, fs, fg, acc, t2);
                     continue;
                 }
                 double x[L], Eb[L], Vb[L];
@@ -400,7 +450,7 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
                         if (!(x[kk] == x[kk])) continue;
                         T gs, gg;
                         strip_pixel<T, false>(x[kk], scalar_traits<T>::make(Eb[kk], 0.0),
-                                              scalar_traits<T>::make(Vb[kk], 0.0), zero, zero, k, acc, gs, gg);
+                                              scalar_traits<T>::make(Vb[kk], 0.0), zero, zero, k, acc, gs, gg, tl);
                     }
                     continue;
                 }
@@ -432,7 +482,7 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
                             E = Eb[kk] + Es;
                             V = Vb[kk] + Vs;
                         }
-                        strip_pixel<T, DERIV>(x[kk], E, V, fs[kk], fg[kk], k, acc, gs, gg);
+                        strip_pixel<T, DERIV>(x[kk], E, V, fs[kk], fg[kk], k, acc, gs, gg, tl);
                     }
                     fs[kk] = gs;
                     fg[kk] = gg;
@@ -592,18 +642,23 @@ __global__ void __launch_bounds__(256) k_gather_planes(RenderArgs a, const TileD
     }
 }
 
-// Elementwise table-driven exp, for testing it against the device library.
-__global__ void __launch_bounds__(256) k_debug_exp(const double* __restrict__ x, double* __restrict__ y, int n) {
+// Elementwise table-driven exp (fn 0), table-driven log (fn 1) and Newton reciprocal (fn 2),
+// for testing them against the host's libm.
+__global__ void __launch_bounds__(256) k_debug_math(int fn, const double* __restrict__ x, double* __restrict__ y,
+                                                    int n) {
     __shared__ double t2[64];
+    __shared__ double2 tl[128];
+    fill_log_table(tl);
     fill_exp_table(t2);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = fexp(x[i], t2);
+    if (i >= n) return;
+    y[i] = fn == 0 ? fexp(x[i], t2) : fn == 1 ? flog(x[i], tl) : frcp(x[i]);
 }
 
 // ----------------------------------------------------------------------- launchers
-hipError_t launch_debug_exp(const double* x, double* y, int n, hipStream_t st) {
+hipError_t launch_debug_math(int fn, const double* x, double* y, int n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_debug_exp, dim3((n + 255) / 256), dim3(256), 0, st, x, y, n);
+    hipLaunchKernelGGL(k_debug_math, dim3((n + 255) / 256), dim3(256), 0, st, fn, x, y, n);
     return hipGetLastError();
 }
 

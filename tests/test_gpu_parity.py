@@ -247,10 +247,30 @@ def test_table_exp_accuracy(B):
                         rng.uniform(-1e-3, 1e-3, 10000), [0.0, -0.0, 1.0, -1.0, 700.0, -700.0, -744.0, 709.0],
                         np.log(2.0) / 64 * np.arange(-200, 200)])
     say("case table exp", x.size)
-    y = B.debug_exp(torch.tensor(x, device="cuda")).cpu().numpy()
+    y = B.debug_math(B.FN_EXP, torch.tensor(x, device="cuda")).cpu().numpy()
     ref = np.exp(x)
     normal = ref >= 2.2250738585072014e-308
     ulp = np.spacing(ref[normal])
     err = np.abs(y[normal] - ref[normal]) / ulp
     assert err.max() <= 4.0, err.max()
     assert np.all(np.abs(y[~normal] - ref[~normal]) <= 4 * 5e-324)
+
+
+def test_table_log_and_reciprocal_accuracy(B):
+    """The pixel term's table-driven log and Newton reciprocal against the host libm."""
+    rng = np.random.default_rng(10)
+    x = np.concatenate([np.exp(rng.uniform(-700.0, 700.0, 200000)), rng.uniform(50.0, 1e5, 200000),
+                        rng.uniform(0.25, 4.0, 100000), [1.0, 2.0, 0.5, 1e-300, 1e300, 3.0, 7.0],
+                        0.5 + (np.arange(128) + 0.5) / 256.0, 0.5 + np.arange(129) / 256.0])
+    say("case table log / rcp", x.size)
+    xd = torch.tensor(x, device="cuda")
+    lg = B.debug_math(B.FN_LOG, xd).cpu().numpy()
+    ref = np.log(x)
+    # a few ulps relative; near x = 1 the m ln2 and log F terms cancel: a few 1e-16 absolute
+    err = np.abs(lg - ref)
+    assert np.all(err <= 4 * np.spacing(np.abs(ref)) + 4e-16), (err / np.maximum(np.spacing(np.abs(ref)), 1e-300)).max()
+    far = np.abs(x - 1.0) > 0.5
+    assert (err[far] / np.spacing(np.abs(ref[far]))).max() <= 4.0
+    rc = B.debug_math(B.FN_RCP, xd).cpu().numpy()
+    ok = np.abs(x) < 1e307
+    assert np.all(np.abs(rc[ok] - 1.0 / x[ok]) <= 1.0 * np.spacing(1.0 / x[ok]))
