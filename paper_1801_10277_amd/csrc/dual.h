@@ -50,12 +50,24 @@ __host__ __device__ inline double tangent_of(dual x) { return x.t; }
 __host__ __device__ inline double value_with_tangent(double base, double) { return base; }
 __host__ __device__ inline dual value_with_tangent(double base, dual own) { return mkd(base, own.t); }
 
+// Unroll factor of the loops over the 42 galaxy Gaussians.  Value arithmetic: two at a
+// time, so that one component's table loads and seed overlap the other's rows (measured
+// best of 1, 2, 3, 6).  Dual (value + tangent) arithmetic keeps one: its kernels already
+// hold 256 VGPRs plus accumulation registers, and the two-at-a-time fused adjoint with
+// neighbour backgrounds at 16-row strips returned wrong tangents (values correct) in a
+// build whose only difference was this factor.
+#ifndef CELESTE_GAL_UNROLL
+#define CELESTE_GAL_UNROLL 2
+#endif
+
 template <class T> struct scalar_traits;
 template <> struct scalar_traits<double> {
     static constexpr int width = 1;
+    static constexpr int gal_unroll = CELESTE_GAL_UNROLL;
     __host__ __device__ static double make(double v, double) { return v; }
 };
 template <> struct scalar_traits<dual> {
     static constexpr int width = 2;
+    static constexpr int gal_unroll = 1;
     __host__ __device__ static dual make(double v, double t) { return mkd(v, t); }
 };

@@ -5,10 +5,6 @@
 #pragma once
 #include "internal.h"
 
-#ifndef CELESTE_GAL_UNROLL
-#define CELESTE_GAL_UNROLL 1
-#endif
-
 namespace cel {
 
 // log flux_b = log r + sum_k BSIGN[b][k] c_k with c_k = log(flux_{k+1} / flux_k),

@@ -64,7 +64,7 @@ __device__ __forceinline__ void strip_values(const T* __restrict__ tab, double p
             }
         }
     }
-#pragma unroll CELESTE_GAL_UNROLL
+#pragma unroll scalar_traits<T>::gal_unroll
     for (int c = NPSF; c < NCOMP; ++c) {
         const T* e = tab + c * CST;
         T n, rt, pdx0, pdy0;
@@ -109,7 +109,7 @@ __device__ __forceinline__ void strip_adjoint(const T* __restrict__ tab, double 
         acc[A_UX] += pdxc * m0 + e[F_PXY] * m1;
         acc[A_UY] += pdyc * m0 + e[F_PYY] * m1;
     }
-#pragma unroll CELESTE_GAL_UNROLL
+#pragma unroll scalar_traits<T>::gal_unroll
     for (int c = NPSF; c < NCOMP; ++c) {
         const T* e = tab + c * CST;
         T n, rt, pdx0, pdy0;
