@@ -28,26 +28,31 @@ METRIC = "source-pixel ELBO+grad evals/s (FP64), % FP64 peak; batched vs plain a
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector peak (vendor figure)
 
 # Algorithmic FP64 operations, counted from the formulas the kernels evaluate (add, sub,
-# mul, div = 1 each).  exp in the strip seeds is the table-driven exp (64/ln2 scaling,
-# two-part reduction, degree-5 polynomial, table product: 16 FLOPs); elsewhere exp = 27
+# mul, div = 1 each, FMA = 2).  The strip kernels' own elementary functions: table-driven
+# exp (64/ln2 scaling, two-part reduction, degree-5 polynomial, table product: 16 FLOPs),
+# table-driven log (breakpoint, reduced argument, degree-6 log1p, m ln2 recombination:
+# 20 FLOPs), reciprocal (hardware estimate + two Newton steps: 9 FLOPs).  Elsewhere exp = 27
 # and log = 78, the FP64 operations of one call of the ROCm device library's exp and log on
 # gfx950 (read from this build's ISA).
 EXP_FLOPS = 27
-FEXP_FLOPS = 16
 LOG_FLOPS = 78
+FEXP_FLOPS = 16
+FLOG_FLOPS = 20
+FRCP_FLOPS = 9
 N_STAR, N_GAL = 3, 42                   # Gaussians per (source, image): 3 star, 3 x (8 + 6) galaxy
 
 # Strip algorithm (what runs): per strip of L rows and per Gaussian, the value and the
 # first row ratio at the top row (2 exps + 16 FLOPs), then per row 2 multiplies for the
 # recurrence plus the accumulation.  Pass A (profile values) runs in the render's strip
-# pass and its values are stored; the fused adjoint runs the pixel terms and pass B
-# (seed again, 3 moment accumulations per row, a fold per strip).
+# pass and its values are stored; the fused adjoint runs the pixel terms and pass B (seed
+# again; per row one FMA and one (star) or two (galaxy) running-sum adds; per strip the
+# moments from the running sums and the fold into the ten intermediates).
 SEED = 16 + 2 * FEXP_FLOPS
 PASS_A_PER_STRIP = (N_STAR + N_GAL) * SEED
 PASS_A_PER_VISIT = N_STAR * 3 + N_GAL * 4
-PASS_B_PER_STRIP = (N_STAR + N_GAL) * SEED + N_STAR * 12 + N_GAL * 46
-PASS_B_PER_VISIT = N_STAR * 6 + N_GAL * 8
-PIXEL_PER_VISIT = 46 + LOG_FLOPS
+PASS_B_PER_STRIP = (N_STAR + N_GAL) * SEED + N_STAR * 14 + N_GAL * 53
+PASS_B_PER_VISIT = N_STAR * 5 + N_GAL * 6
+PIXEL_PER_VISIT = 40 + FLOG_FLOPS + FRCP_FLOPS
 GATHER_PER_VISIT = 11
 RENDER_PER_STRIP, RENDER_PER_VISIT = PASS_A_PER_STRIP, PASS_A_PER_VISIT + GATHER_PER_VISIT
 ADJ_PER_STRIP, ADJ_PER_VISIT = PASS_B_PER_STRIP, PASS_B_PER_VISIT + PIXEL_PER_VISIT
