@@ -32,6 +32,32 @@ def clone(f):
     return copy.deepcopy(f)
 
 
+def _boxes_meet(a, b):
+    return (a[0] == b[0] and a[1] < b[1] + b[3] and b[1] < a[1] + a[3] and a[2] < b[2] + b[4]
+            and b[2] < a[2] + a[4])
+
+
+def neighbourhood(f, s, theta=None):
+    """Source s with every source that has a box meeting one of s's boxes (same image), in
+    their original order, over the same images: (sub-field, index of s in it).  Pixels of
+    s's boxes see exactly these sources, so s's ELBO, gradient and Newton steps (others
+    fixed) are those of the full field."""
+    th = f.theta if theta is None else theta
+    ptr = np.asarray(f.patch_ptr)
+    mine = f.boxes[ptr[s]:ptr[s + 1]]
+    keep = []
+    for t in range(f.n_src):
+        if t == s or any(_boxes_meet(a, b) for a in mine for b in f.boxes[ptr[t]:ptr[t + 1]]):
+            keep.append(t)
+    g = copy.copy(f)
+    g.theta = np.ascontiguousarray(th[keep])
+    g.boxes = np.ascontiguousarray(np.concatenate([f.boxes[ptr[t]:ptr[t + 1]] for t in keep]))
+    counts = [ptr[t + 1] - ptr[t] for t in keep]
+    g.patch_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    g.truth = {}
+    return g, keep.index(s)
+
+
 def single_source(synth, size=41, side=None, star=True, q=None, seed=3, psf_sigmas=None,
                   psf_weights=None, center=None, shape=None, sky=150.0, n_bands=1, band0=2,
                   r_var=0.01, c_var=0.01):

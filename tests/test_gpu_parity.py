@@ -224,20 +224,24 @@ def test_masked_pixels(B, O, synth):
 
 
 def test_config2_full_size_sampled(B, O, synth):
-    """Full field at the autotuned launch configuration used by the benchmark."""
+    """Full field at the benchmark's launch configuration (plan default, graph replay), then
+    at the autotuned one."""
     f = synth.make_config(2)
     plan = B.Plan(f)
     theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
-    plan.autotune(theta, reps=1)
-    plan.use_graph(True)
-    say("case config2 full", plan.info())
-    e, g = plan.elbo_grad(theta)
-    e, g = e.cpu().numpy(), g.cpu().numpy()
     P = O.Problem(f)
-    for s in [0, 517, 1999]:
-        val, gref, gabs = O.source_grad(P, s)
-        within(np.array([e[s]]), np.array([val[0] + val[1]]), np.array([abs(val[2]) + abs(val[1])]), "c2 elbo")
-        within(g[s, :27], gref, gabs, "c2 grad s=%d" % s)
+    refs = {s: O.source_grad(P, s) for s in [0, 517, 1999]}
+    for tuned in (False, True):
+        if tuned:
+            plan.autotune(theta, reps=1)
+        plan.use_graph(True)
+        say("case config2 full", "autotuned" if tuned else "default", plan.info())
+        e, g = plan.elbo_grad(theta)
+        e, g = e.cpu().numpy(), g.cpu().numpy()
+        for s, (val, gref, gabs) in refs.items():
+            within(np.array([e[s]]), np.array([val[0] + val[1]]), np.array([abs(val[2]) + abs(val[1])]), "c2 elbo")
+            within(g[s, :27], gref, gabs, "c2 grad s=%d" % s)
+        plan.use_graph(False)
 
 
 def test_table_exp_accuracy(B):

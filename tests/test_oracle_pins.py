@@ -471,3 +471,18 @@ def test_masked_pixels_are_skipped(synth, O):
     E, V = O.render(P, f, 0)
     term_x = v0[0] - v2[0]       # x * (log E - V / 2E^2) part for the original count
     np.testing.assert_allclose(v0[0] - v1[0], term_x - E.ravel()[k], rtol=1e-9)
+
+
+def test_neighbourhood_reduction_keeps_source_terms(synth, O):
+    """The test-side reduction to a source's overlapping neighbours leaves its ELBO and
+    gradient unchanged (every pixel of its boxes sees the same sources)."""
+    from conftest import neighbourhood
+    f = synth.make_config(1)
+    P = O.Problem(f)
+    for s in (0, 9):
+        g, j = neighbourhood(f, s)
+        assert 1 <= g.n_src <= f.n_src
+        v_full, g_full, _ = O.source_grad(P, s)
+        v_sub, g_sub, _ = O.source_grad(O.Problem(g), j)
+        np.testing.assert_allclose(v_sub, v_full, rtol=1e-15, atol=0)
+        np.testing.assert_allclose(g_sub, g_full, rtol=1e-14, atol=1e-14 * np.abs(g_full).max())
