@@ -88,6 +88,7 @@ struct celeste_plan {
     double* d_tab2 = nullptr;    // dual tables
     double* d_coef2 = nullptr;
     double* d_partials = nullptr;
+    double* d_kk = nullptr;          // [cap_items][NKK] brightness-factor Hessian blocks
     double* d_E = nullptr;
     double* d_V = nullptr;
     double* d_bg = nullptr;
@@ -460,8 +461,10 @@ int render(celeste_plan* p, hipStream_t st) {
     return CELESTE_OK;
 }
 
+// kk: also the brightness-factor block of every box's intermediate Hessian (double gradient
+// passes that precede hessian_from_intermediates).
 int adjoint(celeste_plan* p, const Sel& items, const uint8_t* active, bool tangent, int base, bool deriv,
-            hipStream_t st, int grid_override = 0) {
+            hipStream_t st, int grid_override = 0, bool kk = false) {
     AdjArgs a{};
     a.g = p->geom();
     a.items = items;
@@ -478,6 +481,7 @@ int adjoint(celeste_plan* p, const Sel& items, const uint8_t* active, bool tange
     if (base == BASE_PLANES && p->render_mode == 3) base = BASE_FG;
     a.fg = ((base == BASE_PLANES || base == BASE_FG) && p->fg_valid) ? p->d_fg : nullptr;
     a.partials = p->d_partials;
+    a.kk = kk ? p->d_kk : nullptr;
     a.status = p->d_status;
     const int grid = grid_override > 0 ? grid_override : p->persistent_grid();
     HIPCHK(launch_adjoint(a, tangent, base, deriv, grid, p->wpb, p->rows, st));
@@ -524,10 +528,10 @@ int background(celeste_plan* p, const Sel& items, hipStream_t st) {
 }
 
 // Dense Hessians of the listed sources (d_hess by list position).  Expects the item
-// partials of a double gradient pass over `item` in d_partials.  Ten tangent passes along
-// the boxes' intermediates (brightness factors, position, frac_dev, shape covariance)
-// give each box's 10x10 Hessian of its pixel terms; the chain rule and its tangent
-// assemble the 27x27 blocks.
+// partials and brightness-factor blocks (kk) of a double gradient pass over `item`.  With
+// six tangent passes along the boxes' other intermediates (position, frac_dev, shape
+// covariance) they give each box's 10x10 Hessian of its pixel terms; the chain rule and
+// its tangent assemble the 27x27 blocks.
 int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& src, const Sel& pair, const Sel& item,
                                int base, hipStream_t st);
 
@@ -618,11 +622,15 @@ int fill_f64(double* d, const Sel& srcs, double v, hipStream_t st) {
 
 int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& src, const Sel& pair, const Sel& item,
                                int base, hipStream_t st) {
-    HIPCHK(launch_pair_reduce(pair, p->d_pairs, p->d_partials, false, 0, p->d_gw, p->d_hw, p->d_status, st));
-    for (int i = 0; i < 10; ++i) {
+    HIPCHK(launch_pair_reduce(pair, p->d_pairs, p->d_partials, p->d_kk, false, 0, p->d_gw, p->d_hw, p->d_status,
+                              st));
+    // the brightness-factor block came with the gradient pass; tangent passes along the six
+    // position / frac_dev / shape intermediates give the rest (by symmetry, their k rows too)
+    for (int i = W_UX; i < NW; ++i) {
         CHK(prep(p, theta, pair, true, DIR_W, nullptr, i, st));
         CHK(adjoint(p, item, nullptr, true, base, true, st));
-        HIPCHK(launch_pair_reduce(pair, p->d_pairs, p->d_partials, true, i, p->d_gw, p->d_hw, p->d_status, st));
+        HIPCHK(launch_pair_reduce(pair, p->d_pairs, p->d_partials, nullptr, true, i, p->d_gw, p->d_hw, p->d_status,
+                                  st));
     }
     HIPCHK(launch_assemble_hessian(src, p->geom(), p->d_patch_ptr, theta, p->d_gw, p->d_hw, p->d_hess, p->d_status,
                                    st));
@@ -653,7 +661,7 @@ int newton_run(celeste_plan* p, double* theta, const Sel& src, const Sel& pair, 
     tr.status = p->d_status;
     for (int it = 0; it < n_steps; ++it) {
         CHK(prep(p, theta, pair, false, DIR_NONE, nullptr, 0, st));
-        CHK(adjoint(p, item, nullptr, false, BASE_BG, true, st));
+        CHK(adjoint(p, item, nullptr, false, BASE_BG, true, st, 0, true));
         CHK(finalize(p, theta, src, nullptr, false, DIR_NONE, nullptr, 0, true, p->d_elbo_cur, p->d_grad, nullptr,
                      0, false, st));
         CHK(hessian_from_intermediates(p, theta, src, pair, item, BASE_BG, st));
@@ -702,7 +710,7 @@ void celeste_plan_destroy(celeste_plan* p) {
                     p->d_tile_sums, p->d_status, p->d_counter, p->d_grad, p->d_hess, p->d_theta_trial,
                     p->d_pred, p->d_elbo_cur, p->d_elbo_trial, p->d_radius, p->d_done, p->d_list_src,
                     p->d_list_pair, p->d_list_item, p->d_cls_items, p->d_pair_lgamma, p->d_fg, p->d_gw,
-                    p->d_hw};
+                    p->d_hw, p->d_kk};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -780,6 +788,7 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     A(dalloc(&p->d_tab2, np * NCOMP * CST * 2, W));
     A(dalloc(&p->d_coef2, np * NCOEF * 2, W));
     A(dalloc(&p->d_partials, max_items * NACC * 2, W));
+    A(dalloc(&p->d_kk, max_items * NKK, W));
     A(dalloc(&p->d_E, (size_t)p->n_pix, W));
     A(dalloc(&p->d_V, (size_t)p->n_pix, W));
     A(dalloc(&p->d_bg, (size_t)p->n_visits * 2, W));
@@ -1015,7 +1024,7 @@ int celeste_hessian(celeste_plan* p, const double* theta, const int32_t* src, in
     CHK(validate_theta(p, theta, nullptr, nullptr, p->n_src, st));
     CHK(prep(p, theta, all.pair, false, DIR_NONE, nullptr, 0, st));
     CHK(render(p, st));
-    CHK(adjoint(p, si, nullptr, false, BASE_PLANES, true, st));
+    CHK(adjoint(p, si, nullptr, false, BASE_PLANES, true, st, 0, true));
     CHK(hessian_from_intermediates(p, theta, ss, sp, si, BASE_PLANES, st));
     HIPCHK(hipMemcpyAsync(hess, p->d_hess, (size_t)n * NP * NP * sizeof(double), hipMemcpyDeviceToDevice, st));
     return CELESTE_OK;

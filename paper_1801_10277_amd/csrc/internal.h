@@ -45,6 +45,16 @@ enum AccField {
     NACC
 };
 
+// Intermediate quantities of one (source, image) pair through which the pixel terms depend
+// on the source's parameters: the brightness factors k1..k4, the position, frac_dev and the
+// galaxy shape covariance.  The order matches the accumulators A_K1..A_SYY (index + 1).
+enum WField { W_K1 = 0, W_K2, W_K3, W_K4, W_UX, W_UY, W_FDEV, W_SXX, W_SXY, W_SYY, NW };
+
+// Second derivatives of a box's pixel sum in its brightness factors k1..k4 (the k-block of
+// the intermediate Hessian): (k1k1, k1k2, k2k2, k1k3, k1k4, k2k3, k2k4); the (k3, k4) block
+// is zero.  Stored per work item with one pad entry.
+enum KKField { KK_11, KK_12, KK_22, KK_13, KK_14, KK_23, KK_24, NKK_USED, NKK = 8 };
+
 struct PairDev {              // one box (source, image)
     int32_t src, img, r0, c0, h, w;
     int64_t visit_off;        // first visit of the box in the global visit numbering
@@ -133,6 +143,8 @@ struct AdjArgs {
     const double* bg;          // [n_visits][2]
     const double* fg;          // [n_visits][2] own profile values from the render, or null
     double* partials;          // [n_items_total][NACC] of T
+    double* kk;                // [n_items_total][NKK]: brightness-factor block of the box's
+                               // intermediate Hessian (double gradient passes), or null
     const int* status;
 };
 
@@ -191,11 +203,11 @@ hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st);
 hipError_t launch_fill_u8_sel(uint8_t* p, const Sel& s, uint8_t v, hipStream_t st);
 hipError_t launch_fill_f64_sel(double* p, const Sel& s, double v, hipStream_t st);
 
-// Per-box sums of item partials: value parts into gw[pair][NACC] (double pass) or the
-// tangent parts of accumulators 1..10 into hw[pair][dir][10] (tangent pass along a
-// pair-intermediate direction).
-hipError_t launch_pair_reduce(const Sel& pairs, const PairDev* dpairs, const double* partials, bool tangent, int dir,
-                              double* gw, double* hw, const int* status, hipStream_t st);
+// Per-box sums of item partials: value parts into gw[pair][NACC] and, with kk, the k-block
+// hw[pair][0..3][0..3] (double pass), or the tangent parts of accumulators 1..10 into
+// hw[pair][dir][10] (tangent pass along a pair-intermediate direction).
+hipError_t launch_pair_reduce(const Sel& pairs, const PairDev* dpairs, const double* partials, const double* kk,
+                              bool tangent, int dir, double* gw, double* hw, const int* status, hipStream_t st);
 // 27x27 Hessians of the listed sources (hess by list position) from gw, hw and the KL.
 hipError_t launch_assemble_hessian(const Sel& srcs, const Geometry& g, const int32_t* patch_ptr,
                                    const double* theta, const double* gw, const double* hw, double* hess,

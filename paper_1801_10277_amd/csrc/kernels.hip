@@ -235,7 +235,8 @@ __global__ void __launch_bounds__(64) k_finalize(FinArgs a) {
 
 // Per-box sums of the item partials (fixed order).
 __global__ void __launch_bounds__(128) k_pair_reduce(Sel sel, const PairDev* __restrict__ pairs,
-                                                     const double* __restrict__ partials, int tangent, int dir,
+                                                     const double* __restrict__ partials,
+                                                     const double* __restrict__ kk, int tangent, int dir,
                                                      double* __restrict__ gw, double* __restrict__ hw,
                                                      const int* status) {
     if (*status) return;
@@ -260,6 +261,20 @@ __global__ void __launch_bounds__(128) k_pair_reduce(Sel sel, const PairDev* __r
     } else {
         double* o = gw + (size_t)pi * NACC;
         for (int f = 0; f < NACC; ++f) o[f] = z[f];
+        if (kk) {
+            // brightness-factor block hw[pair][0..3][0..3] (symmetric; the (k3, k4) block is 0)
+            double h[NKK_USED];
+            for (int f = 0; f < NKK_USED; ++f) h[f] = 0.0;
+            for (int it = pd.item_begin; it < pd.item_end; ++it)
+                for (int f = 0; f < NKK_USED; ++f) h[f] += kk[(size_t)it * NKK + f];
+            const double blk[4][4] = {{h[KK_11], h[KK_12], h[KK_13], h[KK_14]},
+                                      {h[KK_12], h[KK_22], h[KK_23], h[KK_24]},
+                                      {h[KK_13], h[KK_23], 0.0, 0.0},
+                                      {h[KK_14], h[KK_24], 0.0, 0.0}};
+            double* hb = hw + (size_t)pi * NW * NW;
+            for (int i = 0; i < 4; ++i)
+                for (int f = 0; f < 4; ++f) hb[i * NW + f] = blk[i][f];
+        }
     }
 }
 
@@ -291,7 +306,14 @@ __global__ void __launch_bounds__(128) k_assemble_hessian(Sel srcs, Geometry g, 
         z[A_VAL] = mkd(gz[A_VAL], 0.0);
         for (int a = 0; a < NW; ++a) {
             double tz = 0.0;
-            for (int i = 0; i < NW; ++i) tz += h[i * NW + a] * w[i].t;
+            // hw[dir][f] = c_f d2L / dw_dir dw_f with c = 2 for the A_SXX, A_SYY accumulators
+            // and 1 otherwise.  Rows 0..3 (brightness directions) hold only their k-block; the
+            // rest of those rows is c_a times the symmetric entry of the tangent pass along a.
+            for (int i = 0; i < NW; ++i) {
+                const double hia = (i < 4 && a >= 4) ? (a == W_SXX || a == W_SYY ? 2.0 : 1.0) * h[a * NW + i]
+                                                     : h[i * NW + a];
+                tz += hia * w[i].t;
+            }
             z[a + 1] = mkd(gz[a + 1], tz);
         }
         chain_pair<dual>(p, im, z, gh);
@@ -397,10 +419,10 @@ hipError_t launch_fill_f64_sel(double* p, const Sel& s, double v, hipStream_t st
     return hipGetLastError();
 }
 
-hipError_t launch_pair_reduce(const Sel& sel, const PairDev* dpairs, const double* partials, bool tangent, int dir,
-                              double* gw, double* hw, const int* status, hipStream_t st) {
+hipError_t launch_pair_reduce(const Sel& sel, const PairDev* dpairs, const double* partials, const double* kk,
+                              bool tangent, int dir, double* gw, double* hw, const int* status, hipStream_t st) {
     if (sel.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pair_reduce, dim3((sel.n + 127) / 128), dim3(128), 0, st, sel, dpairs, partials,
+    hipLaunchKernelGGL(k_pair_reduce, dim3((sel.n + 127) / 128), dim3(128), 0, st, sel, dpairs, partials, kk,
                        tangent ? 1 : 0, dir, gw, hw, status);
     return hipGetLastError();
 }

@@ -157,10 +157,6 @@ __device__ inline void write_comp(T* e, T cx, T cy, T sxx, T sxy, T syy, double 
     e[F_RDY] = exp(-(sxx * inv));
 }
 
-// Intermediate quantities of one (source, image) pair through which the pixel terms depend
-// on the source's parameters: the brightness factors k1..k4, the position, frac_dev and the
-// galaxy shape covariance.  The order matches the accumulators A_K1..A_SYY (index + 1).
-enum WField { W_K1 = 0, W_K2, W_K3, W_K4, W_UX, W_UY, W_FDEV, W_SXX, W_SXY, W_SYY, NW };
 
 template <class T>
 __device__ inline void pair_w(const T* p, const celeste_image& im, T* w) {

@@ -168,6 +168,30 @@ __device__ __forceinline__ void strip_pixel(double x, T E, T V, T fs, T fg, cons
     }
 }
 
+// Second derivatives of one pixel term in the box's brightness factors k1..k4, added into
+// h[NKK]: with l_EE = -x/E^2 - 3xV/E^4, l_EV = x/E^3, l_V = -x/(2E^2) (l_VV = 0), dE/dk =
+// (fs, fg, 0, 0) and dV/dk = (-2 Es fs, -2 Es fg, fs^2, fg^2), d2V/dk1dk1 = -2 fs^2,
+// d2V/dk1dk2 = -2 fs fg, d2V/dk2dk2 = -2 fg^2:
+// h_ij = l_EE E_i E_j + l_EV (E_i V_j + V_i E_j) + l_V V_ij.
+__device__ __forceinline__ void pixel_kk(double x, double E, double V, double fs, double fg, const double* k,
+                                         double* h) {
+    const double inv = frcp(E);
+    const double inv2 = inv * inv;
+    const double lEE = -x * inv2 * (1.0 + 3.0 * (V * inv2));
+    const double lEV = x * inv2 * inv;
+    const double lV = -0.5 * x * inv2;
+    const double Es = k[C_K1] * fs + k[C_K2] * fg;
+    const double Q = lEE - 4.0 * lEV * Es - 2.0 * lV;
+    const double a = lEV * fs, b = lEV * fg;
+    h[KK_11] += Q * (fs * fs);
+    h[KK_12] += Q * (fs * fg);
+    h[KK_22] += Q * (fg * fg);
+    h[KK_13] += a * (fs * fs);
+    h[KK_14] += a * (fg * fg);
+    h[KK_23] += b * (fs * fs);
+    h[KK_24] += b * (fg * fg);
+}
+
 // Sky plus the light of every other box of the image that covers each row of the strip.
 template <int L>
 __device__ __forceinline__ void strip_background(const PairDev& p, const PairDev* __restrict__ pairs,
@@ -290,7 +314,9 @@ __global__ void __launch_bounds__(256) k_render_strips(Sel sel, const Item* __re
 }
 
 // ----------------------------------------------------------------------- adjoint
-template <class T, int BASE, bool DERIV, int L, bool FGM>
+// KK (double gradient passes over planes, stored backgrounds or stored values only): also
+// the brightness-factor block of each box's intermediate Hessian, per item into a.kk.
+template <class T, int BASE, bool DERIV, int L, bool FGM, bool KK>
 __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* __restrict__ items,
                                                         const PairDev* __restrict__ pairs,
                                                         const celeste_image* __restrict__ images,
@@ -326,6 +352,9 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
             T acc[NACC];
 #pragma unroll
             for (int f = 0; f < NACC; ++f) acc[f] = zero;
+            double kh[NKK_USED];
+#pragma unroll
+            for (int f = 0; f < NKK_USED; ++f) kh[f] = 0.0;
             for (int q = lane; q < it.count; q += 64) {
                 int c, r0, nrow;
                 strip_geometry(p, it.start + q, L, c, r0, nrow);
@@ -369,6 +398,7 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
                                 V = Vb[kk] + Vs;
                             }
                             strip_pixel<T, true>(cx_, E, V, fsk, fgk, k, acc, gs, gg, tl);
+                            if constexpr (KK) pixel_kk(cx_, E, V, fsk, fgk, k, kh);
                         }
                         Gs[kk] = gs;
                         Gg[kk] = gg;
@@ -418,6 +448,7 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
                                 V = cv_ + Vs;
                             }
                             strip_pixel<T, true>(cx_, E, V, fs[kk], fg[kk], k, acc, gs, gg, tl);
+                            if constexpr (KK) pixel_kk(cx_, E, V, fs[kk], fg[kk], k, kh);
                         }
                         fs[kk] = gs;
                         fg[kk] = gg;
@@ -503,6 +534,13 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
             for (int f = 0; f < NACC; ++f) {
                 const T s = wave_sum(acc[f]);
                 if (lane == 0) out[f] = s;
+            }
+            if constexpr (KK) {
+#pragma unroll
+                for (int f = 0; f < NKK_USED; ++f) {
+                    const double s = wave_sum(kh[f]);
+                    if (lane == 0) a.kk[(size_t)ii * NKK + f] = s;
+                }
             }
         }
         j = a.dynamic ? next_item_s(a.counter, lane) : j + nw;
@@ -734,31 +772,50 @@ hipError_t launch_render_strips(const Sel& sel, const Geometry& g, const double*
     return hipGetLastError();
 }
 
-template <class T, int BASE, bool DERIV, int L>
-static void adjs(const AdjArgs& a, int grid, int wpb, hipStream_t st) {
+template <class T, int BASE, bool DERIV, int L, bool FGM, bool KK>
+static void adjk(const AdjArgs& a, int grid, int wpb, hipStream_t st) {
     const Geometry& g = a.g;
+    hipLaunchKernelGGL((k_adjoint_strips<T, BASE, DERIV, L, FGM, KK>), dim3(grid), dim3(64 * wpb), 0, st, a,
+                       g.items, g.pairs, g.images, g.nbr, g.x, a.E, a.V, a.bg, a.tab, a.coef, a.tab_val, a.coef_val,
+                       a.active, a.fg, a.partials);
+}
+
+template <class T, int BASE, bool DERIV, int L>
+static hipError_t adjs(const AdjArgs& a, int grid, int wpb, hipStream_t st) {
+    constexpr bool is_double = std::is_same<T, double>::value;
     // own profile values from the render's stored values: double passes over planes or stored values
-    constexpr bool own_fg = std::is_same<T, double>::value && (BASE == BASE_PLANES || BASE == BASE_FG);
+    constexpr bool own_fg = is_double && (BASE == BASE_PLANES || BASE == BASE_FG);
+    // the k-block of the intermediate Hessian: double gradient passes on the streamed paths
+    constexpr bool can_kk = is_double && DERIV && (BASE == BASE_PLANES || BASE == BASE_FG || BASE == BASE_BG);
+    if (a.kk && !can_kk) return hipErrorInvalidValue;
     if constexpr (own_fg) {
         if (a.fg) {
-            hipLaunchKernelGGL((k_adjoint_strips<T, BASE, DERIV, L, true>), dim3(grid), dim3(64 * wpb), 0, st, a,
-                               g.items, g.pairs, g.images, g.nbr, g.x, a.E, a.V, a.bg, a.tab, a.coef, a.tab_val,
-                               a.coef_val, a.active, a.fg, a.partials);
-            return;
+            if constexpr (can_kk) {
+                if (a.kk) {
+                    adjk<T, BASE, DERIV, L, true, true>(a, grid, wpb, st);
+                    return hipSuccess;
+                }
+            }
+            adjk<T, BASE, DERIV, L, true, false>(a, grid, wpb, st);
+            return hipSuccess;
         }
     }
-    hipLaunchKernelGGL((k_adjoint_strips<T, BASE, DERIV, L, false>), dim3(grid), dim3(64 * wpb), 0, st, a, g.items,
-                       g.pairs, g.images, g.nbr, g.x, a.E, a.V, a.bg, a.tab, a.coef, a.tab_val, a.coef_val,
-                       a.active, a.fg, a.partials);
+    if constexpr (can_kk && BASE != BASE_FG) {
+        if (a.kk) {
+            adjk<T, BASE, DERIV, L, false, true>(a, grid, wpb, st);
+            return hipSuccess;
+        }
+    }
+    adjk<T, BASE, DERIV, L, false, false>(a, grid, wpb, st);
+    return hipSuccess;
 }
 
 template <class T, int BASE, bool DERIV>
 static hipError_t adjs_L(const AdjArgs& a, int grid, int wpb, int L, hipStream_t st) {
-    if (L == 8) adjs<T, BASE, DERIV, 8>(a, grid, wpb, st);
-    else if (L == 4) adjs<T, BASE, DERIV, 4>(a, grid, wpb, st);
-    else if (L == 16) adjs<T, BASE, DERIV, 16>(a, grid, wpb, st);
-    else return hipErrorInvalidValue;
-    return hipSuccess;
+    if (L == 8) return adjs<T, BASE, DERIV, 8>(a, grid, wpb, st);
+    if (L == 4) return adjs<T, BASE, DERIV, 4>(a, grid, wpb, st);
+    if (L == 16) return adjs<T, BASE, DERIV, 16>(a, grid, wpb, st);
+    return hipErrorInvalidValue;
 }
 
 template <class T, int BASE>
