@@ -3,8 +3,9 @@
 // an eigendecomposition, Section VI-B).  One 64-lane work-group per source:
 //  1. map gradient and Hessian to unconstrained coordinates (logit of q, frac_dev and
 //     axis ratio; log of radius and of every variance; identity otherwise);
-//  2. cyclic Jacobi eigendecomposition of the 27x27 model Hessian in LDS, each rotation
-//     applied by the lanes in parallel;
+//  2. Jacobi eigendecomposition of the 27x27 model Hessian in LDS with the round-robin
+//     ordering (27 padded to 28 indices: each of the 27 steps of a sweep rotates 14
+//     disjoint index pairs at once), the rotations applied by the lanes in parallel;
 //  3. exact subproblem  min g'p + p'Bp/2, |p| <= radius  in the eigenbasis: interior
 //     Newton step, else the secular equation |p(mu)| = radius by safeguarded Newton
 //     (Nocedal & Wright, Alg. 4.3), with the hard case handled along the eigenvector of
@@ -18,6 +19,8 @@
 namespace cel {
 
 constexpr int LD = 28;   // padded LDS row
+constexpr int NJ = 28;   // Jacobi index range: the 27 parameters and one idle index
+constexpr int NPAIR = NJ / 2;
 
 __device__ inline int param_kind(int i) {
     // 1: logit, 2: log, 0: identity
@@ -60,8 +63,10 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
     const int j = blockIdx.x;
     const int s = sel_at(a.srcs, j);
     const int t = threadIdx.x;
-    __shared__ double B[NP][LD];
-    __shared__ double Q[NP][LD];
+    __shared__ double B[NJ][LD];
+    __shared__ double Q[NJ][LD];
+    __shared__ double rot_c[NPAIR], rot_s[NPAIR];
+    __shared__ int rot_p[NPAIR], rot_q[NPAIR];
     __shared__ double gm[NP], eta[NP], d1[NP], lam[NP], gh[NP], ph[NP], pv[NP];
     __shared__ double sh_red[64];
     __shared__ int sh_done;
@@ -78,11 +83,14 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         lam[t] = p2 * gr[t];   // diagonal curvature term of the ELBO
     }
     __syncthreads();
-    if (t < NP) {
-        for (int c = 0; c < NP; ++c) {
-            const double hs = 0.5 * (H[t * NP + c] + H[c * NP + t]);
-            double b = -d1[t] * hs * d1[c];
-            if (c == t) b -= lam[t];
+    if (t < NJ) {
+        for (int c = 0; c < NJ; ++c) {
+            double b = 0.0;
+            if (t < NP && c < NP) {
+                const double hs = 0.5 * (H[t * NP + c] + H[c * NP + t]);
+                b = -d1[t] * hs * d1[c];
+                if (c == t) b -= lam[t];
+            }
             B[t][c] = b;
             Q[t][c] = (c == t) ? 1.0 : 0.0;
         }
@@ -108,7 +116,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         }
         return;
     }
-    // ---- cyclic Jacobi
+    // ---- Jacobi sweeps (round-robin order)
     for (int sweep = 0; sweep < 30; ++sweep) {
         double off = 0.0, tot = 0.0;
         if (t < NP)
@@ -128,37 +136,56 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         for (int i = 0; i < NP; ++i) tots += sh_red[i];
         __syncthreads();
         if (!(offs > 1e-30 * tots) || offs == 0.0) break;
-        for (int p = 0; p < NP - 1; ++p) {
-            for (int q = p + 1; q < NP; ++q) {
+        for (int r = 0; r < NJ - 1; ++r) {
+            // round r of the circle schedule: index 0 fixed, the others rotated by r
+            if (t < NPAIR) {
+                const int i0 = t, i1 = NJ - 1 - t;
+                const int a0 = i0 == 0 ? 0 : 1 + (i0 - 1 + r) % (NJ - 1);
+                const int a1 = 1 + (i1 - 1 + r) % (NJ - 1);
+                const int p = a0 < a1 ? a0 : a1, q = a0 < a1 ? a1 : a0;
+                double c = 1.0, sn = 0.0;
                 const double apq = B[p][q];
-                if (apq == 0.0) continue;   // uniform across the block
-                const double app = B[p][p], aqq = B[q][q];
-                const double tau = (aqq - app) / (2.0 * apq);
-                const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                const double c = 1.0 / sqrt(1.0 + tt * tt);
-                const double sn = tt * c;
-                __syncthreads();
-                if (t < NP) {
-                    const double bkp = B[t][p], bkq = B[t][q];
-                    B[t][p] = c * bkp - sn * bkq;
-                    B[t][q] = sn * bkp + c * bkq;
-                    const double qkp = Q[t][p], qkq = Q[t][q];
-                    Q[t][p] = c * qkp - sn * qkq;
-                    Q[t][q] = sn * qkp + c * qkq;
+                if (q < NP && apq != 0.0) {
+                    const double app = B[p][p], aqq = B[q][q];
+                    const double tau = (aqq - app) / (2.0 * apq);
+                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    sn = tt * c;
                 }
-                __syncthreads();
-                if (t < NP) {
-                    const double bpk = B[p][t], bqk = B[q][t];
-                    B[p][t] = c * bpk - sn * bqk;
-                    B[q][t] = sn * bpk + c * bqk;
-                }
-                __syncthreads();
-                if (t == 0) {
-                    B[p][q] = 0.0;
-                    B[q][p] = 0.0;
-                }
-                __syncthreads();
+                rot_p[t] = p;
+                rot_q[t] = q;
+                rot_c[t] = c;
+                rot_s[t] = sn;
             }
+            __syncthreads();
+            // B <- B J and Q <- Q J for all pairs (disjoint column pairs)
+            for (int idx = t; idx < NPAIR * NJ; idx += 64) {
+                const int k = idx / NJ, row = idx - k * NJ;
+                const int p = rot_p[k], q = rot_q[k];
+                const double c = rot_c[k], sn = rot_s[k];
+                const double bkp = B[row][p], bkq = B[row][q];
+                B[row][p] = c * bkp - sn * bkq;
+                B[row][q] = sn * bkp + c * bkq;
+                const double qkp = Q[row][p], qkq = Q[row][q];
+                Q[row][p] = c * qkp - sn * qkq;
+                Q[row][q] = sn * qkp + c * qkq;
+            }
+            __syncthreads();
+            // B <- J^T B (disjoint row pairs)
+            for (int idx = t; idx < NPAIR * NJ; idx += 64) {
+                const int k = idx / NJ, col = idx - k * NJ;
+                const int p = rot_p[k], q = rot_q[k];
+                const double c = rot_c[k], sn = rot_s[k];
+                const double bpk = B[p][col], bqk = B[q][col];
+                B[p][col] = c * bpk - sn * bqk;
+                B[q][col] = sn * bpk + c * bqk;
+            }
+            __syncthreads();
+            if (t < NPAIR && rot_s[t] != 0.0) {
+                B[rot_p[t]][rot_q[t]] = 0.0;
+                B[rot_q[t]][rot_p[t]] = 0.0;
+            }
+            __syncthreads();
         }
     }
     if (t < NP) {
