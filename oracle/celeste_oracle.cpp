@@ -11,7 +11,10 @@
 // log-likelihood analytic up to a second-order (delta-method) expansion of
 // E[log F].  Everything the paper leaves to the cited model is taken from an
 // explicit, listed reading (the model constants below, the parameter layout, the
-// mixture tables passed in as inputs).
+// mixture tables passed in as inputs).  An image's metadata (its sky location and
+// observing conditions, Section III) is read as: a sky level per pixel (a constant or a
+// map), a calibration factor, a PSF mixture in the image frame, and a local linear
+// astrometry (origin and 2x2 matrix) from world to image coordinates.
 //
 // Structure: every pixel quantity is written once, as a template on the scalar
 // type.  T = double gives values; T = Dual<double,27> (forward-mode AD over the
@@ -158,7 +161,14 @@ struct OImage {
     int64_t off;                 // offset of the image in x
     double sky, iota, ox, oy;    // sky level, calibration, world (x, y) of pixel (0, 0)
     double psf[3][6];            // (w, xi_x, xi_y, S_xx, S_xy, S_yy) per PSF component
+    const double* sky_map;       // sky level of every pixel [H][W], or null: `sky` everywhere
+    double wcs[2][2];            // image-frame offset = wcs * (world offset from the origin)
 };
+
+// Sky level of pixel (r, c) of an image: the per-pixel map when the image has one.
+inline double sky_at(const OImage& im, int r, int c) {
+    return im.sky_map ? im.sky_map[(int64_t)r * im.W + c] : im.sky;
+}
 struct OBox { int32_t img, r0, c0, h, w; };
 struct OProblem {
     int32_t n_img, n_src;
@@ -233,14 +243,23 @@ T normal2(double px, double py, const T& mx, const T& my, const T& sxx, const T&
 }
 
 // PSF-convolved star and galaxy profiles of a source at the centre of pixel
-// (row, col) of image im: pixel centre is (x = col, y = row) in the image frame,
-// and the image frame is world minus the image origin.
+// (row, col) of image im: pixel centre is (x = col, y = row) in the image frame.  A
+// world point u maps to the image frame as wcs (u - origin), the image's local linear
+// astrometry, so a world-frame galaxy covariance S appears as wcs S wcs^T; the PSF is
+// given in the image frame.
 template <class T>
 void profiles(const OProblem& P, const OImage& im, const Src<T>& s, double px, double py,
               T& fstar, T& fgal) {
-    T mx0 = s.ux - im.ox, my0 = s.uy - im.oy;
-    T sxx, sxy, syy;
-    galaxy_cov(s, sxx, sxy, syy);
+    const double(&A)[2][2] = im.wcs;
+    T wx = s.ux - im.ox, wy = s.uy - im.oy;
+    T mx0 = A[0][0] * wx + A[0][1] * wy, my0 = A[1][0] * wx + A[1][1] * wy;
+    T wxx, wxy, wyy;
+    galaxy_cov(s, wxx, wxy, wyy);
+    // wcs S wcs^T
+    T sxx = (A[0][0] * A[0][0]) * wxx + (2.0 * A[0][0] * A[0][1]) * wxy + (A[0][1] * A[0][1]) * wyy;
+    T sxy = (A[0][0] * A[1][0]) * wxx + (A[0][0] * A[1][1] + A[0][1] * A[1][0]) * wxy +
+            (A[0][1] * A[1][1]) * wyy;
+    T syy = (A[1][0] * A[1][0]) * wxx + (2.0 * A[1][0] * A[1][1]) * wxy + (A[1][1] * A[1][1]) * wyy;
     fstar = T(0.0);
     T fdev(0.0), fexp(0.0);
     for (int k = 0; k < 3; ++k) {
@@ -291,7 +310,7 @@ inline bool box_has(const OBox& b, int r, int c) {
 // (r, c); `skip` = -1 includes all sources.
 void background(const OProblem& P, int n, int r, int c, int skip, double& E, double& V) {
     const OImage& im = P.img[n];
-    E = im.sky;
+    E = sky_at(im, r, c);
     V = 0.0;
     for (int t = 0; t < P.n_src; ++t) {
         if (t == skip) continue;

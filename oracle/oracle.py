@@ -30,7 +30,8 @@ def build(force=False):
 class OImage(C.Structure):
     _fields_ = [("band", C.c_int32), ("H", C.c_int32), ("W", C.c_int32), ("pad", C.c_int32),
                 ("off", C.c_int64), ("sky", C.c_double), ("iota", C.c_double),
-                ("ox", C.c_double), ("oy", C.c_double), ("psf", C.c_double * 18)]
+                ("ox", C.c_double), ("oy", C.c_double), ("psf", C.c_double * 18),
+                ("sky_map", C.POINTER(C.c_double)), ("wcs", C.c_double * 4)]
 
 
 class OProblem(C.Structure):
@@ -90,7 +91,17 @@ class Problem:
             im.ox, im.oy = float(f.img_origin[i, 0]), float(f.img_origin[i, 1])
             for k, v in enumerate(np.asarray(f.img_psf[i], np.float64).reshape(-1)):
                 im.psf[k] = float(v)
+            A = f.wcs(i)
+            for k, v in enumerate(np.asarray(A, np.float64).reshape(-1)):
+                im.wcs[k] = float(v)
         self.imgs = imgs
+        # per-pixel sky maps: same layout as x
+        self.sky_map = None
+        if getattr(f, "sky_map", None) is not None:
+            self.sky_map = np.ascontiguousarray(f.sky_map, np.float64)
+            for i in range(n):
+                imgs[i].sky_map = C.cast(C.c_void_p(self.sky_map.ctypes.data + 8 * int(f.img_off[i])),
+                                         C.POINTER(C.c_double))
         self.x = np.ascontiguousarray(f.x, np.float64)
         self.ptr = np.ascontiguousarray(f.patch_ptr, np.int32)
         self.box = np.ascontiguousarray(f.boxes, np.int32).reshape(-1)

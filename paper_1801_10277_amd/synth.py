@@ -75,6 +75,11 @@ class Field:
     flags: int = FLAG_INCLUDE_KL
     truth: dict = field(default_factory=dict)
     name: str = ""
+    img_wcs: np.ndarray = None  # f64 [n_img, 2, 2] image offset = wcs @ world offset; None: identity
+    sky_map: np.ndarray = None  # f64 [n_pix] per-pixel sky level, layout of x; None: img_sky
+
+    def wcs(self, n):
+        return np.eye(2) if self.img_wcs is None else np.asarray(self.img_wcs[n], np.float64)
 
     @property
     def n_src(self):
@@ -156,13 +161,18 @@ def _sample_offsets(rng, kind, fdev, rho, phi, re, b_exp, b_dev):
 
 
 def _render_image(rng, H, W, sky, iota, origin, psf, band, src_pos, src_kind, src_flux,
-                  src_shape, b_exp, b_dev, max_photons_chunk=1_000_000):
-    """Poisson sky plus binned photons of every source (world positions src_pos)."""
-    img = rng.poisson(sky, size=(H, W)).astype(np.float64)
+                  src_shape, b_exp, b_dev, max_photons_chunk=1_000_000, wcs=None, sky_map=None):
+    """Poisson sky plus binned photons of every source (world positions src_pos).  A
+    photon's world offset from its source maps to the image through wcs; the PSF blur is
+    drawn in the image frame."""
+    A = np.eye(2) if wcs is None else np.asarray(wcs, np.float64)
+    img = rng.poisson(sky if sky_map is None else sky_map, size=(H, W)).astype(np.float64)
     lam = iota * src_flux[:, band]
     # only sources whose light can reach the image (generous 300 px margin)
-    px = src_pos[:, 0] - origin[0]
-    py = src_pos[:, 1] - origin[1]
+    wx = src_pos[:, 0] - origin[0]
+    wy = src_pos[:, 1] - origin[1]
+    px = A[0, 0] * wx + A[0, 1] * wy
+    py = A[1, 0] * wx + A[1, 1] * wy
     near = (px > -300) & (px < W + 300) & (py > -300) & (py < H + 300)
     idx = np.nonzero(near)[0]
     if idx.size == 0:
@@ -190,8 +200,8 @@ def _render_image(rng, H, W, sky, iota, origin, psf, band, src_pos, src_kind, sr
             sig = np.sqrt(psf[k, 3])
             ex = psf[k, 1] + sig * rng.standard_normal(rep.size)
             ey = psf[k, 2] + sig * rng.standard_normal(rep.size)
-            xx = px[s] + dx + ex
-            yy = py[s] + dy + ey
+            xx = px[s] + A[0, 0] * dx + A[0, 1] * dy + ex
+            yy = py[s] + A[1, 0] * dx + A[1, 1] * dy + ey
             col = np.floor(xx + 0.5).astype(np.int64)
             row = np.floor(yy + 0.5).astype(np.int64)
             ok = (col >= 0) & (col < W) & (row >= 0) & (row < H)
@@ -269,6 +279,16 @@ def _assemble(rng, images_meta, pos, kind, flux, colours, shape, box_sides, thet
     img_iota = np.array([m.get("iota", 1.0) for m in images_meta])
     img_origin = np.array([m["origin"] for m in images_meta], np.float64).reshape(n_img, 2)
     img_psf = np.array([m["psf"] for m in images_meta])
+    has_wcs = any("wcs" in m for m in images_meta)
+    img_wcs = (np.array([m.get("wcs", np.eye(2)) for m in images_meta], np.float64).reshape(n_img, 2, 2)
+               if has_wcs else None)
+    sky_map = None
+    if any("sky_map" in m for m in images_meta):
+        sky_map = np.empty(int(sizes.sum()))
+        for n, m in enumerate(images_meta):
+            sm = m.get("sky_map")
+            sky_map[img_off[n]:img_off[n] + sizes[n]] = (np.full(int(sizes[n]), img_sky[n]) if sm is None
+                                                         else np.asarray(sm, np.float64).reshape(-1))
     band_flux = _band_fluxes(flux, colours)
     x = np.empty(int(sizes.sum()))
     # one independent stream per image (spawned from the field's stream), so images can
@@ -278,12 +298,16 @@ def _assemble(rng, images_meta, pos, kind, flux, colours, shape, box_sides, thet
 
     def draw(n):
         r = streams[n]
+        smap = None if sky_map is None else sky_map[img_off[n]:img_off[n] + sizes[n]].reshape(
+            int(img_H[n]), int(img_W[n]))
         if render:
             im = _render_image(r, int(img_H[n]), int(img_W[n]), img_sky[n], img_iota[n],
                                img_origin[n], img_psf[n], int(img_band[n]), pos, kind,
-                               band_flux, shape, b_exp, b_dev)
+                               band_flux, shape, b_exp, b_dev,
+                               wcs=None if img_wcs is None else img_wcs[n], sky_map=smap)
         else:
-            im = r.poisson(img_sky[n], size=(int(img_H[n]), int(img_W[n]))).astype(float)
+            im = r.poisson(img_sky[n] if smap is None else smap,
+                           size=(int(img_H[n]), int(img_W[n]))).astype(float)
         x[img_off[n]:img_off[n] + sizes[n]] = im.reshape(-1)
 
     workers = min(n_img, _workers())
@@ -301,6 +325,8 @@ def _assemble(rng, images_meta, pos, kind, flux, colours, shape, box_sides, thet
     for s in range(S):
         for n in range(n_img):
             c = theta[s, :2] - img_origin[n]
+            if img_wcs is not None:
+                c = img_wcs[n] @ c
             b = _box(c, int(box_sides[s]), int(box_sides[s]), int(img_H[n]), int(img_W[n]))
             if b is not None:
                 boxes.append((n,) + b)
@@ -314,7 +340,28 @@ def _assemble(rng, images_meta, pos, kind, flux, colours, shape, box_sides, thet
                  prior_phi=phi, prior_r=prior_r, prior_c=prior_c,
                  truth={"pos": pos, "kind": kind, "flux": flux, "colours": colours,
                         "shape": shape},
-                 name=name)
+                 name=name, img_wcs=img_wcs, sky_map=sky_map)
+
+
+def _realistic_meta(rng, meta, wcs=True, sky_map=True):
+    """Adds per-image metadata beyond a constant sky and a pure translation: a local
+    linear astrometry (rotation up to 0.3 rad, per-axis scale 0.97-1.03, small shear) and a
+    smooth sky map (linear gradients up to +-20% and a 10% sinusoid around the level)."""
+    for m in meta:
+        if wcs:
+            a = rng.uniform(-0.3, 0.3)
+            R = np.array([[np.cos(a), -np.sin(a)], [np.sin(a), np.cos(a)]])
+            Sc = np.array([[rng.uniform(0.97, 1.03), rng.uniform(-0.02, 0.02)],
+                           [0.0, rng.uniform(0.97, 1.03)]])
+            m["wcs"] = Sc @ R
+        if sky_map:
+            H, W = m["H"], m["W"]
+            rr, cc = np.meshgrid(np.arange(H) / max(H - 1, 1), np.arange(W) / max(W - 1, 1), indexing="ij")
+            g = rng.uniform(-0.2, 0.2, 2)
+            amp, f1, f2, ph = rng.uniform(0.0, 0.1), rng.uniform(0.5, 2.0), rng.uniform(0.5, 2.0), rng.uniform(0, 6.3)
+            m["sky_map"] = m["sky"] * (1.0 + g[0] * (rr - 0.5) + g[1] * (cc - 0.5)
+                                       + amp * np.sin(2 * np.pi * (f1 * rr + f2 * cc) + ph))
+    return meta
 
 
 def _single_field_images(rng, H, W, bands=range(N_BANDS), origin=(0.0, 0.0)):
@@ -359,16 +406,21 @@ LOGR_SD_FIELD = 1.267
 LOGR_RANGE_FIELD = (np.log(50.0), np.log(1e5))
 
 
-def sdss_field(S=2000, H=1489, W=2048, seed=1002, render=True, name="config2"):
+def sdss_field(S=2000, H=1489, W=2048, seed=1002, render=True, name="config2", realistic=False):
     """SDSS-shaped field: S sources uniform over a W x H frame (a Poisson process conditioned
     on its count), 40% stars, patch side log-uniform in [21, 101] px (odd), r-band
-    brightness log-normal truncated to [50, 1e5] e-."""
+    brightness log-normal truncated to [50, 1e5] e-.  realistic=True adds a local linear
+    astrometry and a sky map per image and sizes each patch by brightness and radius
+    (odd side 10 log10(flux) + 4 radius + 5, clipped to [21, 101])."""
     rng = np.random.default_rng(seed)
     imgs = _single_field_images(rng, H, W)
     kind, flux, colours, shape = _truth_draw(rng, S, 0.4, LOGR_MEAN_FIELD, LOGR_SD_FIELD,
                                              LOGR_RANGE_FIELD)
     pos = np.stack([rng.uniform(0.0, W - 1.0, S), rng.uniform(0.0, H - 1.0, S)], axis=1)
     sides = _odd(np.exp(rng.uniform(np.log(21.0), np.log(101.0), S)))
+    if realistic:
+        _realistic_meta(np.random.default_rng(seed + 7919), imgs)
+        sides = _odd(np.clip(10.0 * np.log10(flux) + 4.0 * shape[:, 3] + 5.0, 21.0, 101.0))
     theta = _theta_from_truth(rng, pos, flux, colours, shape)
     return _assemble(rng, imgs, pos, kind, flux, colours, shape, sides, theta,
                      0.4, LOGR_MEAN_FIELD, LOGR_SD_FIELD, name, render=render)
@@ -421,7 +473,7 @@ def make_config(i, seed=None, **kw):
 
 
 def tiny(S=2, n_bands=2, size=15, side=9, seed=7, sky=(100.0, 200.0), psf_xi=False,
-         anisotropic_psf=False, star_prob=0.5):
+         anisotropic_psf=False, star_prob=0.5, wcs=False, sky_map=False):
     """Small problem for tests: S sources in a size x size region, one image per band."""
     rng = np.random.default_rng(seed)
     bands = list(range(n_bands)) if n_bands <= N_BANDS else list(range(N_BANDS))
@@ -438,6 +490,8 @@ def tiny(S=2, n_bands=2, size=15, side=9, seed=7, sky=(100.0, 200.0), psf_xi=Fal
             psf[:, 4] = rng.uniform(-0.4, 0.4, 3) * a * c
         imgs.append({"band": b, "H": size, "W": size,
                      "sky": float(rng.uniform(*sky)), "origin": (0.0, 0.0), "psf": psf})
+    if wcs or sky_map:
+        _realistic_meta(np.random.default_rng(seed + 7919), imgs, wcs=wcs, sky_map=sky_map)
     kind, flux, colours, shape = _truth_draw(rng, S, star_prob, np.log(1000.0), 1.0, None)
     pos = rng.uniform(size * 0.25, size * 0.75, (S, 2))
     theta = _theta_from_truth(rng, pos, flux, colours, shape)
