@@ -8,18 +8,20 @@
  * steps for many sources at once (Section IV-D) and block-coordinate-ascent sweeps
  * over conflict-free batches of sources (Section IV-D).
  *
- * Model, per image n (band b_n, sky level eps_n, calibration iota_n, 3-component
- * Gaussian PSF) and pixel m (centre (x = col, y = row) in the image frame, which is
- * the world frame minus the image origin):
+ * Model, per image n (band b_n, sky level eps_n(m), calibration iota_n, 3-component
+ * Gaussian PSF in the image frame, local linear astrometry: a world point u is at
+ * image-frame position wcs_n (u - origin_n)) and pixel m (centre (x = col, y = row) in
+ * the image frame) - the image metadata of Section III read this way:
  *   E_s(m)   = iota_n [q a_star f_star(m) + (1-q) a_gal f_gal(m)]
  *   Var_s(m) = iota_n^2 [q b_star f_star^2 + (1-q) b_gal f_gal^2] - E_s(m)^2
- *   E(m) = eps_n + sum_t E_t(m),  V(m) = sum_t Var_t(m)   over sources t whose box
+ *   E(m) = eps_n(m) + sum_t E_t(m),  V(m) = sum_t Var_t(m)   over sources t whose box
  *   in image n contains m;  a = E[flux_b], b = E[flux_b^2] of the log-normal band flux;
  *   pixel term  l(m) = x_m (log E - V / (2 E^2)) - E   (second-order expansion of
  *   E[log F] about E[F]);  ELBO_s = sum over s's own boxes of l(m) - KL_s.
  * f_star is the PSF; f_gal mixes an exponential and a de Vaucouleurs profile (each a
  * Gaussian mixture given in the problem description) sheared by the galaxy shape
- * radius^2 R(angle) diag(1, ratio^2) R(angle)^T and convolved with the PSF.
+ * radius^2 R(angle) diag(1, ratio^2) R(angle)^T (world frame; wcs S wcs^T in the image)
+ * and convolved with the PSF.
  *
  * Parameters: theta is a device array [n_src][32] of float64, one row per source:
  *   0 u_x, 1 u_y (world pixels), 2 frac_dev in [0,1], 3 axis ratio in (0,1],
@@ -49,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CELESTE_ABI_VERSION 2
+#define CELESTE_ABI_VERSION 3
 
 enum celeste_status {
     CELESTE_OK = 0,
@@ -76,10 +78,16 @@ typedef struct celeste_image {
     int32_t H, W;
     int32_t reserved;
     int64_t pix_offset;   /* offset of pixel (0, 0) in x */
-    double sky;           /* eps_n > 0, expected sky counts per pixel */
+    double sky;           /* eps_n > 0, expected sky counts per pixel (when sky_map is NULL) */
     double iota;          /* iota_n > 0, counts per unit flux */
-    double origin_x, origin_y;   /* world coordinates of pixel (row 0, col 0) */
-    double psf[3][6];     /* per component: weight > 0, mean offset x, y, covariance xx, xy, yy */
+    double origin_x, origin_y;   /* world coordinates mapped to pixel (row 0, col 0) */
+    double psf[3][6];     /* per component: weight > 0, mean offset x, y, covariance xx, xy, yy
+                             (image frame) */
+    const double* sky_map;   /* device [H][W] row-major sky level of every pixel (> 0), or NULL:
+                                `sky` everywhere.  Owned by the caller, alive as long as the plan */
+    double wcs[2][2];     /* local linear astrometry: image-frame offset (x = col, y = row) =
+                             wcs * (world point - origin); identity for a pure translation.
+                             A galaxy's world-frame shape covariance S appears as wcs S wcs^T */
 } celeste_image;
 
 /* A source's patch ("active pixels") in one image: rows r0..r0+h-1, cols c0..c0+w-1. */

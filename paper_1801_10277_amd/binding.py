@@ -33,7 +33,8 @@ EXPORTS = ["celeste_plan_create", "celeste_plan_destroy", "celeste_plan_get_info
 class celeste_image(C.Structure):
     _fields_ = [("band", C.c_int32), ("H", C.c_int32), ("W", C.c_int32), ("reserved", C.c_int32),
                 ("pix_offset", C.c_int64), ("sky", C.c_double), ("iota", C.c_double),
-                ("origin_x", C.c_double), ("origin_y", C.c_double), ("psf", C.c_double * 18)]
+                ("origin_x", C.c_double), ("origin_y", C.c_double), ("psf", C.c_double * 18),
+                ("sky_map", C.c_void_p), ("wcs", C.c_double * 4)]
 
 
 class celeste_box(C.Structure):
@@ -155,6 +156,8 @@ class Plan:
         self.S = f.n_src
         self.check_status = check_status
         self.x = torch.as_tensor(np.ascontiguousarray(f.x, np.float64)).to(device)
+        smap = getattr(f, "sky_map", None)
+        self.sky_map = None if smap is None else torch.as_tensor(np.ascontiguousarray(smap, np.float64)).to(device)
         n = f.n_img
         imgs = (celeste_image * n)()
         for i in range(n):
@@ -165,6 +168,10 @@ class Plan:
             im.origin_x, im.origin_y = float(f.img_origin[i, 0]), float(f.img_origin[i, 1])
             for k, v in enumerate(np.asarray(f.img_psf[i], np.float64).reshape(-1)):
                 im.psf[k] = float(v)
+            for k, v in enumerate(np.asarray(f.wcs(i), np.float64).reshape(-1)):
+                im.wcs[k] = float(v)
+            if self.sky_map is not None:
+                im.sky_map = self.sky_map.data_ptr() + 8 * int(f.img_off[i])
         ptr = np.ascontiguousarray(f.patch_ptr, np.int32)
         nb = int(ptr[-1])
         boxes = (celeste_box * max(nb, 1))()

@@ -316,6 +316,20 @@ void drop_graph(celeste_plan* p) {
 }
 
 // ---------------------------------------------------------------- validation
+// Every sky-map entry finite and > 0 (a synchronous copy of each map; plan creation only).
+int validate_sky_maps(const celeste_problem_desc* d) {
+    std::vector<double> buf;
+    for (int n = 0; n < d->n_img; ++n) {
+        const celeste_image& im = d->images[n];
+        if (!im.sky_map) continue;
+        buf.resize((size_t)im.H * im.W);
+        HIPCHK(hipMemcpy(buf.data(), im.sky_map, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (double v : buf)
+            if (!(v > 0.0) || !finite(v)) return CELESTE_EINVAL;
+    }
+    return CELESTE_OK;
+}
+
 int validate_desc(const celeste_problem_desc* d) {
     if (!d || d->n_img <= 0 || d->n_src <= 0 || !d->images || !d->x || !d->patch_ptr || d->n_pix <= 0)
         return CELESTE_EINVAL;
@@ -326,6 +340,12 @@ int validate_desc(const celeste_problem_desc* d) {
         if (im.pix_offset + (int64_t)im.H * im.W > d->n_pix) return CELESTE_EINVAL;
         if (!(im.sky > 0.0) || !finite(im.sky) || !(im.iota > 0.0) || !finite(im.iota)) return CELESTE_EINVAL;
         if (!finite(im.origin_x) || !finite(im.origin_y)) return CELESTE_EINVAL;
+        {
+            const double a = im.wcs[0][0], b = im.wcs[0][1], c = im.wcs[1][0], e = im.wcs[1][1];
+            if (!finite(a) || !finite(b) || !finite(c) || !finite(e)) return CELESTE_EINVAL;
+            const double mx = std::max(std::max(std::fabs(a), std::fabs(b)), std::max(std::fabs(c), std::fabs(e)));
+            if (!(std::fabs(a * e - b * c) >= 1e-6 * mx * mx)) return CELESTE_EINVAL;   // invertible
+        }
         for (int k = 0; k < NPSF; ++k) {
             const double* ps = im.psf[k];
             for (int f = 0; f < 6; ++f)
@@ -722,7 +742,8 @@ void celeste_plan_destroy(celeste_plan* p) {
 int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     if (!out) return CELESTE_EINVAL;
     *out = nullptr;
-    const int v = validate_desc(d);
+    int v = validate_desc(d);
+    if (v == CELESTE_OK) v = validate_sky_maps(d);
     if (v != CELESTE_OK) return v;
     celeste_plan* p = new celeste_plan();
     HIPCHK(hipGetDevice(&p->device));

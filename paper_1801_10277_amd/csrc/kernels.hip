@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(256) k_render(RenderArgs a, const TileDev* __r
         r[k] = td.r0 + lane / a.tile_w + k * rows_per_pass;
         inside[k] = r[k] < im.H && c < im.W;
         covered[k] = false;
-        E[k] = im.sky;
+        E[k] = inside[k] ? sky_at(im, r[k], c) : im.sky;
         V[k] = 0.0;
         px[k] = (double)c;
         py[k] = (double)r[k];

@@ -12,6 +12,11 @@ namespace cel {
 __device__ __constant__ static const signed char BSIGN[5][4] = {
     {-1, -1, 0, 0}, {0, -1, 0, 0}, {0, 0, 0, 0}, {0, 0, 1, 0}, {0, 0, 1, 1}};
 
+// Sky level of pixel (r, c) (inside the image) of an image: its map when it has one.
+__device__ __forceinline__ double sky_at(const celeste_image& im, int r, int c) {
+    return im.sky_map ? im.sky_map[(size_t)r * im.W + c] : im.sky;
+}
+
 constexpr double LOG_2PI = 1.8378770664093454836;
 
 // Table-driven exponential (P. T. P. Tang, "Table-driven implementation of the exponential
@@ -168,10 +173,17 @@ __device__ inline void pair_w(const T* p, const celeste_image& im, T* w) {
     w[W_K2] = io * ((1.0 - q) * a[1]);
     w[W_K3] = (io * io) * (q * b[0]);
     w[W_K4] = (io * io) * ((1.0 - q) * b[1]);
-    w[W_UX] = p[0];
-    w[W_UY] = p[1];
+    // position and galaxy shape in the image frame: wcs (u - origin), wcs S wcs^T
+    const double a00 = im.wcs[0][0], a01 = im.wcs[0][1], a10 = im.wcs[1][0], a11 = im.wcs[1][1];
+    const T wx = p[0] - im.origin_x, wy = p[1] - im.origin_y;
+    w[W_UX] = a00 * wx + a01 * wy;
+    w[W_UY] = a10 * wx + a11 * wy;
     w[W_FDEV] = p[2];
-    shape_cov(p, w[W_SXX], w[W_SXY], w[W_SYY]);
+    T sxx, sxy, syy;
+    shape_cov(p, sxx, sxy, syy);
+    w[W_SXX] = (a00 * a00) * sxx + (2.0 * a00 * a01) * sxy + (a01 * a01) * syy;
+    w[W_SXY] = (a00 * a10) * sxx + (a00 * a11 + a01 * a10) * sxy + (a01 * a11) * syy;
+    w[W_SYY] = (a10 * a10) * sxx + (2.0 * a10 * a11) * sxy + (a11 * a11) * syy;
 }
 
 // Table of the 45 Gaussians (components: 3 star, then per PSF component 8 de Vaucouleurs
@@ -182,7 +194,7 @@ __device__ inline void pair_w(const T* p, const celeste_image& im, T* w) {
 template <class T>
 __device__ inline void build_comp_from_w(const T* w, const celeste_image& im, const Consts& K, int c, T* e) {
     const T sxx = w[W_SXX], sxy = w[W_SXY], syy = w[W_SYY];
-    const T ux = w[W_UX] - im.origin_x, uy = w[W_UY] - im.origin_y;
+    const T ux = w[W_UX], uy = w[W_UY];
     const T fdev = w[W_FDEV];
     const int k = c < NPSF ? c : (c - NPSF) / NGAL_PER_PSF;
     const double* ps = im.psf[k];
@@ -267,10 +279,18 @@ __device__ inline void chain_pair(const T* p, const celeste_image& im, const T* 
             }
         }
     }
-    g[0] += z[A_UX];
-    g[1] += z[A_UY];
+    // position: d/du = wcs^T d/d(image-frame position)
+    const double a00 = im.wcs[0][0], a01 = im.wcs[0][1], a10 = im.wcs[1][0], a11 = im.wcs[1][1];
+    g[0] += a00 * z[A_UX] + a10 * z[A_UY];
+    g[1] += a01 * z[A_UX] + a11 * z[A_UY];
     g[2] += z[A_FDEV];
-    const T Gxx = 0.5 * z[A_SXX], Gxy = z[A_SXY], Gyy = 0.5 * z[A_SYY];
+    // shape: with the symmetric gradient G of the image-frame covariance (off-diagonal
+    // entries half of d/dSxy), the world-frame one is wcs^T G wcs
+    const T Pxx = 0.5 * z[A_SXX], Pxy = 0.5 * z[A_SXY], Pyy = 0.5 * z[A_SYY];
+    const T Mxx = Pxx * a00 + Pxy * a10, Mxy = Pxx * a01 + Pxy * a11;
+    const T Myx = Pxy * a00 + Pyy * a10, Myy = Pxy * a01 + Pyy * a11;
+    const T Gxx = a00 * Mxx + a10 * Myx, Gyy = a01 * Mxy + a11 * Myy;
+    const T Gxy = 2.0 * (a00 * Mxy + a10 * Myy);
     const T c = cos(p[4]), s = sin(p[4]);
     const T re = p[5], r2 = re * re, rho = p[3], q2 = rho * rho;
     const T cs = c * s, c2 = c * c, s2 = s * s, om = 1.0 - q2;

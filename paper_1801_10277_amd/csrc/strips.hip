@@ -196,11 +196,11 @@ __device__ __forceinline__ void pixel_kk(double x, double E, double V, double fs
 template <int L>
 __device__ __forceinline__ void strip_background(const PairDev& p, const PairDev* __restrict__ pairs,
                                                  const int32_t* __restrict__ nbr, const double* __restrict__ tabv,
-                                                 const double* __restrict__ coefv, double sky, int c, int r0,
-                                                 double* Eb, double* Vb, const double* __restrict__ t2) {
+                                                 const double* __restrict__ coefv, const celeste_image& im, int c,
+                                                 int r0, double* Eb, double* Vb, const double* __restrict__ t2) {
 #pragma unroll
     for (int k = 0; k < L; ++k) {
-        Eb[k] = sky;
+        Eb[k] = r0 + k < im.H ? sky_at(im, r0 + k, c) : im.sky;
         Vb[k] = 0.0;
     }
     for (int q = p.nbr_begin; q < p.nbr_end; ++q) {
@@ -228,11 +228,11 @@ template <int L>
 __device__ __forceinline__ void strip_background_fg(const PairDev& p, const PairDev* __restrict__ pairs,
                                                     const int32_t* __restrict__ nbr,
                                                     const double* __restrict__ coefv,
-                                                    const double* __restrict__ fgm, double sky, int c, int r0,
+                                                    const double* __restrict__ fgm, const celeste_image& im, int c, int r0,
                                                     double* Eb, double* Vb) {
 #pragma unroll
     for (int k = 0; k < L; ++k) {
-        Eb[k] = sky;
+        Eb[k] = r0 + k < im.H ? sky_at(im, r0 + k, c) : im.sky;
         Vb[k] = 0.0;
     }
     for (int q = p.nbr_begin; q < p.nbr_end; ++q) {
@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(256) k_fill_planes(const celeste_image* __rest
     const celeste_image& im = images[blockIdx.y];
     const int64_t npix = (int64_t)im.H * im.W;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += (int64_t)gridDim.x * blockDim.x) {
-        E[im.pix_offset + i] = im.sky;
+        E[im.pix_offset + i] = im.sky_map ? im.sky_map[i] : im.sky;
         V[im.pix_offset + i] = 0.0;
     }
 }
@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
                     // into pass B.
                     double Eb[L], Vb[L];
                     if constexpr (BASE == BASE_FG)
-                        strip_background_fg<L>(p, pairs, nbr, coefv, fgm, im.sky, c, r0, Eb, Vb);
+                        strip_background_fg<L>(p, pairs, nbr, coefv, fgm, im, c, r0, Eb, Vb);
                     auto row_load = [&](int rr, double& x_, double& e_, double& v_, double& s_, double& g_) {
                         const size_t gi = (size_t)im.pix_offset + (size_t)(r0 + rr) * im.W + c;
                         const size_t vi = (size_t)p.visit_off + (size_t)(r0 + rr - p.r0) * p.w + (c - p.c0);
@@ -462,9 +462,9 @@ __global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* _
                 }
                 double x[L], Eb[L], Vb[L];
                 if (BASE == BASE_NBR) {
-                    strip_background<L>(p, pairs, nbr, tabv, coefv, im.sky, c, r0, Eb, Vb, t2);
+                    strip_background<L>(p, pairs, nbr, tabv, coefv, im, c, r0, Eb, Vb, t2);
                 } else if (BASE == BASE_FG) {
-                    strip_background_fg<L>(p, pairs, nbr, coefv, fgm, im.sky, c, r0, Eb, Vb);
+                    strip_background_fg<L>(p, pairs, nbr, coefv, fgm, im, c, r0, Eb, Vb);
                 }
 #pragma unroll
                 for (int kk = 0; kk < L; ++kk) {
@@ -570,7 +570,7 @@ __global__ void __launch_bounds__(256) k_background_strips(BgArgs a, const Item*
             int c, r0, nrow;
             strip_geometry(p, it.start + q, L, c, r0, nrow);
             double Eb[L], Vb[L];
-            strip_background<L>(p, pairs, nbr, tabv, coefv, im.sky, c, r0, Eb, Vb, t2);
+            strip_background<L>(p, pairs, nbr, tabv, coefv, im, c, r0, Eb, Vb, t2);
 #pragma unroll
             for (int k = 0; k < L; ++k) {
                 if (k >= nrow) break;
@@ -659,7 +659,7 @@ __global__ void __launch_bounds__(256) k_gather_planes(RenderArgs a, const TileD
 #pragma unroll
     for (int k = 0; k < RP; ++k) {
         r[k] = td.r0 + lane / a.tile_w + k * rows_per_pass;
-        E[k] = im.sky;
+        E[k] = (r[k] < im.H && c < im.W) ? sky_at(im, r[k], c) : im.sky;
         V[k] = 0.0;
     }
     for (int j = td.list_begin; j < td.list_end; ++j) {

@@ -77,3 +77,20 @@ def test_sweep_config4_full_size_sampled(B, O, synth):
         say("  oracle value source", s, "neighbourhood", g.n_src)
         v = O.source_value(O.Problem(g), j)
         np.testing.assert_allclose(e[s], v[0] + v[1], rtol=1e-9, atol=1e-12 * (abs(v[2]) + abs(v[1])))
+
+
+def test_realistic_field_full_size_sampled(B, O, synth):
+    """The 2000-source field with astrometry, sky maps and brightness-sized patches, at the
+    benchmark's launch (graph replay): sampled ELBO and gradients against the oracle."""
+    f = synth.sdss_field(2000, realistic=True)
+    plan = B.Plan(f)
+    plan.use_graph(True)
+    theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+    say("case realistic field", plan.info())
+    e, g = plan.elbo_grad(theta)
+    e, g = e.cpu().numpy(), g.cpu().numpy()
+    for s in (3, 1001, 1998):
+        sub, j = neighbourhood(f, s)
+        val, gref, gabs = O.source_grad(O.Problem(sub), j)
+        np.testing.assert_allclose(e[s], val[0] + val[1], rtol=1e-9, atol=1e-12 * (abs(val[2]) + abs(val[1])))
+        assert np.all(np.abs(g[s, :27] - gref) <= 1e-9 * np.abs(gref) + 1e-12 * gabs), s

@@ -125,3 +125,17 @@ def test_domain_error_leaves_outputs(B, synth):
         plan.elbo(theta, out=elbo)
     assert e.value.code == B.CELESTE_EDOMAIN
     assert torch.all(elbo == 7.0)
+
+
+def test_newton_with_astrometry_and_sky_maps(B, N, synth):
+    f = synth.tiny(S=3, n_bands=2, size=19, side=13, seed=171, wcs=True, sky_map=True)
+    plan = B.Plan(f)
+    theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+    say("case newton wcs-sky")
+    elbo, radius = plan.newton(theta, [0, 1, 2], 2)
+    th_gpu, elbo, radius = theta.cpu().numpy(), elbo.cpu().numpy(), radius.cpu().numpy()
+    for s in range(3):
+        row, fend, R = N.newton_steps(f, f.theta, s, 2)
+        assert np.all(np.abs(th_gpu[s, :27] - row) <= 1e-6 * (1 + np.abs(row))), s
+        np.testing.assert_allclose(elbo[s], fend, rtol=1e-9)
+        assert radius[s] == R

@@ -278,3 +278,27 @@ def test_table_log_and_reciprocal_accuracy(B):
     rc = B.debug_math(B.FN_RCP, xd).cpu().numpy()
     ok = np.abs(x) < 1e307
     assert np.all(np.abs(rc[ok] - 1.0 / x[ok]) <= 1.0 * np.spacing(1.0 / x[ok]))
+
+
+def test_astrometry_and_sky_maps(B, O, synth):
+    """Rotated, scaled and sheared astrometry plus per-pixel sky maps: ELBO and gradient
+    (batched and plain), HVP, dense Hessian and total ELBO against the oracle."""
+    f = synth.tiny(S=3, n_bands=3, size=21, side=13, seed=161, psf_xi=True, anisotropic_psf=True,
+                   wcs=True, sky_map=True)
+    f.img_origin[1] = [0.6, -0.4]
+    plan, theta = check_field(B, O, f, range(3), name="wcs-sky")
+    rng = np.random.default_rng(3)
+    v = np.zeros((3, 32))
+    v[:, :27] = rng.standard_normal((3, 27))
+    say("case wcs-sky hvp / hessian / total")
+    hv = plan.hvp(theta, torch.tensor(v, device="cuda")).cpu().numpy()
+    P = O.Problem(f)
+    for s in range(3):
+        ref, habs = O.source_hvp(P, s, v[s])
+        within(hv[s, :27], ref, habs, "wcs-sky hvp s=%d" % s)
+    H = plan.hessian(theta, [2, 0]).cpu().numpy()
+    for k, s in enumerate([2, 0]):
+        Href = O.source_hessian(P, s)
+        np.testing.assert_allclose(H[k], Href, rtol=1e-8, atol=1e-11 * np.abs(Href).max())
+    t = plan.total_elbo(theta).cpu().numpy()[0]
+    np.testing.assert_allclose(t, O.total_elbo(P), rtol=1e-11)
