@@ -216,6 +216,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 512 MiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--workload", choices=("elbo_grad", "newton", "sweep"), default="elbo_grad")
+    ap.add_argument("--realistic", action="store_true",
+                    help="field with per-image astrometry, sky maps and brightness-sized patches")
     ap.add_argument("--newton-steps", type=int, default=None)
     ap.add_argument("--sweeps", type=int, default=3)
     args = ap.parse_args()
@@ -236,7 +238,7 @@ def main():
 
     log("generating the field ...")
     t = time.perf_counter()
-    f = synth.sdss_field(args.sources)
+    f = synth.sdss_field(args.sources, realistic=args.realistic)
     log("field ready in %.1f s: %d sources, %d boxes, %d visits" % (time.perf_counter() - t, f.n_src,
                                                                     len(f.boxes), f.visits()))
     dev = torch.device("cuda:0")
@@ -341,8 +343,10 @@ def main():
     out = {"metric": METRIC, "value": value, "unit": "source-pixel ELBO+grad evals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "SDSS-shaped field, %d sources, 5 bands x 2048x1489 px, batched "
-                                  "fused launch replayed as a HIP graph" % f.n_src,
+           "config": {"workload": "SDSS-shaped field%s, %d sources, 5 bands x 2048x1489 px, batched "
+                                  "fused launch replayed as a HIP graph"
+                                  % (" with astrometry, sky maps and brightness-sized patches" if args.realistic
+                                     else "", f.n_src),
                       "sources": f.n_src, "visits_per_step": visits, "form": "batched",
                       "launch": {k: info[k] for k in LAUNCH_KEYS},
                       "phase_ms": [round(v, 4) for v in phase],
