@@ -139,3 +139,22 @@ def test_newton_with_astrometry_and_sky_maps(B, N, synth):
         assert np.all(np.abs(th_gpu[s, :27] - row) <= 1e-6 * (1 + np.abs(row))), s
         np.testing.assert_allclose(elbo[s], fend, rtol=1e-9)
         assert radius[s] == R
+
+
+def test_plan_rejects_bad_image_metadata(B, synth):
+    """A sky map with a non-positive entry or a singular astrometry is refused at plan
+    creation (host check of the map, before anything else is allocated)."""
+    f = synth.tiny(S=2, n_bands=2, size=15, side=9, seed=181, wcs=True, sky_map=True)
+    bad = f.sky_map.copy()
+    bad[37] = 0.0
+    g = type(f)(**{**f.__dict__, "sky_map": bad})
+    with pytest.raises(B.CelesteError) as e:
+        B.Plan(g)
+    assert e.value.code == B.CELESTE_EINVAL
+    w = f.img_wcs.copy()
+    w[1] = [[1.0, 2.0], [0.5, 1.0]]
+    h = type(f)(**{**f.__dict__, "img_wcs": w})
+    with pytest.raises(B.CelesteError) as e:
+        B.Plan(h)
+    assert e.value.code == B.CELESTE_EINVAL
+    B.Plan(f)
