@@ -186,8 +186,6 @@ __device__ inline void pair_w(const T* p, const celeste_image& im, T* w) {
     w[W_SYY] = (a10 * a10) * sxx + (2.0 * a10 * a11) * sxy + (a11 * a11) * syy;
 }
 
-// Table of the 45 Gaussians (components: 3 star, then per PSF component 8 de Vaucouleurs
-// and 6 exponential) and the k1..k4 factors from the intermediates w of a pair.
 // Table entry c (0 <= c < NCOMP) of one box from its intermediates w.  Layout: the NPSF
 // star components, then per PSF component its NDEV de Vaucouleurs and NEXP exponential
 // components.  One lane per entry builds a box's table.

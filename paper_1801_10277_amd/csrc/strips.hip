@@ -316,8 +316,11 @@ __global__ void __launch_bounds__(256) k_render_strips(Sel sel, const Item* __re
 // ----------------------------------------------------------------------- adjoint
 // KK (double gradient passes over planes, stored backgrounds or stored values only): also
 // the brightness-factor block of each box's intermediate Hessian, per item into a.kk.
+// At least two waves per SIMD: the dual-number variants would otherwise take 256 VGPRs
+// plus accumulation registers and run one wave per SIMD; with the bound they spill a few
+// hundred bytes per lane and run 17% faster (the value variants fit without spilling).
 template <class T, int BASE, bool DERIV, int L, bool FGM, bool KK>
-__global__ void __launch_bounds__(256) k_adjoint_strips(AdjArgs a, const Item* __restrict__ items,
+__global__ void __launch_bounds__(256, 2) k_adjoint_strips(AdjArgs a, const Item* __restrict__ items,
                                                         const PairDev* __restrict__ pairs,
                                                         const celeste_image* __restrict__ images,
                                                         const int32_t* __restrict__ nbr,
