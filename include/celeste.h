@@ -146,16 +146,18 @@ typedef struct celeste_plan_info {
 
 typedef struct celeste_plan celeste_plan;
 
-/* Validates the geometry (Section III model: boxes inside images, positive PSF
- * covariances and weights, sky and iota > 0, mixture variances > 0, one box per
- * (source, image)), bins boxes into render tiles and work items, and allocates the
- * plan-owned device workspace.  The only call that allocates.  Synchronous.
- * Returns CELESTE_EINVAL (nothing allocated) or CELESTE_ENOMEM on failure. */
+/* Validates the problem (Section III model: boxes inside images, positive PSF
+ * covariances (eigenvalues >= 0.01 px^2) and weights, sky (every sky-map entry) and
+ * iota > 0, invertible astrometry, mixture variances > 0, one box per (source, image)),
+ * bins boxes into render tiles and work items, and allocates the plan-owned device
+ * workspace.  The only call that allocates.  Synchronous.  *out receives the plan.
+ * Returns CELESTE_EINVAL (nothing allocated), CELESTE_ENOMEM or CELESTE_EHIP. */
 int celeste_plan_create(const celeste_problem_desc* desc, celeste_plan** out);
 
 /* Frees the plan's own memory (never the caller's).  NULL is a no-op. */
 void celeste_plan_destroy(celeste_plan* plan);
 
+/* Sizes and the current launch configuration (host *info). */
 int celeste_plan_get_info(const celeste_plan* plan, celeste_plan_info* info);
 
 /* Per-source ELBO_s (Eq. (1) restricted to s's boxes, other sources fixed) into
@@ -178,7 +180,10 @@ int celeste_hvp(celeste_plan* plan, const double* theta, const double* v, double
                 double* grad, hipStream_t stream);
 
 /* Dense per-source Hessians hess[k][27][27] (device, row-major) of the n listed
- * sources src[k] (host list), from 27 tangent-adjoint passes. */
+ * sources src[k] (host list of distinct ids; CELESTE_EINVAL otherwise), the exact
+ * second derivatives of Section IV-D: each box's Hessian in its ten intermediates
+ * (brightness factors from the gradient pass, six tangent-adjoint passes for position,
+ * frac_dev and shape) pushed through the chain rule and its tangent, plus the KL. */
 int celeste_hessian(celeste_plan* plan, const double* theta, const int32_t* src, int n,
                     double* hess, hipStream_t stream);
 
@@ -259,7 +264,9 @@ const char* celeste_last_hip_error(void);
 enum { CELESTE_FN_EXP = 0, CELESTE_FN_LOG = 1, CELESTE_FN_RCP = 2 };
 int celeste_debug_math(int fn, const double* x, double* y, int n, hipStream_t stream);
 
+/* Text of a status code (static storage). */
 const char* celeste_status_string(int status);
+/* CELESTE_ABI_VERSION of the library. */
 int celeste_version(void);
 
 #ifdef __cplusplus
