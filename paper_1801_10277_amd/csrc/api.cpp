@@ -548,10 +548,10 @@ int background(celeste_plan* p, const Sel& items, hipStream_t st) {
 }
 
 // Dense Hessians of the listed sources (d_hess by list position).  Expects the item
-// partials and brightness-factor blocks (kk) of a double gradient pass over `item`.  With
-// six tangent passes along the boxes' other intermediates (position, frac_dev, shape
-// covariance) they give each box's 10x10 Hessian of its pixel terms; the chain rule and
-// its tangent assemble the 27x27 blocks.
+// partials and pixel-level Hessian rows (kk: brightness factors and frac_dev) of a double
+// gradient pass over `item` on stored backgrounds.  With five tangent passes along the
+// boxes' other intermediates (position, shape covariance) they give each box's 10x10
+// Hessian of its pixel terms; the chain rule and its tangent assemble the 27x27 blocks.
 int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& src, const Sel& pair, const Sel& item,
                                int base, hipStream_t st);
 
@@ -644,9 +644,11 @@ int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& 
                                int base, hipStream_t st) {
     HIPCHK(launch_pair_reduce(pair, p->d_pairs, p->d_partials, p->d_kk, false, 0, p->d_gw, p->d_hw, p->d_status,
                               st));
-    // the brightness-factor block came with the gradient pass; tangent passes along the six
-    // position / frac_dev / shape intermediates give the rest (by symmetry, their k rows too)
+    // the brightness-factor and frac_dev rows came with the gradient pass; tangent passes
+    // along the five position and shape intermediates give the rest (by symmetry, the other
+    // rows' remaining entries too)
     for (int i = W_UX; i < NW; ++i) {
+        if (i == W_FDEV) continue;
         CHK(prep(p, theta, pair, true, DIR_W, nullptr, i, st));
         CHK(adjoint(p, item, nullptr, true, base, true, st));
         HIPCHK(launch_pair_reduce(pair, p->d_pairs, p->d_partials, nullptr, true, i, p->d_gw, p->d_hw, p->d_status,
@@ -1043,10 +1045,11 @@ int celeste_hessian(celeste_plan* p, const double* theta, const int32_t* src, in
     const Sel si{p->d_list_item, 0, (int32_t)hs.item.size()};
     const Scope all = scope_all(p);
     CHK(validate_theta(p, theta, nullptr, nullptr, p->n_src, st));
+    // stored per-visit backgrounds, as in a Newton iteration
     CHK(prep(p, theta, all.pair, false, DIR_NONE, nullptr, 0, st));
-    CHK(render(p, st));
-    CHK(adjoint(p, si, nullptr, false, BASE_PLANES, true, st, 0, true));
-    CHK(hessian_from_intermediates(p, theta, ss, sp, si, BASE_PLANES, st));
+    CHK(background(p, si, st));
+    CHK(adjoint(p, si, nullptr, false, BASE_BG, true, st, 0, true));
+    CHK(hessian_from_intermediates(p, theta, ss, sp, si, BASE_BG, st));
     HIPCHK(hipMemcpyAsync(hess, p->d_hess, (size_t)n * NP * NP * sizeof(double), hipMemcpyDeviceToDevice, st));
     return CELESTE_OK;
 }

@@ -50,10 +50,11 @@ enum AccField {
 // galaxy shape covariance.  The order matches the accumulators A_K1..A_SYY (index + 1).
 enum WField { W_K1 = 0, W_K2, W_K3, W_K4, W_UX, W_UY, W_FDEV, W_SXX, W_SXY, W_SYY, NW };
 
-// Second derivatives of a box's pixel sum in its brightness factors k1..k4 (the k-block of
-// the intermediate Hessian): (k1k1, k1k2, k2k2, k1k3, k1k4, k2k3, k2k4); the (k3, k4) block
-// is zero.  Stored per work item with one pad entry.
-enum KKField { KK_11, KK_12, KK_22, KK_13, KK_14, KK_23, KK_24, NKK_USED, NKK = 8 };
+// Second derivatives of a box's pixel sum in its brightness factors k1..k4 and frac_dev f
+// (the pixel-level rows of the intermediate Hessian): (k1k1, k1k2, k2k2, k1k3, k1k4, k2k3,
+// k2k4, fk1, fk2, fk3, fk4, ff); the (k3, k4) block is zero.  Stored per work item, padded.
+enum KKField { KK_11, KK_12, KK_22, KK_13, KK_14, KK_23, KK_24, KK_F1, KK_F2, KK_F3, KK_F4, KK_FF, NKK_USED,
+               NKK = 16 };
 
 struct PairDev {              // one box (source, image)
     int32_t src, img, r0, c0, h, w;

@@ -262,18 +262,20 @@ __global__ void __launch_bounds__(128) k_pair_reduce(Sel sel, const PairDev* __r
         double* o = gw + (size_t)pi * NACC;
         for (int f = 0; f < NACC; ++f) o[f] = z[f];
         if (kk) {
-            // brightness-factor block hw[pair][0..3][0..3] (symmetric; the (k3, k4) block is 0)
+            // pixel-level block of hw[pair] over (k1..k4, frac_dev), symmetric; (k3, k4) is 0
             double h[NKK_USED];
             for (int f = 0; f < NKK_USED; ++f) h[f] = 0.0;
             for (int it = pd.item_begin; it < pd.item_end; ++it)
                 for (int f = 0; f < NKK_USED; ++f) h[f] += kk[(size_t)it * NKK + f];
-            const double blk[4][4] = {{h[KK_11], h[KK_12], h[KK_13], h[KK_14]},
-                                      {h[KK_12], h[KK_22], h[KK_23], h[KK_24]},
-                                      {h[KK_13], h[KK_23], 0.0, 0.0},
-                                      {h[KK_14], h[KK_24], 0.0, 0.0}};
+            const double blk[5][5] = {{h[KK_11], h[KK_12], h[KK_13], h[KK_14], h[KK_F1]},
+                                      {h[KK_12], h[KK_22], h[KK_23], h[KK_24], h[KK_F2]},
+                                      {h[KK_13], h[KK_23], 0.0, 0.0, h[KK_F3]},
+                                      {h[KK_14], h[KK_24], 0.0, 0.0, h[KK_F4]},
+                                      {h[KK_F1], h[KK_F2], h[KK_F3], h[KK_F4], h[KK_FF]}};
+            const int idx[5] = {W_K1, W_K2, W_K3, W_K4, W_FDEV};
             double* hb = hw + (size_t)pi * NW * NW;
-            for (int i = 0; i < 4; ++i)
-                for (int f = 0; f < 4; ++f) hb[i * NW + f] = blk[i][f];
+            for (int i = 0; i < 5; ++i)
+                for (int f = 0; f < 5; ++f) hb[idx[i] * NW + idx[f]] = blk[i][f];
         }
     }
 }
@@ -307,10 +309,12 @@ __global__ void __launch_bounds__(128) k_assemble_hessian(Sel srcs, Geometry g, 
         for (int a = 0; a < NW; ++a) {
             double tz = 0.0;
             // hw[dir][f] = c_f d2L / dw_dir dw_f with c = 2 for the A_SXX, A_SYY accumulators
-            // and 1 otherwise.  Rows 0..3 (brightness directions) hold only their k-block; the
-            // rest of those rows is c_a times the symmetric entry of the tangent pass along a.
+            // and 1 otherwise.  The pixel-level rows (brightness factors, frac_dev) hold only
+            // their own block; the rest of such a row is c_a times the symmetric entry of the
+            // tangent pass along a.
             for (int i = 0; i < NW; ++i) {
-                const double hia = (i < 4 && a >= 4) ? (a == W_SXX || a == W_SYY ? 2.0 : 1.0) * h[a * NW + i]
+                const bool pix_i = i < 4 || i == W_FDEV, pix_a = a < 4 || a == W_FDEV;
+                const double hia = (pix_i && !pix_a) ? (a == W_SXX || a == W_SYY ? 2.0 : 1.0) * h[a * NW + i]
                                                      : h[i * NW + a];
                 tz += hia * w[i].t;
             }

@@ -43,12 +43,18 @@ __device__ __forceinline__ void strip_seed(const T* e, double px, double py0, T&
 }
 
 // Pass A: star and galaxy profile values down the strip.
-template <class T, int L>
+// SGN: also fgd[k] = sum of the de Vaucouleurs minus the exponential components (d fg /
+// d frac_dev).
+template <class T, int L, bool SGN = false>
 __device__ __forceinline__ void strip_values(const T* __restrict__ tab, double px, double py0, T* fs, T* fg,
-                                             const double* __restrict__ t2) {
+                                             const double* __restrict__ t2, T* fgd = nullptr) {
     const T zero = scalar_traits<T>::make(0.0, 0.0);
 #pragma unroll
     for (int k = 0; k < L; ++k) fs[k] = fg[k] = zero;
+    if constexpr (SGN) {
+#pragma unroll
+        for (int k = 0; k < L; ++k) fgd[k] = zero;
+    }
 #pragma unroll
     for (int c = 0; c < NPSF; ++c) {
         const T* e = tab + c * CST;
@@ -73,6 +79,7 @@ __device__ __forceinline__ void strip_values(const T* __restrict__ tab, double p
 #pragma unroll
         for (int k = 0; k < L; ++k) {
             fg[k] += n * wt;
+            if constexpr (SGN) fgd[k] += n * e[F_SGN];
             if (k + 1 < L) {
                 n = n * rt;
                 rt = rt * rdy;
@@ -173,11 +180,18 @@ __device__ __forceinline__ void strip_pixel(double x, T E, T V, T fs, T fg, cons
 // (fs, fg, 0, 0) and dV/dk = (-2 Es fs, -2 Es fg, fs^2, fg^2), d2V/dk1dk1 = -2 fs^2,
 // d2V/dk1dk2 = -2 fs fg, d2V/dk2dk2 = -2 fg^2:
 // h_ij = l_EE E_i E_j + l_EV (E_i V_j + V_i E_j) + l_V V_ij.
-__device__ __forceinline__ void pixel_kk(double x, double E, double V, double fs, double fg, const double* k,
-                                         double* h) {
+// frac_dev f enters only through the galaxy profile, fg = f fgd_dev + (1 - f) fg_exp, so
+// dfg/df = fgd (the dev minus the exp profile) and, with E_f = k2 fgd,
+// V_f = 2 fgd (k4 fg - Es k2), V_ff = 2 fgd^2 (k4 - k2^2), V_f1 = -2 fs k2 fgd,
+// V_f2 = -2 (fg k2 + Es) fgd, V_f4 = 2 fg fgd, E_f2 = fgd:
+// h_fi = l_EE E_f E_i + l_EV (E_f V_i + V_f E_i) + l_V V_fi + l_E E_fi.
+__device__ __forceinline__ void pixel_kk(double x, double E, double V, double fs, double fg, double fgd,
+                                         const double* k, double* h) {
     const double inv = frcp(E);
     const double inv2 = inv * inv;
-    const double lEE = -x * inv2 * (1.0 + 3.0 * (V * inv2));
+    const double r = V * inv2;
+    const double lE = x * inv * (1.0 + r) - 1.0;
+    const double lEE = -x * inv2 * (1.0 + 3.0 * r);
     const double lEV = x * inv2 * inv;
     const double lV = -0.5 * x * inv2;
     const double Es = k[C_K1] * fs + k[C_K2] * fg;
@@ -190,6 +204,14 @@ __device__ __forceinline__ void pixel_kk(double x, double E, double V, double fs
     h[KK_14] += a * (fg * fg);
     h[KK_23] += b * (fs * fs);
     h[KK_24] += b * (fg * fg);
+    const double Ef = k[C_K2] * fgd;
+    const double Vf = 2.0 * fgd * (k[C_K4] * fg - Es * k[C_K2]);
+    h[KK_F1] += lEE * (Ef * fs) + lEV * (Ef * (-2.0 * Es * fs) + Vf * fs) + lV * (-2.0 * fs * k[C_K2] * fgd);
+    h[KK_F2] += lEE * (Ef * fg) + lEV * (Ef * (-2.0 * Es * fg) + Vf * fg) +
+                lV * (-2.0 * (fg * k[C_K2] + Es) * fgd) + lE * fgd;
+    h[KK_F3] += lEV * Ef * (fs * fs);
+    h[KK_F4] += lEV * Ef * (fg * fg) + lV * (2.0 * fg * fgd);
+    h[KK_FF] += lEE * (Ef * Ef) + 2.0 * lEV * (Ef * Vf) + lV * (2.0 * fgd * fgd * (k[C_K4] - k[C_K2] * k[C_K2]));
 }
 
 // Sky plus the light of every other box of the image that covers each row of the strip.
@@ -401,7 +423,6 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_strips(AdjArgs a, const Item
                                 V = Vb[kk] + Vs;
                             }
                             strip_pixel<T, true>(cx_, E, V, fsk, fgk, k, acc, gs, gg, tl);
-                            if constexpr (KK) pixel_kk(cx_, E, V, fsk, fgk, k, kh);
                         }
                         Gs[kk] = gs;
                         Gg[kk] = gg;
@@ -417,8 +438,8 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_strips(AdjArgs a, const Item
                 }
                 if constexpr (DERIV && !FGM && (BASE == BASE_PLANES || BASE == BASE_BG)) {
                     // Own values from pass A, then the pixel rows streamed as above.
-                    T fs[L], fg[L];
-                    strip_values<T, L>(tab, px, py0, fs, fg, t2);
+                    T fs[L], fg[L], fgd[KK ? L : 1];
+                    strip_values<T, L, KK>(tab, px, py0, fs, fg, t2, fgd);
                     const double* xs_i = xs + im.pix_offset;
                     auto row_load = [&](int rr, double& x_, double& e_, double& v_) {
                         const size_t gi = (size_t)(r0 + rr) * im.W + c;
@@ -451,7 +472,7 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_strips(AdjArgs a, const Item
                                 V = cv_ + Vs;
                             }
                             strip_pixel<T, true>(cx_, E, V, fs[kk], fg[kk], k, acc, gs, gg, tl);
-                            if constexpr (KK) pixel_kk(cx_, E, V, fs[kk], fg[kk], k, kh);
+                            if constexpr (KK) pixel_kk(cx_, E, V, fs[kk], fg[kk], fgd[kk], k, kh);
                         }
                         fs[kk] = gs;
                         fg[kk] = gg;
@@ -788,24 +809,19 @@ static hipError_t adjs(const AdjArgs& a, int grid, int wpb, hipStream_t st) {
     constexpr bool is_double = std::is_same<T, double>::value;
     // own profile values from the render's stored values: double passes over planes or stored values
     constexpr bool own_fg = is_double && (BASE == BASE_PLANES || BASE == BASE_FG);
-    // the k-block of the intermediate Hessian: double gradient passes on the streamed paths
-    constexpr bool can_kk = is_double && DERIV && (BASE == BASE_PLANES || BASE == BASE_FG || BASE == BASE_BG);
+    // the pixel-level rows of the intermediate Hessian: double gradient passes over stored
+    // backgrounds (own values from pass A, which also gives d fg / d frac_dev)
+    constexpr bool can_kk = is_double && DERIV && BASE == BASE_BG;
     if (a.kk && !can_kk) return hipErrorInvalidValue;
-    if constexpr (own_fg) {
-        if (a.fg) {
-            if constexpr (can_kk) {
-                if (a.kk) {
-                    adjk<T, BASE, DERIV, L, true, true>(a, grid, wpb, st);
-                    return hipSuccess;
-                }
-            }
-            adjk<T, BASE, DERIV, L, true, false>(a, grid, wpb, st);
+    if constexpr (can_kk) {
+        if (a.kk) {
+            adjk<T, BASE, DERIV, L, false, true>(a, grid, wpb, st);
             return hipSuccess;
         }
     }
-    if constexpr (can_kk && BASE != BASE_FG) {
-        if (a.kk) {
-            adjk<T, BASE, DERIV, L, false, true>(a, grid, wpb, st);
+    if constexpr (own_fg) {
+        if (a.fg) {
+            adjk<T, BASE, DERIV, L, true, false>(a, grid, wpb, st);
             return hipSuccess;
         }
     }
