@@ -446,16 +446,18 @@ int render_tiles(celeste_plan* p, bool sums, hipStream_t st) {
 
 // E and V planes of all sources.  Mode 2: every box's own profile values (one parallel
 // strip pass), then a tile gather; mode 1: tiles evaluate the Gaussians; mode 0: sky fill,
-// then one strip launch per conflict-free class.
-int render(celeste_plan* p, hipStream_t st) {
+// then one strip launch per conflict-free class.  sums: also the per-tile sums of the
+// pixel terms of covered pixels into d_tile_sums (modes 0 and 1 then use the tiles).
+int render(celeste_plan* p, hipStream_t st, bool sums = false) {
     p->fg_valid = false;
-    if (p->render_mode == 1) return render_tiles(p, false, st);
+    if (p->render_mode == 1 || (sums && p->render_mode == 0)) return render_tiles(p, sums, st);
     if (p->render_mode == 2 || p->render_mode == 3) {
         const Geometry g = p->geom();
         const Sel all{nullptr, 0, (int32_t)p->items.size()};
         HIPCHK(launch_strip_fg(all, g, p->d_tab1, p->d_fg, p->rows, p->persistent_grid(), p->wpb, p->d_status, st));
         p->fg_valid = true;
-        if (p->render_mode == 3) return CELESTE_OK;   // no planes: the adjoint gathers from stored values
+        // mode 3: no planes (the adjoint gathers from stored values) unless sums are asked for
+        if (p->render_mode == 3 && !sums) return CELESTE_OK;
         RenderArgs a{};
         a.g = g;
         a.tiles = p->d_tiles;
@@ -466,6 +468,7 @@ int render(celeste_plan* p, hipStream_t st) {
         a.coef = p->d_coef1;
         a.E = p->d_E;
         a.V = p->d_V;
+        a.tile_sums = sums ? p->d_tile_sums : nullptr;
         a.status = p->d_status;
         HIPCHK(launch_gather_planes(a, p->d_fg, 4, st));
         p->fg_valid = true;
@@ -481,8 +484,8 @@ int render(celeste_plan* p, hipStream_t st) {
     return CELESTE_OK;
 }
 
-// kk: also the brightness-factor block of every box's intermediate Hessian (double gradient
-// passes that precede hessian_from_intermediates).
+// kk: also the pixel-level rows (brightness factors, frac_dev) of every box's intermediate
+// Hessian (double gradient passes on stored backgrounds before hessian_from_intermediates).
 int adjoint(celeste_plan* p, const Sel& items, const uint8_t* active, bool tangent, int base, bool deriv,
             hipStream_t st, int grid_override = 0, bool kk = false) {
     AdjArgs a{};
@@ -1059,7 +1062,7 @@ int celeste_total_elbo(celeste_plan* p, const double* theta, double* out, hipStr
     const Scope sc = scope_all(p);
     CHK(validate_theta(p, theta, nullptr, nullptr, p->n_src, st));
     CHK(prep(p, theta, sc.pair, false, DIR_NONE, nullptr, 0, st));
-    CHK(render_tiles(p, true, st));
+    CHK(render(p, st, true));
     HIPCHK(launch_tile_total(p->d_tile_sums, (int)p->tiles.size(), theta, p->consts, p->n_src, out, p->d_status, st));
     return CELESTE_OK;
 }

@@ -2,7 +2,8 @@
 //
 // Work decomposition:
 //  * k_prep:      one wave per (source, image) box, one lane per table entry, builds the
-//                 box's 45-Gaussian table and brightness factors (value, or value + tangent).
+//                 box's 45-Gaussian table (staged in LDS, written out contiguously) and
+//                 brightness factors (value, or value + tangent).
 //  * k_render:    one wave per render tile sums E[F] and Var[F] of every box that
 //                 covers each pixel, in box order (deterministic, no atomics), and
 //                 optionally the pixel terms of covered pixels (total ELBO).
@@ -64,33 +65,43 @@ __global__ void __launch_bounds__(256) k_validate(const double* __restrict__ the
 template <class T>
 __global__ void __launch_bounds__(256) k_prep(PrepArgs a) {
     if (*a.status) return;
-    const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    // the box's table is staged in LDS and written out contiguously by the whole wave
+    constexpr int TW = NCOMP * CST * scalar_traits<T>::width;   // doubles per table
+    __shared__ double stage[4][TW];
+    const int wave = threadIdx.x >> 6;
+    const int j = blockIdx.x * (blockDim.x >> 6) + wave;
     const int lane = threadIdx.x & 63;
-    if (j >= a.pairs.n) return;
-    const int pi = sel_at(a.pairs, j);
-    const PairDev pd = a.g.pairs[pi];
-    const celeste_image& im = a.g.images[pd.img];
-    T* tab = reinterpret_cast<T*>(a.tab) + (size_t)pi * NCOMP * CST;
-    T* coef = reinterpret_cast<T*>(a.coef) + (size_t)pi * NCOEF;
-    T w[NW];
-    if (a.dir_mode == DIR_W) {
-        // tangent along one of the box's intermediates
-        double p[NP], wv[NW];
-        for (int i = 0; i < NP; ++i) p[i] = a.theta[(size_t)pd.src * ROW + i];
-        pair_w<double>(p, im, wv);
-        for (int i = 0; i < NW; ++i) w[i] = scalar_traits<T>::make(wv[i], i == a.dir_unit ? 1.0 : 0.0);
-    } else {
-        T p[NP];
-        for (int i = 0; i < NP; ++i) p[i] = seed<T>(a.theta, a.dir, a.dir_mode, a.dir_unit, pd.src, i);
-        pair_w<T>(p, im, w);
+    const bool valid = j < a.pairs.n;
+    const int pi = valid ? sel_at(a.pairs, j) : 0;
+    if (valid) {
+        const PairDev pd = a.g.pairs[pi];
+        const celeste_image& im = a.g.images[pd.img];
+        T* coef = reinterpret_cast<T*>(a.coef) + (size_t)pi * NCOEF;
+        T w[NW];
+        if (a.dir_mode == DIR_W) {
+            // tangent along one of the box's intermediates
+            double p[NP], wd[NW];
+            for (int i = 0; i < NP; ++i) p[i] = a.theta[(size_t)pd.src * ROW + i];
+            pair_w<double>(p, im, wd);
+            for (int i = 0; i < NW; ++i) w[i] = scalar_traits<T>::make(wd[i], i == a.dir_unit ? 1.0 : 0.0);
+        } else {
+            T p[NP];
+            for (int i = 0; i < NP; ++i) p[i] = seed<T>(a.theta, a.dir, a.dir_mode, a.dir_unit, pd.src, i);
+            pair_w<T>(p, im, w);
+        }
+        if (lane < NCOMP) {
+            build_comp_from_w<T>(w, im, a.g.consts, lane, reinterpret_cast<T*>(stage[wave]) + lane * CST);
+        } else if (lane == NCOMP) {
+            coef[C_K1] = w[W_K1];
+            coef[C_K2] = w[W_K2];
+            coef[C_K3] = w[W_K3];
+            coef[C_K4] = w[W_K4];
+        }
     }
-    if (lane < NCOMP) {
-        build_comp_from_w<T>(w, im, a.g.consts, lane, tab + lane * CST);
-    } else if (lane == NCOMP) {
-        coef[C_K1] = w[W_K1];
-        coef[C_K2] = w[W_K2];
-        coef[C_K3] = w[W_K3];
-        coef[C_K4] = w[W_K4];
+    __syncthreads();
+    if (valid) {
+        double* out = reinterpret_cast<double*>(a.tab) + (size_t)pi * TW;
+        for (int i = lane; i < TW; i += 64) out[i] = stage[wave][i];
     }
 }
 

@@ -662,14 +662,15 @@ __global__ void __launch_bounds__(256) k_strip_fg(Sel sel, const Item* __restric
 // Render pass 2: E and V of every pixel of a tile, summing the stored own values of the
 // tile's boxes in ascending box order (deterministic, no atomics).  Tile = (64 / tile_w * RP)
 // rows x tile_w columns; lane l owns rows l / tile_w + k (64 / tile_w), k < RP.
-template <int RP>
+template <int RP, bool SUMS>
 __global__ void __launch_bounds__(256) k_gather_planes(RenderArgs a, const TileDev* __restrict__ tiles,
                                                        const int32_t* __restrict__ tile_list,
                                                        const PairDev* __restrict__ pairs,
                                                        const celeste_image* __restrict__ images,
                                                        const double* __restrict__ coef,
                                                        const double* __restrict__ fgm, double* __restrict__ Eout,
-                                                       double* __restrict__ Vout) {
+                                                       double* __restrict__ Vout, const double* __restrict__ xs,
+                                                       double* __restrict__ tile_sums) {
     if (*a.status) return;
     const int lane = threadIdx.x & 63;
     const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -680,11 +681,13 @@ __global__ void __launch_bounds__(256) k_gather_planes(RenderArgs a, const TileD
     const int c = td.c0 + lane % a.tile_w;
     int r[RP];
     double E[RP], V[RP];
+    bool covered[RP];
 #pragma unroll
     for (int k = 0; k < RP; ++k) {
         r[k] = td.r0 + lane / a.tile_w + k * rows_per_pass;
         E[k] = (r[k] < im.H && c < im.W) ? sky_at(im, r[k], c) : im.sky;
         V[k] = 0.0;
+        covered[k] = false;
     }
     for (int j = td.list_begin; j < td.list_end; ++j) {
         const int pi = __builtin_amdgcn_readfirstlane(tile_list[j]);
@@ -699,14 +702,29 @@ __global__ void __launch_bounds__(256) k_gather_planes(RenderArgs a, const TileD
             const double Et = k1 * fs + k2 * fg;
             E[k] += Et;
             V[k] += k3 * fs * fs + k4 * fg * fg - Et * Et;
+            if constexpr (SUMS) covered[k] = true;
         }
     }
+    double l = 0.0;
 #pragma unroll
     for (int k = 0; k < RP; ++k) {
         if (r[k] >= im.H || c >= im.W) continue;
         const size_t gi = (size_t)im.pix_offset + (size_t)r[k] * im.W + c;
         Eout[gi] = E[k];
         Vout[gi] = V[k];
+        if constexpr (SUMS) {
+            // pixel term of a pixel some box covers (the total ELBO counts each such pixel once)
+            const double x = xs[gi];
+            if (covered[k] && x == x) {
+                double lk = x * (log(E[k]) - 0.5 * V[k] / (E[k] * E[k])) - E[k];
+                if (a.g.consts.flags & CELESTE_INCLUDE_LGAMMA) lk -= lgamma(x + 1.0);
+                l += lk;
+            }
+        }
+    }
+    if constexpr (SUMS) {
+        l = wave_sum(l);
+        if (lane == 0) tile_sums[t] = l;
     }
 }
 
@@ -767,11 +785,18 @@ hipError_t launch_gather_planes(const RenderArgs& a, const double* fg, int wpb, 
     const dim3 grid((a.n_tiles + wpb - 1) / wpb);
     const int rp = a.tile_h * a.tile_w / 64;
     const Geometry& g = a.g;
-#define GATHER_ARGS a, a.tiles, a.tile_list, g.pairs, g.images, a.coef, fg, a.E, a.V
-    if (rp == 1) hipLaunchKernelGGL(k_gather_planes<1>, grid, dim3(64 * wpb), 0, st, GATHER_ARGS);
-    else if (rp == 2) hipLaunchKernelGGL(k_gather_planes<2>, grid, dim3(64 * wpb), 0, st, GATHER_ARGS);
-    else if (rp == 4) hipLaunchKernelGGL(k_gather_planes<4>, grid, dim3(64 * wpb), 0, st, GATHER_ARGS);
-    else return hipErrorInvalidValue;
+#define GATHER_ARGS a, a.tiles, a.tile_list, g.pairs, g.images, a.coef, fg, a.E, a.V, g.x, a.tile_sums
+    if (a.tile_sums) {
+        if (rp == 1) hipLaunchKernelGGL((k_gather_planes<1, true>), grid, dim3(64 * wpb), 0, st, GATHER_ARGS);
+        else if (rp == 2) hipLaunchKernelGGL((k_gather_planes<2, true>), grid, dim3(64 * wpb), 0, st, GATHER_ARGS);
+        else if (rp == 4) hipLaunchKernelGGL((k_gather_planes<4, true>), grid, dim3(64 * wpb), 0, st, GATHER_ARGS);
+        else return hipErrorInvalidValue;
+    } else {
+        if (rp == 1) hipLaunchKernelGGL((k_gather_planes<1, false>), grid, dim3(64 * wpb), 0, st, GATHER_ARGS);
+        else if (rp == 2) hipLaunchKernelGGL((k_gather_planes<2, false>), grid, dim3(64 * wpb), 0, st, GATHER_ARGS);
+        else if (rp == 4) hipLaunchKernelGGL((k_gather_planes<4, false>), grid, dim3(64 * wpb), 0, st, GATHER_ARGS);
+        else return hipErrorInvalidValue;
+    }
 #undef GATHER_ARGS
     return hipGetLastError();
 }
