@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CELESTE_ABI_VERSION 3
+#define CELESTE_ABI_VERSION 4
 
 enum celeste_status {
     CELESTE_OK = 0,
@@ -210,6 +210,39 @@ int celeste_total_elbo(celeste_plan* plan, const double* theta, double* out, hip
  * batch_src (host [n_src]) receive the CSR schedule, *n_batches its length. */
 int celeste_color_batches(const celeste_plan* plan, uint64_t seed, int32_t* batch_ptr,
                           int32_t* batch_src, int32_t* n_batches);
+
+/* Conflict graph of Section IV-D: sources s != t are adjacent when a patch box of s and
+ * a patch box of t lie on the same image and share a pixel.  Host call.  adj_ptr (host
+ * [n_src + 1]) and adj (host [cap]) receive it as CSR, each row sorted ascending without
+ * repeats; *n_adj (host) receives the number of entries (twice the edge count).  If cap
+ * is smaller than that, nothing is written but *n_adj and the call returns
+ * CELESTE_EINVAL, so a first call with cap = 0 sizes the buffer. */
+int celeste_conflict_graph(const celeste_plan* plan, int32_t* adj_ptr, int32_t* adj, int64_t cap,
+                           int64_t* n_adj);
+
+/* Cyclades schedule (Section IV-D, after Pan et al. 2016) as conflict-free batches for
+ * celeste_sweep.  Pure host code: needs no plan and no GPU.
+ *   n, adj_ptr [n + 1], adj: an undirected conflict graph as CSR (host; each edge in
+ *     both rows; repeats allowed).
+ *   order [n] (host): a permutation of 0..n-1, the random sampling order drawn by the
+ *     caller.  It is cut into consecutive samples of sample_size sources (the last one
+ *     shorter); every source is sampled once (without replacement).
+ *   Within a sample, the conflict graph restricted to the sample splits into connected
+ *   components.  Components run side by side; the members of one component run one
+ *   after another in sample order.  Batch r of a sample (a "round") holds the r-th member
+ *   of every component that has more than r members, listed in sample order, so a
+ *   sample of largest component size R yields R batches, and the batches of a sample
+ *   precede those of the next.  No two members of a batch are adjacent, and the result
+ *   of celeste_sweep over one epoch equals serial block coordinate ascent in `order`.
+ *   batch_ptr (host [n + 1]) and batch_src (host [n]) receive the CSR schedule,
+ *   *n_batches its length, *n_components (host, or NULL) the number of components
+ *   summed over samples.
+ * CELESTE_EINVAL for n < 0, sample_size < 1, a row pointer that is not non-decreasing
+ * from 0, a neighbour outside 0..n-1, or an order that is not a permutation (outputs
+ * untouched). */
+int celeste_cyclades_batches(int32_t n, const int32_t* adj_ptr, const int32_t* adj,
+                             const int32_t* order, int32_t sample_size, int32_t* batch_ptr,
+                             int32_t* batch_src, int32_t* n_batches, int32_t* n_components);
 
 /* Block coordinate ascent: n_sweeps passes over the batches (host CSR batch_ptr,
  * batch_src), each batch optimised by params->newton_steps Newton trust-region

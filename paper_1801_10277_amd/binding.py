@@ -27,7 +27,8 @@ EXPORTS = ["celeste_plan_create", "celeste_plan_destroy", "celeste_plan_get_info
            "celeste_elbo_grad", "celeste_hvp", "celeste_hessian", "celeste_newton", "celeste_total_elbo",
            "celeste_color_batches", "celeste_sweep", "celeste_plan_set_launch", "celeste_autotune",
            "celeste_plan_use_graph", "celeste_plan_profile", "celeste_plan_status", "celeste_last_hip_error",
-           "celeste_status_string", "celeste_version", "celeste_debug_math"]
+           "celeste_status_string", "celeste_version", "celeste_debug_math", "celeste_conflict_graph",
+           "celeste_cyclades_batches"]
 
 
 class celeste_image(C.Structure):
@@ -91,6 +92,8 @@ def lib():
     L.celeste_total_elbo.argtypes = [vp, dp, dp, vp]
     L.celeste_color_batches.argtypes = [vp, C.c_uint64, ip, ip, ip]
     L.celeste_sweep.argtypes = [vp, dp, ip, ip, C.c_int, C.c_int, C.POINTER(celeste_tr_params), dp, vp]
+    L.celeste_conflict_graph.argtypes = [vp, ip, ip, C.c_int64, C.POINTER(C.c_int64)]
+    L.celeste_cyclades_batches.argtypes = [C.c_int32, ip, ip, ip, C.c_int32, ip, ip, ip, ip]
     L.celeste_plan_set_launch.argtypes = [vp] + [C.c_int] * 8
     L.celeste_autotune.argtypes = [vp, dp, C.c_int, C.POINTER(C.c_double), vp]
     L.celeste_plan_use_graph.argtypes = [vp, C.c_int]
@@ -135,6 +138,29 @@ def tr_params(radius0=1.0, radius_max=1e3, eta_accept=0.1, gtol=1e-8, newton_ste
 
 
 FN_EXP, FN_LOG, FN_RCP = 0, 1, 2
+
+
+def _i32p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def cyclades_batches(adj_ptr, adj, order, sample_size):
+    """celeste_cyclades_batches on host arrays (no GPU needed): (batch_ptr, batch_src,
+    n_components)."""
+    adj_ptr = np.ascontiguousarray(adj_ptr, np.int32)
+    adj = np.ascontiguousarray(adj, np.int32)
+    order = np.ascontiguousarray(order, np.int32)
+    n = len(adj_ptr) - 1
+    if len(order) != n:
+        raise CelesteError(CELESTE_EINVAL, "celeste_cyclades_batches")
+    bp = np.zeros(n + 1, np.int32)
+    bs = np.zeros(max(n, 1), np.int32)
+    nb, nc = C.c_int32(), C.c_int32()
+    check(lib().celeste_cyclades_batches(n, _i32p(adj_ptr), _i32p(adj) if len(adj) else None,
+                                         _i32p(order) if n else None, sample_size, _i32p(bp), _i32p(bs),
+                                         C.byref(nb), C.byref(nc)), "celeste_cyclades_batches")
+    return bp[:nb.value + 1].copy(), bs[:n].copy(), nc.value
+
 
 
 def debug_math(fn, x):
@@ -290,6 +316,27 @@ class Plan:
                                           src.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(nb)),
               "celeste_color_batches")
         return ptr[:nb.value + 1].copy(), src
+
+    def conflict_graph(self):
+        """Box-overlap conflict graph as host CSR (adj_ptr [S + 1], adj)."""
+        ptr = np.zeros(self.S + 1, np.int32)
+        n = C.c_int64()
+        code = lib().celeste_conflict_graph(self.h, _i32p(ptr), None, 0, C.byref(n))
+        if code != CELESTE_EINVAL or n.value == 0:
+            check(code, "celeste_conflict_graph")
+        adj = np.zeros(max(n.value, 1), np.int32)
+        check(lib().celeste_conflict_graph(self.h, _i32p(ptr), _i32p(adj), len(adj), C.byref(n)),
+              "celeste_conflict_graph")
+        return ptr, adj[:n.value].copy()
+
+    def cyclades_batches(self, seed, sample_size, graph=None):
+        """Cyclades schedule of one epoch: the sampling order is a seeded permutation of the
+        sources; `graph` is conflict_graph()'s result, fetched when None.  Returns
+        (batch_ptr, batch_src, n_components, order)."""
+        order = np.random.default_rng(seed).permutation(self.S).astype(np.int32)
+        ptr, adj = self.conflict_graph() if graph is None else graph
+        bp, bs, nc = cyclades_batches(ptr, adj, order, sample_size)
+        return bp, bs, nc, order
 
     def sweep(self, theta, batch_ptr, batch_src, n_sweeps, params=None):
         import torch

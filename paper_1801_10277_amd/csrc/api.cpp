@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1139,6 +1140,100 @@ int celeste_color_batches(const celeste_plan* p, uint64_t seed, int32_t* batch_p
     std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
     for (int s = 0; s < S; ++s) batch_src[fill[color[s]]++] = s;
     *n_batches = n_col;
+    return CELESTE_OK;
+}
+
+int celeste_conflict_graph(const celeste_plan* p, int32_t* adj_ptr, int32_t* adj, int64_t cap, int64_t* n_adj) {
+    if (!p || !adj_ptr || !n_adj || cap < 0 || (cap > 0 && !adj)) return CELESTE_EINVAL;
+    const int S = p->n_src;
+    std::vector<std::vector<int32_t>> rows(S);
+    for (const PairDev& pd : p->pairs)
+        for (int k = pd.nbr_begin; k < pd.nbr_end; ++k) {
+            const int t = p->pairs[p->nbr[k]].src;
+            if (t != pd.src) rows[pd.src].push_back(t);
+        }
+    int64_t total = 0;
+    for (auto& r : rows) {
+        std::sort(r.begin(), r.end());
+        r.erase(std::unique(r.begin(), r.end()), r.end());
+        total += (int64_t)r.size();
+    }
+    *n_adj = total;
+    if (total > cap || total > INT32_MAX) return CELESTE_EINVAL;
+    int64_t k = 0;
+    for (int s = 0; s < S; ++s) {
+        adj_ptr[s] = (int32_t)k;
+        for (int32_t t : rows[s]) adj[k++] = t;
+    }
+    adj_ptr[S] = (int32_t)k;
+    return CELESTE_OK;
+}
+
+int celeste_cyclades_batches(int32_t n, const int32_t* adj_ptr, const int32_t* adj, const int32_t* order,
+                             int32_t sample_size, int32_t* batch_ptr, int32_t* batch_src, int32_t* n_batches,
+                             int32_t* n_components) {
+    if (n < 0 || sample_size < 1 || !adj_ptr || !batch_ptr || !n_batches || (n > 0 && (!order || !batch_src)))
+        return CELESTE_EINVAL;
+    if (adj_ptr[0] != 0) return CELESTE_EINVAL;
+    for (int s = 0; s < n; ++s)
+        if (adj_ptr[s + 1] < adj_ptr[s]) return CELESTE_EINVAL;
+    if (adj_ptr[n] > 0 && !adj) return CELESTE_EINVAL;
+    for (int32_t k = 0; k < adj_ptr[n]; ++k)
+        if (adj[k] < 0 || adj[k] >= n) return CELESTE_EINVAL;
+    std::vector<int32_t> pos(n, -1);   // position inside the current sample, -1 outside it
+    for (int i = 0; i < n; ++i) {
+        if (order[i] < 0 || order[i] >= n || pos[order[i]] != -1) return CELESTE_EINVAL;
+        pos[order[i]] = 0;
+    }
+    std::fill(pos.begin(), pos.end(), -1);
+    // disjoint-set forest over sample positions; the root of a set is its earliest member
+    std::vector<int32_t> parent, comp_rank, member_round, round_cnt;
+    auto find = [&](int32_t a) {
+        while (parent[a] != a) {
+            parent[a] = parent[parent[a]];
+            a = parent[a];
+        }
+        return a;
+    };
+    int32_t nb = 0, out = 0, comps = 0;
+    batch_ptr[0] = 0;
+    for (int32_t b0 = 0; b0 < n; b0 += sample_size) {
+        const int32_t m = std::min(sample_size, n - b0);
+        const int32_t* smp = order + b0;
+        for (int32_t i = 0; i < m; ++i) pos[smp[i]] = i;
+        parent.resize(m);
+        std::iota(parent.begin(), parent.end(), 0);
+        for (int32_t i = 0; i < m; ++i)
+            for (int32_t k = adj_ptr[smp[i]]; k < adj_ptr[smp[i] + 1]; ++k) {
+                const int32_t j = pos[adj[k]];
+                if (j < 0) continue;
+                const int32_t a = find(i), c = find(j);
+                if (a != c) parent[std::max(a, c)] = std::min(a, c);
+            }
+        // round of a member = how many earlier members its component already has
+        comp_rank.assign(m, 0);
+        member_round.resize(m);
+        int32_t rounds = 0;
+        for (int32_t i = 0; i < m; ++i) {
+            const int32_t r = find(i);
+            if (r == i) ++comps;
+            member_round[i] = comp_rank[r]++;
+            rounds = std::max(rounds, member_round[i] + 1);
+        }
+        // counting sort by round, stable in sample order
+        round_cnt.assign(rounds + 1, 0);
+        for (int32_t i = 0; i < m; ++i) round_cnt[member_round[i] + 1]++;
+        for (int32_t r = 0; r < rounds; ++r) {
+            round_cnt[r + 1] += round_cnt[r];
+            batch_ptr[nb + r + 1] = out + round_cnt[r + 1];
+        }
+        for (int32_t i = 0; i < m; ++i) batch_src[out + round_cnt[member_round[i]]++] = smp[i];
+        nb += rounds;
+        out += m;
+        for (int32_t i = 0; i < m; ++i) pos[smp[i]] = -1;
+    }
+    *n_batches = nb;
+    if (n_components) *n_components = comps;
     return CELESTE_OK;
 }
 

@@ -103,6 +103,44 @@ def test_sweep_trajectory(B, N, O, synth):
     assert np.all(np.abs(t1 - th[:, :27]) <= 1e-6 * (1 + np.abs(th[:, :27])))
 
 
+def test_conflict_graph_matches_oracle(B, synth):
+    from oracle import schedule as Sch
+    for f in (synth.tiny(S=8, n_bands=2, size=33, side=9, seed=73), synth.config1()):
+        say("case conflict graph", f.n_src)
+        plan = B.Plan(f)
+        ptr, adj = plan.conflict_graph()
+        assert Sch.adjacency_sets(ptr, adj) == Sch.conflict_graph(f)
+        for s in range(f.n_src):
+            assert np.all(np.diff(adj[ptr[s]:ptr[s + 1]]) > 0)   # sorted, no repeats
+
+
+def test_cyclades_epoch_equals_serial_bca(B, N, O, synth):
+    """One epoch over the Cyclades rounds (Section IV-D) gives the parameters of serial
+    block coordinate ascent in the sampling order, replayed on the oracle one source at
+    a time with every other source at its current value."""
+    from oracle import schedule as Sch
+    f = synth.tiny(S=8, n_bands=2, size=33, side=9, seed=73)
+    plan = B.Plan(f)
+    bp, bs, nc, order = plan.cyclades_batches(seed=5, sample_size=5)
+    rounds = [bs[bp[b]:bp[b + 1]].tolist() for b in range(len(bp) - 1)]
+    assert (rounds, nc) == Sch.cyclades_rounds(Sch.conflict_graph(f), order, 5)
+    assert max(len(r) for r in rounds) >= 2 and len(rounds) > 2   # side by side and serial both occur
+    say("case cyclades epoch", order.tolist(), rounds)
+    theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+    params = B.tr_params(newton_steps=2)
+    trace = plan.sweep(theta, bp, bs, 1, params).cpu().numpy()
+    th = f.theta.copy()
+    for s in order:
+        row, _, _ = N.newton_steps(f, th, int(s), 2)
+        th[s, :27] = row
+    t1 = theta.cpu().numpy()
+    assert np.all(np.abs(t1[:, :27] - th[:, :27]) <= 1e-6 * (1 + np.abs(th[:, :27])))
+    np.testing.assert_array_equal(t1[:, 27:], 0.0)
+    np.testing.assert_allclose(trace[0], O.total_elbo(O.Problem(f)), rtol=1e-11)
+    np.testing.assert_allclose(trace[1], O.total_elbo(O.Problem(f, t1)), rtol=1e-11)
+    assert trace[1] >= trace[0]
+
+
 def test_sweep_rejects_conflicting_batch(B, synth):
     f = synth.tiny(S=3, n_bands=1, size=15, side=11, seed=81)
     plan = B.Plan(f)
