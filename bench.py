@@ -125,6 +125,15 @@ def cpu_baseline(f, theta_gpu_grad, elbo_gpu, seconds):
                       "gradient, OpenMP over sources" % (done, f.n_src, visits, dt)}, rel_e, rel_g, done
 
 
+def apply_launch(plan, text):
+    """--launch chunk,waves_per_block,grid,dynamic,strip_rows,render_mode[,tile_h,tile_w]"""
+    vals = [int(v) for v in text.split(",")]
+    ch, wpb, grid, dyn, rows, rmode = vals[:6]
+    th, tw = vals[6:8] if len(vals) >= 8 else (16, 16)
+    plan.set_launch(chunk=ch, waves_per_block=wpb, grid_blocks=grid, dynamic=dyn, strip_rows=rows,
+                    render_mode=rmode, tile_h=th, tile_w=tw)
+
+
 def run_newton(args):
     """Config 3: 1024 sources of the field generator, N trust-region Newton iterations of
     every source (others held at their entry values), all on the device."""
@@ -134,6 +143,9 @@ def run_newton(args):
     f = synth.config3()
     dev = torch.device("cuda:0")
     plan = B.Plan(f, check_status=False)
+    if args.launch:
+        apply_launch(plan, args.launch)
+    plan.set_hessian_mode(args.hessian_mode)
     theta0 = torch.tensor(f.theta, dtype=torch.float64, device=dev)
     src = np.arange(f.n_src, dtype=np.int32)
     params = B.tr_params()
@@ -157,6 +169,7 @@ def run_newton(args):
            "config": {"workload": "1024 sources, 5 bands x 2048x1489 px, %d iterations, others fixed"
                                   % args.newton_steps, "visits_per_evaluation": visits,
                       "seconds": dt, "visit_iterations_per_s": visits * args.newton_steps / dt,
+                      "launch": {k: plan.info()[k] for k in LAUNCH_KEYS}, "hessian_mode": args.hessian_mode,
                       "mean_elbo_gain": float(np.mean(e1 - e0)), "min_elbo_gain": float(np.min(e1 - e0)),
                       "sources_improved": int(np.sum(e1 > e0))}}
     print(json.dumps(out), flush=True)
@@ -175,6 +188,9 @@ def run_sweep(args):
         time.perf_counter() - t, f.n_img, f.n_src, len(f.boxes), f.visits()))
     dev = torch.device("cuda:0")
     plan = B.Plan(f, check_status=False)
+    if args.launch:
+        apply_launch(plan, args.launch)
+    plan.set_hessian_mode(args.hessian_mode)
     log("plan: %s" % plan.info())
     theta = torch.tensor(f.theta, dtype=torch.float64, device=dev)
     params = B.tr_params(newton_steps=args.newton_steps)
@@ -211,6 +227,7 @@ def run_sweep(args):
                                   "%s, %d Newton steps per batch visit"
                                   % (f.n_src, sched, args.newton_steps),
                       "schedule": args.schedule, "batches_per_sweep": rounds,
+                      "launch": {k: plan.info()[k] for k in LAUNCH_KEYS}, "hessian_mode": args.hessian_mode,
                       "seconds": dt, "visits_per_evaluation": plan.info()["n_visits"],
                       "elbo_trace": [float(v) for v in trace],
                       "monotone": bool(np.all(np.diff(trace) >= 0))}}
@@ -242,6 +259,8 @@ def main():
     ap.add_argument("--schedule", choices=("colour", "cyclades"), default="colour",
                     help="sweep workload: greedy colouring, or Cyclades sampling (Section IV-D)")
     ap.add_argument("--sample-size", type=int, default=2000, help="Cyclades sample size")
+    ap.add_argument("--hessian-mode", type=int, default=0, choices=(0, 1),
+                    help="Newton / sweep Hessian rows: 0 closed form (default), 1 tangent passes")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -272,11 +291,7 @@ def main():
     grad = torch.zeros(f.n_src, 32, dtype=torch.float64, device=dev)
 
     if args.launch:
-        vals = [int(v) for v in args.launch.split(",")]
-        ch, wpb, grid, dyn, rows, rmode = vals[:6]
-        th, tw = vals[6:8] if len(vals) >= 8 else (16, 16)
-        plan.set_launch(chunk=ch, waves_per_block=wpb, grid_blocks=grid, dynamic=dyn, strip_rows=rows,
-                        render_mode=rmode, tile_h=th, tile_w=tw)
+        apply_launch(plan, args.launch)
         info = plan.info()
     elif args.tune:
         ms = plan.autotune(theta, reps=3)

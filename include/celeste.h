@@ -204,6 +204,14 @@ int celeste_newton(celeste_plan* plan, double* theta_inout, const int32_t* src, 
  * out[0] (device). */
 int celeste_total_elbo(celeste_plan* plan, const double* theta, double* out, hipStream_t stream);
 
+/* How celeste_hessian, celeste_newton and celeste_sweep form the position and shape rows
+ * of each box's Hessian in its intermediates (Section IV-D: exact Hessians).  mode 0 (the
+ * default): one pass evaluating those second derivatives in closed form pixel by pixel;
+ * mode 1: five tangent (dual-number) passes of the adjoint along the position and shape
+ * intermediates.  Both give the same Hessian up to rounding.  CELESTE_EINVAL for another
+ * mode.  Host call; affects later calls only. */
+int celeste_plan_set_hessian_mode(celeste_plan* plan, int mode);
+
 /* Greedy colouring of the box-overlap graph in a seeded random order: every batch is
  * a set of sources no two of which share a pixel of any image (the conflict-free
  * schedule of Section IV-D).  Host call.  batch_ptr (host [n_src + 1]) and

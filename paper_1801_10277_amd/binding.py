@@ -28,7 +28,7 @@ EXPORTS = ["celeste_plan_create", "celeste_plan_destroy", "celeste_plan_get_info
            "celeste_color_batches", "celeste_sweep", "celeste_plan_set_launch", "celeste_autotune",
            "celeste_plan_use_graph", "celeste_plan_profile", "celeste_plan_status", "celeste_last_hip_error",
            "celeste_status_string", "celeste_version", "celeste_debug_math", "celeste_conflict_graph",
-           "celeste_cyclades_batches"]
+           "celeste_cyclades_batches", "celeste_plan_set_hessian_mode"]
 
 
 class celeste_image(C.Structure):
@@ -92,6 +92,7 @@ def lib():
     L.celeste_total_elbo.argtypes = [vp, dp, dp, vp]
     L.celeste_color_batches.argtypes = [vp, C.c_uint64, ip, ip, ip]
     L.celeste_sweep.argtypes = [vp, dp, ip, ip, C.c_int, C.c_int, C.POINTER(celeste_tr_params), dp, vp]
+    L.celeste_plan_set_hessian_mode.argtypes = [vp, C.c_int]
     L.celeste_conflict_graph.argtypes = [vp, ip, ip, C.c_int64, C.POINTER(C.c_int64)]
     L.celeste_cyclades_batches.argtypes = [C.c_int32, ip, ip, ip, C.c_int32, ip, ip, ip, ip]
     L.celeste_plan_set_launch.argtypes = [vp] + [C.c_int] * 8
@@ -316,6 +317,10 @@ class Plan:
                                           src.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(nb)),
               "celeste_color_batches")
         return ptr[:nb.value + 1].copy(), src
+
+    def set_hessian_mode(self, mode):
+        """0: closed-form position / shape Hessian rows (default); 1: tangent passes."""
+        check(lib().celeste_plan_set_hessian_mode(self.h, mode), "celeste_plan_set_hessian_mode")
 
     def conflict_graph(self):
         """Box-overlap conflict graph as host CSR (adj_ptr [S + 1], adj)."""

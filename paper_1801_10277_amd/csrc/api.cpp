@@ -90,6 +90,8 @@ struct celeste_plan {
     double* d_coef2 = nullptr;
     double* d_partials = nullptr;
     double* d_kk = nullptr;          // [cap_items][NKK] brightness-factor Hessian blocks
+    double* d_hg = nullptr;          // [cap_items][NHG] closed-form position / shape Hessian blocks
+    int hess_mode = 0;               // 0: closed-form block pass, 1: tangent passes of the adjoint
     double* d_E = nullptr;
     double* d_V = nullptr;
     double* d_bg = nullptr;
@@ -506,6 +508,12 @@ int adjoint(celeste_plan* p, const Sel& items, const uint8_t* active, bool tange
     a.fg = ((base == BASE_PLANES || base == BASE_FG) && p->fg_valid) ? p->d_fg : nullptr;
     a.partials = p->d_partials;
     a.kk = kk ? p->d_kk : nullptr;
+    if (kk) {
+        // the pass also leaves the listed boxes' own profile values in d_fg for the
+        // closed-form Hessian pass, so d_fg no longer holds a render's values
+        a.fg_out = p->d_fg;
+        p->fg_valid = false;
+    }
     a.status = p->d_status;
     const int grid = grid_override > 0 ? grid_override : p->persistent_grid();
     HIPCHK(launch_adjoint(a, tangent, base, deriv, grid, p->wpb, p->rows, st));
@@ -648,9 +656,26 @@ int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& 
                                int base, hipStream_t st) {
     HIPCHK(launch_pair_reduce(pair, p->d_pairs, p->d_partials, p->d_kk, false, 0, p->d_gw, p->d_hw, p->d_status,
                               st));
-    // the brightness-factor and frac_dev rows came with the gradient pass; tangent passes
-    // along the five position and shape intermediates give the rest (by symmetry, the other
-    // rows' remaining entries too)
+    // the brightness-factor and frac_dev rows came with the gradient pass; the five position
+    // and shape rows (by symmetry, the other rows' remaining entries too) come from the
+    // closed-form pass over the stored backgrounds, or from tangent passes of the adjoint
+    if (p->hess_mode == 0 && base == BASE_BG) {
+        AdjArgs a{};
+        a.g = p->geom();
+        a.items = item;
+        a.tab = p->d_tab1;
+        a.coef = p->d_coef1;
+        a.bg = p->d_bg;
+        a.fg = p->d_fg;
+        a.dynamic = p->dynamic;
+        a.counter = p->d_counter;
+        a.status = p->d_status;
+        HIPCHK(launch_hess_geom(a, p->d_hg, p->persistent_grid(), p->wpb, p->rows, st));
+        HIPCHK(launch_pair_hess(pair, p->d_pairs, p->d_hg, p->d_hw, p->d_status, st));
+        HIPCHK(launch_assemble_hessian(src, p->geom(), p->d_patch_ptr, theta, p->d_gw, p->d_hw, p->d_hess,
+                                       p->d_status, st));
+        return CELESTE_OK;
+    }
     for (int i = W_UX; i < NW; ++i) {
         if (i == W_FDEV) continue;
         CHK(prep(p, theta, pair, true, DIR_W, nullptr, i, st));
@@ -736,7 +761,7 @@ void celeste_plan_destroy(celeste_plan* p) {
                     p->d_tile_sums, p->d_status, p->d_counter, p->d_grad, p->d_hess, p->d_theta_trial,
                     p->d_pred, p->d_elbo_cur, p->d_elbo_trial, p->d_radius, p->d_done, p->d_list_src,
                     p->d_list_pair, p->d_list_item, p->d_cls_items, p->d_pair_lgamma, p->d_fg, p->d_gw,
-                    p->d_hw, p->d_kk};
+                    p->d_hw, p->d_kk, p->d_hg};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -816,6 +841,7 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     A(dalloc(&p->d_coef2, np * NCOEF * 2, W));
     A(dalloc(&p->d_partials, max_items * NACC * 2, W));
     A(dalloc(&p->d_kk, max_items * NKK, W));
+    A(dalloc(&p->d_hg, max_items * NHG, W));
     A(dalloc(&p->d_E, (size_t)p->n_pix, W));
     A(dalloc(&p->d_V, (size_t)p->n_pix, W));
     A(dalloc(&p->d_bg, (size_t)p->n_visits * 2, W));
@@ -1140,6 +1166,12 @@ int celeste_color_batches(const celeste_plan* p, uint64_t seed, int32_t* batch_p
     std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
     for (int s = 0; s < S; ++s) batch_src[fill[color[s]]++] = s;
     *n_batches = n_col;
+    return CELESTE_OK;
+}
+
+int celeste_plan_set_hessian_mode(celeste_plan* p, int mode) {
+    if (!p || mode < 0 || mode > 1) return CELESTE_EINVAL;
+    p->hess_mode = mode;
     return CELESTE_OK;
 }
 

@@ -56,6 +56,27 @@ enum WField { W_K1 = 0, W_K2, W_K3, W_K4, W_UX, W_UY, W_FDEV, W_SXX, W_SXY, W_SY
 enum KKField { KK_11, KK_12, KK_22, KK_13, KK_14, KK_23, KK_24, KK_F1, KK_F2, KK_F3, KK_F4, KK_FF, NKK_USED,
                NKK = 16 };
 
+// Closed-form block of a box's intermediate Hessian (k_hess_geom), in the accumulator
+// scaling (s_ij = c_ij d/dS_ij, c = 2 on the diagonal): NHG_GEO entries between the
+// geometric intermediates (ux, uy, frac_dev, Sxx, Sxy, Syy) = 0..5, every pair but
+// (frac_dev, frac_dev), then 4 entries (k1..k4) for each of ux, uy, Sxx, Sxy, Syy.
+enum HGField {
+    HG_XX, HG_XY, HG_YY, HG_XF, HG_YF,
+    HG_X_SXX, HG_X_SXY, HG_X_SYY, HG_Y_SXX, HG_Y_SXY, HG_Y_SYY,
+    HG_F_SXX, HG_F_SXY, HG_F_SYY,
+    HG_SXX_SXX, HG_SXX_SXY, HG_SXX_SYY, HG_SXY_SXY, HG_SXY_SYY, HG_SYY_SYY,
+    NHG_GEO,
+    NHG = NHG_GEO + 20
+};
+__host__ __device__ constexpr int hg_row(int q) {
+    constexpr int r[NHG_GEO] = {0, 0, 1, 0, 1, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 3, 3, 4, 4, 5};
+    return r[q];
+}
+__host__ __device__ constexpr int hg_col(int q) {
+    constexpr int c[NHG_GEO] = {0, 1, 1, 2, 2, 3, 4, 5, 3, 4, 5, 3, 4, 5, 3, 4, 5, 4, 5, 5};
+    return c[q];
+}
+
 struct PairDev {              // one box (source, image)
     int32_t src, img, r0, c0, h, w;
     int64_t visit_off;        // first visit of the box in the global visit numbering
@@ -146,6 +167,8 @@ struct AdjArgs {
     double* partials;          // [n_items_total][NACC] of T
     double* kk;                // [n_items_total][NKK]: brightness-factor block of the box's
                                // intermediate Hessian (double gradient passes), or null
+    double* fg_out;            // [n_visits][2]: own profile values written by the passes that
+                               // fill kk, or null
     const int* status;
 };
 
@@ -187,6 +210,10 @@ hipError_t launch_render(const RenderArgs& a, int waves_per_block, hipStream_t s
 hipError_t launch_adjoint(const AdjArgs& a, bool tangent, int base_mode, bool deriv, int grid,
                           int waves_per_block, int strip_rows, hipStream_t st);
 hipError_t launch_background(const BgArgs& a, int grid, int waves_per_block, int strip_rows, hipStream_t st);
+// Closed-form geometric block of each listed item's box Hessian into hg[item][NHG]
+// (tables a.tab / a.coef in double, stored backgrounds a.bg, own values a.fg).
+hipError_t launch_hess_geom(const AdjArgs& a, double* hg, int grid, int waves_per_block, int strip_rows,
+                            hipStream_t st);
 hipError_t launch_debug_math(int fn, const double* x, double* y, int n, hipStream_t st);
 hipError_t launch_pair_lgamma(const Geometry& g, int n_pairs, double* out, hipStream_t st);
 hipError_t launch_fill_planes(const celeste_image* images, int n_img, int max_pix, double* E, double* V,
@@ -209,6 +236,10 @@ hipError_t launch_fill_f64_sel(double* p, const Sel& s, double v, hipStream_t st
 // hw[pair][dir][10] (tangent pass along a pair-intermediate direction).
 hipError_t launch_pair_reduce(const Sel& pairs, const PairDev* dpairs, const double* partials, const double* kk,
                               bool tangent, int dir, double* gw, double* hw, const int* status, hipStream_t st);
+// Per-box sums of hg into the position and shape rows of hw[pair] (hw[pair][dir][f] =
+// c_f d2L / dw_dir dw_f, as the tangent passes give them).
+hipError_t launch_pair_hess(const Sel& pairs, const PairDev* dpairs, const double* hg, double* hw, const int* status,
+                            hipStream_t st);
 // 27x27 Hessians of the listed sources (hess by list position) from gw, hw and the KL.
 hipError_t launch_assemble_hessian(const Sel& srcs, const Geometry& g, const int32_t* patch_ptr,
                                    const double* theta, const double* gw, const double* hw, double* hess,

@@ -291,6 +291,44 @@ __global__ void __launch_bounds__(128) k_pair_reduce(Sel sel, const PairDev* __r
     }
 }
 
+// Position and shape rows of each listed box's intermediate Hessian from the closed-form
+// item sums: hw[dir][f] = (entry between dir and f) / c_dir, the entries being in the
+// accumulator scaling c_dir c_f d2L / dw_dir dw_f (c = 2 for Sxx, Syy).
+__global__ void __launch_bounds__(128) k_pair_hess(Sel sel, const PairDev* __restrict__ pairs,
+                                                   const double* __restrict__ hg, double* __restrict__ hw,
+                                                   const int* status) {
+    if (*status) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= sel.n) return;
+    const int pi = sel_at(sel, j);
+    const PairDev pd = pairs[pi];
+    double h[NHG];
+    for (int f = 0; f < NHG; ++f) h[f] = 0.0;
+    for (int it = pd.item_begin; it < pd.item_end; ++it)
+        for (int f = 0; f < NHG; ++f) h[f] += hg[(size_t)it * NHG + f];
+    // geometric index of each intermediate (-1: brightness factor)
+    const int geo[NW] = {-1, -1, -1, -1, 0, 1, 2, 3, 4, 5};
+    double* o = hw + (size_t)pi * NW * NW;
+    for (int q = 0; q < 5; ++q) {
+        const int dir = q < 2 ? W_UX + q : W_SXX + (q - 2);
+        const double inv_c = (dir == W_SXX || dir == W_SYY) ? 0.5 : 1.0;
+        const int gd = geo[dir];
+        for (int f = 0; f < NW; ++f) {
+            double v;
+            if (f < 4) {
+                v = h[NHG_GEO + 4 * q + f];
+            } else {
+                const int gf = geo[f];
+                const int lo = gd < gf ? gd : gf, hi = gd < gf ? gf : gd;
+                int e = 0;
+                while (e < NHG_GEO && !(hg_row(e) == lo && hg_col(e) == hi)) ++e;
+                v = h[e];
+            }
+            o[dir * NW + f] = v * inv_c;
+        }
+    }
+}
+
 // Hessian of ELBO_s: column d is the tangent, along parameter d, of the chain rule
 // J^T z applied to the pair gradients z (value gw, tangent hw * (dw / dtheta_d)), plus the
 // KL term.  One thread per (listed source, direction).
@@ -439,6 +477,13 @@ hipError_t launch_pair_reduce(const Sel& sel, const PairDev* dpairs, const doubl
     if (sel.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pair_reduce, dim3((sel.n + 127) / 128), dim3(128), 0, st, sel, dpairs, partials, kk,
                        tangent ? 1 : 0, dir, gw, hw, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_hess(const Sel& sel, const PairDev* dpairs, const double* hg, double* hw, const int* status,
+                            hipStream_t st) {
+    if (sel.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pair_hess, dim3((sel.n + 127) / 128), dim3(128), 0, st, sel, dpairs, hg, hw, status);
     return hipGetLastError();
 }
 

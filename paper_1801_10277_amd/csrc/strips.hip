@@ -460,6 +460,14 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_strips(AdjArgs a, const Item
                         double nx_ = 0.0, ne_ = 0.0, nv_ = 0.0;
                         if (kk + 1 < L) row_load(kk + 1 < nrow ? kk + 1 : 0, nx_, ne_, nv_);
                         T gs = zero, gg = zero;
+                        if constexpr (KK) {
+                            // own values for the closed-form Hessian pass that follows
+                            if (a.fg_out && kk < nrow) {
+                                const size_t vi = (size_t)p.visit_off + (size_t)(r0 + kk - p.r0) * p.w + (c - p.c0);
+                                a.fg_out[2 * vi] = fs[kk];
+                                a.fg_out[2 * vi + 1] = fg[kk];
+                            }
+                        }
                         if (kk < nrow && cx_ == cx_) {
                             const T Es = k[C_K1] * fs[kk] + k[C_K2] * fg[kk];
                             const T Vs = k[C_K3] * (fs[kk] * fs[kk]) + k[C_K4] * (fg[kk] * fg[kk]) - Es * Es;
@@ -566,6 +574,189 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_strips(AdjArgs a, const Item
                     if (lane == 0) a.kk[(size_t)ii * NKK + f] = s;
                 }
             }
+        }
+        j = a.dynamic ? next_item_s(a.counter, lane) : j + nw;
+    }
+}
+
+// ------------------------------------------------- closed-form geometric Hessian block
+// Second derivatives of a box's pixel sum in its position, frac_dev and shape intermediates
+// (the exact Hessians of Section IV-D), evaluated pixel by pixel in closed form.  For a
+// component n = w N(m; mu, C) with z = P (m - mu), P = C^-1 = [[a, b], [b, d]] and
+// D_ij = z_i z_j - P_ij, and with the operators d/du_i (position) and s_ij = c_ij d/dS_ij
+// (c = 2 on the diagonal: the accumulator scaling of the gradient pass) on a galaxy
+// component of covariance C = nu S + PSF:
+//   d n/du_i = n z_i,                 d2 n/du_i du_j = n D_ij,
+//   s_ij n = nu n D_ij,               d/du_i s_kl n = nu n (z_i D_kl - P_ki z_l - P_li z_k),
+//   s_ij s_kl n = nu^2 n (D_ij D_kl - T_ij,kl),
+// where, from s_ij z = -nu P E_ij z and s_ij P = -nu P E_ij P (E_xx = 2 e_x e_x^T,
+// E_xy = e_x e_y^T + e_y e_x^T, E_yy = 2 e_y e_y^T), T_ij,kl is y_k z_l + z_k y_l - Q_kl with
+// y = P E_ij z and Q = P E_ij P, linear in D:
+//   T_xx,xx = 4a Dxx + 2a^2,  T_xx,xy = 2a Dxy + 2b Dxx + 2ab,  T_xx,yy = 4b Dxy + 2b^2,
+//   T_xy,xy = a Dyy + 2b Dxy + d Dxx + ad + b^2,  T_xy,yy = 2b Dyy + 2d Dxy + 2bd,
+//   T_yy,yy = 4d Dyy + 2d^2.
+// frac_dev enters the galaxy profile linearly (weight +1 de Vaucouleurs, -1 exponential).
+// With the pixel term l(E, V), E = Eb + k1 fs + k2 fg, V = Vb + k3 fs^2 + k4 fg^2 - Es^2
+// (Es = k1 fs + k2 fg), l_VV = 0 and the row weights Gs, Gg of the gradient pass, the entry
+// between geometric intermediates g, h is
+//   (l_EE - 2 l_V) E_g E_h + l_EV (E_g V_h + V_g E_h) + 2 l_V (k3 fs_g fs_h + k4 fg_g fg_h)
+//   + Gs fs_gh + Gg fg_gh,
+// and the entry between g and k_i follows from dE/dk = (fs, fg, 0, 0) and
+// dV/dk = (-2 Es fs, -2 Es fg, fs^2, fg^2).  Entry layout: see HGField.
+__device__ __forceinline__ void hess_pixel(const double* __restrict__ tab, const double* __restrict__ nu_s,
+                                           double px, double py, double x, double Eb, double Vb, double fs,
+                                           double fg, const double* k, double* H, const double* __restrict__ t2) {
+    // pixel scalars first (own values from the gradient pass), so that the second
+    // derivatives go straight into H with their row weights
+    const double Es = k[C_K1] * fs + k[C_K2] * fg;
+    const double E = Eb + Es;
+    const double V = Vb + k[C_K3] * (fs * fs) + k[C_K4] * (fg * fg) - Es * Es;
+    const double inv = frcp(E);
+    const double inv2 = inv * inv;
+    const double r = V * inv2;
+    const double lE = x * inv * (1.0 + r) - 1.0;
+    const double lV = -0.5 * x * inv2;
+    const double lEE = -x * inv2 * (1.0 + 3.0 * r);
+    const double lEV = x * inv2 * inv;
+    const double A = lE - 2.0 * Es * lV;
+    const double Gs = A * k[C_K1] + 2.0 * lV * (k[C_K3] * fs);
+    const double Gg = A * k[C_K2] + 2.0 * lV * (k[C_K4] * fg);
+    double S[2] = {0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < NPSF; ++c) {
+        const double* e = tab + c * CST;
+        const double dx = px - e[F_CX], dy = py - e[F_CY];
+        const double a = e[F_PXX], b = e[F_PXY], d = e[F_PYY];
+        const double zx = a * dx + b * dy, zy = b * dx + d * dy;
+        const double n = fexp(e[F_LOGW] - 0.5 * (dx * zx + dy * zy), t2);
+        const double gn = Gs * n;
+        S[0] += n * zx;
+        S[1] += n * zy;
+        H[HG_XX] += gn * (zx * zx - a);
+        H[HG_XY] += gn * (zx * zy - b);
+        H[HG_YY] += gn * (zy * zy - d);
+    }
+    double F[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) F[i] = 0.0;
+    for (int c = NPSF; c < NCOMP; ++c) {
+        const double* e = tab + c * CST;
+        const double nu = nu_s[(c - NPSF) % NGAL_PER_PSF];
+        const double dx = px - e[F_CX], dy = py - e[F_CY];
+        const double a = e[F_PXX], b = e[F_PXY], d = e[F_PYY];
+        const double zx = a * dx + b * dy, zy = b * dx + d * dy;
+        const double n = fexp(e[F_LOGW] - 0.5 * (dx * zx + dy * zy), t2);
+        const double wn = e[F_WT] * n, sn = e[F_SGN] * n, vn = e[F_WNU] * n;
+        const double Dxx = zx * zx - a, Dxy = zx * zy - b, Dyy = zy * zy - d;
+        F[0] += wn * zx;
+        F[1] += wn * zy;
+        F[2] += sn;
+        F[3] += vn * Dxx;
+        F[4] += vn * Dxy;
+        F[5] += vn * Dyy;
+        const double wg = Gg * wn, sg = Gg * sn, vg = Gg * vn;
+        const double sgn = sg * nu, vgn = vg * nu;
+        H[HG_XX] += wg * Dxx;
+        H[HG_XY] += wg * Dxy;
+        H[HG_YY] += wg * Dyy;
+        H[HG_XF] += sg * zx;
+        H[HG_YF] += sg * zy;
+        H[HG_X_SXX] += vg * (zx * (Dxx - 2.0 * a));
+        H[HG_X_SXY] += vg * (zx * Dxy - a * zy - b * zx);
+        H[HG_X_SYY] += vg * (zx * Dyy - 2.0 * b * zy);
+        H[HG_Y_SXX] += vg * (zy * Dxx - 2.0 * b * zx);
+        H[HG_Y_SXY] += vg * (zy * Dxy - b * zy - d * zx);
+        H[HG_Y_SYY] += vg * (zy * (Dyy - 2.0 * d));
+        H[HG_F_SXX] += sgn * Dxx;
+        H[HG_F_SXY] += sgn * Dxy;
+        H[HG_F_SYY] += sgn * Dyy;
+        H[HG_SXX_SXX] += vgn * (Dxx * Dxx - 4.0 * a * Dxx - 2.0 * (a * a));
+        H[HG_SXX_SXY] += vgn * (Dxx * Dxy - 2.0 * a * Dxy - 2.0 * b * Dxx - 2.0 * (a * b));
+        H[HG_SXX_SYY] += vgn * (Dxx * Dyy - 4.0 * b * Dxy - 2.0 * (b * b));
+        H[HG_SXY_SXY] += vgn * (Dxy * Dxy - a * Dyy - 2.0 * b * Dxy - d * Dxx - (a * d + b * b));
+        H[HG_SXY_SYY] += vgn * (Dxy * Dyy - 2.0 * b * Dyy - 2.0 * d * Dxy - 2.0 * (b * d));
+        H[HG_SYY_SYY] += vgn * (Dyy * Dyy - 4.0 * d * Dyy - 2.0 * (d * d));
+    }
+    // first-derivative products: E_g, V_g over (ux, uy, frac_dev, Sxx, Sxy, Syy)
+    double Eg[6], Vg[6];
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+        const double Sg = g < 2 ? S[g] : 0.0;
+        Eg[g] = k[C_K1] * Sg + k[C_K2] * F[g];
+        Vg[g] = 2.0 * (k[C_K3] * fs) * Sg + 2.0 * (k[C_K4] * fg) * F[g] - 2.0 * Es * Eg[g];
+    }
+    const double lEE2 = lEE - 2.0 * lV, lV2 = 2.0 * lV;
+#pragma unroll
+    for (int q = 0; q < NHG_GEO; ++q) {
+        const int g = hg_row(q), h = hg_col(q);
+        double v = (lEE2 * Eg[g] + lEV * Vg[g]) * Eg[h] + (lEV * Eg[g]) * Vg[h] + lV2 * k[C_K4] * F[g] * F[h];
+        if (g < 2 && h < 2) v += lV2 * k[C_K3] * S[g] * S[h];
+        H[q] += v;
+    }
+    const double Rc = lEE - 2.0 * lEV * Es - 2.0 * lV;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const int g = q < 2 ? q : q + 1;
+        const double Sg = g < 2 ? S[g] : 0.0;
+        const double R = Rc * Eg[g] + lEV * Vg[g];
+        double* o = H + NHG_GEO + 4 * q;
+        o[0] += fs * R + A * Sg;
+        o[1] += fg * R + A * F[g];
+        o[2] += lEV * (fs * fs) * Eg[g] + lV2 * fs * Sg;
+        o[3] += lEV * (fg * fg) * Eg[g] + lV2 * fg * F[g];
+    }
+}
+
+// One wave per work item, one lane per strip; each lane walks its strip's pixels (stored
+// backgrounds and own profile values of the listed boxes) and the wave sums the NHG
+// entries into hg[item].
+template <int L>
+__global__ void __launch_bounds__(256) k_hess_geom(AdjArgs a, const Item* __restrict__ items,
+                                                   const PairDev* __restrict__ pairs,
+                                                   const celeste_image* __restrict__ images,
+                                                   const double* __restrict__ xs, const double* __restrict__ bg,
+                                                   const double* __restrict__ tabp,
+                                                   const double* __restrict__ coefp,
+                                                   const double* __restrict__ own, double* __restrict__ hg) {
+    if (*a.status) return;
+    __shared__ double t2[64];
+    __shared__ double nu_s[NGAL_PER_PSF];
+    if (threadIdx.x < NGAL_PER_PSF)
+        nu_s[threadIdx.x] =
+            threadIdx.x < NDEV ? a.g.consts.dev_nu[threadIdx.x] : a.g.consts.exp_nu[threadIdx.x - NDEV];
+    fill_exp_table(t2);
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int nw = gridDim.x * wpb;
+    int j = a.dynamic ? next_item_s(a.counter, lane) : blockIdx.x * wpb + (threadIdx.x >> 6);
+    while (j < a.items.n) {
+        const int ii = __builtin_amdgcn_readfirstlane(sel_at(a.items, j));
+        const Item it = items[ii];
+        const PairDev p = pairs[it.pair];
+        const celeste_image& im = images[p.img];
+        const double* tab = tabp + (size_t)it.pair * NCOMP * CST;
+        const double* kp = coefp + (size_t)it.pair * NCOEF;
+        const double k[NCOEF] = {kp[0], kp[1], kp[2], kp[3]};
+        double H[NHG];
+#pragma unroll
+        for (int f = 0; f < NHG; ++f) H[f] = 0.0;
+        for (int q = lane; q < it.count; q += 64) {
+            int c, r0, nrow;
+            strip_geometry(p, it.start + q, L, c, r0, nrow);
+            for (int kk = 0; kk < nrow; ++kk) {
+                const int r = r0 + kk;
+                const double x = xs[(size_t)im.pix_offset + (size_t)r * im.W + c];
+                if (!(x == x)) continue;
+                const size_t vi = (size_t)p.visit_off + (size_t)(r - p.r0) * p.w + (c - p.c0);
+                hess_pixel(tab, nu_s, (double)c, (double)r, x, bg[2 * vi], bg[2 * vi + 1], own[2 * vi],
+                           own[2 * vi + 1], k, H, t2);
+            }
+        }
+        double* out = hg + (size_t)ii * NHG;
+#pragma unroll
+        for (int f = 0; f < NHG; ++f) {
+            const double v = wave_sum(H[f]);
+            if (lane == 0) out[f] = v;
         }
         j = a.dynamic ? next_item_s(a.counter, lane) : j + nw;
     }
@@ -892,6 +1083,32 @@ hipError_t launch_adjoint(const AdjArgs& a, bool tangent, int base, bool deriv, 
     const hipError_t e = tangent ? adjs_B<dual>(a, base, deriv, grid, wpb, L, st)
                                  : adjs_B<double>(a, base, deriv, grid, wpb, L, st);
     if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_hess_geom(const AdjArgs& a, double* hg, int grid, int wpb, int L, hipStream_t st) {
+    if (a.items.n <= 0) return hipSuccess;
+    if (a.dynamic) {
+        hipError_t e = launch_fill_int(a.counter, 0, 1, st);
+        if (e != hipSuccess) return e;
+    } else {
+        const int need = (a.items.n + wpb - 1) / wpb;
+        if (grid > need) grid = need;
+    }
+    if (grid < 1) grid = 1;
+    const Geometry& g = a.g;
+#define CEL_HG(LL)                                                                                                \
+    hipLaunchKernelGGL(k_hess_geom<LL>, dim3(grid), dim3(64 * wpb), 0, st, a, g.items, g.pairs, g.images, g.x, a.bg, \
+                       a.tab, a.coef, a.fg, hg)
+    if (L == 16)
+        CEL_HG(16);
+    else if (L == 8)
+        CEL_HG(8);
+    else if (L == 4)
+        CEL_HG(4);
+    else
+        return hipErrorInvalidValue;
+#undef CEL_HG
     return hipGetLastError();
 }
 
