@@ -249,6 +249,70 @@ def test_source_without_boxes_and_ragged_boxes(B, O, synth):
     check_field(B, O, f, range(3), name="ragged")
 
 
+def test_degenerate_parameter_values(B, O, synth):
+    """Parameters on the edges of their domain: frac_dev 0 and 1, a round galaxy, an angle
+    many periods out, q next to 0 and 1, a galaxy far smaller than the PSF and one larger
+    than its box.  ELBO, gradient (both modes), HVP and the closed-form Hessian."""
+    f = synth.tiny(S=4, n_bands=2, size=21, side=11, seed=171)
+    th = f.theta.copy()
+    th[0, 2], th[0, 3] = 0.0, 1.0
+    th[1, 2], th[1, 4] = 1.0, 7.0 * np.pi + 0.3
+    th[2, 6], th[2, 5] = 1e-9, 0.02
+    th[3, 6], th[3, 5] = 1.0 - 1e-9, 25.0
+    f.theta = th
+    plan, theta = check_field(B, O, f, range(4), name="degenerate")
+    P = O.Problem(f)
+    rng = np.random.default_rng(17)
+    v = np.zeros((4, 32))
+    v[:, :27] = rng.standard_normal((4, 27))
+    say("case degenerate hvp / hessian")
+    hv = plan.hvp(theta, torch.tensor(v, device="cuda")).cpu().numpy()
+    H = plan.hessian(theta, [0, 1, 2, 3]).cpu().numpy()
+    for s in range(4):
+        ref, habs = O.source_hvp(P, s, v[s])
+        within(hv[s, :27], ref, habs, "degenerate hvp s=%d" % s)
+        Href = O.source_hessian(P, s)
+        np.testing.assert_allclose(H[s], Href, rtol=1e-8, atol=1e-11 * np.abs(Href).max())
+
+
+def test_field_without_any_box(B, O, synth):
+    """No source has a patch: every ELBO is -KL, the total ELBO is -sum KL, and the
+    Hessian is the KL's."""
+    f = synth.tiny(S=3, n_bands=2, size=15, side=9, seed=181)
+    f.boxes = f.boxes[:0]
+    f.patch_ptr = np.zeros_like(f.patch_ptr)
+    plan, theta = check_field(B, O, f, range(3), name="no-box")
+    P = O.Problem(f)
+    say("case no-box hessian / total")
+    H = plan.hessian(theta, [2, 1, 0]).cpu().numpy()
+    for k, s in enumerate([2, 1, 0]):
+        Href = O.source_hessian(P, s)
+        np.testing.assert_allclose(H[k], Href, rtol=1e-9, atol=1e-12 * np.abs(Href).max())
+    t = plan.total_elbo(theta).cpu().numpy()[0]
+    np.testing.assert_allclose(t, O.total_elbo(P), rtol=1e-12)
+
+
+def test_single_pixel_and_whole_image_boxes(B, O, synth):
+    """1 x 1 boxes in opposite image corners and a box covering a whole image."""
+    f = synth.tiny(S=3, n_bands=2, size=17, side=9, seed=191)
+    H_, W_ = 17, 17
+    b = f.boxes.copy()
+    for k in range(len(b)):
+        src = int(np.searchsorted(f.patch_ptr, k, side="right") - 1)
+        if src == 0:
+            b[k, 1:] = (0, 0, 1, 1) if b[k, 0] == 0 else (H_ - 1, W_ - 1, 1, 1)
+        elif src == 1:
+            b[k, 1:] = (0, 0, H_, W_)
+    f.boxes = b
+    plan, theta = check_field(B, O, f, range(3), name="corner-boxes")
+    P = O.Problem(f)
+    say("case corner-boxes hessian")
+    H = plan.hessian(theta, [0, 1, 2]).cpu().numpy()
+    for s in range(3):
+        Href = O.source_hessian(P, s)
+        np.testing.assert_allclose(H[s], Href, rtol=1e-8, atol=1e-11 * np.abs(Href).max())
+
+
 def test_masked_pixels(B, O, synth):
     f = synth.tiny(S=2, n_bands=2, size=19, side=13, seed=141)
     rng = np.random.default_rng(5)
