@@ -926,7 +926,42 @@ __global__ void __launch_bounds__(256) k_gather_planes(RenderArgs a, const TileD
         V[k] = 0.0;
         covered[k] = false;
     }
-    for (int j = td.list_begin; j < td.list_end; ++j) {
+    // boxes in list order (the sums are fixed-order); GU boxes' loads are issued before any
+    // of them is added, so that their latencies overlap (config 2, 16 x 16 tiles: 0.533 ->
+    // 0.499 ms for the render; four or eight boxes at a time cost occupancy and are slower)
+    constexpr int GU = RP == 4 ? 2 : 4;   // two at 4 rows per lane keeps 7 waves per SIMD
+    int j = td.list_begin;
+    for (; j + GU <= td.list_end; j += GU) {
+        double2 v[GU][RP];
+        bool in[GU][RP];
+        double kk[GU][NCOEF];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int pi = __builtin_amdgcn_readfirstlane(tile_list[j + u]);
+            const PairDev o = pairs[pi];
+            const double* kp = coef + (size_t)pi * NCOEF;
+#pragma unroll
+            for (int q = 0; q < NCOEF; ++q) kk[u][q] = kp[q];
+#pragma unroll
+            for (int k = 0; k < RP; ++k) {
+                in[u][k] = !(r[k] < o.r0 || r[k] >= o.r0 + o.h || c < o.c0 || c >= o.c0 + o.w);
+                const size_t vi = (size_t)o.visit_off + (size_t)(r[k] - o.r0) * o.w + (c - o.c0);
+                v[u][k] = in[u][k] ? reinterpret_cast<const double2*>(fgm)[vi] : make_double2(0.0, 0.0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GU; ++u)
+#pragma unroll
+            for (int k = 0; k < RP; ++k) {
+                if (!in[u][k]) continue;
+                const double fs = v[u][k].x, fg = v[u][k].y;
+                const double Et = kk[u][C_K1] * fs + kk[u][C_K2] * fg;
+                E[k] += Et;
+                V[k] += kk[u][C_K3] * fs * fs + kk[u][C_K4] * fg * fg - Et * Et;
+                if constexpr (SUMS) covered[k] = true;
+            }
+    }
+    for (; j < td.list_end; ++j) {
         const int pi = __builtin_amdgcn_readfirstlane(tile_list[j]);
         const PairDev o = pairs[pi];
         const double* kp = coef + (size_t)pi * NCOEF;
