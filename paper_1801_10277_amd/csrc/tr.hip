@@ -1,6 +1,7 @@
 // Batched Newton trust-region step (Section IV-D of Regier et al. 2018: Newton's method
 // with exact Hessians and a trust region; the trust-region subproblem is solved through
-// an eigendecomposition, Section VI-B).  One 64-lane work-group per source:
+// an eigendecomposition, Section VI-B).  One work-group per source (64 lanes, or 256 for
+// small batches):
 //  1. map gradient and Hessian to unconstrained coordinates (logit of q, frac_dev and
 //     axis ratio; log of radius and of every variance; identity otherwise);
 //  2. Jacobi eigendecomposition of the 27x27 model Hessian in LDS with the round-robin
@@ -21,6 +22,7 @@ namespace cel {
 constexpr int LD = 28;   // padded LDS row
 constexpr int NJ = 28;   // Jacobi index range: the 27 parameters and one idle index
 constexpr int NPAIR = NJ / 2;
+constexpr int TR_WIDE_BELOW = 512;   // batches smaller than this take 256-lane work-groups
 
 __device__ inline int param_kind(int i) {
     // 1: logit, 2: log, 0: identity
@@ -58,7 +60,8 @@ __device__ inline double from_unconstrained(int i, double eta) {
     return eta;
 }
 
-__global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
+template <int TRB>
+__global__ void __launch_bounds__(TRB) k_tr_solve(TrArgs a) {
     if (*a.status) return;
     const int j = blockIdx.x;
     const int s = sel_at(a.srcs, j);
@@ -83,21 +86,20 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         lam[t] = p2 * gr[t];   // diagonal curvature term of the ELBO
     }
     __syncthreads();
-    if (t < NJ) {
-        for (int c = 0; c < NJ; ++c) {
-            double b = 0.0;
-            if (t < NP && c < NP) {
-                const double hs = 0.5 * (H[t * NP + c] + H[c * NP + t]);
-                b = -d1[t] * hs * d1[c];
-                if (c == t) b -= lam[t];
-            }
-            B[t][c] = b;
-            Q[t][c] = (c == t) ? 1.0 : 0.0;
+    for (int idx = t; idx < NJ * NJ; idx += TRB) {
+        const int r = idx / NJ, c = idx - r * NJ;
+        double b = 0.0;
+        if (r < NP && c < NP) {
+            const double hs = 0.5 * (H[r * NP + c] + H[c * NP + r]);
+            b = -d1[r] * hs * d1[c];
+            if (c == r) b -= lam[r];
         }
+        B[r][c] = b;
+        Q[r][c] = (c == r) ? 1.0 : 0.0;
     }
     // stop test on the unconstrained gradient
     double gmax = (t < NP) ? fabs(gm[t]) : 0.0;
-    sh_red[t] = gmax;
+    if (t < 64) sh_red[t] = gmax;
     __syncthreads();
     if (t == 0) {
         double m = 0.0;
@@ -125,12 +127,12 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
                 tot += v;
                 if (c != t) off += v;
             }
-        sh_red[t] = off;
+        if (t < 64) sh_red[t] = off;
         __syncthreads();
         double offs = 0.0;
         for (int i = 0; i < NP; ++i) offs += sh_red[i];
         __syncthreads();
-        sh_red[t] = tot;
+        if (t < 64) sh_red[t] = tot;
         __syncthreads();
         double tots = 0.0;
         for (int i = 0; i < NP; ++i) tots += sh_red[i];
@@ -159,7 +161,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
             }
             __syncthreads();
             // B <- B J and Q <- Q J for all pairs (disjoint column pairs)
-            for (int idx = t; idx < NPAIR * NJ; idx += 64) {
+            for (int idx = t; idx < NPAIR * NJ; idx += TRB) {
                 const int k = idx / NJ, row = idx - k * NJ;
                 const int p = rot_p[k], q = rot_q[k];
                 const double c = rot_c[k], sn = rot_s[k];
@@ -172,7 +174,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
             }
             __syncthreads();
             // B <- J^T B (disjoint row pairs)
-            for (int idx = t; idx < NPAIR * NJ; idx += 64) {
+            for (int idx = t; idx < NPAIR * NJ; idx += TRB) {
                 const int k = idx / NJ, col = idx - k * NJ;
                 const int p = rot_p[k], q = rot_q[k];
                 const double c = rot_c[k], sn = rot_s[k];
@@ -302,7 +304,13 @@ __global__ void __launch_bounds__(128) k_tr_update(TrArgs a) {
 
 hipError_t launch_tr_solve(const TrArgs& a, hipStream_t st) {
     if (a.srcs.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tr_solve, dim3(a.srcs.n), dim3(64), 0, st, a);
+    // a large batch keeps every SIMD busy with one wave per source; a small one gains from
+    // spreading each rotation update over four waves (Cyclades rounds on the 20000-source
+    // region: 5% per epoch; 256 lanes for 1024 sources would cost 10% per Newton iteration)
+    if (a.srcs.n < TR_WIDE_BELOW)
+        hipLaunchKernelGGL(k_tr_solve<256>, dim3(a.srcs.n), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_tr_solve<64>, dim3(a.srcs.n), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 
