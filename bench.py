@@ -242,6 +242,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-hvp", action="store_true")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the launch first (default: the plan's default launch, which the "
                          "committed counter profile was taken at)")
@@ -360,6 +361,22 @@ def main():
         plain = {"visits_per_s": visits / pdt, "ms_per_step": 1e3 * pdt}
         log("plain: %.3f ms/step, %.3e visits/s" % (1e3 * pdt, visits / pdt))
 
+    # Hessian-vector products of every source (one tangent pass of the whole path), same field
+    hvp = None
+    if not args.no_hvp:
+        v = torch.zeros_like(grad)
+        v[:, :27] = torch.randn(f.n_src, 27, dtype=torch.float64, generator=torch.Generator().manual_seed(7)).to(dev)
+        plan.hvp(theta, v)
+        torch.cuda.synchronize()
+        n_hvp = 10
+        t0 = time.perf_counter()
+        for _ in range(n_hvp):
+            plan.hvp(theta, v)
+        torch.cuda.synchronize()
+        hdt = (time.perf_counter() - t0) / n_hvp
+        hvp = {"ms_per_call": round(1e3 * hdt, 4), "visits_per_s": visits / hdt}
+        log("hvp: %.3f ms per call, %.3e visits/s" % (1e3 * hdt, visits / hdt))
+
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -394,6 +411,7 @@ def main():
                       "direct_formula_equivalent_tflops": round(direct_equiv, 3),
                       "plain": plain,
                       "batched_vs_plain": (value / plain["visits_per_s"]) if plain else None,
+                      "hvp_all_sources": hvp,
                       "parity_vs_oracle": parity},
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
