@@ -1,28 +1,53 @@
 // Batched Newton trust-region step (Section IV-D of Regier et al. 2018: Newton's method
-// with exact Hessians and a trust region; the trust-region subproblem is solved through
-// an eigendecomposition, Section VI-B).  One work-group per source (64 lanes, or 256 for
-// small batches):
+// with exact Hessians and a trust region; the paper solves the trust-region subproblem
+// through an eigendecomposition, Section VI-B).  One wave per source:
 //  1. map gradient and Hessian to unconstrained coordinates (logit of q, frac_dev and
 //     axis ratio; log of radius and of every variance; identity otherwise);
-//  2. Jacobi eigendecomposition of the 27x27 model Hessian in LDS with the round-robin
-//     ordering (27 padded to 28 indices: each of the 27 steps of a sweep rotates 14
-//     disjoint index pairs at once), the rotations applied by the lanes in parallel;
-//  3. exact subproblem  min g'p + p'Bp/2, |p| <= radius  in the eigenbasis: interior
-//     Newton step, else the secular equation |p(mu)| = radius by safeguarded Newton
-//     (Nocedal & Wright, Alg. 4.3), with the hard case handled along the eigenvector of
-//     the smallest eigenvalue;
-//  4. trial point and predicted increase.
+//  2. Householder reduction of the 27x27 model Hessian to tridiagonal form T = Q^T B Q in
+//     LDS, the lanes owning the rows of the reflections;
+//  3. exact subproblem  min g'p + p'Bp/2, |p| <= radius  on T (More and Sorensen's
+//     method; Nocedal & Wright, Alg. 4.3): positive pivots of T's factorisation at mu = 0
+//     make T positive definite and allow the interior Newton step; otherwise the smallest
+//     eigenvalue of T by Sturm-sequence multisection brackets the secular equation
+//     |p(mu)| = radius, solved by safeguarded Newton with two O(n) solves per step;
+//  4. near the hard case (gradient nearly orthogonal to the lowest eigenvector), the full
+//     eigendecomposition instead: implicit QL with Wilkinson's shift on T (Golub and Van
+//     Loan, Matrix Computations, Sec. 8.3; Bowdler, Martin, Reinsch and Wilkinson, Numer.
+//     Math. 11, 1968) and the subproblem in the eigenbasis, the hard case along the
+//     eigenvector of the smallest eigenvalue;
+//  5. trial point and predicted increase.
 // k_tr_update compares the actual and predicted increase and updates point and radius.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "model.h"
 
 namespace cel {
 
 constexpr int LD = 28;   // padded LDS row
-constexpr int NJ = 28;   // Jacobi index range: the 27 parameters and one idle index
-constexpr int NPAIR = NJ / 2;
-constexpr int TR_WIDE_BELOW = 512;   // batches smaller than this take 256-lane work-groups
+constexpr int NJ = 28;   // rows of the LDS matrices (27 parameters, padded)
+constexpr int QL_MAX_ITER = 60;   // QL iterations per eigenvalue before giving up
+constexpr double EPS_D = 2.220446049250313e-16;   // 2^-52
+
+// Value of v in lane i (i wave-uniform).
+__device__ inline double lane_get(double v, int i) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, i);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), i);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wave-wide minimum and maximum (every lane receives the result).
+__device__ inline double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
 
 __device__ inline int param_kind(int i) {
     // 1: logit, 2: log, 0: identity
@@ -60,16 +85,14 @@ __device__ inline double from_unconstrained(int i, double eta) {
     return eta;
 }
 
-template <int TRB>
-__global__ void __launch_bounds__(TRB) k_tr_solve(TrArgs a) {
+__global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
     if (*a.status) return;
     const int j = blockIdx.x;
     const int s = sel_at(a.srcs, j);
     const int t = threadIdx.x;
     __shared__ double B[NJ][LD];
     __shared__ double Q[NJ][LD];
-    __shared__ double rot_c[NPAIR], rot_s[NPAIR];
-    __shared__ int rot_p[NPAIR], rot_q[NPAIR];
+    __shared__ double vs[NJ], ws[NJ], dd[NJ], ee[NJ];
     __shared__ double gm[NP], eta[NP], d1[NP], lam[NP], gh[NP], ph[NP], pv[NP];
     __shared__ double sh_red[64];
     __shared__ int sh_done;
@@ -86,7 +109,7 @@ __global__ void __launch_bounds__(TRB) k_tr_solve(TrArgs a) {
         lam[t] = p2 * gr[t];   // diagonal curvature term of the ELBO
     }
     __syncthreads();
-    for (int idx = t; idx < NJ * NJ; idx += TRB) {
+    for (int idx = t; idx < NJ * NJ; idx += 64) {
         const int r = idx / NJ, c = idx - r * NJ;
         double b = 0.0;
         if (r < NP && c < NP) {
@@ -99,7 +122,7 @@ __global__ void __launch_bounds__(TRB) k_tr_solve(TrArgs a) {
     }
     // stop test on the unconstrained gradient
     double gmax = (t < NP) ? fabs(gm[t]) : 0.0;
-    if (t < 64) sh_red[t] = gmax;
+    sh_red[t] = gmax;
     __syncthreads();
     if (t == 0) {
         double m = 0.0;
@@ -118,80 +141,266 @@ __global__ void __launch_bounds__(TRB) k_tr_solve(TrArgs a) {
         }
         return;
     }
-    // ---- Jacobi sweeps (round-robin order)
-    for (int sweep = 0; sweep < 30; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        if (t < NP)
-            for (int c = 0; c < NP; ++c) {
-                const double v = B[t][c] * B[t][c];
-                tot += v;
-                if (c != t) off += v;
-            }
-        if (t < 64) sh_red[t] = off;
-        __syncthreads();
-        double offs = 0.0;
-        for (int i = 0; i < NP; ++i) offs += sh_red[i];
-        __syncthreads();
-        if (t < 64) sh_red[t] = tot;
-        __syncthreads();
-        double tots = 0.0;
-        for (int i = 0; i < NP; ++i) tots += sh_red[i];
-        __syncthreads();
-        if (!(offs > 1e-30 * tots) || offs == 0.0) break;
-        for (int r = 0; r < NJ - 1; ++r) {
-            // round r of the circle schedule: index 0 fixed, the others rotated by r
-            if (t < NPAIR) {
-                const int i0 = t, i1 = NJ - 1 - t;
-                const int a0 = i0 == 0 ? 0 : 1 + (i0 - 1 + r) % (NJ - 1);
-                const int a1 = 1 + (i1 - 1 + r) % (NJ - 1);
-                const int p = a0 < a1 ? a0 : a1, q = a0 < a1 ? a1 : a0;
-                double c = 1.0, sn = 0.0;
-                const double apq = B[p][q];
-                if (q < NP && apq != 0.0) {
-                    const double app = B[p][p], aqq = B[q][q];
-                    const double tau = (aqq - app) / (2.0 * apq);
-                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + tt * tt);
-                    sn = tt * c;
-                }
-                rot_p[t] = p;
-                rot_q[t] = q;
-                rot_c[t] = c;
-                rot_s[t] = sn;
-            }
+    // ---- Householder reduction B = Q T Q^T, T tridiagonal: diagonal dd, ee[i] couples
+    // rows i and i + 1.  Lane i owns row i; the reflector v (zero outside k+1..26) and
+    // w = p - (v.p) beta/2 v with p = beta B v go through LDS.
+    for (int k = 0; k + 2 < NP; ++k) {
+        const double x0 = B[k + 1][k];
+        const double ci = (t >= k + 2 && t < NP) ? B[t][k] : 0.0;
+        const double sigma = wave_sum(ci * ci);
+        const double dk = B[k][k];
+        if (sigma == 0.0) {   // already tridiagonal in this column (uniform branch)
+            dd[k] = dk;
+            ee[k] = x0;
             __syncthreads();
-            // B <- B J and Q <- Q J for all pairs (disjoint column pairs)
-            for (int idx = t; idx < NPAIR * NJ; idx += TRB) {
-                const int k = idx / NJ, row = idx - k * NJ;
-                const int p = rot_p[k], q = rot_q[k];
-                const double c = rot_c[k], sn = rot_s[k];
-                const double bkp = B[row][p], bkq = B[row][q];
-                B[row][p] = c * bkp - sn * bkq;
-                B[row][q] = sn * bkp + c * bkq;
-                const double qkp = Q[row][p], qkq = Q[row][q];
-                Q[row][p] = c * qkp - sn * qkq;
-                Q[row][q] = sn * qkp + c * qkq;
+            continue;
+        }
+        const double mu = sqrt(x0 * x0 + sigma);
+        const double alpha = x0 > 0.0 ? -mu : mu;
+        const double v0 = x0 - alpha;
+        const double beta = 2.0 / (v0 * v0 + sigma);
+        const double vi = (t == k + 1) ? v0 : ci;
+        if (t < NJ) vs[t] = vi;
+        dd[k] = dk;
+        ee[k] = alpha;
+        __syncthreads();
+        // full-length loops (v and w vanish outside k+1..26), unrolled so that the LDS
+        // reads of a loop are all in flight together
+        double pi = 0.0;
+        if (t > k && t < NP) {
+#pragma unroll
+            for (int c = 0; c < NP; ++c) pi += B[t][c] * vs[c];
+            pi *= beta;
+        }
+        const double K = 0.5 * beta * wave_sum(vi * pi);
+        const double wi = pi - K * vi;
+        if (t < NJ) ws[t] = wi;
+        __syncthreads();
+        if (t > k && t < NP) {
+#pragma unroll
+            for (int c = 0; c < NP; ++c) B[t][c] -= vi * ws[c] + wi * vs[c];
+        }
+        if (t < NP) {
+            double q = 0.0;
+#pragma unroll
+            for (int c = 0; c < NP; ++c) q += Q[t][c] * vs[c];
+            q *= beta;
+#pragma unroll
+            for (int c = 0; c < NP; ++c) Q[t][c] -= q * vs[c];
+        }
+        __syncthreads();
+    }
+    dd[NP - 2] = B[NP - 2][NP - 2];
+    dd[NP - 1] = B[NP - 1][NP - 1];
+    ee[NP - 2] = B[NP - 1][NP - 2];
+    ee[NP - 1] = 0.0;
+    __syncthreads();
+    // ---- subproblem on the tridiagonal matrix T = Q^T B Q (Moré and Sorensen's method,
+    // Nocedal & Wright, Alg. 4.3, with T's factorisations instead of B's): lane i keeps
+    // d_i, e_i (e_i couples i and i + 1) and the i-th entries of the vectors; scalar
+    // recurrences run in every lane alike on values read with a wave-uniform index.
+    double dv = (t < NP) ? dd[t] : 0.0, ev = (t < NP) ? ee[t] : 0.0;
+    const double R = a.radius[s];
+    double gtv = 0.0;   // Q^T g
+    if (t < NP)
+        for (int k = 0; k < NP; ++k) gtv += Q[k][t] * gm[k];
+    const double gn = sqrt(wave_sum(gtv * gtv));
+    // smallest eigenvalue of T (needed when T is indefinite): Sturm counts at 64 points of
+    // the bracket per round
+    auto smallest_eigenvalue = [&]() {
+        double lo_e, hi_e;
+        {
+            const double em1 = __shfl(ev, t > 0 ? t - 1 : 0, 64);
+            const double rad = (t < NP) ? fabs(t > 0 ? em1 : 0.0) + fabs(t < NP - 1 ? ev : 0.0) : 0.0;
+            lo_e = wave_min((t < NP) ? dv - rad : INFINITY);
+            hi_e = wave_max((t < NP) ? dv + rad : -INFINITY);
+        }
+        for (int round = 0; round < 40; ++round) {
+            const double w = hi_e - lo_e;
+            if (!(w > 4.0 * EPS_D * fmax(fabs(lo_e), fabs(hi_e)) + 1e-300)) break;
+            const double x = lo_e + w * ((double)(t + 1) / 65.0);
+            int cnt = 0;
+            double q = lane_get(dv, 0) - x;
+            if (q == 0.0) q = -1e-300;
+            cnt += q < 0.0;
+            for (int i = 1; i < NP; ++i) {
+                const double e1 = lane_get(ev, i - 1);
+                q = lane_get(dv, i) - x - e1 * e1 / q;
+                if (q == 0.0) q = -1e-300;
+                cnt += q < 0.0;
             }
-            __syncthreads();
-            // B <- J^T B (disjoint row pairs)
-            for (int idx = t; idx < NPAIR * NJ; idx += TRB) {
-                const int k = idx / NJ, col = idx - k * NJ;
-                const int p = rot_p[k], q = rot_q[k];
-                const double c = rot_c[k], sn = rot_s[k];
-                const double bpk = B[p][col], bqk = B[q][col];
-                B[p][col] = c * bpk - sn * bqk;
-                B[q][col] = sn * bpk + c * bqk;
+            const unsigned long long hit = __ballot(cnt >= 1);
+            const int k = hit ? __ffsll((long long)hit) - 1 : 64;
+            const double nlo = k == 0 ? lo_e : lane_get(x, k - 1);
+            const double nhi = k < 64 ? lane_get(x, k) : hi_e;
+            if (nlo == lo_e && nhi == hi_e) break;
+            lo_e = nlo;
+            hi_e = nhi;
+        }
+        return 0.5 * (lo_e + hi_e);
+    };
+    // factorisation of T + mu I (no pivoting: positive definite whenever it is used) and
+    // the two triangular sweeps
+    double cpv = 0.0, idv = 0.0;
+    auto factor = [&](double mu) {   // returns whether every pivot is positive
+        double cprev = 0.0;
+        bool pos = true;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const double em1 = i > 0 ? lane_get(ev, i - 1) : 0.0;
+            const double den = lane_get(dv, i) + mu - em1 * cprev;
+            pos = pos && den > 0.0;
+            const double inv = 1.0 / den;
+            cprev = i < NP - 1 ? lane_get(ev, i) * inv : 0.0;
+            cpv = t == i ? cprev : cpv;
+            idv = t == i ? inv : idv;
+        }
+        return pos;
+    };
+    auto subst = [&](double rhs) {
+        double rprev = 0.0, rpv = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const double em1 = i > 0 ? lane_get(ev, i - 1) : 0.0;
+            rprev = (lane_get(rhs, i) - em1 * rprev) * lane_get(idv, i);
+            rpv = t == i ? rprev : rpv;
+        }
+        double ynext = rprev, yv = t == NP - 1 ? rprev : 0.0;
+#pragma unroll
+        for (int i = NP - 2; i >= 0; --i) {
+            ynext = lane_get(rpv, i) - lane_get(cpv, i) * ynext;
+            yv = t == i ? ynext : yv;
+        }
+        return yv;
+    };
+    bool fast = false;
+    double yv = 0.0;
+    // positive pivots at mu = 0: T is positive definite (the smallest eigenvalue is
+    // positive), so try the interior Newton step and bracket the secular equation from 0
+    const bool pd = factor(0.0);
+    if (pd) {
+        yv = subst(-gtv);
+        fast = wave_sum(yv * yv) <= R * R;
+    }
+    if (!fast) {
+        const double lmin_t = pd ? 0.0 : smallest_eigenvalue();
+        const double lo0 = fmax(0.0, -lmin_t);
+        bool hard = false;
+        if (lo0 > 0.0) {
+            // nearly the hard case (g almost orthogonal to the lowest eigenvector) goes to
+            // the eigenbasis below
+            const double scale = fmax(fabs(lmin_t), wave_max((t < NP) ? fabs(dv) + 2.0 * fabs(ev) : 0.0));
+            factor(lo0 + 1e-12 * scale);
+            const double yp = subst(-gtv);
+            const double n2 = wave_sum(yp * yp);
+            hard = n2 < R * R;   // (an overflowing norm is the opposite of the hard case)
+        }
+        if (!hard) {
+            double lo = lo0, hi = lo0 + gn / R + 1e-300;
+            double mu = hi;
+            for (int itn = 0; itn < 200; ++itn) {
+                factor(mu);
+                yv = subst(-gtv);
+                const double wv = subst(yv);
+                const double n2 = wave_sum(yv * yv), d3 = wave_sum(yv * wv);
+                const double nrm = sqrt(n2);
+                if (fabs(nrm - R) <= 1e-13 * R) break;
+                if (nrm > R) lo = mu;
+                else hi = mu;
+                double nmu = mu + (nrm - R) / R * (n2 / d3);
+                if (!(nmu > lo && nmu < hi)) nmu = 0.5 * (lo + hi);
+                if (nmu == mu) break;
+                mu = nmu;
             }
-            __syncthreads();
-            if (t < NPAIR && rot_s[t] != 0.0) {
-                B[rot_p[t]][rot_q[t]] = 0.0;
-                B[rot_q[t]][rot_p[t]] = 0.0;
-            }
-            __syncthreads();
+            factor(mu);
+            yv = subst(-gtv);
+            fast = true;
         }
     }
+    if (fast) {
+        // predicted increase -(g.p + p.B.p/2) with p = Q y: g.p = gt.y, p.B.p = y.T.y
+        const double ynext = __shfl(yv, t < NP - 1 ? t + 1 : t, 64);
+        const double tyy = (t < NP) ? dv * yv * yv + (t < NP - 1 ? 2.0 * ev * yv * ynext : 0.0) : 0.0;
+        const double pr = -(wave_sum(gtv * yv) + 0.5 * wave_sum(tyy));
+        const double pn = sqrt(wave_sum(yv * yv));
+        if (t < NP) ph[t] = yv;
+        if (t == 0) {
+            a.pred[2 * s] = pr;
+            a.pred[2 * s + 1] = pn;
+        }
+        __syncthreads();
+        if (t < NP) {
+            double pp = 0.0;
+            for (int i = 0; i < NP; ++i) pp += Q[t][i] * ph[i];
+            trial[t] = from_unconstrained(t, eta[t] + pp);
+        } else if (t < ROW) {
+            trial[t] = 0.0;
+        }
+        return;
+    }
+    // ---- otherwise the full eigendecomposition: implicit QL on T.  Lane i keeps d_i and e_i in registers;
+    // the scalar recurrence runs in every lane alike on values read across lanes with a
+    // wave-uniform index, and lane i applies the rotations to row i of Q (in LDS).
+    bool converged = true;
+    for (int l = 0; l < NP && converged; ++l) {
+        for (int iter = 0;; ++iter) {
+            int m = l;
+            for (; m < NP - 1; ++m)
+                if (fabs(lane_get(ev, m)) <= EPS_D * (fabs(lane_get(dv, m)) + fabs(lane_get(dv, m + 1)))) break;
+            if (m == l) break;
+            if (iter == QL_MAX_ITER) {
+                converged = false;
+                break;
+            }
+            const double el = lane_get(ev, l), dl = lane_get(dv, l);
+            double g = (lane_get(dv, l + 1) - dl) / (2.0 * el);
+            double r = hypot(g, 1.0);
+            g = lane_get(dv, m) - dl + el / (g + copysign(r, g));
+            double sn = 1.0, cs = 1.0, p = 0.0;
+            bool deflated = false;
+            for (int i = m - 1; i >= l; --i) {
+                const double ei = lane_get(ev, i);
+                const double f = sn * ei, b = cs * ei;
+                r = hypot(f, g);
+                ev = t == i + 1 ? r : ev;
+                if (r == 0.0) {   // underflow: the matrix splits here
+                    dv = t == i + 1 ? dv - p : dv;
+                    ev = t == m ? 0.0 : ev;
+                    deflated = true;
+                    break;
+                }
+                const double rinv = 1.0 / r;
+                sn = f * rinv;
+                cs = g * rinv;
+                g = lane_get(dv, i + 1) - p;
+                r = (lane_get(dv, i) - g) * sn + 2.0 * cs * b;
+                p = sn * r;
+                dv = t == i + 1 ? g + p : dv;
+                g = cs * r - b;
+                if (t < NP) {
+                    const double zi = Q[t][i], zn = Q[t][i + 1];
+                    Q[t][i + 1] = sn * zi + cs * zn;
+                    Q[t][i] = cs * zi - sn * zn;
+                }
+            }
+            if (deflated) continue;
+            dv = t == l ? dv - p : dv;
+            ev = t == l ? g : (t == m ? 0.0 : ev);
+        }
+    }
+    if (t < NJ) dd[t] = dv;
+    __syncthreads();
+    if (!converged) {   // no step this iteration: the source stops (not met in practice)
+        if (t < ROW) trial[t] = (t < NP) ? th[t] : 0.0;
+        if (t == 0) {
+            a.pred[2 * s] = 0.0;
+            a.pred[2 * s + 1] = 0.0;
+            a.done[s] = 1;
+        }
+        return;
+    }
     if (t < NP) {
-        lam[t] = B[t][t];
+        lam[t] = dd[t];
         double g = 0.0;
         for (int k = 0; k < NP; ++k) g += Q[k][t] * gm[k];
         gh[t] = g;
@@ -199,7 +408,6 @@ __global__ void __launch_bounds__(TRB) k_tr_solve(TrArgs a) {
     __syncthreads();
     // ---- subproblem in the eigenbasis (lane 0)
     if (t == 0) {
-        const double R = a.radius[s];
         double lmin = lam[0], lmax = fabs(lam[0]), gn2 = 0.0;
         int imin = 0;
         for (int i = 0; i < NP; ++i) {
@@ -304,13 +512,7 @@ __global__ void __launch_bounds__(128) k_tr_update(TrArgs a) {
 
 hipError_t launch_tr_solve(const TrArgs& a, hipStream_t st) {
     if (a.srcs.n <= 0) return hipSuccess;
-    // a large batch keeps every SIMD busy with one wave per source; a small one gains from
-    // spreading each rotation update over four waves (Cyclades rounds on the 20000-source
-    // region: 5% per epoch; 256 lanes for 1024 sources would cost 10% per Newton iteration)
-    if (a.srcs.n < TR_WIDE_BELOW)
-        hipLaunchKernelGGL(k_tr_solve<256>, dim3(a.srcs.n), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_tr_solve<64>, dim3(a.srcs.n), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_tr_solve, dim3(a.srcs.n), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 
