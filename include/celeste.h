@@ -182,8 +182,9 @@ int celeste_hvp(celeste_plan* plan, const double* theta, const double* v, double
 /* Dense per-source Hessians hess[k][27][27] (device, row-major) of the n listed
  * sources src[k] (host list of distinct ids; CELESTE_EINVAL otherwise), the exact
  * second derivatives of Section IV-D: each box's Hessian in its ten intermediates
- * (brightness factors from the gradient pass, six tangent-adjoint passes for position,
- * frac_dev and shape) pushed through the chain rule and its tangent, plus the KL. */
+ * (brightness factors and frac_dev from the gradient pass, position and shape from a
+ * closed-form pass, or from tangent-adjoint passes: celeste_plan_set_hessian_mode)
+ * pushed through the chain rule and its tangent, plus the KL. */
 int celeste_hessian(celeste_plan* plan, const double* theta, const int32_t* src, int n,
                     double* hess, hipStream_t stream);
 
@@ -191,8 +192,9 @@ int celeste_hessian(celeste_plan* plan, const double* theta, const int32_t* src,
  * distinct).  Each listed source is optimised with every other source held at its
  * value in theta at entry.  Per iteration: gradient, dense 27x27 Hessian, exact
  * trust-region subproblem in unconstrained coordinates (logit of q, frac_dev, axis
- * ratio; log of radius and variances) by a Jacobi eigendecomposition and a secular
- * equation, trial evaluation, accept/reject and radius update - all on the device.
+ * ratio; log of radius and variances) on the Householder tridiagonal form of the
+ * Hessian (secular equation; the eigendecomposition near the hard case), trial
+ * evaluation, accept/reject and radius update - all on the device.
  * theta_inout (device [n_src][32]) is updated in place; radius (device [n_src]) is
  * read and written (initialise with params->radius0); elbo_out (device [n_src] or
  * NULL) receives the final ELBO_s of the listed sources. */

@@ -562,8 +562,9 @@ int background(celeste_plan* p, const Sel& items, hipStream_t st) {
 
 // Dense Hessians of the listed sources (d_hess by list position).  Expects the item
 // partials and pixel-level Hessian rows (kk: brightness factors and frac_dev) of a double
-// gradient pass over `item` on stored backgrounds.  With five tangent passes along the
-// boxes' other intermediates (position, shape covariance) they give each box's 10x10
+// gradient pass over `item` on stored backgrounds (and, for the closed-form pass, the
+// own profile values that pass stores).  With the position and shape rows (closed-form
+// pass, or five tangent passes along those intermediates) they give each box's 10x10
 // Hessian of its pixel terms; the chain rule and its tangent assemble the 27x27 blocks.
 int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& src, const Sel& pair, const Sel& item,
                                int base, hipStream_t st);
