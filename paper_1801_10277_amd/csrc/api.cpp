@@ -1,6 +1,6 @@
 // Host side of libceleste: plan construction (validation, box binning, work items,
 // overlap lists), the C entry points, HIP graph capture of the batched evaluation, the
-// launch-configuration autotuner, conflict-free batching and the sweep driver.
+// launch-configuration autotuner, conflict-free batching and the sweep loop.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
