@@ -55,6 +55,22 @@ def test_newton_matches_oracle_overlapping_sources(B, N, O, synth, steps):
     np.testing.assert_array_equal(th_gpu[:, 27:], 0.0)
 
 
+def test_newton_same_with_either_hessian_mode(B, synth):
+    """Newton iterations with the closed-form Hessian rows (default) and with the tangent
+    passes reach the same parameters."""
+    f = synth.tiny(S=5, n_bands=2, size=23, side=11, seed=13)
+    out = []
+    for mode in (0, 1):
+        plan = B.Plan(f)
+        plan.set_hessian_mode(mode)
+        theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+        say("case newton hessian mode", mode)
+        plan.newton(theta, list(range(5)), 4)
+        out.append(theta.cpu().numpy())
+    scale = 1.0 + np.abs(out[1])
+    assert np.all(np.abs(out[0] - out[1]) <= 1e-8 * scale), np.max(np.abs(out[0] - out[1]) / scale)
+
+
 def test_conflict_free_batch_equals_one_at_a_time(B, synth):
     f = synth.tiny(S=4, n_bands=2, size=31, side=9, seed=61)
     plan = B.Plan(f)
