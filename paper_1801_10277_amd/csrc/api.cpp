@@ -104,6 +104,9 @@ struct celeste_plan {
     int* d_counter = nullptr;
     double* d_grad = nullptr;
     double* d_hess = nullptr;
+    double* d_grad_trial = nullptr;  // gradient and Hessian at the Newton trial points
+    double* d_hess_trial = nullptr;
+    uint8_t* d_accepted = nullptr;
     double* d_gw = nullptr;      // [n_pairs][11] per-box gradient sums
     double* d_hw = nullptr;      // [n_pairs][10][10] per-box Hessian of the pixel part w.r.t. its intermediates
     double* d_theta_trial = nullptr;
@@ -567,7 +570,7 @@ int background(celeste_plan* p, const Sel& items, hipStream_t st) {
 // pass, or five tangent passes along those intermediates) they give each box's 10x10
 // Hessian of its pixel terms; the chain rule and its tangent assemble the 27x27 blocks.
 int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& src, const Sel& pair, const Sel& item,
-                               int base, hipStream_t st);
+                               int base, double* hess, hipStream_t st);
 
 #define CHK(x)                              \
     do {                                    \
@@ -655,7 +658,7 @@ int fill_f64(double* d, const Sel& srcs, double v, hipStream_t st) {
 }
 
 int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& src, const Sel& pair, const Sel& item,
-                               int base, hipStream_t st) {
+                               int base, double* hess, hipStream_t st) {
     HIPCHK(launch_pair_reduce(pair, p->d_pairs, p->d_partials, p->d_kk, false, 0, p->d_gw, p->d_hw, p->d_status,
                               st));
     // the brightness-factor and frac_dev rows came with the gradient pass; the five position
@@ -675,8 +678,8 @@ int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& 
         HIPCHK(launch_hess_consts(pair, p->d_tab1, p->consts, p->d_hc, p->d_status, st));
         HIPCHK(launch_hess_geom(a, p->d_hc, p->d_hg, p->persistent_grid(), p->wpb, p->rows, st));
         HIPCHK(launch_pair_hess(pair, p->d_pairs, p->d_hg, p->d_hw, p->d_status, st));
-        HIPCHK(launch_assemble_hessian(src, p->geom(), p->d_patch_ptr, theta, p->d_gw, p->d_hw, p->d_hess,
-                                       p->d_status, st));
+        HIPCHK(launch_assemble_hessian(src, p->geom(), p->d_patch_ptr, theta, p->d_gw, p->d_hw, hess, p->d_status,
+                                       st));
         return CELESTE_OK;
     }
     for (int i = W_UX; i < NW; ++i) {
@@ -686,8 +689,7 @@ int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& 
         HIPCHK(launch_pair_reduce(pair, p->d_pairs, p->d_partials, nullptr, true, i, p->d_gw, p->d_hw, p->d_status,
                                   st));
     }
-    HIPCHK(launch_assemble_hessian(src, p->geom(), p->d_patch_ptr, theta, p->d_gw, p->d_hw, p->d_hess, p->d_status,
-                                   st));
+    HIPCHK(launch_assemble_hessian(src, p->geom(), p->d_patch_ptr, theta, p->d_gw, p->d_hw, hess, p->d_status, st));
     return CELESTE_OK;
 }
 
@@ -703,6 +705,9 @@ int newton_run(celeste_plan* p, double* theta, const Sel& src, const Sel& pair, 
     tr.theta = theta;
     tr.grad = p->d_grad;
     tr.hess = p->d_hess;
+    tr.grad_trial = p->d_grad_trial;
+    tr.hess_trial = p->d_hess_trial;
+    tr.accepted = p->d_accepted;
     tr.radius = radius;
     tr.theta_trial = p->d_theta_trial;
     tr.pred = p->d_pred;
@@ -713,18 +718,26 @@ int newton_run(celeste_plan* p, double* theta, const Sel& src, const Sel& pair, 
     tr.radius_max = prm->radius_max;
     tr.gtol = prm->gtol;
     tr.status = p->d_status;
+    if (n_steps <= 0) return CELESTE_OK;
+    // value, gradient and Hessian at the entry point
+    CHK(prep(p, theta, pair, false, DIR_NONE, nullptr, 0, st));
+    CHK(adjoint(p, item, nullptr, false, BASE_BG, true, st, 0, true));
+    CHK(finalize(p, theta, src, nullptr, false, DIR_NONE, nullptr, 0, true, p->d_elbo_cur, p->d_grad, nullptr, 0,
+                 false, st));
+    CHK(hessian_from_intermediates(p, theta, src, pair, item, BASE_BG, p->d_hess, st));
     for (int it = 0; it < n_steps; ++it) {
-        CHK(prep(p, theta, pair, false, DIR_NONE, nullptr, 0, st));
-        CHK(adjoint(p, item, nullptr, false, BASE_BG, true, st, 0, true));
-        CHK(finalize(p, theta, src, nullptr, false, DIR_NONE, nullptr, 0, true, p->d_elbo_cur, p->d_grad, nullptr,
-                     0, false, st));
-        CHK(hessian_from_intermediates(p, theta, src, pair, item, BASE_BG, st));
         HIPCHK(launch_tr_solve(tr, st));
+        // the trial point: its value and, except after the last step, its gradient and
+        // Hessian, which become the current ones where the step is accepted (a rejected
+        // step keeps the point and with it the current gradient and Hessian)
+        const bool more = it + 1 < n_steps;
         CHK(prep(p, p->d_theta_trial, pair, false, DIR_NONE, nullptr, 0, st));
-        CHK(adjoint(p, item, nullptr, false, BASE_BG, false, st));
-        CHK(finalize(p, p->d_theta_trial, src, nullptr, false, DIR_NONE, nullptr, 0, false, p->d_elbo_trial, nullptr,
-                     nullptr, 0, false, st));
+        CHK(adjoint(p, item, nullptr, false, BASE_BG, more, st, 0, more));
+        CHK(finalize(p, p->d_theta_trial, src, nullptr, false, DIR_NONE, nullptr, 0, more, p->d_elbo_trial,
+                     more ? p->d_grad_trial : nullptr, nullptr, 0, false, st));
+        if (more) CHK(hessian_from_intermediates(p, p->d_theta_trial, src, pair, item, BASE_BG, p->d_hess_trial, st));
         HIPCHK(launch_tr_update(tr, st));
+        if (more) HIPCHK(launch_tr_adopt(tr, st));
     }
     return CELESTE_OK;
 }
@@ -764,7 +777,7 @@ void celeste_plan_destroy(celeste_plan* p) {
                     p->d_tile_sums, p->d_status, p->d_counter, p->d_grad, p->d_hess, p->d_theta_trial,
                     p->d_pred, p->d_elbo_cur, p->d_elbo_trial, p->d_radius, p->d_done, p->d_list_src,
                     p->d_list_pair, p->d_list_item, p->d_cls_items, p->d_pair_lgamma, p->d_fg, p->d_gw,
-                    p->d_hw, p->d_kk, p->d_hg, p->d_hc};
+                    p->d_hw, p->d_kk, p->d_hg, p->d_hc, p->d_grad_trial, p->d_hess_trial, p->d_accepted};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -857,6 +870,9 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     const size_t S = (size_t)p->n_src;
     A(dalloc(&p->d_grad, S * ROW, W));
     A(dalloc(&p->d_hess, S * NP * NP, W));
+    A(dalloc(&p->d_grad_trial, S * ROW, W));
+    A(dalloc(&p->d_hess_trial, S * NP * NP, W));
+    A(dalloc(&p->d_accepted, S, W));
     A(dalloc(&p->d_gw, np * NACC, W));
     A(dalloc(&p->d_hw, np * 100, W));
     A(dalloc(&p->d_theta_trial, S * ROW, W));
@@ -1083,7 +1099,7 @@ int celeste_hessian(celeste_plan* p, const double* theta, const int32_t* src, in
     CHK(prep(p, theta, all.pair, false, DIR_NONE, nullptr, 0, st));
     CHK(background(p, si, st));
     CHK(adjoint(p, si, nullptr, false, BASE_BG, true, st, 0, true));
-    CHK(hessian_from_intermediates(p, theta, ss, sp, si, BASE_BG, st));
+    CHK(hessian_from_intermediates(p, theta, ss, sp, si, BASE_BG, p->d_hess, st));
     HIPCHK(hipMemcpyAsync(hess, p->d_hess, (size_t)n * NP * NP * sizeof(double), hipMemcpyDeviceToDevice, st));
     return CELESTE_OK;
 }

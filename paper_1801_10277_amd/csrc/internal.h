@@ -261,8 +261,11 @@ hipError_t launch_assemble_hessian(const Sel& srcs, const Geometry& g, const int
 struct TrArgs {
     Sel srcs;
     double* theta;             // [S][32] current point, updated by tr_update
-    const double* grad;        // [S][32] natural-space gradient at theta
-    const double* hess;        // [n][27][27] by list position
+    double* grad;              // [S][32] natural-space gradient at theta
+    double* hess;              // [n][27][27] by list position
+    const double* grad_trial;  // [S][32] gradient at the trial point, or null
+    const double* hess_trial;  // [n][27][27] Hessian at the trial point, or null
+    uint8_t* accepted;         // [S] set by tr_update: the trial point became the current one
     double* radius;            // [S]
     double* theta_trial;       // [S][32]
     double* pred;              // [S] predicted increase
@@ -274,5 +277,7 @@ struct TrArgs {
 };
 hipError_t launch_tr_solve(const TrArgs& a, hipStream_t st);
 hipError_t launch_tr_update(const TrArgs& a, hipStream_t st);
+// Gradient and Hessian of the trial point become the current ones where it was accepted.
+hipError_t launch_tr_adopt(const TrArgs& a, hipStream_t st);
 
 }  // namespace cel

@@ -16,7 +16,8 @@
 //     Math. 11, 1968) and the subproblem in the eigenbasis, the hard case along the
 //     eigenvector of the smallest eigenvalue;
 //  5. trial point and predicted increase.
-// k_tr_update compares the actual and predicted increase and updates point and radius.
+// k_tr_update compares the actual and predicted increase and updates point and radius;
+// k_tr_adopt then takes over the trial point's gradient and Hessian where it was accepted.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -490,6 +491,7 @@ __global__ void __launch_bounds__(128) k_tr_update(TrArgs a) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= a.srcs.n) return;
     const int s = sel_at(a.srcs, j);
+    a.accepted[s] = 0;
     if (a.done[s]) return;
     const double f0 = a.elbo_cur[s], f1 = a.elbo_trial[s];
     const double pr = a.pred[2 * s], pn = a.pred[2 * s + 1];
@@ -504,6 +506,7 @@ __global__ void __launch_bounds__(128) k_tr_update(TrArgs a) {
         const double* tr = a.theta_trial + (size_t)s * ROW;
         for (int i = 0; i < NP; ++i) th[i] = tr[i];
         a.elbo_cur[s] = f1;
+        a.accepted[s] = 1;
     }
     // no further progress possible at working precision
     if (!(pr > 1e-15 * fabs(f0)) || R < 1e-12) a.done[s] = 1;
@@ -513,6 +516,24 @@ __global__ void __launch_bounds__(128) k_tr_update(TrArgs a) {
 hipError_t launch_tr_solve(const TrArgs& a, hipStream_t st) {
     if (a.srcs.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_tr_solve, dim3(a.srcs.n), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+// One work-group per listed source.
+__global__ void __launch_bounds__(256) k_tr_adopt(TrArgs a) {
+    if (*a.status) return;
+    const int j = blockIdx.x;
+    const int s = sel_at(a.srcs, j);
+    if (!a.accepted[s]) return;
+    const double* hs = a.hess_trial + (size_t)j * NP * NP;
+    double* hd = a.hess + (size_t)j * NP * NP;
+    for (int i = threadIdx.x; i < NP * NP; i += blockDim.x) hd[i] = hs[i];
+    if (threadIdx.x < ROW) a.grad[(size_t)s * ROW + threadIdx.x] = a.grad_trial[(size_t)s * ROW + threadIdx.x];
+}
+
+hipError_t launch_tr_adopt(const TrArgs& a, hipStream_t st) {
+    if (a.srcs.n <= 0 || !a.hess_trial || !a.grad_trial) return hipSuccess;
+    hipLaunchKernelGGL(k_tr_adopt, dim3(a.srcs.n), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
