@@ -551,12 +551,15 @@ int finalize(celeste_plan* p, const double* theta, const Sel& srcs, const uint8_
     return CELESTE_OK;
 }
 
-int background(celeste_plan* p, const Sel& items, hipStream_t st) {
+// Background of the listed visits: the other boxes' Gaussians evaluated from the current
+// tables, or (stored = true) their stored own values, which must be current.
+int background(celeste_plan* p, const Sel& items, hipStream_t st, bool stored = false) {
     BgArgs a{};
     a.g = p->geom();
     a.items = items;
     a.tab_val = p->d_tab1;
     a.coef_val = p->d_coef1;
+    a.fg = stored ? p->d_fg : nullptr;
     a.bg = p->d_bg;
     a.status = p->d_status;
     HIPCHK(launch_background(a, p->persistent_grid(), p->wpb, p->rows, st));
@@ -694,12 +697,18 @@ int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& 
 }
 
 // Newton trust-region iterations for one source set; lists already on the device.
+// stored_bg: every box's stored own values and coefficients are current (sweeps keep them
+// so), and the background is summed from them instead of evaluated.
 int newton_run(celeste_plan* p, double* theta, const Sel& src, const Sel& pair, const Sel& item, int n_steps,
-               const celeste_tr_params* prm, double* radius, hipStream_t st) {
-    const Scope all = scope_all(p);
+               const celeste_tr_params* prm, double* radius, hipStream_t st, bool stored_bg = false) {
     // background of every listed visit with all sources at their entry values
-    CHK(prep(p, theta, all.pair, false, DIR_NONE, nullptr, 0, st));
-    CHK(background(p, item, st));
+    if (stored_bg) {
+        CHK(background(p, item, st, true));
+    } else {
+        const Scope all = scope_all(p);
+        CHK(prep(p, theta, all.pair, false, DIR_NONE, nullptr, 0, st));
+        CHK(background(p, item, st));
+    }
     TrArgs tr{};
     tr.srcs = src;
     tr.theta = theta;
@@ -1355,6 +1364,10 @@ int celeste_sweep(celeste_plan* p, double* theta, const int32_t* batch_ptr, cons
         return hip_fail(hipGetLastError(), "sweep list upload");
     }
     int rc = CELESTE_OK;
+    // With the strip render, the total ELBO leaves every box's own profile values and
+    // coefficients current; each batch then takes its background from them, and its boxes
+    // are rendered again at their new parameters before the next batch.
+    const bool stored = p->render_mode == 2 || p->render_mode == 3;
     do {
         rc = celeste_total_elbo(p, theta, elbo_trace, st);
         if (rc != CELESTE_OK) break;
@@ -1369,7 +1382,13 @@ int celeste_sweep(celeste_plan* p, double* theta, const int32_t* batch_ptr, cons
                 // fresh trust region for every visit of a batch
                 rc = fill_f64(p->d_radius, ss, prm->radius0, st);
                 if (rc != CELESTE_OK) break;
-                rc = newton_run(p, theta, ss, sp, si, prm->newton_steps, prm, p->d_radius, st);
+                rc = newton_run(p, theta, ss, sp, si, prm->newton_steps, prm, p->d_radius, st, stored);
+                if (rc != CELESTE_OK || !stored) continue;
+                rc = prep(p, theta, sp, false, DIR_NONE, nullptr, 0, st);
+                if (rc == CELESTE_OK &&
+                    launch_strip_fg(si, p->geom(), p->d_tab1, p->d_fg, p->rows, p->persistent_grid(), p->wpb,
+                                    p->d_status, st) != hipSuccess)
+                    rc = hip_fail(hipGetLastError(), "sweep render");
             }
             if (rc == CELESTE_OK) rc = celeste_total_elbo(p, theta, elbo_trace + sw + 1, st);
         }

@@ -186,6 +186,7 @@ struct BgArgs {
     Sel items;
     const double* tab_val;
     const double* coef_val;
+    const double* fg;          // [n_visits][2] current stored own values: background from them, or null
     double* bg;
     const int* status;
 };

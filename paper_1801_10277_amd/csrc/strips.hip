@@ -843,6 +843,41 @@ __global__ void __launch_bounds__(256) k_background_strips(BgArgs a, const Item*
     }
 }
 
+// Background of the listed visits from the other boxes' stored own profile values (sweeps:
+// the stored values are kept current box by box), no Gaussian evaluated.
+template <int L>
+__global__ void __launch_bounds__(256) k_background_fg(BgArgs a, const Item* __restrict__ items,
+                                                       const PairDev* __restrict__ pairs,
+                                                       const celeste_image* __restrict__ images,
+                                                       const int32_t* __restrict__ nbr,
+                                                       const double* __restrict__ coefv,
+                                                       const double* __restrict__ fgm, double* __restrict__ bg) {
+    if (*a.status) return;
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int nw = gridDim.x * wpb;
+    for (int j = blockIdx.x * wpb + (threadIdx.x >> 6); j < a.items.n; j += nw) {
+        const int ii = __builtin_amdgcn_readfirstlane(sel_at(a.items, j));
+        const Item it = items[ii];
+        const PairDev p = pairs[it.pair];
+        const celeste_image& im = images[p.img];
+        for (int q = lane; q < it.count; q += 64) {
+            int c, r0, nrow;
+            strip_geometry(p, it.start + q, L, c, r0, nrow);
+            double Eb[L], Vb[L];
+            strip_background_fg<L>(p, pairs, nbr, coefv, fgm, im, c, r0, Eb, Vb);
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                if (k < nrow) {
+                    const size_t vi = (size_t)p.visit_off + (size_t)(r0 + k - p.r0) * p.w + (c - p.c0);
+                    bg[2 * vi] = Eb[k];
+                    bg[2 * vi + 1] = Vb[k];
+                }
+            }
+        }
+    }
+}
+
 // Sum over each box of log(x!) (masked pixels excluded): a constant of the pixel terms,
 // computed once per plan, one wave per box, fixed-order reduction.
 __global__ void __launch_bounds__(256) k_pair_lgamma(const PairDev* __restrict__ pairs, int n_pairs,
@@ -1237,6 +1272,20 @@ hipError_t launch_background(const BgArgs& a, int grid, int wpb, int L, hipStrea
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
     const Geometry& g = a.g;
+    if (a.fg) {
+        if (L == 8)
+            hipLaunchKernelGGL(k_background_fg<8>, dim3(grid), dim3(64 * wpb), 0, st, a, g.items, g.pairs, g.images,
+                               g.nbr, a.coef_val, a.fg, a.bg);
+        else if (L == 4)
+            hipLaunchKernelGGL(k_background_fg<4>, dim3(grid), dim3(64 * wpb), 0, st, a, g.items, g.pairs, g.images,
+                               g.nbr, a.coef_val, a.fg, a.bg);
+        else if (L == 16)
+            hipLaunchKernelGGL(k_background_fg<16>, dim3(grid), dim3(64 * wpb), 0, st, a, g.items, g.pairs, g.images,
+                               g.nbr, a.coef_val, a.fg, a.bg);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     if (L == 8)
         hipLaunchKernelGGL(k_background_strips<8>, dim3(grid), dim3(64 * wpb), 0, st, a, g.items, g.pairs, g.images,
                            g.nbr, a.tab_val, a.coef_val, a.bg);
