@@ -157,6 +157,26 @@ def test_cyclades_epoch_equals_serial_bca(B, N, O, synth):
     assert trace[1] >= trace[0]
 
 
+def test_sweep_stored_and_evaluated_backgrounds_agree(B, synth):
+    """A sweep with the strip render (batch backgrounds summed from stored values) and one
+    with the tile render at another strip height (backgrounds evaluated from the tables)
+    reach the same parameters and ELBO trace."""
+    f = synth.tiny(S=6, n_bands=2, size=29, side=11, seed=77)
+    out = []
+    for launch in (dict(), dict(strip_rows=8, render_mode=1)):
+        plan = B.Plan(f)
+        if launch:
+            plan.set_launch(**launch)
+        ptr, src = plan.color_batches(seed=2)
+        theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+        say("case sweep backgrounds", launch)
+        trace = plan.sweep(theta, ptr, src, 2, B.tr_params(newton_steps=3)).cpu().numpy()
+        out.append((theta.cpu().numpy(), trace))
+    (t0, e0), (t1, e1) = out
+    assert np.all(np.abs(t0 - t1) <= 1e-8 * (1.0 + np.abs(t1))), np.max(np.abs(t0 - t1))
+    np.testing.assert_allclose(e0, e1, rtol=1e-12)
+
+
 def test_sweep_rejects_conflicting_batch(B, synth):
     f = synth.tiny(S=3, n_bands=1, size=15, side=11, seed=81)
     plan = B.Plan(f)
