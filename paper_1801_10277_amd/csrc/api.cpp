@@ -107,6 +107,7 @@ struct celeste_plan {
     double* d_grad_trial = nullptr;  // gradient and Hessian at the Newton trial points
     double* d_hess_trial = nullptr;
     uint8_t* d_accepted = nullptr;
+    uint8_t* d_live = nullptr;
     double* d_gw = nullptr;      // [n_pairs][11] per-box gradient sums
     double* d_hw = nullptr;      // [n_pairs][10][10] per-box Hessian of the pixel part w.r.t. its intermediates
     double* d_theta_trial = nullptr;
@@ -572,8 +573,10 @@ int background(celeste_plan* p, const Sel& items, hipStream_t st, bool stored = 
 // own profile values that pass stores).  With the position and shape rows (closed-form
 // pass, or five tangent passes along those intermediates) they give each box's 10x10
 // Hessian of its pixel terms; the chain rule and its tangent assemble the 27x27 blocks.
+// With `active`, the closed-form pass covers only the boxes of the sources it marks (the
+// other sources' blocks are left undefined).
 int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& src, const Sel& pair, const Sel& item,
-                               int base, double* hess, hipStream_t st);
+                               int base, double* hess, hipStream_t st, const uint8_t* active = nullptr);
 
 #define CHK(x)                              \
     do {                                    \
@@ -661,7 +664,7 @@ int fill_f64(double* d, const Sel& srcs, double v, hipStream_t st) {
 }
 
 int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& src, const Sel& pair, const Sel& item,
-                               int base, double* hess, hipStream_t st) {
+                               int base, double* hess, hipStream_t st, const uint8_t* active) {
     HIPCHK(launch_pair_reduce(pair, p->d_pairs, p->d_partials, p->d_kk, false, 0, p->d_gw, p->d_hw, p->d_status,
                               st));
     // the brightness-factor and frac_dev rows came with the gradient pass; the five position
@@ -671,6 +674,7 @@ int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& 
         AdjArgs a{};
         a.g = p->geom();
         a.items = item;
+        a.active = active;
         a.tab = p->d_tab1;
         a.coef = p->d_coef1;
         a.bg = p->d_bg;
@@ -717,6 +721,7 @@ int newton_run(celeste_plan* p, double* theta, const Sel& src, const Sel& pair, 
     tr.grad_trial = p->d_grad_trial;
     tr.hess_trial = p->d_hess_trial;
     tr.accepted = p->d_accepted;
+    tr.live = p->d_live;
     tr.radius = radius;
     tr.theta_trial = p->d_theta_trial;
     tr.pred = p->d_pred;
@@ -736,17 +741,21 @@ int newton_run(celeste_plan* p, double* theta, const Sel& src, const Sel& pair, 
     CHK(hessian_from_intermediates(p, theta, src, pair, item, BASE_BG, p->d_hess, st));
     for (int it = 0; it < n_steps; ++it) {
         HIPCHK(launch_tr_solve(tr, st));
-        // the trial point: its value and, except after the last step, its gradient and
-        // Hessian, which become the current ones where the step is accepted (a rejected
-        // step keeps the point and with it the current gradient and Hessian)
+        // the trial point of every source still stepping (d_live): its value and, except
+        // after the last step, its gradient; then, for the sources whose step was accepted,
+        // its Hessian, and gradient and Hessian become the current ones (a rejected step
+        // keeps the point and with it the current gradient and Hessian)
         const bool more = it + 1 < n_steps;
         CHK(prep(p, p->d_theta_trial, pair, false, DIR_NONE, nullptr, 0, st));
-        CHK(adjoint(p, item, nullptr, false, BASE_BG, more, st, 0, more));
-        CHK(finalize(p, p->d_theta_trial, src, nullptr, false, DIR_NONE, nullptr, 0, more, p->d_elbo_trial,
+        CHK(adjoint(p, item, p->d_live, false, BASE_BG, more, st, 0, more));
+        CHK(finalize(p, p->d_theta_trial, src, p->d_live, false, DIR_NONE, nullptr, 0, more, p->d_elbo_trial,
                      more ? p->d_grad_trial : nullptr, nullptr, 0, false, st));
-        if (more) CHK(hessian_from_intermediates(p, p->d_theta_trial, src, pair, item, BASE_BG, p->d_hess_trial, st));
         HIPCHK(launch_tr_update(tr, st));
-        if (more) HIPCHK(launch_tr_adopt(tr, st));
+        if (more) {
+            CHK(hessian_from_intermediates(p, p->d_theta_trial, src, pair, item, BASE_BG, p->d_hess_trial, st,
+                                           p->d_accepted));
+            HIPCHK(launch_tr_adopt(tr, st));
+        }
     }
     return CELESTE_OK;
 }
@@ -786,7 +795,7 @@ void celeste_plan_destroy(celeste_plan* p) {
                     p->d_tile_sums, p->d_status, p->d_counter, p->d_grad, p->d_hess, p->d_theta_trial,
                     p->d_pred, p->d_elbo_cur, p->d_elbo_trial, p->d_radius, p->d_done, p->d_list_src,
                     p->d_list_pair, p->d_list_item, p->d_cls_items, p->d_pair_lgamma, p->d_fg, p->d_gw,
-                    p->d_hw, p->d_kk, p->d_hg, p->d_hc, p->d_grad_trial, p->d_hess_trial, p->d_accepted};
+                    p->d_hw, p->d_kk, p->d_hg, p->d_hc, p->d_grad_trial, p->d_hess_trial, p->d_accepted, p->d_live};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -882,6 +891,7 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     A(dalloc(&p->d_grad_trial, S * ROW, W));
     A(dalloc(&p->d_hess_trial, S * NP * NP, W));
     A(dalloc(&p->d_accepted, S, W));
+    A(dalloc(&p->d_live, S, W));
     A(dalloc(&p->d_gw, np * NACC, W));
     A(dalloc(&p->d_hw, np * 100, W));
     A(dalloc(&p->d_theta_trial, S * ROW, W));

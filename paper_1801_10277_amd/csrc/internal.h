@@ -273,6 +273,7 @@ struct TrArgs {
     double* elbo_cur;          // [S]
     const double* elbo_trial;  // [S]
     uint8_t* done;             // [S]
+    uint8_t* live;             // [S] set by tr_solve: the source takes a step this iteration
     double eta_accept, radius_max, gtol;
     int* status;
 };

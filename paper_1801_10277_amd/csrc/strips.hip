@@ -745,7 +745,8 @@ __device__ __forceinline__ void hess_pixels(const double* __restrict__ tab, cons
 
 // One wave per work item, one lane per strip; each lane walks its strip's pixels (stored
 // backgrounds and own profile values of the listed boxes) HPX rows at a time and the wave
-// sums the NHG entries into hg[item].  Launched with two rows and two waves per SIMD (a
+// sums the NHG entries into hg[item]; the items of sources outside a.active (when given)
+// get zeros.  Launched with two rows and two waves per SIMD (a
 // few dozen bytes of spills per lane): on 1024 sources 24% faster per Newton iteration
 // than one row, and faster than three rows (more spills) or four rows at one wave.
 template <int L, int HPX>
@@ -768,6 +769,11 @@ __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __r
         const int ii = __builtin_amdgcn_readfirstlane(sel_at(a.items, j));
         const Item it = items[ii];
         const PairDev p = pairs[it.pair];
+        if (a.active && !a.active[p.src]) {
+            if (lane < NHG) hg[(size_t)ii * NHG + lane] = 0.0;
+            j = a.dynamic ? next_item_s(a.counter, lane) : j + nw;
+            continue;
+        }
         const celeste_image& im = images[p.img];
         const double* tab = tabp + (size_t)it.pair * NCOMP * CST;
         const double* hc = hcp + (size_t)it.pair * NGAL * NHC;

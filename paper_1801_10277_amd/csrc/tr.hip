@@ -130,6 +130,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         for (int i = 0; i < NP; ++i) m = fmax(m, sh_red[i]);
         sh_done = (a.done[s] || !(m >= a.gtol)) ? 1 : 0;
         if (!(m == m)) sh_done = 1;
+        a.live[s] = sh_done ? 0 : 1;
     }
     __syncthreads();
     double* trial = a.theta_trial + (size_t)s * ROW;
@@ -397,6 +398,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
             a.pred[2 * s] = 0.0;
             a.pred[2 * s + 1] = 0.0;
             a.done[s] = 1;
+            a.live[s] = 0;
         }
         return;
     }
