@@ -643,6 +643,7 @@ struct HostScope {
 };
 
 void scope_lists(const celeste_plan* p, const int32_t* src, int n, HostScope& hs) {
+    const size_t i0 = hs.item.size();
     for (int j = 0; j < n; ++j) {
         const int s = src[j];
         hs.src.push_back(s);
@@ -651,6 +652,20 @@ void scope_lists(const celeste_plan* p, const int32_t* src, int n, HostScope& hs
             for (int it = p->pairs[pi].item_begin; it < p->pairs[pi].item_end; ++it) hs.item.push_back(it);
         }
     }
+    // items of more strips first, so that a launch over the list ends on short items and its
+    // last waves finish close together (every item writes its own outputs and the box sums
+    // run in item order: the list order changes no result)
+    // (a stable counting sort on the strip count)
+    const size_t n_it = hs.item.size() - i0;
+    if (n_it < 2) return;
+    int mx = 0;
+    for (size_t i = i0; i < hs.item.size(); ++i) mx = std::max(mx, (int)p->items[hs.item[i]].count);
+    std::vector<size_t> pos(mx + 2, 0);
+    for (size_t i = i0; i < hs.item.size(); ++i) pos[mx - p->items[hs.item[i]].count + 1]++;
+    for (int k = 1; k <= mx + 1; ++k) pos[k] += pos[k - 1];
+    std::vector<int32_t> out(n_it);
+    for (size_t i = i0; i < hs.item.size(); ++i) out[pos[mx - p->items[hs.item[i]].count]++] = hs.item[i];
+    std::copy(out.begin(), out.end(), hs.item.begin() + i0);
 }
 
 int fill_u8(uint8_t* d, const Sel& srcs, uint8_t v, hipStream_t st) {
