@@ -140,7 +140,7 @@ def run_newton(args):
     import numpy as np
     import torch
     from paper_1801_10277_amd import binding as B, synth
-    f = synth.config3()
+    f = synth.field_1024src()
     dev = torch.device("cuda:0")
     plan = B.Plan(f, check_status=False)
     if args.launch:
@@ -183,7 +183,7 @@ def run_sweep(args):
     from paper_1801_10277_amd import binding as B, synth
     log("generating the sky region ...")
     t = time.perf_counter()
-    f = synth.config4()
+    f = synth.sky_region_20000src()
     log("region ready in %.1f s: %d images, %d sources, %d boxes, %d visits" % (
         time.perf_counter() - t, f.n_img, f.n_src, len(f.boxes), f.visits()))
     dev = torch.device("cuda:0")

@@ -973,7 +973,7 @@ __global__ void __launch_bounds__(256) k_gather_planes(RenderArgs a, const TileD
         covered[k] = false;
     }
     // boxes in list order (the sums are fixed-order); GU boxes' loads are issued before any
-    // of them is added, so that their latencies overlap (config 2, 16 x 16 tiles: 0.533 ->
+    // of them is added, so that their latencies overlap (2000-source field, 16 x 16 tiles: 0.533 ->
     // 0.499 ms for the render; four or eight boxes at a time cost occupancy and are slower)
     constexpr int GU = RP == 4 ? 2 : 4;   // two at 4 rows per lane keeps 7 waves per SIMD
     int j = td.list_begin;

@@ -378,7 +378,7 @@ def _odd(side):
 # the five workloads
 
 
-def config0(seed=None):
+def single_source(seed=None):
     """One source (star w.p. 0.5) centred in a 41x41 patch in each of 5 bands."""
     rng = np.random.default_rng(1000 if seed is None else seed)
     imgs = _single_field_images(rng, 41, 41)
@@ -386,10 +386,10 @@ def config0(seed=None):
     pos = np.array([[20.0, 20.0]])
     theta = _theta_from_truth(rng, pos, flux, colours, shape)
     return _assemble(rng, imgs, pos, kind, flux, colours, shape, np.array([41]), theta,
-                     0.5, np.log(1000.0), 1.0, "config0")
+                     0.5, np.log(1000.0), 1.0, "single_source")
 
 
-def config1(seed=None):
+def region_16src(seed=None):
     """16 overlapping sources, uniform positions, 5-band 256x256 region, 61x61 patches."""
     rng = np.random.default_rng(1001 if seed is None else seed)
     imgs = _single_field_images(rng, 256, 256)
@@ -398,7 +398,7 @@ def config1(seed=None):
     pos = rng.uniform(0.0, 255.0, (S, 2))
     theta = _theta_from_truth(rng, pos, flux, colours, shape)
     return _assemble(rng, imgs, pos, kind, flux, colours, shape, np.full(S, 61), theta,
-                     0.5, np.log(1000.0), 1.0, "config1")
+                     0.5, np.log(1000.0), 1.0, "region_16src")
 
 
 LOGR_MEAN_FIELD = 7.71
@@ -406,7 +406,7 @@ LOGR_SD_FIELD = 1.267
 LOGR_RANGE_FIELD = (np.log(50.0), np.log(1e5))
 
 
-def sdss_field(S=2000, H=1489, W=2048, seed=1002, render=True, name="config2", realistic=False):
+def sdss_field(S=2000, H=1489, W=2048, seed=1002, render=True, name="field_2000src", realistic=False):
     """SDSS-shaped field: S sources uniform over a W x H frame (a Poisson process conditioned
     on its count), 40% stars, patch side log-uniform in [21, 101] px (odd), r-band
     brightness log-normal truncated to [50, 1e5] e-.  realistic=True adds a local linear
@@ -426,13 +426,13 @@ def sdss_field(S=2000, H=1489, W=2048, seed=1002, render=True, name="config2", r
                      0.4, LOGR_MEAN_FIELD, LOGR_SD_FIELD, name, render=render)
 
 
-def config2(seed=None, render=True):
-    return sdss_field(2000, seed=1002 if seed is None else seed, render=render, name="config2")
+def field_2000src(seed=None, render=True):
+    return sdss_field(2000, seed=1002 if seed is None else seed, render=render, name="field_2000src")
 
 
-def config3(seed=None, render=True):
+def field_1024src(seed=None, render=True):
     """1024 sources from the field generator, plus a seeded HVP direction per source."""
-    f = sdss_field(1024, seed=1003 if seed is None else seed, render=render, name="config3")
+    f = sdss_field(1024, seed=1003 if seed is None else seed, render=render, name="field_1024src")
     rng = np.random.default_rng((1003 if seed is None else seed) + 77)
     v = np.zeros_like(f.theta)
     v[:, :N_PARAM] = rng.standard_normal((f.n_src, N_PARAM))
@@ -441,7 +441,7 @@ def config3(seed=None, render=True):
 
 
 def sky_region(n_fx=4, n_fy=4, epochs=2, S=20000, H=1489, W=2048, overlap=128,
-               max_offset=500.0, seed=1004, render=True, name="config4"):
+               max_offset=500.0, seed=1004, render=True, name="sky_region_20000src"):
     """n_fx x n_fy fields on a grid overlapping by `overlap` px, each seen in `epochs`
     epochs whose frames are shifted by U[0, max_offset)^2 px, with a PSF per
     (field, epoch, band); S sources uniform over the union of the grid."""
@@ -464,12 +464,8 @@ def sky_region(n_fx=4, n_fy=4, epochs=2, S=20000, H=1489, W=2048, overlap=128,
                      0.4, LOGR_MEAN_FIELD, LOGR_SD_FIELD, name, render=render)
 
 
-def config4(seed=None, render=True):
+def sky_region_20000src(seed=None, render=True):
     return sky_region(seed=1004 if seed is None else seed, render=render)
-
-
-def make_config(i, seed=None, **kw):
-    return (config0, config1, config2, config3, config4)[i](seed=seed, **kw)
 
 
 def tiny(S=2, n_bands=2, size=15, side=9, seed=7, sky=(100.0, 200.0), psf_xi=False,

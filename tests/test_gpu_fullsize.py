@@ -39,13 +39,13 @@ def smallest(f, candidates, k):
     return [candidates[i] for i in np.argsort(px, kind="stable")[:k]]
 
 
-def test_newton_config3_full_size_sampled(B, N, synth):
+def test_newton_field_1024src_full_size_sampled(B, N, synth):
     """One trust-region Newton step of all 1024 sources (others at their entry values), as
     the Newton benchmark runs it; sampled sources against the oracle's step."""
-    f = synth.config3()
+    f = synth.field_1024src()
     plan = B.Plan(f)
     theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
-    say("case newton config3 full", plan.info())
+    say("case newton field_1024src full", plan.info())
     elbo, radius = plan.newton(theta, np.arange(f.n_src, dtype=np.int32), 1)
     th, elbo, radius = theta.cpu().numpy(), elbo.cpu().numpy(), radius.cpu().numpy()
     for s in smallest(f, list(range(0, f.n_src, 97)), 2):
@@ -57,15 +57,15 @@ def test_newton_config3_full_size_sampled(B, N, synth):
         assert radius[s] == R
 
 
-def test_sweep_config4_full_size_sampled(B, O, synth):
+def test_sweep_sky_region_20000src_full_size_sampled(B, O, synth):
     """One block-coordinate-ascent sweep over the 160-image region (conflict-free batches,
     two Newton steps per batch visit): monotone total ELBO, and the per-source ELBO of the
     final parameters on sampled sources against the oracle."""
-    f = synth.config4()
+    f = synth.sky_region_20000src()
     plan = B.Plan(f)
     theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
     ptr, src = plan.color_batches(seed=4)
-    say("case sweep config4 full", plan.info(), "batches", len(ptr) - 1)
+    say("case sweep sky_region_20000src full", plan.info(), "batches", len(ptr) - 1)
     trace = plan.sweep(theta, ptr, src, 1, B.tr_params(newton_steps=2)).cpu().numpy()
     assert trace[1] >= trace[0]
     e = plan.elbo(theta).cpu().numpy()

@@ -121,7 +121,7 @@ def test_sweep_trajectory(B, N, O, synth):
 
 def test_conflict_graph_matches_oracle(B, synth):
     from oracle import schedule as Sch
-    for f in (synth.tiny(S=8, n_bands=2, size=33, side=9, seed=73), synth.config1()):
+    for f in (synth.tiny(S=8, n_bands=2, size=33, side=9, seed=73), synth.region_16src()):
         say("case conflict graph", f.n_src)
         plan = B.Plan(f)
         ptr, adj = plan.conflict_graph()

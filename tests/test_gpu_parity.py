@@ -75,21 +75,21 @@ def test_tiny_general_psf_and_origin(B, O, synth):
     check_field(B, O, f, range(2), name="tiny-psf")
 
 
-def test_config0(B, O, synth):
-    f = synth.make_config(0)
-    check_field(B, O, f, [0], name="config0")
+def test_single_source(B, O, synth):
+    f = synth.single_source()
+    check_field(B, O, f, [0], name="single_source")
 
 
-def test_config1_sampled(B, O, synth):
-    f = synth.make_config(1)
-    check_field(B, O, f, [0, 7, 15], name="config1")
+def test_region_16src_sampled(B, O, synth):
+    f = synth.region_16src()
+    check_field(B, O, f, [0, 7, 15], name="region_16src")
 
 
-def test_plain_equals_batched_config1(B, synth):
-    f = synth.make_config(1)
+def test_plain_equals_batched_region_16src(B, synth):
+    f = synth.region_16src()
     theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
     plan = B.Plan(f)
-    say("case config1 plain-vs-batched")
+    say("case region_16src plain-vs-batched")
     e1, g1 = plan.elbo_grad(theta, mode=1)
     e0, g0 = plan.elbo_grad(theta, mode=0)
     np.testing.assert_allclose(e0.cpu().numpy(), e1.cpu().numpy(), rtol=1e-11)
@@ -320,10 +320,10 @@ def test_masked_pixels(B, O, synth):
     check_field(B, O, f, range(2), name="masked")
 
 
-def test_config2_full_size_sampled(B, O, synth):
+def test_field_2000src_full_size_sampled(B, O, synth):
     """Full field at the benchmark's launch configuration (plan default, graph replay), then
     at the autotuned one."""
-    f = synth.make_config(2)
+    f = synth.field_2000src()
     plan = B.Plan(f)
     theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
     P = O.Problem(f)
@@ -332,7 +332,7 @@ def test_config2_full_size_sampled(B, O, synth):
         if tuned:
             plan.autotune(theta, reps=1)
         plan.use_graph(True)
-        say("case config2 full", "autotuned" if tuned else "default", plan.info())
+        say("case field_2000src full", "autotuned" if tuned else "default", plan.info())
         e, g = plan.elbo_grad(theta)
         e, g = e.cpu().numpy(), g.cpu().numpy()
         for s, (val, gref, gabs) in refs.items():

@@ -479,7 +479,7 @@ def test_neighbourhood_reduction_keeps_source_terms(synth, O):
     """The test-side reduction to a source's overlapping neighbours leaves its ELBO and
     gradient unchanged (every pixel of its boxes sees the same sources)."""
     from conftest import neighbourhood
-    f = synth.make_config(1)
+    f = synth.region_16src()
     P = O.Problem(f)
     for s in (0, 9):
         g, j = neighbourhood(f, s)

@@ -152,7 +152,7 @@ def test_library_schedule_equals_oracle(n, p, B, seed):
 
 def test_library_schedule_on_field_graph(synth):
     from paper_1801_10277_amd import binding as Bd
-    f = synth.config1()
+    f = synth.region_16src()
     adj = Sch.conflict_graph(f)
     ptr, nbr = to_csr(adj)
     for B, seed in [(4, 1), (8, 2), (f.n_src, 3)]:
