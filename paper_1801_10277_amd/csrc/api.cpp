@@ -456,31 +456,37 @@ int render_tiles(celeste_plan* p, bool sums, hipStream_t st) {
 // strip pass), then a tile gather; mode 1: tiles evaluate the Gaussians; mode 0: sky fill,
 // then one strip launch per conflict-free class.  sums: also the per-tile sums of the
 // pixel terms of covered pixels into d_tile_sums (modes 0 and 1 then use the tiles).
+// Planes (and with `sums` the per-tile ELBO sums) gathered from every box's stored own
+// profile values and brightness coefficients, which must be current.
+int gather(celeste_plan* p, bool sums, hipStream_t st) {
+    RenderArgs a{};
+    a.g = p->geom();
+    a.tiles = p->d_tiles;
+    a.tile_list = p->d_tile_list;
+    a.n_tiles = (int32_t)p->tiles.size();
+    a.tile_h = p->tile_h;
+    a.tile_w = p->tile_w;
+    a.coef = p->d_coef1;
+    a.E = p->d_E;
+    a.V = p->d_V;
+    a.tile_sums = sums ? p->d_tile_sums : nullptr;
+    a.status = p->d_status;
+    HIPCHK(launch_gather_planes(a, p->d_fg, 4, st));
+    p->fg_valid = true;
+    return CELESTE_OK;
+}
+
 int render(celeste_plan* p, hipStream_t st, bool sums = false) {
     p->fg_valid = false;
     if (p->render_mode == 1 || (sums && p->render_mode == 0)) return render_tiles(p, sums, st);
     if (p->render_mode == 2 || p->render_mode == 3) {
-        const Geometry g = p->geom();
         const Sel all{nullptr, 0, (int32_t)p->items.size()};
-        HIPCHK(launch_strip_fg(all, g, p->d_tab1, p->d_fg, p->rows, p->persistent_grid(), p->wpb, p->d_status, st));
+        HIPCHK(launch_strip_fg(all, p->geom(), p->d_tab1, p->d_fg, p->rows, p->persistent_grid(), p->wpb,
+                               p->d_status, st));
         p->fg_valid = true;
         // mode 3: no planes (the adjoint gathers from stored values) unless sums are asked for
         if (p->render_mode == 3 && !sums) return CELESTE_OK;
-        RenderArgs a{};
-        a.g = g;
-        a.tiles = p->d_tiles;
-        a.tile_list = p->d_tile_list;
-        a.n_tiles = (int32_t)p->tiles.size();
-        a.tile_h = p->tile_h;
-        a.tile_w = p->tile_w;
-        a.coef = p->d_coef1;
-        a.E = p->d_E;
-        a.V = p->d_V;
-        a.tile_sums = sums ? p->d_tile_sums : nullptr;
-        a.status = p->d_status;
-        HIPCHK(launch_gather_planes(a, p->d_fg, 4, st));
-        p->fg_valid = true;
-        return CELESTE_OK;
+        return gather(p, sums, st);
     }
     HIPCHK(launch_fill_planes(p->d_images, p->n_img, p->max_pix, p->d_E, p->d_V, p->d_status, st));
     const Geometry g = p->geom();
@@ -1415,7 +1421,18 @@ int celeste_sweep(celeste_plan* p, double* theta, const int32_t* batch_ptr, cons
                                     p->d_status, st) != hipSuccess)
                     rc = hip_fail(hipGetLastError(), "sweep render");
             }
-            if (rc == CELESTE_OK) rc = celeste_total_elbo(p, theta, elbo_trace + sw + 1, st);
+            if (rc != CELESTE_OK) break;
+            if (stored) {
+                // every box's stored own values and coefficients are current: the total
+                // needs the gather only, not the strip pass
+                rc = gather(p, true, st);
+                if (rc == CELESTE_OK &&
+                    launch_tile_total(p->d_tile_sums, (int)p->tiles.size(), theta, p->consts, p->n_src,
+                                      elbo_trace + sw + 1, p->d_status, st) != hipSuccess)
+                    rc = hip_fail(hipGetLastError(), "sweep total");
+            } else {
+                rc = celeste_total_elbo(p, theta, elbo_trace + sw + 1, st);
+            }
         }
     } while (0);
     cleanup();
