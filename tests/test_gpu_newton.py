@@ -55,6 +55,31 @@ def test_newton_matches_oracle_overlapping_sources(B, N, O, synth, steps):
     np.testing.assert_array_equal(th_gpu[:, 27:], 0.0)
 
 
+@pytest.mark.parametrize("gtol", [1.0, 10.0, 1e30])
+def test_newton_gradient_stop_matches_oracle(B, N, synth, gtol):
+    """A source stops once its largest unconstrained gradient entry is below gtol.  On this
+    field with 6 iterations, gtol 1 stops sources 1 and 2 early but not source 0, gtol 10
+    stops all three at different iterations, and gtol 1e30 stops every source before its
+    first step (no gradient within 10% of either threshold, so rounding cannot move a
+    stop).  Parameters, ELBO and radius match the oracle's iterations with the same rule."""
+    f = synth.tiny(S=3, n_bands=2, size=17, side=11, seed=12)
+    plan = B.Plan(f)
+    theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+    say("case newton gtol", gtol)
+    elbo, radius = plan.newton(theta, [0, 1, 2], 6, params=B.tr_params(gtol=gtol))
+    th_gpu = theta.cpu().numpy()
+    elbo, radius = elbo.cpu().numpy(), radius.cpu().numpy()
+    for s in range(3):
+        row, fend, R = N.newton_steps(f, f.theta, s, 6, gtol=gtol)
+        scale = 1.0 + np.abs(row)
+        assert np.all(np.abs(th_gpu[s, :27] - row) <= 1e-6 * scale), (s, np.abs(th_gpu[s, :27] - row) / scale)
+        np.testing.assert_allclose(elbo[s], fend, rtol=1e-9)
+        assert radius[s] == R
+    if gtol == 1e30:
+        np.testing.assert_array_equal(th_gpu, f.theta)
+        np.testing.assert_array_equal(radius, 1.0)
+
+
 def test_newton_same_with_either_hessian_mode(B, synth):
     """Newton iterations with the closed-form Hessian rows (default) and with the tangent
     passes reach the same parameters."""
