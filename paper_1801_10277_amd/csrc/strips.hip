@@ -747,9 +747,10 @@ __device__ __forceinline__ void hess_pixels(const double* __restrict__ tab, cons
 // the listed boxes) are cut into runs of HPX rows of one strip; the runs, taken by row
 // index and then by strip, are dealt round-robin to the lanes, so that an item of fewer
 // than 64 strips still fills the wave.  The wave sums the NHG entries into hg[item]; the
-// items of sources outside a.active (when given) get zeros.  Launched with two rows and two waves per SIMD (a
-// few dozen bytes of spills per lane): on 1024 sources 24% faster per Newton iteration
-// than one row, and faster than three rows (more spills) or four rows at one wave.
+// items of sources outside a.active (when given) get zeros.  Launched with two rows and
+// two waves per SIMD (a few bytes of spills per lane): on 1024 sources 24% faster per
+// Newton iteration than one row, and faster than three rows (more spills) or four rows at
+// one wave.
 template <int L, int HPX>
 __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __restrict__ items,
                                                    const PairDev* __restrict__ pairs,
