@@ -1177,7 +1177,18 @@ int celeste_newton(celeste_plan* p, double* theta, const int32_t* src, int n, in
     const Sel si{p->d_list_item, 0, (int32_t)hs.item.size()};
     CHK(validate_theta(p, theta, nullptr, p->d_list_src, n, st));
     CHK(fill_u8(p->d_done, ss, 0, st));
-    CHK(newton_run(p, theta, ss, sp, si, n_steps, prm, radius, st));
+    // with the strip render, every box's own profile values are stored once and the listed
+    // visits take their background from them (cheaper than evaluating the neighbours'
+    // Gaussians per visit)
+    const bool stored = p->render_mode == 2 || p->render_mode == 3;
+    if (stored && n_steps > 0) {
+        const Scope all = scope_all(p);
+        CHK(prep(p, theta, all.pair, false, DIR_NONE, nullptr, 0, st));
+        HIPCHK(launch_strip_fg(all.item, p->geom(), p->d_tab1, p->d_fg, p->rows, p->persistent_grid(), p->wpb,
+                               p->d_status, st));
+        p->fg_valid = false;
+    }
+    CHK(newton_run(p, theta, ss, sp, si, n_steps, prm, radius, st, stored && n_steps > 0));
     if (elbo_out) {
         // final ELBO_s at the returned point
         CHK(prep(p, theta, sp, false, DIR_NONE, nullptr, 0, st));
