@@ -452,10 +452,6 @@ int render_tiles(celeste_plan* p, bool sums, hipStream_t st) {
     return CELESTE_OK;
 }
 
-// E and V planes of all sources.  Mode 2: every box's own profile values (one parallel
-// strip pass), then a tile gather; mode 1: tiles evaluate the Gaussians; mode 0: sky fill,
-// then one strip launch per conflict-free class.  sums: also the per-tile sums of the
-// pixel terms of covered pixels into d_tile_sums (modes 0 and 1 then use the tiles).
 // Planes (and with `sums` the per-tile ELBO sums) gathered from every box's stored own
 // profile values and brightness coefficients, which must be current.
 int gather(celeste_plan* p, bool sums, hipStream_t st) {
@@ -476,6 +472,10 @@ int gather(celeste_plan* p, bool sums, hipStream_t st) {
     return CELESTE_OK;
 }
 
+// E and V planes of all sources.  Mode 2: every box's own profile values (one parallel
+// strip pass), then a tile gather; mode 1: tiles evaluate the Gaussians; mode 0: sky fill,
+// then one strip launch per conflict-free class.  sums: also the per-tile sums of the
+// pixel terms of covered pixels into d_tile_sums (modes 0 and 1 then use the tiles).
 int render(celeste_plan* p, hipStream_t st, bool sums = false) {
     p->fg_valid = false;
     if (p->render_mode == 1 || (sums && p->render_mode == 0)) return render_tiles(p, sums, st);
@@ -660,8 +660,8 @@ void scope_lists(const celeste_plan* p, const int32_t* src, int n, HostScope& hs
     }
     // items of more strips first, so that a launch over the list ends on short items and its
     // last waves finish close together (every item writes its own outputs and the box sums
-    // run in item order: the list order changes no result)
-    // (a stable counting sort on the strip count)
+    // run in item order: the list order changes no result); a stable counting sort on the
+    // strip count
     const size_t n_it = hs.item.size() - i0;
     if (n_it < 2) return;
     int mx = 0;
