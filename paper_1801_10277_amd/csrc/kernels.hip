@@ -376,12 +376,14 @@ __global__ void __launch_bounds__(128) k_assemble_hessian(Sel srcs, Geometry g, 
     for (int i = 0; i < NP; ++i) o[i] = gh[i].t;
 }
 
-// Total ELBO: fixed-order sum of the per-tile pixel sums minus every source's KL.
-__global__ void __launch_bounds__(256) k_tile_total(const double* tile_sums, int n_tiles,
-                                                    const double* theta, Consts K, int S,
-                                                    double* out, const int* status) {
+// Total ELBO: fixed-order sum of the per-tile pixel sums minus every source's KL, by one
+// work-group of TT_THREADS threads.
+constexpr int TT_THREADS = 1024;
+__global__ void __launch_bounds__(TT_THREADS) k_tile_total(const double* tile_sums, int n_tiles,
+                                                           const double* theta, Consts K, int S,
+                                                           double* out, const int* status) {
     if (*status) return;
-    __shared__ double red[256];
+    __shared__ double red[TT_THREADS];
     double acc = 0.0;
     for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) acc += tile_sums[t];
     if (K.flags & CELESTE_INCLUDE_KL) {
@@ -393,7 +395,7 @@ __global__ void __launch_bounds__(256) k_tile_total(const double* tile_sums, int
     }
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = TT_THREADS / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
@@ -456,7 +458,7 @@ hipError_t launch_finalize(const FinArgs& a, bool tangent, hipStream_t st) {
 
 hipError_t launch_tile_total(const double* tile_sums, int n_tiles, const double* theta, const Consts& c,
                              int S, double* out, const int* status, hipStream_t st) {
-    hipLaunchKernelGGL(k_tile_total, dim3(1), dim3(256), 0, st, tile_sums, n_tiles, theta, c, S, out, status);
+    hipLaunchKernelGGL(k_tile_total, dim3(1), dim3(TT_THREADS), 0, st, tile_sums, n_tiles, theta, c, S, out, status);
     return hipGetLastError();
 }
 
