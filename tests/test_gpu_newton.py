@@ -80,6 +80,26 @@ def test_newton_gradient_stop_matches_oracle(B, N, synth, gtol):
         np.testing.assert_array_equal(radius, 1.0)
 
 
+def test_newton_stored_and_evaluated_backgrounds_agree(B, synth):
+    """Newton iterations with the strip render (backgrounds summed from every box's stored
+    own values) and with the tile render (backgrounds evaluated from the tables) reach the
+    same parameters and ELBO."""
+    f = synth.tiny(S=6, n_bands=2, size=29, side=11, seed=78)
+    out = []
+    for launch in (dict(), dict(render_mode=1)):
+        plan = B.Plan(f)
+        if launch:
+            plan.set_launch(**launch)
+        theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+        say("case newton backgrounds", launch)
+        elbo, radius = plan.newton(theta, list(range(6)), 4)
+        out.append((theta.cpu().numpy(), elbo.cpu().numpy(), radius.cpu().numpy()))
+    (t0, e0, r0), (t1, e1, r1) = out
+    assert np.all(np.abs(t0 - t1) <= 1e-8 * (1.0 + np.abs(t1))), np.max(np.abs(t0 - t1))
+    np.testing.assert_allclose(e0, e1, rtol=1e-12)
+    np.testing.assert_array_equal(r0, r1)
+
+
 def test_newton_same_with_either_hessian_mode(B, synth):
     """Newton iterations with the closed-form Hessian rows (default) and with the tangent
     passes reach the same parameters."""
