@@ -1135,9 +1135,16 @@ int celeste_hessian(celeste_plan* p, const double* theta, const int32_t* src, in
     const Sel si{p->d_list_item, 0, (int32_t)hs.item.size()};
     const Scope all = scope_all(p);
     CHK(validate_theta(p, theta, nullptr, nullptr, p->n_src, st));
-    // stored per-visit backgrounds, as in a Newton iteration
+    // stored per-visit backgrounds, as in a Newton iteration (with the strip render, summed
+    // from every box's stored own values)
     CHK(prep(p, theta, all.pair, false, DIR_NONE, nullptr, 0, st));
-    CHK(background(p, si, st));
+    if (p->render_mode == 2 || p->render_mode == 3) {
+        HIPCHK(launch_strip_fg(all.item, p->geom(), p->d_tab1, p->d_fg, p->rows, p->persistent_grid(), p->wpb,
+                               p->d_status, st));
+        CHK(background(p, si, st, true));
+    } else {
+        CHK(background(p, si, st));
+    }
     CHK(adjoint(p, si, nullptr, false, BASE_BG, true, st, 0, true));
     CHK(hessian_from_intermediates(p, theta, ss, sp, si, BASE_BG, p->d_hess, st));
     HIPCHK(hipMemcpyAsync(hess, p->d_hess, (size_t)n * NP * NP * sizeof(double), hipMemcpyDeviceToDevice, st));
