@@ -36,6 +36,43 @@ def test_subproblem_satisfies_optimality_conditions(seed):
             assert m(q) >= m(p) - 1e-9 * max(1.0, abs(m(p)))
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_subproblem_hard_case(seed):
+    """Hard case of the trust-region subproblem (Nocedal & Wright, Section 4.3): B has a
+    negative lowest eigenvalue lambda_1 and g is orthogonal to its eigenvector q_1, and the
+    radius exceeds |(B - lambda_1 I)^+ g|.  Then mu = -lambda_1 and the solution is that
+    pseudo-inverse step completed along q_1 to the boundary: |p| = R, (B + mu I) p = -g,
+    B + mu I positive semidefinite, and q_1^T p = +-sqrt(R^2 - |rest|^2)."""
+    rng = np.random.default_rng(100 + seed)
+    n = 27
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.sort(rng.uniform(-2.0, 5.0, n))
+    lam[0] = -3.0 - seed                              # simple, negative lowest eigenvalue
+    B = (Q * lam) @ Q.T
+    gh = rng.standard_normal(n)
+    gh[0] = 0.0                                       # g orthogonal to q_1
+    g = Q @ gh
+    rest = gh[1:] / (lam[1:] - lam[0])                # |(B - lambda_1 I)^+ g| in the eigenbasis
+    R = 1.5 * np.linalg.norm(rest) + 0.1 * seed
+    p, *_ = N.subproblem(g, B, R)
+    assert abs(np.linalg.norm(p) - R) <= 1e-12 * R
+    mu = -lam[0]
+    np.testing.assert_allclose(B @ p + mu * p, -g, atol=1e-10 * max(1.0, np.abs(g).max()))
+    assert np.linalg.eigvalsh(B + mu * np.eye(n)).min() >= -1e-10
+    tau = np.sqrt(R * R - rest @ rest)
+    np.testing.assert_allclose(abs(Q[:, 0] @ p), tau, rtol=1e-10)
+    # the component orthogonal to q_1 is -(B - lambda_1 I)^+ g
+    np.testing.assert_allclose(Q[:, 1:].T @ p, -rest, rtol=1e-10, atol=1e-12 * R)
+    # the model value is the global minimum over the ball: -sum over the eigenbasis
+    m = lambda q: g @ q + 0.5 * q @ B @ q
+    best = -0.5 * np.sum(gh[1:] ** 2 * (lam[1:] + 2 * mu) / (lam[1:] + mu) ** 2) + 0.5 * lam[0] * tau ** 2
+    np.testing.assert_allclose(m(p), best, rtol=1e-10)
+    for _ in range(200):
+        q = rng.standard_normal(n)
+        q *= R * rng.random() ** (1.0 / n) / np.linalg.norm(q)
+        assert m(q) >= m(p) - 1e-9 * abs(m(p))
+
+
 def test_transforms_round_trip_and_derivatives():
     rng = np.random.default_rng(0)
     th = np.abs(rng.uniform(0.1, 0.9, 27))

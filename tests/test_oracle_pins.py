@@ -456,6 +456,81 @@ def test_total_elbo_equals_sum_when_boxes_disjoint(synth, O):
     np.testing.assert_allclose(tot, O.source_elbo(P, 0) + O.source_elbo(P, 1), rtol=1e-14)
 
 
+def _poisson_limit_field(synth, wcs=False):
+    """Four sources with overlapping boxes of different sizes on two images, known types
+    (q = 1 star, q = 0 galaxy) and numerically zero brightness and colour variances, so
+    that every source's band flux is the deterministic exp(log flux)."""
+    f = synth.tiny(S=4, n_bands=2, size=23, side=9, seed=97, psf_xi=True, anisotropic_psf=True, wcs=wcs)
+    f.flags = synth.FLAG_INCLUDE_LGAMMA
+    f.theta[:, 6] = [1.0, 0.0, 1.0, 0.0]
+    f.theta[:, :2] = [[8.2, 8.9], [12.4, 11.1], [10.3, 14.6], [14.8, 9.7]]
+    f.theta[:, 2:6] = [[0.2, 0.7, 0.4, 1.3], [0.6, 0.5, 1.9, 2.1], [0.9, 0.8, 2.5, 1.0],
+                       [0.1, 0.3, 0.2, 1.7]]
+    for base in (7, 17):
+        f.theta[:, base + 1] = 1e-30
+        f.theta[:, base + 6:base + 10] = 1e-30
+    # boxes: (img, r0, c0, h, w); every pair of sources overlaps somewhere, some pixels are
+    # covered by three or four boxes, and each box differs between the two images
+    f.boxes = np.array([[0, 3, 2, 11, 13], [1, 4, 3, 9, 9],
+                        [0, 5, 6, 13, 11], [1, 6, 7, 11, 9],
+                        [0, 9, 4, 12, 12], [1, 8, 5, 13, 11],
+                        [0, 2, 9, 15, 11], [1, 3, 10, 11, 10]], np.int32)
+    f.patch_ptr = np.array([0, 2, 4, 6, 8], np.int32)
+    return f
+
+
+def _poisson_rates(f, n):
+    """Sky plus the light of every source whose box in image n covers the pixel, at every
+    pixel of image n (scipy densities); and the union of the boxes as a mask."""
+    H, W = int(f.img_H[n]), int(f.img_W[n])
+    yy, xx = np.mgrid[0:H, 0:W]
+    pts = np.stack([xx.ravel(), yy.ravel()], 1).astype(float)
+    lam = np.full(H * W, float(f.img_sky[n]))
+    union = np.zeros((H, W), bool)
+    b = int(f.img_band[n])
+    for s in range(f.n_src):
+        for img, r0, c0, h, w in f.boxes[f.patch_ptr[s]:f.patch_ptr[s + 1]]:
+            if img != n:
+                continue
+            inbox = np.zeros((H, W), bool)
+            inbox[r0:r0 + h, c0:c0 + w] = True
+            union |= inbox
+            th = f.theta[s]
+            star = th[6] == 1.0
+            base = 7 if star else 17
+            flux = np.exp(th[base] + B[b] @ th[base + 2:base + 6])
+            fs, fg = scipy_profiles(f, s, n, pts)
+            lam += np.where(inbox.ravel(), f.img_iota[n] * flux * (fs if star else fg), 0.0)
+    return lam, union.ravel()
+
+
+@pytest.mark.parametrize("wcs", [False, True])
+def test_total_elbo_overlapping_boxes_is_poisson_loglik_of_union(synth, O, wcs):
+    """In the zero-variance, known-type limit the total ELBO is the Poisson log-likelihood
+    of every pixel of the union of the boxes, each counted once, at the rate summed over the
+    sources whose box covers it; a pixel counted twice, or a source added outside its box,
+    fails.  Each source's ELBO_s is the same sum over its own boxes only."""
+    f = _poisson_limit_field(synth, wcs=wcs)
+    P = O.Problem(f)
+    total = 0.0
+    own = np.zeros(f.n_src)
+    for n in range(f.n_img):
+        lam, union = _poisson_rates(f, n)
+        lp = stats.poisson.logpmf(f.image(n).ravel(), lam)
+        total += lp[union].sum()
+        H, W = int(f.img_H[n]), int(f.img_W[n])
+        for s in range(f.n_src):
+            for img, r0, c0, h, w in f.boxes[f.patch_ptr[s]:f.patch_ptr[s + 1]]:
+                if img == n:
+                    own[s] += lp.reshape(H, W)[r0:r0 + h, c0:c0 + w].sum()
+    # the boxes really overlap: the union is smaller than the sum of the box areas
+    assert sum(int(h * w) for _, _, _, h, w in f.boxes) > sum(
+        int(_poisson_rates(f, n)[1].sum()) for n in range(f.n_img)) + 100
+    np.testing.assert_allclose(O.total_elbo(P), total, rtol=1e-12)
+    for s in range(f.n_src):
+        np.testing.assert_allclose(O.source_value(P, s)[0], own[s], rtol=1e-12)
+
+
 def test_masked_pixels_are_skipped(synth, O):
     f = synth.tiny(S=1, n_bands=1, size=11, side=11, seed=61)
     P = O.Problem(f)
