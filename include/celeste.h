@@ -150,7 +150,11 @@ typedef struct celeste_plan celeste_plan;
  * covariances (eigenvalues >= 0.01 px^2) and weights, sky (every sky-map entry) and
  * iota > 0, invertible astrometry, mixture variances > 0, one box per (source, image)),
  * bins boxes into render tiles and work items, and allocates the plan-owned device
- * workspace.  The only call that allocates.  Synchronous.  *out receives the plan.
+ * workspace, sized for every later evaluation, Hessian, Newton and sweep call.  Besides
+ * this call only celeste_plan_set_launch (grown tile buffers for smaller tiles),
+ * celeste_autotune (its own timing outputs) and celeste_sweep (temporary list buffers
+ * when a schedule lists sources more often than once in total) allocate device memory.
+ * Synchronous.  *out receives the plan.
  * Returns CELESTE_EINVAL (nothing allocated), CELESTE_ENOMEM or CELESTE_EHIP. */
 int celeste_plan_create(const celeste_problem_desc* desc, celeste_plan** out);
 
@@ -167,15 +171,19 @@ int celeste_elbo(celeste_plan* plan, const double* theta, const uint8_t* active,
                  double* elbo, hipStream_t stream);
 
 /* ELBO_s and its gradient with respect to theta[s][0..26] (device grad[n_src][32],
- * entries 27..31 set to 0), from the hand-written adjoint; pixel intermediates are
- * recomputed, not stored. */
+ * entries 27..31 set to 0), from the hand-written adjoint of Eq. (1)'s pixel terms
+ * (Section III model) plus the KL's closed-form gradient.  No per-pixel tape: with
+ * render modes 0 and 1 the fused adjoint recomputes each visit's own profile values; with
+ * modes 2 (the default) and 3 the render stores them (16 B per visit in plan memory) and
+ * the adjoint reads them back instead of evaluating the 45 Gaussians a second time. */
 int celeste_elbo_grad(celeste_plan* plan, const double* theta, const uint8_t* active, int mode,
                       double* elbo, double* grad, hipStream_t stream);
 
-/* Block-diagonal Hessian-vector product: hv[s] = (d^2 ELBO_s / d theta_s^2) v[s]
- * (device [n_src][32]; entries 27..31 of v ignored, of hv set to 0).  Computed as the
- * forward-mode tangent of the adjoint.  grad (device [n_src][32] or NULL) receives the
- * gradient as a by-product.  All sources, batched form. */
+/* Block-diagonal Hessian-vector product (the exact second derivatives Newton's method
+ * needs, Section IV-D): hv[s] = (d^2 ELBO_s / d theta_s^2) v[s] (device [n_src][32];
+ * entries 27..31 of v ignored, of hv set to 0).  Computed as the forward-mode tangent of
+ * the adjoint.  grad (device [n_src][32] or NULL) receives the gradient as a by-product.
+ * All sources, batched form. */
 int celeste_hvp(celeste_plan* plan, const double* theta, const double* v, double* hv,
                 double* grad, hipStream_t stream);
 
@@ -184,7 +192,9 @@ int celeste_hvp(celeste_plan* plan, const double* theta, const double* v, double
  * second derivatives of Section IV-D: each box's Hessian in its ten intermediates
  * (brightness factors and frac_dev from the gradient pass, position and shape from a
  * closed-form pass, or from tangent-adjoint passes: celeste_plan_set_hessian_mode)
- * pushed through the chain rule and its tangent, plus the KL. */
+ * pushed through the chain rule and its tangent, plus the KL.  Synchronous: it waits for
+ * `stream`, then uploads the source, box and item lists with blocking copies before it
+ * queues its kernels on `stream`. */
 int celeste_hessian(celeste_plan* plan, const double* theta, const int32_t* src, int n,
                     double* hess, hipStream_t stream);
 
@@ -197,7 +207,9 @@ int celeste_hessian(celeste_plan* plan, const double* theta, const int32_t* src,
  * evaluation, accept/reject and radius update - all on the device.
  * theta_inout (device [n_src][32]) is updated in place; radius (device [n_src]) is
  * read and written (initialise with params->radius0); elbo_out (device [n_src] or
- * NULL) receives the final ELBO_s of the listed sources. */
+ * NULL) receives the final ELBO_s of the listed sources.  Synchronous at entry: it waits
+ * for `stream` and uploads the lists with blocking copies; the iterations themselves are
+ * queued on `stream` with no further host synchronisation. */
 int celeste_newton(celeste_plan* plan, double* theta_inout, const int32_t* src, int n,
                    int n_steps, const celeste_tr_params* params, double* radius,
                    double* elbo_out, hipStream_t stream);
@@ -254,11 +266,16 @@ int celeste_cyclades_batches(int32_t n, const int32_t* adj_ptr, const int32_t* a
                              const int32_t* order, int32_t sample_size, int32_t* batch_ptr,
                              int32_t* batch_src, int32_t* n_batches, int32_t* n_components);
 
-/* Block coordinate ascent: n_sweeps passes over the batches (host CSR batch_ptr,
+/* Block coordinate ascent (Section IV-D: each source's parameters form a block, optimised
+ * by Newton's method with the overlapping sources held fixed; conflict-free batches of
+ * sources run together): n_sweeps passes over the batches (host CSR batch_ptr,
  * batch_src), each batch optimised by params->newton_steps Newton trust-region
  * iterations with all other sources fixed.  Batches must be conflict-free
  * (CELESTE_ECONFLICT otherwise, nothing run).  elbo_trace (device [n_sweeps + 1])
- * receives the total ELBO before the first sweep and after each sweep. */
+ * receives the total ELBO before the first sweep and after each sweep.  Synchronous at
+ * entry (it waits for `stream` and uploads every batch's lists once, with blocking copies)
+ * and at exit when it allocated temporary list buffers; the sweeps are queued on `stream`
+ * with no host synchronisation between batches. */
 int celeste_sweep(celeste_plan* plan, double* theta_inout, const int32_t* batch_ptr,
                   const int32_t* batch_src, int n_batches, int n_sweeps,
                   const celeste_tr_params* params, double* elbo_trace, hipStream_t stream);

@@ -442,6 +442,23 @@ int oracle_source_hvp(const OProblem* P, int s, const double* v, double* hv, dou
     return 0;
 }
 
+// Dense Hessian of the per-source ELBO: column d is the Hessian-vector product along the
+// unit vector e_d (the 27 columns run in parallel, OpenMP); habs[i][d] is that product's
+// sum of |per-visit terms| for entry i.  Row-major H[i][d] and habs[i][d].
+int oracle_source_hessian(const OProblem* P, int s, double* H, double* habs) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int d = 0; d < 27; ++d) {
+        double e[27], hv[27], ha[27];
+        for (int i = 0; i < 27; ++i) e[i] = (i == d) ? 1.0 : 0.0;
+        oracle_source_hvp(P, s, e, hv, ha);
+        for (int i = 0; i < 27; ++i) {
+            H[i * 27 + d] = hv[i];
+            habs[i * 27 + d] = ha[i];
+        }
+    }
+    return 0;
+}
+
 // E[F] and Var[F] at every pixel of image n (sky + all covering sources).
 int oracle_render(const OProblem* P, int n, double* E, double* V) {
     const OImage& im = P->img[n];

@@ -122,9 +122,9 @@ def newton_steps(f, theta_in, s, n_steps, radius0=1.0, radius_max=1e3, eta_accep
         th = theta_in.copy()
         th[s, :27] = row
         P = O.Problem(f, th)
-        val, g, _ = O.source_grad(P, s)
+        val, g, gabs = O.source_grad(P, s)
         f0 = val[0] + val[1]
-        H = O.source_hessian(P, s)
+        H, Habs = O.source_hessian(P, s, with_abs=True)
         eta, d1, d2 = to_unconstrained(row)
         gm = -d1 * g
         B = -(d1[:, None] * (0.5 * (H + H.T)) * d1[None, :]) - np.diag(d2 * g)
@@ -144,7 +144,8 @@ def newton_steps(f, theta_in, s, n_steps, radius0=1.0, radius_max=1e3, eta_accep
         elif rho > 0.75 and pn >= 0.99 * Rold:
             R = min(2 * R, radius_max)
         if record is not None:
-            record.append({"f0": f0, "f1": f1, "pred": pred, "rho": rho, "radius": Rold})
+            record.append({"f0": f0, "f1": f1, "pred": pred, "rho": rho, "radius": Rold, "theta": row.copy(),
+                           "grad": g, "gabs": gabs, "hess": H, "habs": Habs, "B": B, "g_eta": gm, "step": p})
         f_before = f0
         if finite and rho > eta_accept:
             row = trial

@@ -58,6 +58,7 @@ def lib():
         L.oracle_source_value.argtypes = [P, C.c_int, dp]
         L.oracle_source_grad.argtypes = [P, C.c_int, dp, dp, dp]
         L.oracle_source_hvp.argtypes = [P, C.c_int, dp, dp, dp]
+        L.oracle_source_hessian.argtypes = [P, C.c_int, dp, dp]
         L.oracle_render.argtypes = [P, C.c_int, dp, dp]
         L.oracle_source_light.argtypes = [P, C.c_int, C.c_int, dp, dp]
         L.oracle_profiles.argtypes = [P, C.c_int, C.c_int, C.c_double, C.c_double, dp]
@@ -157,13 +158,13 @@ def source_hvp(prob, s, v):
     return hv, ha
 
 
-def source_hessian(prob, s):
+def source_hessian(prob, s, with_abs=False):
+    """27 x 27 Hessian of ELBO_s (columns: Hessian-vector products along unit vectors, in
+    parallel); with_abs also returns the per-entry sums of |per-visit terms|."""
     H = np.zeros((27, 27))
-    for i in range(27):
-        e = np.zeros(27)
-        e[i] = 1.0
-        H[:, i] = source_hvp(prob, s, e)[0]
-    return H
+    Ha = np.zeros((27, 27))
+    lib().oracle_source_hessian(prob.ref, s, _dp(H), _dp(Ha))
+    return (H, Ha) if with_abs else H
 
 
 def render(prob, f, n):

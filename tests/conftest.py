@@ -93,3 +93,121 @@ def single_source(synth, size=41, side=None, star=True, q=None, seed=3, psf_sigm
         f.boxes = np.array([[n, r0, r0, r1 - r0, r1 - r0] for n in range(n_bands)], np.int32)
     f.patch_ptr = np.array([0, n_bands], np.int32)
     return f
+
+
+# ---------------------------------------------------------------- derived tolerances
+REL = 1e-9      # relative gate of the parity tests (per value, gradient and HVP entry)
+FLOOR = 1e-12   # times the sum of |per-visit terms|: FP64 summation error ~ log2(n) eps G
+
+
+def hessian_within(H, Href, Habs, what):
+    """Per-element bound of a dense Hessian, the gradient's gate applied entry by entry:
+    |H - Href| <= 1e-9 |Href| + 1e-12 Habs (Habs: the oracle's sum of |per-visit terms|).
+    Returns the largest pure relative error."""
+    err = np.abs(H - Href)
+    bound = REL * np.abs(Href) + FLOOR * Habs
+    bad = err > bound
+    assert not bad.any(), "%s: max err/bound %.3g at %s" % (
+        what, (err / np.maximum(bound, 1e-300)).max(), np.argwhere(bad)[:5].tolist())
+    return float((err / np.maximum(np.abs(Href), 1e-300)).max())
+
+
+def newton_step_bound(N, f, theta, s, radius, gtol=1e-8):
+    """One trust-region step of source s from `theta` (every other source fixed) with radius
+    `radius` on the oracle, and a first-order bound on |theta_gpu - theta_oracle| after it,
+    given that the device's gradient and Hessian meet the per-entry gates (1e-9 relative +
+    1e-12 of the sum of |per-visit terms|).
+
+    In unconstrained coordinates the step solves (B + mu I) p = -g with |p| = R when mu > 0.
+    Perturbing g and B by dg, dB (and mu so that |p| stays R) moves p by
+    dp = -P M^-1 (dg + dB p), M = B + mu I, P = I - M^-1 p p^T / (p^T M^-1 p) (P = I for an
+    interior step), so |dp| <= |P M^-1| (|dg| + |dB|_F |p|); both solves stop the secular
+    equation at |p| within 1e-13 R, which adds 2e-13 R |P M^-1| |M|.  theta_i moves by
+    |theta_i'(eta_i + p_i)| |dp|.  A source that stops before stepping keeps theta exactly
+    (bound 0).  Returns (bound[27], oracle row, oracle ELBO_s, oracle radius)."""
+    rec = []
+    row, fend, R = N.newton_steps(f, theta, s, 1, radius0=radius, gtol=gtol, record=rec)
+    if not rec:
+        return np.zeros(27), row, fend, R
+    r0 = rec[0]
+    g, gabs, H, Habs, B, p = r0["grad"], r0["gabs"], r0["hess"], r0["habs"], r0["B"], r0["step"]
+    eta, d1, d2 = N.to_unconstrained(theta[s, :27])
+    dg = REL * np.abs(g) + FLOOR * gabs
+    dH = REL * np.abs(H) + FLOOR * Habs
+    dgm = np.abs(d1) * dg
+    dB = np.abs(d1)[:, None] * dH * np.abs(d1)[None, :] + np.diag(np.abs(d2) * dg)
+    pn = np.linalg.norm(p)
+    res = -r0["g_eta"] - B @ p
+    mu = max(0.0, (res @ p) / (p @ p)) if pn > 0 else 0.0
+    M = B + mu * np.eye(27)
+    Minv = np.linalg.inv(M)
+    if mu > 0:
+        Mp = Minv @ p
+        Proj = np.eye(27) - np.outer(Mp, p) / (p @ Mp)
+    else:
+        Proj = np.eye(27)
+    PM = np.linalg.norm(Proj @ Minv, 2)
+    dp = PM * (np.linalg.norm(dgm) + np.linalg.norm(dB) * pn) + 2e-13 * radius * PM * np.linalg.norm(M, 2)
+    th1 = N.from_unconstrained(eta + p)
+    _, t1d, _ = N.to_unconstrained(th1)
+    bound = np.abs(t1d) * dp + 4e-16 * np.abs(th1)
+    return bound, row, fend, R
+
+
+def newton_trajectory_parity(B, N, torch, f, srcs, steps, gtol=1e-8, say=print):
+    """Per-step parity of a Newton run (each listed source optimised with every other source
+    at its entry value): the device's k-step runs give its iterates theta_k (a k-step run
+    takes the same first k steps as a longer one); for every k and listed source, the
+    oracle takes one step from the device's theta_{k-1} and radius_{k-1}, and the device's
+    theta_k must lie within newton_step_bound of it, with the same radius and ELBO_s to
+    1e-9.  Returns the largest |difference| / bound seen (0 when every step was exact)."""
+    plan = B.Plan(f)
+    params = B.tr_params(gtol=gtol)
+    prev_th = f.theta.copy()
+    prev_R = np.full(f.n_src, params.radius0)
+    worst = 0.0
+    for k in range(1, steps + 1):
+        theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+        elbo, radius = plan.newton(theta, np.asarray(srcs, np.int32), k, params=params)
+        thk, ek, Rk = theta.cpu().numpy(), elbo.cpu().numpy(), radius.cpu().numpy()
+        np.testing.assert_array_equal(np.delete(thk, srcs, axis=0), np.delete(f.theta, srcs, axis=0))
+        for s in srcs:
+            base = f.theta.copy()
+            base[s] = prev_th[s]
+            bound, row, fend, R = newton_step_bound(N, f, base, s, prev_R[s], gtol=gtol)
+            diff = np.abs(thk[s, :27] - row)
+            assert np.all(diff <= bound), (k, s, (diff / np.maximum(bound, 1e-300)).max())
+            worst = max(worst, float(np.max(np.where(bound > 0, diff / np.maximum(bound, 1e-300), 0.0))))
+            assert Rk[s] == R, (k, s, Rk[s], R)
+            np.testing.assert_allclose(ek[s], fend, rtol=1e-9)
+        say("  newton step", k, "worst |diff| / bound %.3g" % worst)
+        prev_th, prev_R = thk, Rk
+    return worst
+
+
+def sweep_batch_parity(B, N, torch, f, ptr, src, say=print):
+    """Per-step parity of one block-coordinate-ascent sweep with one Newton step per batch
+    visit: the device's state after batch b comes from a sweep over the schedule's first
+    b + 1 batches; every member of batch b must then lie within newton_step_bound of the
+    oracle's step from the device's state after batch b - 1 (every other source at its
+    current value), non-members must be unchanged.  Returns the largest |diff| / bound."""
+    plan = B.Plan(f)
+    params = B.tr_params(newton_steps=1)
+    prev = f.theta.copy()
+    worst = 0.0
+    for b in range(len(ptr) - 1):
+        theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+        plan.sweep(theta, ptr[:b + 2], src[:ptr[b + 1]], 1, params)
+        cur = theta.cpu().numpy()
+        members = [int(s) for s in src[ptr[b]:ptr[b + 1]]]
+        others = np.ones(f.n_src, bool)
+        others[members] = False
+        np.testing.assert_array_equal(cur[others], prev[others])
+        for s in members:
+            bound, row, _, _ = newton_step_bound(N, f, prev, s, params.radius0)
+            diff = np.abs(cur[s, :27] - row)
+            assert np.all(diff <= bound), (b, s, (diff / np.maximum(bound, 1e-300)).max())
+            worst = max(worst, float(np.max(np.where(bound > 0, diff / np.maximum(bound, 1e-300), 0.0))))
+        say("  batch", b, "members", members, "worst |diff| / bound %.3g" % worst)
+        prev = cur
+    return prev, worst

@@ -25,6 +25,9 @@ class StandInPlan:
         self.calls["hvp"] += 1
         return -(self.a * torch.exp(theta) + 2 * self.b) * v
 
+    def total_elbo(self, theta):
+        return self.elbo_grad(theta)[0].sum().reshape(1)
+
 
 def test_forward_backward_and_double_backward_plumbing():
     from paper_1801_10277_amd import torch_fn
@@ -43,6 +46,58 @@ def test_forward_backward_and_double_backward_plumbing():
     torch.testing.assert_close(g, gr, rtol=1e-14, atol=1e-14)
     torch.testing.assert_close(h, hr, rtol=1e-14, atol=1e-14)
     assert plan.calls == {"elbo_grad": 1, "hvp": 1}
+
+
+def test_total_elbo_plumbing():
+    """The total's backward returns the library gradient scaled by the upstream gradient,
+    and a second differentiation is refused (the total's Hessian is not formed)."""
+    from paper_1801_10277_amd import torch_fn
+    plan = StandInPlan(3)
+    theta = torch.randn(3, 32, dtype=torch.float64, requires_grad=True)
+    t = torch_fn.total_elbo(theta, plan)
+    (g,) = torch.autograd.grad(2.5 * t, theta)
+    ref = theta.detach().clone().requires_grad_(True)
+    (gr,) = torch.autograd.grad(2.5 * -(plan.a * torch.exp(ref) + plan.b * ref ** 2).sum(), ref)
+    torch.testing.assert_close(g, gr, rtol=1e-14, atol=1e-14)
+    t = torch_fn.total_elbo(theta, plan)
+    (g,) = torch.autograd.grad(t, theta, create_graph=True)
+    with pytest.raises(RuntimeError):
+        torch.autograd.grad(g.sum(), theta)
+
+
+@pytest.mark.gpu
+def test_gpu_wrapper_gradients_against_central_differences(synth):
+    """On a field whose boxes overlap: the total ELBO's gradient is the derivative of the
+    total (central differences of celeste_total_elbo); the per-source wrapper's gradient of
+    sum_s w_s ELBO_s in theta_s is w_s d ELBO_s / d theta_s with the other sources held
+    fixed (central differences of ELBO_s in theta_s alone), not the full derivative."""
+    from paper_1801_10277_amd import binding as B, torch_fn
+    assert torch.cuda.is_available()
+    f = synth.tiny(S=3, n_bands=2, size=17, side=11, seed=5)
+    plan = B.Plan(f)
+    theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda", requires_grad=True)
+    (gt,) = torch.autograd.grad(torch_fn.total_elbo(theta, plan), theta)
+    w = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64, device="cuda")
+    (ge,) = torch.autograd.grad((w * torch_fn.elbo(theta, plan)).sum(), theta)
+    gt, ge = gt.cpu().numpy(), ge.cpu().numpy()
+    th0 = f.theta.copy()
+    full_cross = 0.0
+    for s in range(3):
+        for i in (0, 1, 3, 5, 7, 18):
+            h = 1e-6 * max(1.0, abs(th0[s, i]))
+            tp, tm = th0.copy(), th0.copy()
+            tp[s, i] += h
+            tm[s, i] -= h
+            TP = torch.tensor(tp, device="cuda")
+            TM = torch.tensor(tm, device="cuda")
+            fd_tot = (plan.total_elbo(TP).item() - plan.total_elbo(TM).item()) / (2 * h)
+            assert abs(gt[s, i] - fd_tot) <= 1e-5 * abs(fd_tot) + 1e-3, (s, i, gt[s, i], fd_tot)
+            ep, em = plan.elbo(TP).cpu().numpy(), plan.elbo(TM).cpu().numpy()
+            fd_own = (ep[s] - em[s]) / (2 * h)
+            assert abs(ge[s, i] - w[s].item() * fd_own) <= 1e-5 * abs(w[s].item() * fd_own) + 1e-3, (s, i)
+            fd_all = float(w.cpu().numpy() @ (ep - em)) / (2 * h)
+            full_cross = max(full_cross, abs(fd_all - w[s].item() * fd_own))
+    assert full_cross > 1e-2      # the boxes overlap: the left-out cross terms are not zero
 
 
 @pytest.mark.gpu

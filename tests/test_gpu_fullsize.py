@@ -7,7 +7,7 @@ import sys
 import numpy as np
 import pytest
 
-from conftest import neighbourhood
+from conftest import REL, FLOOR, hessian_within, neighbourhood, newton_step_bound
 
 torch = pytest.importorskip("torch")
 
@@ -32,29 +32,72 @@ def N():
     return newton
 
 
-def smallest(f, candidates, k):
+def by_box_area(f, candidates):
+    """Candidates ordered by the total pixel count of their boxes, smallest first."""
     ptr = np.asarray(f.patch_ptr)
     px = [int(np.sum(f.boxes[ptr[s]:ptr[s + 1], 3].astype(np.int64) * f.boxes[ptr[s]:ptr[s + 1], 4]))
           for s in candidates]
-    return [candidates[i] for i in np.argsort(px, kind="stable")[:k]]
+    return [candidates[i] for i in np.argsort(px, kind="stable")]
+
+
+def items_of(f, s, rows=16, chunk=64):
+    """Work items (runs of up to 64 strips of `rows` pixels) of source s's largest box."""
+    b = f.boxes[f.patch_ptr[s]:f.patch_ptr[s + 1]]
+    return int(max((w * ((h + rows - 1) // rows) + chunk - 1) // chunk for _, _, _, h, w in b))
 
 
 def test_newton_field_1024src_full_size_sampled(B, N, synth):
     """One trust-region Newton step of all 1024 sources (others at their entry values), as
-    the Newton benchmark runs it; sampled sources against the oracle's step."""
+    the Newton benchmark runs it; the two smallest and the two largest sampled boxes (the
+    largest span 6 and more work items) against the oracle's step, within the derived
+    one-step bound."""
     f = synth.field_1024src()
     plan = B.Plan(f)
     theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
     say("case newton field_1024src full", plan.info())
     elbo, radius = plan.newton(theta, np.arange(f.n_src, dtype=np.int32), 1)
     th, elbo, radius = theta.cpu().numpy(), elbo.cpu().numpy(), radius.cpu().numpy()
-    for s in smallest(f, list(range(0, f.n_src, 97)), 2):
+    order = by_box_area(f, list(range(0, f.n_src, 97)))
+    picks = order[:2] + order[-2:]
+    assert min(items_of(f, s) for s in order[-2:]) >= 6
+    for s in picks:
         g, j = neighbourhood(f, s)
-        say("  oracle newton source", s, "neighbourhood", g.n_src)
-        row, fend, R = N.newton_steps(g, g.theta, j, 1)
-        assert np.all(np.abs(th[s, :27] - row) <= 1e-6 * (1 + np.abs(row))), s
+        say("  oracle newton source", s, "items", items_of(f, s), "neighbourhood", g.n_src)
+        bound, row, fend, R = newton_step_bound(N, g, g.theta, j, 1.0)
+        diff = np.abs(th[s, :27] - row)
+        assert np.all(diff <= bound), (s, (diff / np.maximum(bound, 1e-300)).max())
+        say("    max |diff| / bound %.3g" % (diff / np.maximum(bound, 1e-300)).max())
         np.testing.assert_allclose(elbo[s], fend, rtol=1e-9)
         assert radius[s] == R
+
+
+def test_second_order_field_1024src_largest_boxes(B, O, synth):
+    """Dense Hessians (celeste_hessian of the listed sources on the full plan) and the
+    Hessian-vector product of every source (celeste_hvp) on the 1024-source field, for the
+    two largest sampled boxes (6 and more work items each), against the oracle on their
+    neighbourhoods: per-entry 1e-9 relative + 1e-12 of the sum of |per-visit terms|."""
+    f = synth.field_1024src()
+    plan = B.Plan(f)
+    theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+    picks = by_box_area(f, list(range(0, f.n_src, 97)))[-2:]
+    say("case second order field_1024src largest", picks)
+    H = plan.hessian(theta, picks).cpu().numpy()
+    rng = np.random.default_rng(23)
+    v = np.zeros((f.n_src, 32))
+    v[:, :27] = rng.standard_normal((f.n_src, 27))
+    hv, g = plan.hvp(theta, torch.tensor(v, device="cuda"), with_grad=True)
+    hv, g = hv.cpu().numpy(), g.cpu().numpy()
+    for k, s in enumerate(picks):
+        sub, j = neighbourhood(f, s)
+        P = O.Problem(sub)
+        say("  oracle hessian source", s, "neighbourhood", sub.n_src)
+        Href, Habs = O.source_hessian(P, j, with_abs=True)
+        say("    hessian max rel %.3g" % hessian_within(H[k], Href, Habs, "hessian s=%d" % s))
+        href, habs = O.source_hvp(P, j, v[s])
+        err = np.abs(hv[s, :27] - href)
+        assert np.all(err <= REL * np.abs(href) + FLOOR * habs), s
+        _, gref, gabs = O.source_grad(P, j)
+        assert np.all(np.abs(g[s, :27] - gref) <= REL * np.abs(gref) + FLOOR * gabs), s
 
 
 def test_sweep_sky_region_20000src_full_size_sampled(B, O, synth):
@@ -68,6 +111,10 @@ def test_sweep_sky_region_20000src_full_size_sampled(B, O, synth):
     say("case sweep sky_region_20000src full", plan.info(), "batches", len(ptr) - 1)
     trace = plan.sweep(theta, ptr, src, 1, B.tr_params(newton_steps=2)).cpu().numpy()
     assert trace[1] >= trace[0]
+    # the trace's last entry, kept up to date from stored own values through the sweep,
+    # equals a fresh total ELBO at the returned parameters
+    tot = plan.total_elbo(theta).cpu().numpy()[0]
+    np.testing.assert_allclose(trace[-1], tot, rtol=1e-12)
     e = plan.elbo(theta).cpu().numpy()
     th = theta.cpu().numpy()
     assert np.any(th[:, :27] != f.theta[:, :27])
