@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CELESTE_ABI_VERSION 4
+#define CELESTE_ABI_VERSION 5
 
 enum celeste_status {
     CELESTE_OK = 0,
@@ -59,7 +59,8 @@ enum celeste_status {
     CELESTE_ECONFLICT = -2,  /* two members of one batch share a pixel */
     CELESTE_EHIP = -3,       /* a HIP runtime call failed (detail: celeste_last_hip_error) */
     CELESTE_ENOMEM = -4,     /* device allocation failed */
-    CELESTE_EDOMAIN = -5     /* theta (or a trust-region trial) left the parameter domain */
+    CELESTE_EDOMAIN = -5,    /* theta (or a trust-region trial) left the parameter domain */
+    CELESTE_ESCRATCH = -6    /* the problem needs more than celeste_elbo_grad_noalloc's static scratch */
 };
 
 enum celeste_mode {
@@ -153,8 +154,8 @@ typedef struct celeste_plan celeste_plan;
  * workspace, sized for every later evaluation, Hessian, Newton and sweep call.  Besides
  * this call only celeste_plan_set_launch (grown tile buffers for smaller tiles),
  * celeste_autotune (its own timing outputs) and celeste_sweep (temporary list buffers
- * when a schedule lists sources more often than once in total) allocate device memory.
- * Synchronous.  *out receives the plan.
+ * when a schedule lists sources more often than once in total) allocate device memory;
+ * celeste_elbo_grad_noalloc never does.  Synchronous.  *out receives the plan.
  * Returns CELESTE_EINVAL (nothing allocated), CELESTE_ENOMEM or CELESTE_EHIP. */
 int celeste_plan_create(const celeste_problem_desc* desc, celeste_plan** out);
 
@@ -178,6 +179,25 @@ int celeste_elbo(celeste_plan* plan, const double* theta, const uint8_t* active,
  * the adjoint reads them back instead of evaluating the 45 Gaussians a second time. */
 int celeste_elbo_grad(celeste_plan* plan, const double* theta, const uint8_t* active, int mode,
                       double* elbo, double* grad, hipStream_t stream);
+
+/* Size of the static device scratch of celeste_elbo_grad_noalloc (bytes, per device). */
+#define CELESTE_NOALLOC_SCRATCH_BYTES (8u << 20)
+
+/* For callers that cannot allocate device memory at the time of the call (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): celeste_elbo_grad
+ * in the batched form (same kernels, bitwise the same results, never a graph replay), with
+ * its per-work-item partial sums and work-queue counter in a static device array of
+ * CELESTE_NOALLOC_SCRATCH_BYTES per device instead of plan memory.  The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine); the array's address is
+ * looked up once per device by celeste_plan_create, and the array lives until the process
+ * ends.  Plans whose work items need more than 8 MiB - 256 B of partial sums (88 B per work
+ * item: 95 322 items, e.g. the 2000-source field at 16- or 8-row strips but not at 4-row
+ * strips) get CELESTE_ESCRATCH with nothing launched and the outputs untouched.  Every call
+ * on one device shares that device's array: calls that overlap on one device (on any plans,
+ * streams or threads) race and must be serialised by the caller.  Otherwise as
+ * celeste_elbo_grad with mode CELESTE_BATCHED. */
+int celeste_elbo_grad_noalloc(celeste_plan* plan, const double* theta, const uint8_t* active, double* elbo,
+                              double* grad, hipStream_t stream);
 
 /* Block-diagonal Hessian-vector product (the exact second derivatives Newton's method
  * needs, Section IV-D): hv[s] = (d^2 ELBO_s / d theta_s^2) v[s] (device [n_src][32];

@@ -19,6 +19,7 @@ CELESTE_ECONFLICT = -2
 CELESTE_EHIP = -3
 CELESTE_ENOMEM = -4
 CELESTE_EDOMAIN = -5
+CELESTE_ESCRATCH = -6
 CELESTE_PLAIN = 0
 CELESTE_BATCHED = 1
 CELESTE_INCLUDE_KL = 1
@@ -28,7 +29,7 @@ EXPORTS = ["celeste_plan_create", "celeste_plan_destroy", "celeste_plan_get_info
            "celeste_color_batches", "celeste_sweep", "celeste_plan_set_launch", "celeste_autotune",
            "celeste_plan_use_graph", "celeste_plan_profile", "celeste_plan_status", "celeste_last_hip_error",
            "celeste_status_string", "celeste_version", "celeste_debug_math", "celeste_conflict_graph",
-           "celeste_cyclades_batches", "celeste_plan_set_hessian_mode"]
+           "celeste_cyclades_batches", "celeste_plan_set_hessian_mode", "celeste_elbo_grad_noalloc"]
 
 
 class celeste_image(C.Structure):
@@ -86,6 +87,7 @@ def lib():
     L.celeste_plan_get_info.argtypes = [vp, C.POINTER(celeste_plan_info)]
     L.celeste_elbo.argtypes = [vp, dp, dp, C.c_int, dp, vp]
     L.celeste_elbo_grad.argtypes = [vp, dp, dp, C.c_int, dp, dp, vp]
+    L.celeste_elbo_grad_noalloc.argtypes = [vp, dp, dp, dp, dp, vp]
     L.celeste_hvp.argtypes = [vp, dp, dp, dp, dp, vp]
     L.celeste_hessian.argtypes = [vp, dp, ip, C.c_int, dp, vp]
     L.celeste_newton.argtypes = [vp, dp, ip, C.c_int, C.c_int, C.POINTER(celeste_tr_params), dp, dp, vp]
@@ -265,6 +267,18 @@ class Plan:
         check(lib().celeste_elbo_grad(self.h, _ptr(theta), _ptr(active), mode, _ptr(elbo), _ptr(grad),
                                       _stream()), "celeste_elbo_grad")
         self._status("celeste_elbo_grad")
+        return elbo, grad
+
+    def elbo_grad_noalloc(self, theta, active=None, elbo=None, grad=None):
+        """celeste_elbo_grad_noalloc: the batched ELBO + gradient with the library's static
+        scratch instead of plan memory (the call itself allocates nothing)."""
+        import torch
+        self._theta(theta)
+        elbo = torch.zeros(self.S, dtype=torch.float64, device=theta.device) if elbo is None else elbo
+        grad = torch.zeros(self.S, 32, dtype=torch.float64, device=theta.device) if grad is None else grad
+        check(lib().celeste_elbo_grad_noalloc(self.h, _ptr(theta), _ptr(active), _ptr(elbo), _ptr(grad),
+                                              _stream()), "celeste_elbo_grad_noalloc")
+        self._status("celeste_elbo_grad_noalloc")
         return elbo, grad
 
     def hvp(self, theta, v, with_grad=False):

@@ -783,6 +783,28 @@ int newton_run(celeste_plan* p, double* theta, const Sel& src, const Sel& pair, 
 
 }  // namespace
 
+namespace cel {
+
+int batched_elbo_grad_scratch(celeste_plan* p, const double* theta, const uint8_t* active, double* elbo,
+                              double* grad, double* partials, int* counter, hipStream_t st) {
+    // the plan's own partials and counter are set aside for this call only (calls on one
+    // plan never overlap)
+    double* const own_partials = p->d_partials;
+    int* const own_counter = p->d_counter;
+    p->d_partials = partials;
+    p->d_counter = counter;
+    const int rc = batched_sequence(p, theta, active, true, elbo, grad, st);
+    p->d_partials = own_partials;
+    p->d_counter = own_counter;
+    return rc;
+}
+
+int64_t plan_item_count(const celeste_plan* p) { return (int64_t)p->items.size(); }
+
+int plan_device(const celeste_plan* p) { return p->device; }
+
+}  // namespace cel
+
 // ================================================================ C entry points
 extern "C" {
 
@@ -804,6 +826,7 @@ const char* celeste_status_string(int s) {
         case CELESTE_EHIP: return "HIP runtime error";
         case CELESTE_ENOMEM: return "device allocation failed";
         case CELESTE_EDOMAIN: return "parameters outside their domain";
+        case CELESTE_ESCRATCH: return "problem larger than the static scratch buffer";
         default: return "unknown status";
     }
 }
@@ -833,6 +856,14 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     if (v != CELESTE_OK) return v;
     celeste_plan* p = new celeste_plan();
     HIPCHK(hipGetDevice(&p->device));
+    {
+        // set-up of the entry point without allocation on this device
+        const int rs = noalloc_attach(p->device);
+        if (rs != CELESTE_OK) {
+            delete p;
+            return rs;
+        }
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, p->device) == hipSuccess && prop.multiProcessorCount > 0)
         p->n_cu = prop.multiProcessorCount;

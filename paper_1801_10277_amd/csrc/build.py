@@ -15,7 +15,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libceleste.so")
-SOURCES = ["kernels.hip", "strips.hip", "tr.hip", "api.cpp"]
+SOURCES = ["kernels.hip", "strips.hip", "tr.hip", "noalloc.hip", "api.cpp"]
 HEADERS = ["dual.h", "internal.h", "model.h"]
 ARCH = os.environ.get("CELESTE_OFFLOAD_ARCH", "gfx950")
 

@@ -258,6 +258,16 @@ hipError_t launch_assemble_hessian(const Sel& srcs, const Geometry& g, const int
                                    const double* theta, const double* gw, const double* hw, double* hess,
                                    const int* status, hipStream_t st);
 
+// Entry point without allocation (noalloc.hip): the batched ELBO + gradient of api.cpp with
+// the per-item partial sums and the work-queue counter at the given device addresses.
+int batched_elbo_grad_scratch(celeste_plan* p, const double* theta, const uint8_t* active, double* elbo,
+                              double* grad, double* partials, int* counter, hipStream_t st);
+int64_t plan_item_count(const celeste_plan* p);
+int plan_device(const celeste_plan* p);
+// Looks up (once per device, with that device current) the device address of the static
+// scratch array of noalloc.hip; CELESTE_OK or CELESTE_EHIP.
+int noalloc_attach(int device);
+
 // Trust region (tr.hip)
 struct TrArgs {
     Sel srcs;
