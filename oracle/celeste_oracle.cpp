@@ -17,9 +17,10 @@
 // astrometry (origin and 2x2 matrix) from world to image coordinates.
 //
 // Structure: every pixel quantity is written once, as a template on the scalar
-// type.  T = double gives values; T = Dual<double,27> (forward-mode AD over the
-// 27 parameters of one source) gives the exact gradient; T = Dual<Dual<double,27>,1>
-// (forward over forward) gives a Hessian-vector product.  No derivative is derived
+// type.  T = double gives values; T = Dual<double,N> (forward-mode AD over the N
+// parameters of one source: 27, or 43 with the colour-prior mixture) gives the exact
+// gradient; T = Dual<Dual<double,N>,1> (forward over forward) gives a Hessian-vector
+// product.  No derivative is derived
 // by hand here.  Loops are the naive definition: for a pixel, every other source
 // whose box in that image contains the pixel is evaluated from scratch.  Sums over
 // pixels use Neumaier compensation.  Build with -O2 -ffp-contract=off, no fast-math.
@@ -170,6 +171,8 @@ inline double sky_at(const OImage& im, int r, int c) {
     return im.sky_map ? im.sky_map[(int64_t)r * im.W + c] : im.sky;
 }
 struct OBox { int32_t img, r0, c0, h, w; };
+const int ROW = 48;              // theta row: 27 model parameters, 16 mixture responsibilities, padding
+const int NMIX = 8;              // components of each type's colour-prior mixture
 struct OProblem {
     int32_t n_img, n_src;
     const OImage* img;
@@ -182,8 +185,11 @@ struct OProblem {
     double prior_r[2][2];        // [type][mean, var] of log reference-band brightness
     double prior_c[2][2][4];     // [type][mean, var][colour]
     int32_t flags, pad;
+    // colour prior as a Gaussian mixture per type (with FLAG_MIX): weights, means and
+    // full covariances of its NMIX components
+    double mix_w[2][NMIX], mix_mean[2][NMIX][4], mix_cov[2][NMIX][4][4];
 };
-enum { FLAG_KL = 1, FLAG_LGAMMA = 2 };
+enum { FLAG_KL = 1, FLAG_LGAMMA = 2, FLAG_MIX = 4 };
 
 const double PI = 3.14159265358979323846;
 
@@ -195,6 +201,7 @@ template <class T>
 struct Src {
     T ux, uy, fdev, rho, phi, re, q;
     T rmu[2], rvar[2], cmu[2][4], cvar[2][4];   // type 0 star, 1 galaxy
+    T kap[2][NMIX];   // responsibilities of the colour-prior mixture components (row 27..42)
 };
 
 template <class T>
@@ -205,6 +212,7 @@ Src<T> load_src(const T* p) {
         const T* b = p + 7 + 10 * a;
         s.rmu[a] = b[0]; s.rvar[a] = b[1];
         for (int k = 0; k < 4; ++k) { s.cmu[a][k] = b[2 + k]; s.cvar[a][k] = b[6 + k]; }
+        for (int d = 0; d < NMIX; ++d) s.kap[a][d] = p[27 + NMIX * a + d];
     }
     return s;
 }
@@ -316,7 +324,7 @@ void background(const OProblem& P, int n, int r, int c, int skip, double& E, dou
         if (t == skip) continue;
         for (int b = P.patch_ptr[t]; b < P.patch_ptr[t + 1]; ++b) {
             if (P.box[b].img != n || !box_has(P.box[b], r, c)) continue;
-            Src<double> st = load_src(P.theta + 32 * (size_t)t);
+            Src<double> st = load_src(P.theta + ROW * (size_t)t);
             double Et, Vt;
             source_moments(P, im, st, (double)c, (double)r, Et, Vt);
             E += Et;
@@ -332,8 +340,61 @@ T kl_normal(const T& m1, const T& v1, double m2, double v2) {
     return 0.5 * (std::log(v2) - log(v1) + (v1 + dm * dm) / v2 - 1.0);
 }
 
+// Inverse and log-determinant of a symmetric positive definite 4 x 4 matrix by its
+// Cholesky factor (prior constants only, plain double).
+void spd4_inverse(const double (&S)[4][4], double (&Pinv)[4][4], double& logdet) {
+    double L[4][4] = {};
+    logdet = 0.0;
+    for (int j = 0; j < 4; ++j) {
+        double d = S[j][j];
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        L[j][j] = std::sqrt(d);
+        logdet += 2.0 * std::log(L[j][j]);
+        for (int i = j + 1; i < 4; ++i) {
+            double v = S[i][j];
+            for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+            L[i][j] = v / L[j][j];
+        }
+    }
+    // columns of S^-1 from L L^T x = e_c
+    for (int c = 0; c < 4; ++c) {
+        double y[4], x[4];
+        for (int i = 0; i < 4; ++i) {
+            double v = (i == c) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) v -= L[i][k] * y[k];
+            y[i] = v / L[i][i];
+        }
+        for (int i = 3; i >= 0; --i) {
+            double v = y[i];
+            for (int k = i + 1; k < 4; ++k) v -= L[k][i] * x[k];
+            x[i] = v / L[i][i];
+        }
+        for (int i = 0; i < 4; ++i) Pinv[i][c] = x[i];
+    }
+}
+
+// KL(N(m, diag v) || N(mu, S)) in 4 dimensions:
+// (tr(S^-1 diag v) + (m - mu)^T S^-1 (m - mu) - 4 + log det S - sum log v) / 2.
+template <class T>
+T kl_diag_full(const T* m, const T* v, const double* mu, const double (&S)[4][4]) {
+    double Pm[4][4], logdet;
+    spd4_inverse(S, Pm, logdet);
+    T d[4];
+    for (int k = 0; k < 4; ++k) d[k] = m[k] - mu[k];
+    T acc = T(logdet - 4.0);
+    for (int k = 0; k < 4; ++k) {
+        acc = acc + Pm[k][k] * v[k] - log(v[k]);
+        for (int l = 0; l < 4; ++l) acc = acc + Pm[k][l] * (d[k] * d[l]);
+    }
+    return 0.5 * acc;
+}
+
 // KL(q(a, r, c) || prior): Bernoulli on the type plus, per type weighted by its
-// probability, the Gaussian KLs of log brightness and of the colours.
+// probability, the Gaussian KL of log brightness and that of the colours.  With the
+// colour-prior mixture (FLAG_MIX) the colours' prior is sum_d w_d N(mu_d, S_d); the
+// variational family adds the component indicator z ~ Cat(kappa) per type, independent of
+// the colours, and the colour term becomes KL(q(c, z) || p(c, z)) =
+// KL(Cat(kappa) || Cat(w)) + sum_d kappa_d KL(N(c_mu, diag c_var) || N(mu_d, S_d)).
 template <class T>
 T kl_source(const OProblem& P, const Src<T>& s) {
     const double phi = P.prior_phi;
@@ -341,8 +402,16 @@ T kl_source(const OProblem& P, const Src<T>& s) {
     T kl = q * log(q / phi) + (1.0 - q) * log((1.0 - q) / (1.0 - phi));
     for (int a = 0; a < 2; ++a) {
         T k = kl_normal(s.rmu[a], s.rvar[a], P.prior_r[a][0], P.prior_r[a][1]);
-        for (int j = 0; j < 4; ++j)
-            k = k + kl_normal(s.cmu[a][j], s.cvar[a][j], P.prior_c[a][0][j], P.prior_c[a][1][j]);
+        if (P.flags & FLAG_MIX) {
+            for (int d = 0; d < NMIX; ++d) {
+                const T kd = s.kap[a][d];
+                k = k + kd * (log(kd / P.mix_w[a][d]) +
+                              kl_diag_full(s.cmu[a], s.cvar[a], P.mix_mean[a][d], P.mix_cov[a][d]));
+            }
+        } else {
+            for (int j = 0; j < 4; ++j)
+                k = k + kl_normal(s.cmu[a][j], s.cvar[a][j], P.prior_c[a][0][j], P.prior_c[a][1][j]);
+        }
         kl = kl + (a == 0 ? q : 1.0 - q) * k;
     }
     return kl;
@@ -383,6 +452,53 @@ void source_elbo(const OProblem& P, int s, const T* p27, Acc& acc, Acc& kl_acc) 
 
 using namespace oracle;
 
+// Number of parameters a source's ELBO depends on: 27, or 43 with the colour-prior mixture
+// (the 16 responsibilities enter the KL only).
+inline int n_params(const OProblem* P) { return (P->flags & FLAG_MIX) ? 43 : 27; }
+
+template <int N>
+void source_grad_n(const OProblem* P, int s, double* val, double* grad, double* gabs) {
+    typedef Dual<double, N> D;
+    D p[ROW];
+    const double* th = P->theta + ROW * (size_t)s;
+    for (int i = 0; i < ROW; ++i) {
+        p[i] = D(th[i]);
+        if (i < N) p[i].d[i] = 1.0;
+    }
+    Acc acc(N + 1), kl(N + 1);
+    source_elbo<D>(*P, s, p, acc, kl);
+    val[0] = acc.get(0);
+    val[1] = kl.get(0);
+    val[2] = acc.a[0];
+    for (int i = 0; i < N; ++i) {
+        grad[i] = acc.get(1 + i) + kl.get(1 + i);
+        gabs[i] = acc.a[1 + i] + kl.a[1 + i];
+    }
+}
+
+template <int N>
+void source_hvp_n(const OProblem* P, int s, const double* v, double* hv, double* habs) {
+    typedef Dual<double, N> D;
+    typedef Dual<D, 1> DD;
+    DD p[ROW];
+    const double* th = P->theta + ROW * (size_t)s;
+    for (int i = 0; i < ROW; ++i) {
+        p[i] = DD(th[i]);
+        if (i < N) {
+            p[i].v.d[i] = 1.0;
+            p[i].d[0] = D(v[i]);
+        }
+    }
+    Acc acc(2 * (N + 1)), kl(2 * (N + 1));
+    source_elbo<DD>(*P, s, p, acc, kl);
+    // layout: [v.v, v.d[0..N-1], d0.v, d0.d[0..N-1]]
+    for (int i = 0; i < N; ++i) {
+        hv[i] = acc.get(N + 1 + 1 + i) + kl.get(N + 1 + 1 + i);
+        habs[i] = acc.a[N + 1 + 1 + i] + kl.a[N + 1 + 1 + i];
+    }
+}
+
+
 extern "C" {
 
 int oracle_version() { return 1; }
@@ -393,67 +509,45 @@ int oracle_sizeof_problem() { return (int)sizeof(OProblem); }
 // out[2] = sum over visits of |pixel term|.
 int oracle_source_value(const OProblem* P, int s, double* out) {
     Acc acc(1), kl(1);
-    source_elbo<double>(*P, s, P->theta + 32 * (size_t)s, acc, kl);
+    source_elbo<double>(*P, s, P->theta + ROW * (size_t)s, acc, kl);
     out[0] = acc.get(0);
     out[1] = kl.get(0);
     out[2] = acc.a[0];
     return 0;
 }
 
-// Per-source ELBO gradient w.r.t. its own 27 parameters (forward-mode duals).
-// val[0..2] as oracle_source_value; grad[27] = d(pixel sum - KL)/d theta_s;
-// gabs[27] = sum over visits of |d pixel term / d theta_s| (plus |d KL|).
+int oracle_n_params(const OProblem* P) { return n_params(P); }
+
+// Per-source ELBO gradient w.r.t. its own parameters (forward-mode duals).
+// val[0..2] as oracle_source_value; grad[n] = d(pixel sum - KL)/d theta_s;
+// gabs[n] = sum over visits of |d pixel term / d theta_s| (plus |d KL|); n = n_params.
 int oracle_source_grad(const OProblem* P, int s, double* val, double* grad, double* gabs) {
-    typedef Dual<double, 27> D;
-    D p[27];
-    const double* th = P->theta + 32 * (size_t)s;
-    for (int i = 0; i < 27; ++i) { p[i] = D(th[i]); p[i].d[i] = 1.0; }
-    Acc acc(28), kl(28);
-    source_elbo<D>(*P, s, p, acc, kl);
-    val[0] = acc.get(0);
-    val[1] = kl.get(0);
-    val[2] = acc.a[0];
-    for (int i = 0; i < 27; ++i) {
-        grad[i] = acc.get(1 + i) + kl.get(1 + i);
-        gabs[i] = acc.a[1 + i] + kl.a[1 + i];
-    }
+    if (n_params(P) == 43) source_grad_n<43>(P, s, val, grad, gabs);
+    else source_grad_n<27>(P, s, val, grad, gabs);
     return 0;
 }
 
 // Hessian-vector product of the per-source ELBO in direction v (forward over forward).
-// hv[27] = H v, habs[27] = sum over visits of |(H_visit v)_i| (plus the KL term's).
+// hv[n] = H v, habs[n] = sum over visits of |(H_visit v)_i| (plus the KL term's).
 int oracle_source_hvp(const OProblem* P, int s, const double* v, double* hv, double* habs) {
-    typedef Dual<double, 27> D;
-    typedef Dual<D, 1> DD;
-    DD p[27];
-    const double* th = P->theta + 32 * (size_t)s;
-    for (int i = 0; i < 27; ++i) {
-        p[i] = DD(th[i]);
-        p[i].v.d[i] = 1.0;
-        p[i].d[0] = D(v[i]);
-    }
-    Acc acc(56), kl(56);
-    source_elbo<DD>(*P, s, p, acc, kl);
-    // layout: [v.v, v.d[0..26], d0.v, d0.d[0..26]]
-    for (int i = 0; i < 27; ++i) {
-        hv[i] = acc.get(28 + 1 + i) + kl.get(28 + 1 + i);
-        habs[i] = acc.a[28 + 1 + i] + kl.a[28 + 1 + i];
-    }
+    if (n_params(P) == 43) source_hvp_n<43>(P, s, v, hv, habs);
+    else source_hvp_n<27>(P, s, v, hv, habs);
     return 0;
 }
 
 // Dense Hessian of the per-source ELBO: column d is the Hessian-vector product along the
-// unit vector e_d (the 27 columns run in parallel, OpenMP); habs[i][d] is that product's
-// sum of |per-visit terms| for entry i.  Row-major H[i][d] and habs[i][d].
+// unit vector e_d (the n columns run in parallel, OpenMP); habs[i][d] is that product's
+// sum of |per-visit terms| for entry i.  Row-major n x n H[i][d] and habs[i][d].
 int oracle_source_hessian(const OProblem* P, int s, double* H, double* habs) {
+    const int n = n_params(P);
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int d = 0; d < 27; ++d) {
-        double e[27], hv[27], ha[27];
-        for (int i = 0; i < 27; ++i) e[i] = (i == d) ? 1.0 : 0.0;
+    for (int d = 0; d < n; ++d) {
+        double e[43], hv[43], ha[43];
+        for (int i = 0; i < n; ++i) e[i] = (i == d) ? 1.0 : 0.0;
         oracle_source_hvp(P, s, e, hv, ha);
-        for (int i = 0; i < 27; ++i) {
-            H[i * 27 + d] = hv[i];
-            habs[i * 27 + d] = ha[i];
+        for (int i = 0; i < n; ++i) {
+            H[i * n + d] = hv[i];
+            habs[i * n + d] = ha[i];
         }
     }
     return 0;
@@ -472,7 +566,7 @@ int oracle_render(const OProblem* P, int n, double* E, double* V) {
 // (used by the mass and symmetry checks).
 int oracle_source_light(const OProblem* P, int s, int n, double* E, double* V) {
     const OImage& im = P->img[n];
-    Src<double> st = load_src(P->theta + 32 * (size_t)s);
+    Src<double> st = load_src(P->theta + ROW * (size_t)s);
     for (int r = 0; r < im.H; ++r)
         for (int c = 0; c < im.W; ++c)
             source_moments(*P, im, st, (double)c, (double)r, E[(int64_t)r * im.W + c],
@@ -482,20 +576,20 @@ int oracle_source_light(const OProblem* P, int s, int n, double* E, double* V) {
 
 // Star and galaxy profile of source s at image-frame point (px, py) of image n.
 int oracle_profiles(const OProblem* P, int s, int n, double px, double py, double* out) {
-    Src<double> st = load_src(P->theta + 32 * (size_t)s);
+    Src<double> st = load_src(P->theta + ROW * (size_t)s);
     profiles(*P, P->img[n], st, px, py, out[0], out[1]);
     return 0;
 }
 
 // E[flux] and E[flux^2] of source s for type a in band b.
 int oracle_flux_moments(const OProblem* P, int s, int a, int b, double* out) {
-    Src<double> st = load_src(P->theta + 32 * (size_t)s);
+    Src<double> st = load_src(P->theta + ROW * (size_t)s);
     flux_moments(st, a, b, out[0], out[1]);
     return 0;
 }
 
 double oracle_kl(const OProblem* P, int s) {
-    Src<double> st = load_src(P->theta + 32 * (size_t)s);
+    Src<double> st = load_src(P->theta + ROW * (size_t)s);
     return kl_source(*P, st);
 }
 
@@ -536,11 +630,12 @@ double oracle_total_elbo(const OProblem* P) {
 }
 
 // Gradients of many sources (the CPU baseline): OpenMP over the listed sources.
-int oracle_grad_many(const OProblem* P, int n, const int32_t* src, double* val3, double* grad27) {
+int oracle_grad_many(const OProblem* P, int n, const int32_t* src, double* val3, double* grad) {
+    const int np = n_params(P);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < n; ++i) {
-        double gabs[27];
-        oracle_source_grad(P, src[i], val3 + 3 * (size_t)i, grad27 + 27 * (size_t)i, gabs);
+        double gabs[43];
+        oracle_source_grad(P, src[i], val3 + 3 * (size_t)i, grad + np * (size_t)i, gabs);
     }
     return 0;
 }

@@ -17,6 +17,12 @@ not as code):
   * ratio rho = actual / predicted increase: rho < 1/4 shrinks the radius by 4;
     rho > 3/4 with a boundary step doubles it (capped); the step is accepted when
     rho > eta_accept; a non-finite trial is rejected and shrinks the radius.
+With the colour-prior mixture (43 parameters: the 16 responsibilities kappa, two
+8-simplices) each simplex is mapped by a softmax with its last logit fixed at zero:
+kappa_d = e^{eta_d} / (1 + sum_{e<7} e^{eta_e}) for d < 7 and kappa_7 = 1 / (1 + ...),
+so the step is taken in 27 + 2 x 7 = 41 unconstrained coordinates; the Hessian there is
+J^T (-H) J minus sum_i g_i (second derivative of theta_i in eta), with the Jacobian J of
+theta(eta).
 Gradient and Hessian come from the oracle's dual numbers; the eigendecomposition is
 numpy's.
 """
@@ -26,6 +32,7 @@ from . import oracle as O
 
 LOGIT = {2, 3, 6}
 LOG = {5} | {7 + 10 * t + o for t in (0, 1) for o in (1, 6, 7, 8, 9)}
+NMIX = 8
 
 
 def to_unconstrained(th):
@@ -55,6 +62,68 @@ def from_unconstrained(eta):
         else:
             th[i] = eta[i]
     return th
+
+
+def softmax_block(kappa):
+    """Unconstrained coordinates of one responsibility simplex: eta_d = log(kappa_d /
+    kappa_7), d < 7; the Jacobian d kappa_d / d eta_e = kappa_d (delta_de - kappa_e)
+    (delta_7e = 0), 8 x 7; and the second derivatives
+    d2 kappa_d / d eta_e d eta_f = kappa_d [(delta_de - kappa_e)(delta_df - kappa_f)
+    - kappa_e (delta_ef - kappa_f)], 8 x 7 x 7."""
+    k = np.asarray(kappa, np.float64)
+    eta = np.log(k[:NMIX - 1]) - np.log(k[NMIX - 1])
+    D = np.zeros((NMIX, NMIX - 1))
+    D[:NMIX - 1, :] = np.eye(NMIX - 1)
+    A = D - k[None, :NMIX - 1]                       # delta_de - kappa_e
+    J = k[:, None] * A
+    kk = k[:NMIX - 1]
+    T = k[:, None, None] * (A[:, :, None] * A[:, None, :]
+                            - (kk[:, None] * (np.eye(NMIX - 1) - kk[None, :]))[None, :, :])
+    return eta, J, T
+
+
+def softmax_from_eta(eta):
+    e = np.exp(np.concatenate([eta, [0.0]]))
+    return e / e.sum()
+
+
+def transform(row, npar):
+    """Unconstrained coordinates of a source row with npar parameters (27, or 43 with the
+    mixture responsibilities): (eta [m], J [npar x m], curvature(g) = sum_i g_i d2 theta_i /
+    d eta^2 [m x m]) with m = 27 or 41."""
+    eta27, d1, d2 = to_unconstrained(row[:27])
+    if npar == 27:
+        return eta27, np.diag(d1), lambda g, absolute=False: np.diag((np.abs(d2) if absolute else d2) * g[:27])
+    m = 27 + 2 * (NMIX - 1)
+    J = np.zeros((npar, m))
+    J[:27, :27] = np.diag(d1)
+    eta = np.zeros(m)
+    eta[:27] = eta27
+    blocks = []
+    for t in range(2):
+        et, Jt, Tt = softmax_block(row[27 + NMIX * t:27 + NMIX * (t + 1)])
+        cs = slice(27 + (NMIX - 1) * t, 27 + (NMIX - 1) * (t + 1))
+        eta[cs] = et
+        J[27 + NMIX * t:27 + NMIX * (t + 1), cs] = Jt
+        blocks.append((cs, slice(27 + NMIX * t, 27 + NMIX * (t + 1)), Tt))
+
+    def curvature(g, absolute=False):
+        f = np.abs if absolute else (lambda x: x)
+        C = np.diag(np.concatenate([f(d2) * g[:27], np.zeros(m - 27)]))
+        for cs, rs, Tt in blocks:
+            C[cs, cs] += np.tensordot(g[rs], f(Tt), axes=1)
+        return C
+
+    return eta, J, curvature
+
+
+def row_from_eta(eta, npar):
+    """Inverse of transform: the npar parameters at unconstrained coordinates eta."""
+    th = from_unconstrained(eta[:27])
+    if npar == 27:
+        return th
+    ks = [softmax_from_eta(eta[27 + (NMIX - 1) * t:27 + (NMIX - 1) * (t + 1)]) for t in range(2)]
+    return np.concatenate([th] + ks)
 
 
 def subproblem(g, B, R):
@@ -104,15 +173,20 @@ def subproblem(g, B, R):
 
 def source_fixed_elbo(f, theta_all, s, row):
     th = theta_all.copy()
-    th[s, :27] = row
+    th[s, :len(row)] = row
     return O.source_elbo(O.Problem(f, th), s)
+
+
+def n_params(f):
+    return 43 if int(f.flags) & O.FLAG_MIX else 27
 
 
 def newton_steps(f, theta_in, s, n_steps, radius0=1.0, radius_max=1e3, eta_accept=0.1, gtol=1e-8,
                  record=None):
     """n_steps trust-region iterations on source s, every other source fixed at theta_in.
-    Returns (theta row [27], ELBO_s, radius)."""
-    row = theta_in[s, :27].copy()
+    Returns (theta row [27 or 43], ELBO_s, radius)."""
+    npar = n_params(f)
+    row = theta_in[s, :npar].copy()
     R = radius0
     done = False
     f0 = None
@@ -120,21 +194,21 @@ def newton_steps(f, theta_in, s, n_steps, radius0=1.0, radius_max=1e3, eta_accep
         if done:
             break
         th = theta_in.copy()
-        th[s, :27] = row
+        th[s, :npar] = row
         P = O.Problem(f, th)
         val, g, gabs = O.source_grad(P, s)
         f0 = val[0] + val[1]
         H, Habs = O.source_hessian(P, s, with_abs=True)
-        eta, d1, d2 = to_unconstrained(row)
-        gm = -d1 * g
-        B = -(d1[:, None] * (0.5 * (H + H.T)) * d1[None, :]) - np.diag(d2 * g)
+        eta, J, curvature = transform(row, npar)
+        gm = -J.T @ g
+        B = -(J.T @ (0.5 * (H + H.T)) @ J) - curvature(g)
         if not np.max(np.abs(gm)) >= gtol:
             done = True
             break
         p, lam, gh, ph = subproblem(gm, B, R)
         pred = -np.sum(gh * ph + 0.5 * lam * ph * ph)
         pn = np.linalg.norm(ph)
-        trial = from_unconstrained(eta + p)
+        trial = row_from_eta(eta + p, npar)
         f1 = source_fixed_elbo(f, theta_in, s, trial)
         finite = np.isfinite(f1)
         rho = (f1 - f0) / pred if (finite and pred > 0) else -1.0

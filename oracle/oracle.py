@@ -42,7 +42,12 @@ class OProblem(C.Structure):
                 ("exp_alpha", C.c_double * 6), ("exp_nu", C.c_double * 6),
                 ("dev_alpha", C.c_double * 8), ("dev_nu", C.c_double * 8),
                 ("prior_phi", C.c_double), ("prior_r", C.c_double * 4),
-                ("prior_c", C.c_double * 16), ("flags", C.c_int32), ("pad", C.c_int32)]
+                ("prior_c", C.c_double * 16), ("flags", C.c_int32), ("pad", C.c_int32),
+                ("mix_w", C.c_double * 16), ("mix_mean", C.c_double * 64), ("mix_cov", C.c_double * 256)]
+
+
+ROW = 48          # theta row width
+FLAG_MIX = 4      # colour prior as a Gaussian mixture (16 responsibilities in the row)
 
 
 _lib = None
@@ -68,6 +73,7 @@ def lib():
         L.oracle_total_elbo.argtypes = [P]
         L.oracle_total_elbo.restype = C.c_double
         L.oracle_grad_many.argtypes = [P, C.c_int, C.POINTER(C.c_int32), dp, dp]
+        L.oracle_n_params.argtypes = [P]
         assert L.oracle_sizeof_image() == C.sizeof(OImage)
         assert L.oracle_sizeof_problem() == C.sizeof(OProblem)
         _lib = L
@@ -107,7 +113,7 @@ class Problem:
         self.ptr = np.ascontiguousarray(f.patch_ptr, np.int32)
         self.box = np.ascontiguousarray(f.boxes, np.int32).reshape(-1)
         th = f.theta if theta is None else theta
-        self.theta = np.ascontiguousarray(th, np.float64).reshape(-1, 32)
+        self.theta = np.ascontiguousarray(th, np.float64).reshape(-1, ROW)
         p = OProblem()
         p.n_img, p.n_src = n, self.theta.shape[0]
         p.img = C.cast(imgs, C.POINTER(OImage))
@@ -125,6 +131,13 @@ class Problem:
         for k, v in enumerate(np.asarray(f.prior_c).reshape(-1)):
             p.prior_c[k] = float(v)
         p.flags = int(f.flags if flags is None else flags)
+        if p.flags & FLAG_MIX:
+            for name, arr in (("mix_w", f.color_mix_w), ("mix_mean", f.color_mix_mean),
+                              ("mix_cov", f.color_mix_cov)):
+                dst = getattr(p, name)
+                for k, v in enumerate(np.asarray(arr, np.float64).reshape(-1)):
+                    dst[k] = float(v)
+        self.n = 43 if p.flags & FLAG_MIX else 27
         self.p = p
         self.ref = C.byref(p)
 
@@ -141,28 +154,34 @@ def source_elbo(prob, s):
     return v[0] + v[1]
 
 
+def n_params(prob):
+    """Parameters of a source's ELBO: 27, or 43 with the colour-prior mixture."""
+    return prob.n
+
+
 def source_grad(prob, s):
-    """Returns (value3, grad[27], gabs[27]) of source s (value3 as source_value)."""
+    """Returns (value3, grad[n], gabs[n]) of source s (value3 as source_value; n =
+    n_params)."""
     val = np.zeros(3)
-    g = np.zeros(27)
-    ga = np.zeros(27)
+    g = np.zeros(prob.n)
+    ga = np.zeros(prob.n)
     lib().oracle_source_grad(prob.ref, s, _dp(val), _dp(g), _dp(ga))
     return val, g, ga
 
 
 def source_hvp(prob, s, v):
-    v = np.ascontiguousarray(np.asarray(v, np.float64)[:27])
-    hv = np.zeros(27)
-    ha = np.zeros(27)
+    v = np.ascontiguousarray(np.asarray(v, np.float64)[:prob.n])
+    hv = np.zeros(prob.n)
+    ha = np.zeros(prob.n)
     lib().oracle_source_hvp(prob.ref, s, _dp(v), _dp(hv), _dp(ha))
     return hv, ha
 
 
 def source_hessian(prob, s, with_abs=False):
-    """27 x 27 Hessian of ELBO_s (columns: Hessian-vector products along unit vectors, in
-    parallel); with_abs also returns the per-entry sums of |per-visit terms|."""
-    H = np.zeros((27, 27))
-    Ha = np.zeros((27, 27))
+    """n x n Hessian of ELBO_s (n = n_params; columns: Hessian-vector products along unit
+    vectors, in parallel); with_abs also returns the per-entry sums of |per-visit terms|."""
+    H = np.zeros((prob.n, prob.n))
+    Ha = np.zeros((prob.n, prob.n))
     lib().oracle_source_hessian(prob.ref, s, _dp(H), _dp(Ha))
     return (H, Ha) if with_abs else H
 
@@ -206,7 +225,7 @@ def total_elbo(prob):
 def grad_many(prob, srcs):
     srcs = np.ascontiguousarray(srcs, np.int32)
     val = np.zeros((len(srcs), 3))
-    g = np.zeros((len(srcs), 27))
+    g = np.zeros((len(srcs), prob.n))
     lib().oracle_grad_many(prob.ref, len(srcs), srcs.ctypes.data_as(C.POINTER(C.c_int32)),
                            _dp(val), _dp(g))
     return val, g

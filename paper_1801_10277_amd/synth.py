@@ -10,7 +10,7 @@ and the photons are binned into pixels on top of Poisson sky counts.
 Both the oracle tests and the GPU path take their inputs from here; nothing here
 imports either of them.
 
-Parameter layout of one source row theta[s, 0:32] (float64):
+Parameter layout of one source row theta[s, 0:48] (float64):
   0 u_x, 1 u_y        world position of the centre, pixels
   2 frac_dev          de Vaucouleurs fraction of the galaxy profile, [0, 1]
   3 axis_ratio        minor/major axis ratio, (0, 1]
@@ -19,7 +19,9 @@ Parameter layout of one source row theta[s, 0:32] (float64):
   6 q_star            variational probability that the source is a star, (0, 1)
   7..16  star:   r_mu, r_var, c_mu[4], c_var[4]
   17..26 galaxy: r_mu, r_var, c_mu[4], c_var[4]
-  27..31 zero padding
+  27..34 star, 35..42 galaxy: responsibilities kappa[8] of the colour-prior mixture
+         components (used with FLAG_COLOR_MIXTURE; zero otherwise)
+  43..47 zero padding
 r is the log reference-band (r-band) brightness, c_k = log(flux_{k+1} / flux_k) the
 colours between adjacent bands u, g, r, i, z; the *_var entries are variances.
 """
@@ -30,7 +32,10 @@ import os
 import numpy as np
 
 N_PARAM = 27
-ROW = 32
+N_MIX = 8                  # components of each type's colour-prior mixture
+N_PARAM_MIX = N_PARAM + 2 * N_MIX
+I_KAPPA = 27
+ROW = 48
 I_UX, I_UY, I_FDEV, I_RHO, I_PHI, I_RE, I_Q = range(7)
 I_STAR = 7
 I_GAL = 17
@@ -38,6 +43,7 @@ N_BANDS = 5
 REF_BAND = 2
 FLAG_INCLUDE_KL = 1
 FLAG_INCLUDE_LGAMMA = 2
+FLAG_COLOR_MIXTURE = 4
 
 _PROFILE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "profiles.json")
 
@@ -64,7 +70,7 @@ class Field:
     x: np.ndarray               # f64 [n_pix] pixel counts, row-major per image
     patch_ptr: np.ndarray       # int32 [S + 1]
     boxes: np.ndarray           # int32 [n_box, 5] (img, r0, c0, h, w)
-    theta: np.ndarray           # f64 [S, 32]
+    theta: np.ndarray           # f64 [S, 48]
     exp_alpha: np.ndarray
     exp_nu: np.ndarray
     dev_alpha: np.ndarray
@@ -77,6 +83,10 @@ class Field:
     name: str = ""
     img_wcs: np.ndarray = None  # f64 [n_img, 2, 2] image offset = wcs @ world offset; None: identity
     sky_map: np.ndarray = None  # f64 [n_pix] per-pixel sky level, layout of x; None: img_sky
+    # colour prior as a Gaussian mixture per type (with FLAG_COLOR_MIXTURE)
+    color_mix_w: np.ndarray = None      # f64 [2, 8] component weights (sum 1)
+    color_mix_mean: np.ndarray = None   # f64 [2, 8, 4]
+    color_mix_cov: np.ndarray = None    # f64 [2, 8, 4, 4] symmetric positive definite
 
     def wcs(self, n):
         return np.eye(2) if self.img_wcs is None else np.asarray(self.img_wcs[n], np.float64)
@@ -493,3 +503,29 @@ def tiny(S=2, n_bands=2, size=15, side=9, seed=7, sky=(100.0, 200.0), psf_xi=Fal
     theta = _theta_from_truth(rng, pos, flux, colours, shape)
     return _assemble(rng, imgs, pos, kind, flux, colours, shape, np.full(S, side), theta,
                      star_prob, np.log(1000.0), 1.0, "tiny")
+
+
+def with_color_mixture(f, seed=0, kappa="random"):
+    """A copy of field f whose colour prior is a Gaussian mixture of N_MIX components per
+    type (seeded draws: Dirichlet(2) weights, N(0, 0.5^2) means, covariances B B^T / 8 +
+    0.01 I with B standard normal), with FLAG_COLOR_MIXTURE set and the responsibilities
+    kappa of every source drawn from Dirichlet(1) ("random") or set to the prior weights
+    ("prior")."""
+    import copy
+    rng = np.random.default_rng(10_000 + seed)
+    g = copy.copy(f)
+    g.color_mix_w = rng.dirichlet(np.full(N_MIX, 2.0), 2)
+    g.color_mix_mean = rng.normal(0.0, 0.5, (2, N_MIX, 4))
+    Bm = rng.standard_normal((2, N_MIX, 4, 4))
+    g.color_mix_cov = np.einsum("tdij,tdkj->tdik", Bm, Bm) / 8.0 + 0.01 * np.eye(4)
+    th = np.array(f.theta, np.float64, copy=True)
+    for t in range(2):
+        cols = slice(I_KAPPA + N_MIX * t, I_KAPPA + N_MIX * (t + 1))
+        if kappa == "prior":
+            th[:, cols] = g.color_mix_w[t]
+        else:
+            th[:, cols] = rng.dirichlet(np.ones(N_MIX), th.shape[0])
+    g.theta = th
+    g.flags = int(f.flags) | FLAG_COLOR_MIXTURE
+    return g
+

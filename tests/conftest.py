@@ -122,35 +122,37 @@ def newton_step_bound(N, f, theta, s, radius, gtol=1e-8):
     Perturbing g and B by dg, dB (and mu so that |p| stays R) moves p by
     dp = -P M^-1 (dg + dB p), M = B + mu I, P = I - M^-1 p p^T / (p^T M^-1 p) (P = I for an
     interior step), so |dp| <= |P M^-1| (|dg| + |dB|_F |p|); both solves stop the secular
-    equation at |p| within 1e-13 R, which adds 2e-13 R |P M^-1| |M|.  theta_i moves by
-    |theta_i'(eta_i + p_i)| |dp|.  A source that stops before stepping keeps theta exactly
+    equation at |p| within 1e-13 R, which adds 2e-13 R |P M^-1| |M|.  theta_i moves by at
+    most |row i of the Jacobian of theta(eta) at the trial point| |dp|.  A source that stops before stepping keeps theta exactly
     (bound 0).  Returns (bound[27], oracle row, oracle ELBO_s, oracle radius)."""
     rec = []
     row, fend, R = N.newton_steps(f, theta, s, 1, radius0=radius, gtol=gtol, record=rec)
+    npar = len(row)
     if not rec:
-        return np.zeros(27), row, fend, R
+        return np.zeros(npar), row, fend, R
     r0 = rec[0]
     g, gabs, H, Habs, B, p = r0["grad"], r0["gabs"], r0["hess"], r0["habs"], r0["B"], r0["step"]
-    eta, d1, d2 = N.to_unconstrained(theta[s, :27])
+    eta, J, curvature = N.transform(theta[s, :npar], npar)
     dg = REL * np.abs(g) + FLOOR * gabs
     dH = REL * np.abs(H) + FLOOR * Habs
-    dgm = np.abs(d1) * dg
-    dB = np.abs(d1)[:, None] * dH * np.abs(d1)[None, :] + np.diag(np.abs(d2) * dg)
+    dgm = np.abs(J).T @ dg
+    dB = np.abs(J).T @ dH @ np.abs(J) + curvature(dg, absolute=True)
+    m = len(p)
     pn = np.linalg.norm(p)
     res = -r0["g_eta"] - B @ p
     mu = max(0.0, (res @ p) / (p @ p)) if pn > 0 else 0.0
-    M = B + mu * np.eye(27)
+    M = B + mu * np.eye(m)
     Minv = np.linalg.inv(M)
     if mu > 0:
         Mp = Minv @ p
-        Proj = np.eye(27) - np.outer(Mp, p) / (p @ Mp)
+        Proj = np.eye(m) - np.outer(Mp, p) / (p @ Mp)
     else:
-        Proj = np.eye(27)
+        Proj = np.eye(m)
     PM = np.linalg.norm(Proj @ Minv, 2)
     dp = PM * (np.linalg.norm(dgm) + np.linalg.norm(dB) * pn) + 2e-13 * radius * PM * np.linalg.norm(M, 2)
-    th1 = N.from_unconstrained(eta + p)
-    _, t1d, _ = N.to_unconstrained(th1)
-    bound = np.abs(t1d) * dp + 4e-16 * np.abs(th1)
+    th1 = N.row_from_eta(eta + p, npar)
+    _, J1, _ = N.transform(th1, npar)
+    bound = np.linalg.norm(J1, axis=1) * dp + 4e-16 * np.abs(th1)
     return bound, row, fend, R
 
 
@@ -175,7 +177,7 @@ def newton_trajectory_parity(B, N, torch, f, srcs, steps, gtol=1e-8, say=print):
             base = f.theta.copy()
             base[s] = prev_th[s]
             bound, row, fend, R = newton_step_bound(N, f, base, s, prev_R[s], gtol=gtol)
-            diff = np.abs(thk[s, :27] - row)
+            diff = np.abs(thk[s, :len(row)] - row)
             assert np.all(diff <= bound), (k, s, (diff / np.maximum(bound, 1e-300)).max())
             worst = max(worst, float(np.max(np.where(bound > 0, diff / np.maximum(bound, 1e-300), 0.0))))
             assert Rk[s] == R, (k, s, Rk[s], R)
@@ -205,7 +207,7 @@ def sweep_batch_parity(B, N, torch, f, ptr, src, say=print):
         np.testing.assert_array_equal(cur[others], prev[others])
         for s in members:
             bound, row, _, _ = newton_step_bound(N, f, prev, s, params.radius0)
-            diff = np.abs(cur[s, :27] - row)
+            diff = np.abs(cur[s, :len(row)] - row)
             assert np.all(diff <= bound), (b, s, (diff / np.maximum(bound, 1e-300)).max())
             worst = max(worst, float(np.max(np.where(bound > 0, diff / np.maximum(bound, 1e-300), 0.0))))
         say("  batch", b, "members", members, "worst |diff| / bound %.3g" % worst)

@@ -104,3 +104,53 @@ def test_iterations_ascend(synth, O):
     th = f.theta.copy()
     th[0, :27] = row
     np.testing.assert_allclose(O.source_elbo(O.Problem(f, th), 0), fend, rtol=1e-13)
+
+
+def test_softmax_transform_derivatives_and_round_trip():
+    """Responsibilities through the softmax with the last logit fixed at 0: round trip,
+    the Jacobian and second derivatives against finite differences, rows of J summing to
+    zero over the simplex (the sum stays 1)."""
+    rng = np.random.default_rng(1)
+    k = rng.dirichlet(np.ones(8))
+    eta, J, T = N.softmax_block(k)
+    np.testing.assert_allclose(N.softmax_from_eta(eta), k, rtol=1e-14)
+    np.testing.assert_allclose(J.sum(0), 0.0, atol=1e-16)
+    h = 1e-5
+    for e in range(7):
+        ep, em = eta.copy(), eta.copy()
+        ep[e] += h
+        em[e] -= h
+        fd = (N.softmax_from_eta(ep) - N.softmax_from_eta(em)) / (2 * h)
+        np.testing.assert_allclose(J[:, e], fd, rtol=1e-8, atol=1e-12)
+        h = 1e-4   # second differences: rounding ~ eps / h^2, truncation ~ h^2
+        for g in range(7):
+            e2 = [eta.copy() for _ in range(4)]
+            e2[0][[e, g]] += h
+            e2[1][e] += h
+            e2[1][g] -= h
+            e2[2][e] -= h
+            e2[2][g] += h
+            e2[3][[e, g]] -= h
+            if e == g:
+                fd2 = (N.softmax_from_eta(eta + np.eye(7)[e] * 2 * h) - 2 * k
+                       + N.softmax_from_eta(eta - np.eye(7)[e] * 2 * h)) / (4 * h * h)
+            else:
+                fd2 = (N.softmax_from_eta(e2[0]) - N.softmax_from_eta(e2[1]) - N.softmax_from_eta(e2[2])
+                       + N.softmax_from_eta(e2[3])) / (4 * h * h)
+            np.testing.assert_allclose(T[:, e, g], fd2, rtol=1e-5, atol=1e-7)
+        h = 1e-5
+
+
+def test_mixture_iterations_ascend_and_stay_on_the_simplex(synth, O):
+    f = synth.with_color_mixture(synth.tiny(S=2, n_bands=2, size=17, side=11, seed=9), seed=6)
+    rec = []
+    row, fend, R = N.newton_steps(f, f.theta, 0, 6, record=rec)
+    assert row.shape == (43,)
+    start = O.source_elbo(O.Problem(f), 0)
+    assert fend > start
+    np.testing.assert_allclose([row[27:35].sum(), row[35:43].sum()], 1.0, rtol=1e-14)
+    assert np.all(row[27:43] > 0)
+    assert any(np.any(r["theta"][27:43] != f.theta[0, 27:43]) for r in rec[1:])
+    th = f.theta.copy()
+    th[0, :43] = row
+    np.testing.assert_allclose(O.source_elbo(O.Problem(f, th), 0), fend, rtol=1e-13)

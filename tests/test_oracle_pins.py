@@ -641,3 +641,97 @@ def test_sky_map_adds_per_pixel(synth, O):
     R = O.Problem(h)
     for s in range(3):
         np.testing.assert_array_equal(O.source_grad(R, s)[1], O.source_grad(Q, s)[1])
+
+
+# ------------------------------------------------------------------ colour-prior mixture
+def test_mixture_kl_monte_carlo(synth, O):
+    """With the colour-prior mixture the KL is E_q[log q(a, r, c, z) - log p(a, r, c, z)]
+    with the component indicator z ~ Cat(kappa) independent of the colours under q and
+    p(c, z | a) = w_z N(c; mean_z, cov_z): Monte Carlo with 1e6 draws, scipy densities for
+    the full-covariance prior components, within 4 standard errors."""
+    f = synth.with_color_mixture(synth.tiny(S=1, n_bands=1, seed=41), seed=3)
+    th = f.theta[0]
+    th[6] = 0.35
+    th[7:17] = [6.9, 0.3, 0.2, -0.3, 0.4, -0.1, 0.05, 0.2, 0.1, 0.12]
+    th[17:27] = [7.2, 0.2, -0.4, 0.1, 0.3, 0.5, 0.15, 0.04, 0.09, 0.25]
+    P = O.Problem(f)
+    rng = np.random.default_rng(5)
+    N = 1_000_000
+    star = rng.random(N) < th[6]
+    lq = np.where(star, np.log(th[6]), np.log1p(-th[6]))
+    lp = np.where(star, np.log(f.prior_phi), np.log1p(-f.prior_phi))
+    for t, base in ((0, 7), (1, 17)):
+        m = star if t == 0 else ~star
+        n = int(m.sum())
+        r = rng.normal(th[base], np.sqrt(th[base + 1]), n)
+        c = rng.normal(th[base + 2:base + 6], np.sqrt(th[base + 6:base + 10]), (n, 4))
+        kap = th[27 + 8 * t:35 + 8 * t]
+        z = rng.choice(8, size=n, p=kap / kap.sum())
+        lqt = (stats.norm.logpdf(r, th[base], np.sqrt(th[base + 1]))
+               + stats.norm.logpdf(c, th[base + 2:base + 6], np.sqrt(th[base + 6:base + 10])).sum(1)
+               + np.log(kap[z]))
+        lpt = stats.norm.logpdf(r, f.prior_r[t, 0], np.sqrt(f.prior_r[t, 1])) + np.log(f.color_mix_w[t][z])
+        for d in range(8):
+            sel = z == d
+            lpt[sel] += stats.multivariate_normal(f.color_mix_mean[t, d], f.color_mix_cov[t, d]).logpdf(c[sel])
+        lq[m] += lqt
+        lp[m] += lpt
+    d = lq - lp
+    kl = O.kl(P, 0)
+    assert abs(d.mean() - kl) < 4 * d.std() / np.sqrt(N), (d.mean(), kl, d.std() / np.sqrt(N))
+
+
+def test_mixture_of_identical_components_reduces_to_single_prior(synth, O):
+    """Eight identical components (weights 1/8, the single prior's mean and diagonal
+    variances) with responsibilities 1/8: the categorical KL vanishes and the colour term
+    is the single Gaussian prior's KL, so ELBO, KL and the gradient in the 27 shared
+    parameters equal the oracle without the mixture."""
+    f = synth.tiny(S=2, n_bands=2, size=15, side=9, seed=43)
+    g = synth.with_color_mixture(f, seed=4, kappa="prior")
+    g.color_mix_w = np.full((2, 8), 1.0 / 8)
+    for t in range(2):
+        g.color_mix_mean[t] = f.prior_c[t, 0]
+        g.color_mix_cov[t] = np.diag(f.prior_c[t, 1])
+    g.theta[:, 27:43] = 1.0 / 8
+    P0, P1 = O.Problem(f), O.Problem(g)
+    for s in range(2):
+        np.testing.assert_allclose(O.kl(P1, s), O.kl(P0, s), rtol=1e-13)
+        v0, g0, _ = O.source_grad(P0, s)
+        v1, g1, _ = O.source_grad(P1, s)
+        np.testing.assert_allclose(v1[:2], v0[:2], rtol=1e-13)
+        np.testing.assert_allclose(g1[:27], g0, rtol=1e-12, atol=1e-12 * np.abs(g0).max())
+        # d KL / d kappa_d = q_a (log(kappa_d / w_d) + 1 + KL_normal) is the same for every d
+        for t, w in ((0, g.theta[s, 6]), (1, 1 - g.theta[s, 6])):
+            kk = g1[27 + 8 * t:35 + 8 * t]
+            np.testing.assert_allclose(kk, kk[0], rtol=1e-12)
+
+
+def test_mixture_gradient_and_hvp_vs_finite_differences(synth, O):
+    """The 43-direction dual-number gradient against central differences of the value
+    (relative step 1e-6), and the Hessian-vector product against differences of the
+    gradient, with the responsibilities moved off the simplex only infinitesimally (the
+    oracle's KL is defined for any positive kappa)."""
+    f = synth.with_color_mixture(synth.tiny(S=2, n_bands=2, size=13, side=9, seed=45), seed=5)
+    P = O.Problem(f)
+    s = 0
+    _, g, _ = O.source_grad(P, s)
+    assert g.shape == (43,)
+    for i in list(range(0, 27, 3)) + list(range(27, 43)):
+        h = 1e-6 * max(1.0, abs(f.theta[s, i]))
+        tp, tm = f.theta.copy(), f.theta.copy()
+        tp[s, i] += h
+        tm[s, i] -= h
+        fd = (O.source_elbo(O.Problem(f, tp), s) - O.source_elbo(O.Problem(f, tm), s)) / (2 * h)
+        assert abs(g[i] - fd) <= 1e-6 * abs(fd) + 1e-4, (i, g[i], fd)
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal(43)
+    hv, _ = O.source_hvp(P, s, v)
+    h = 1e-6
+    tp, tm = f.theta.copy(), f.theta.copy()
+    tp[s, :43] += h * v
+    tm[s, :43] -= h * v
+    fd = (O.source_grad(O.Problem(f, tp), s)[1] - O.source_grad(O.Problem(f, tm), s)[1]) / (2 * h)
+    np.testing.assert_allclose(hv, fd, rtol=1e-5, atol=1e-4 * np.abs(fd).max())
+    w = rng.standard_normal(43)
+    hw, _ = O.source_hvp(P, s, w)
+    np.testing.assert_allclose(w @ hv, v @ hw, rtol=1e-11)
