@@ -289,7 +289,7 @@ def main():
     info = plan.info()
     visits = info["n_visits"]
     elbo = torch.zeros(f.n_src, dtype=torch.float64, device=dev)
-    grad = torch.zeros(f.n_src, 32, dtype=torch.float64, device=dev)
+    grad = torch.zeros(f.n_src, 48, dtype=torch.float64, device=dev)
 
     if args.launch:
         apply_launch(plan, args.launch)

@@ -23,13 +23,18 @@
  * radius^2 R(angle) diag(1, ratio^2) R(angle)^T (world frame; wcs S wcs^T in the image)
  * and convolved with the PSF.
  *
- * Parameters: theta is a device array [n_src][32] of float64, one row per source:
+ * Parameters: theta is a device array [n_src][48] of float64, one row per source:
  *   0 u_x, 1 u_y (world pixels), 2 frac_dev in [0,1], 3 axis ratio in (0,1],
  *   4 angle (rad, counter-clockwise from +x to the major axis), 5 half-light radius
  *   (px, > 0), 6 q = probability of a star in (0,1),
- *   7..16 star: r_mu, r_var, c_mu[4], c_var[4];  17..26 galaxy: same;  27..31 unused.
+ *   7..16 star: r_mu, r_var, c_mu[4], c_var[4];  17..26 galaxy: same;
+ *   27..34 star, 35..42 galaxy: responsibilities kappa[8] of the colour-prior mixture
+ *   components (CELESTE_COLOR_MIXTURE only: each type's eight positive, summing to 1;
+ *   ignored otherwise);  43..47 unused.
  *   r is the log reference-band (r) flux, c_k = log(flux_{k+1}/flux_k) over u,g,r,i,z;
- *   *_var are variances (> 0).  Gradients are taken with respect to these entries.
+ *   *_var are variances (> 0).  A source has n_params = 27 parameters, or 43 with the
+ *   colour-prior mixture (the paper's 44 count the type as a two-entry simplex; here
+ *   q_gal = 1 - q).  Gradients are taken with respect to these entries.
  *
  * Conventions for every call:
  *  - Pointers documented "device" must be device memory of the current HIP device;
@@ -51,7 +56,7 @@
 extern "C" {
 #endif
 
-#define CELESTE_ABI_VERSION 5
+#define CELESTE_ABI_VERSION 6
 
 enum celeste_status {
     CELESTE_OK = 0,
@@ -70,7 +75,11 @@ enum celeste_mode {
 
 enum celeste_flags {
     CELESTE_INCLUDE_KL = 1,       /* subtract KL(q || prior) from each ELBO_s */
-    CELESTE_INCLUDE_LGAMMA = 2    /* include the -log(x!) constant in every pixel term */
+    CELESTE_INCLUDE_LGAMMA = 2,   /* include the -log(x!) constant in every pixel term */
+    CELESTE_COLOR_MIXTURE = 4     /* colour prior: a Gaussian mixture per type (color_mix_*), with
+                                     the component responsibilities kappa in theta (43 parameters):
+                                     a type's colour KL term is KL(Cat(kappa) || Cat(w)) +
+                                     sum_d kappa_d KL(N(c_mu, diag c_var) || N(mean_d, cov_d)) */
 };
 
 /* One image: header of a row-major H x W plane of float64 counts inside x. */
@@ -108,9 +117,14 @@ typedef struct celeste_problem_desc {
     double dev_alpha[8], dev_nu[8];    /* de Vaucouleurs profile */
     double prior_phi;              /* prior probability of a star, (0, 1) */
     double prior_r[2][2];          /* [star, galaxy][mean, variance] of log r-band flux */
-    double prior_c[2][2][4];       /* [star, galaxy][mean, variance][colour k] */
+    double prior_c[2][2][4];       /* [star, galaxy][mean, variance][colour k] (without the mixture) */
     uint32_t flags;                /* celeste_flags */
     int32_t reserved;
+    /* colour-prior mixture (read with CELESTE_COLOR_MIXTURE only): per type 8 components with
+       weights > 0 summing to 1, means and symmetric positive definite covariances */
+    double color_mix_w[2][8];
+    double color_mix_mean[2][8][4];
+    double color_mix_cov[2][8][4][4];
 } celeste_problem_desc;
 
 /* Trust-region constants (Nocedal & Wright, Ch. 4) for celeste_newton / celeste_sweep. */
@@ -141,7 +155,7 @@ typedef struct celeste_plan_info {
                               them); 3: the stored values only - the fused adjoint sums each
                               pixel's background from the overlapping boxes' values, no planes */
     int32_t n_classes;     /* conflict-free classes of boxes (render launches) */
-    int32_t reserved;
+    int32_t n_params;      /* parameters per source: 27, or 43 with CELESTE_COLOR_MIXTURE */
     int64_t workspace_bytes;
 } celeste_plan_info;
 
@@ -171,8 +185,8 @@ int celeste_plan_get_info(const celeste_plan* plan, celeste_plan_info* info);
 int celeste_elbo(celeste_plan* plan, const double* theta, const uint8_t* active, int mode,
                  double* elbo, hipStream_t stream);
 
-/* ELBO_s and its gradient with respect to theta[s][0..26] (device grad[n_src][32],
- * entries 27..31 set to 0), from the hand-written adjoint of Eq. (1)'s pixel terms
+/* ELBO_s and its gradient with respect to theta[s][0..n_params-1] (device
+ * grad[n_src][48], the other entries set to 0), from the hand-written adjoint of Eq. (1)'s pixel terms
  * (Section III model) plus the KL's closed-form gradient.  No per-pixel tape: with
  * render modes 0 and 1 the fused adjoint recomputes each visit's own profile values; with
  * modes 2 (the default) and 3 the render stores them (16 B per visit in plan memory) and
@@ -200,14 +214,14 @@ int celeste_elbo_grad_noalloc(celeste_plan* plan, const double* theta, const uin
                               double* grad, hipStream_t stream);
 
 /* Block-diagonal Hessian-vector product (the exact second derivatives Newton's method
- * needs, Section IV-D): hv[s] = (d^2 ELBO_s / d theta_s^2) v[s] (device [n_src][32];
- * entries 27..31 of v ignored, of hv set to 0).  Computed as the forward-mode tangent of
- * the adjoint.  grad (device [n_src][32] or NULL) receives the gradient as a by-product.
+ * needs, Section IV-D): hv[s] = (d^2 ELBO_s / d theta_s^2) v[s] (device [n_src][48];
+ * entries from n_params on ignored in v and set to 0 in hv).  Computed as the forward-mode tangent of
+ * the adjoint.  grad (device [n_src][48] or NULL) receives the gradient as a by-product.
  * All sources, batched form. */
 int celeste_hvp(celeste_plan* plan, const double* theta, const double* v, double* hv,
                 double* grad, hipStream_t stream);
 
-/* Dense per-source Hessians hess[k][27][27] (device, row-major) of the n listed
+/* Dense per-source Hessians hess[k][n_params][n_params] (device, row-major) of the n listed
  * sources src[k] (host list of distinct ids; CELESTE_EINVAL otherwise), the exact
  * second derivatives of Section IV-D: each box's Hessian in its ten intermediates
  * (brightness factors and frac_dev from the gradient pass, position and shape from a
@@ -220,12 +234,14 @@ int celeste_hessian(celeste_plan* plan, const double* theta, const int32_t* src,
 
 /* Newton trust-region iterations (Section IV-D) for the n sources src[] (host list,
  * distinct).  Each listed source is optimised with every other source held at its
- * value in theta at entry.  Per iteration: gradient, dense 27x27 Hessian, exact
- * trust-region subproblem in unconstrained coordinates (logit of q, frac_dev, axis
- * ratio; log of radius and variances) on the Householder tridiagonal form of the
- * Hessian (secular equation; the eigendecomposition near the hard case), trial
- * evaluation, accept/reject and radius update - all on the device.
- * theta_inout (device [n_src][32]) is updated in place; radius (device [n_src]) is
+ * value in theta at entry.  Per iteration: gradient, dense Hessian (27 x 27, or 43 x 43
+ * with the colour-prior mixture), exact trust-region subproblem in unconstrained
+ * coordinates (logit of q, frac_dev, axis ratio; log of radius and variances; with the
+ * mixture, each type's responsibilities through a softmax whose last logit is fixed at 0:
+ * 41 coordinates) on the Householder tridiagonal form of the Hessian (secular equation;
+ * the eigendecomposition near the hard case), trial evaluation, accept/reject and radius
+ * update - all on the device.
+ * theta_inout (device [n_src][48]) is updated in place; radius (device [n_src]) is
  * read and written (initialise with params->radius0); elbo_out (device [n_src] or
  * NULL) receives the final ELBO_s of the listed sources.  Synchronous at entry: it waits
  * for `stream` and uploads the lists with blocking copies; the iterations themselves are

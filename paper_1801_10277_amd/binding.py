@@ -24,6 +24,8 @@ CELESTE_PLAIN = 0
 CELESTE_BATCHED = 1
 CELESTE_INCLUDE_KL = 1
 CELESTE_INCLUDE_LGAMMA = 2
+CELESTE_COLOR_MIXTURE = 4
+ROW = 48              # theta / gradient row width
 EXPORTS = ["celeste_plan_create", "celeste_plan_destroy", "celeste_plan_get_info", "celeste_elbo",
            "celeste_elbo_grad", "celeste_hvp", "celeste_hessian", "celeste_newton", "celeste_total_elbo",
            "celeste_color_batches", "celeste_sweep", "celeste_plan_set_launch", "celeste_autotune",
@@ -51,7 +53,9 @@ class celeste_problem_desc(C.Structure):
                 ("exp_alpha", C.c_double * 6), ("exp_nu", C.c_double * 6),
                 ("dev_alpha", C.c_double * 8), ("dev_nu", C.c_double * 8),
                 ("prior_phi", C.c_double), ("prior_r", C.c_double * 4), ("prior_c", C.c_double * 16),
-                ("flags", C.c_uint32), ("reserved", C.c_int32)]
+                ("flags", C.c_uint32), ("reserved", C.c_int32),
+                ("color_mix_w", C.c_double * 16), ("color_mix_mean", C.c_double * 64),
+                ("color_mix_cov", C.c_double * 256)]
 
 
 class celeste_tr_params(C.Structure):
@@ -64,7 +68,7 @@ class celeste_plan_info(C.Structure):
                 ("n_tiles", C.c_int64), ("n_nbr", C.c_int64), ("chunk", C.c_int32),
                 ("waves_per_block", C.c_int32), ("grid_blocks", C.c_int32), ("tile_h", C.c_int32),
                 ("tile_w", C.c_int32), ("dynamic_queue", C.c_int32), ("strip_rows", C.c_int32),
-                ("render_mode", C.c_int32), ("n_classes", C.c_int32), ("reserved", C.c_int32),
+                ("render_mode", C.c_int32), ("n_classes", C.c_int32), ("n_params", C.c_int32),
                 ("workspace_bytes", C.c_int64)]
 
 
@@ -224,6 +228,12 @@ class Plan:
         for k, v in enumerate(np.asarray(f.prior_c).reshape(-1)):
             d.prior_c[k] = float(v)
         d.flags = int(f.flags if flags is None else flags)
+        if d.flags & CELESTE_COLOR_MIXTURE:
+            for name in ("color_mix_w", "color_mix_mean", "color_mix_cov"):
+                arr = getattr(d, name)
+                for k, v in enumerate(np.asarray(getattr(f, name), np.float64).reshape(-1)):
+                    arr[k] = float(v)
+        self.n_params = 43 if d.flags & CELESTE_COLOR_MIXTURE else 27
         self.desc = d
         h = C.c_void_p()
         check(L.celeste_plan_create(C.byref(d), C.byref(h)), "celeste_plan_create")
@@ -242,7 +252,7 @@ class Plan:
     def _theta(self, theta):
         import torch
         assert theta.dtype == torch.float64 and theta.is_cuda and theta.is_contiguous()
-        assert theta.shape == (self.S, 32)
+        assert theta.shape == (self.S, ROW)
         return theta
 
     def info(self):
@@ -263,7 +273,7 @@ class Plan:
         import torch
         self._theta(theta)
         elbo = torch.zeros(self.S, dtype=torch.float64, device=theta.device) if elbo is None else elbo
-        grad = torch.zeros(self.S, 32, dtype=torch.float64, device=theta.device) if grad is None else grad
+        grad = torch.zeros(self.S, ROW, dtype=torch.float64, device=theta.device) if grad is None else grad
         check(lib().celeste_elbo_grad(self.h, _ptr(theta), _ptr(active), mode, _ptr(elbo), _ptr(grad),
                                       _stream()), "celeste_elbo_grad")
         self._status("celeste_elbo_grad")
@@ -275,7 +285,7 @@ class Plan:
         import torch
         self._theta(theta)
         elbo = torch.zeros(self.S, dtype=torch.float64, device=theta.device) if elbo is None else elbo
-        grad = torch.zeros(self.S, 32, dtype=torch.float64, device=theta.device) if grad is None else grad
+        grad = torch.zeros(self.S, ROW, dtype=torch.float64, device=theta.device) if grad is None else grad
         check(lib().celeste_elbo_grad_noalloc(self.h, _ptr(theta), _ptr(active), _ptr(elbo), _ptr(grad),
                                               _stream()), "celeste_elbo_grad_noalloc")
         self._status("celeste_elbo_grad_noalloc")
@@ -284,8 +294,8 @@ class Plan:
     def hvp(self, theta, v, with_grad=False):
         import torch
         self._theta(theta)
-        hv = torch.zeros(self.S, 32, dtype=torch.float64, device=theta.device)
-        g = torch.zeros(self.S, 32, dtype=torch.float64, device=theta.device) if with_grad else None
+        hv = torch.zeros(self.S, ROW, dtype=torch.float64, device=theta.device)
+        g = torch.zeros(self.S, ROW, dtype=torch.float64, device=theta.device) if with_grad else None
         check(lib().celeste_hvp(self.h, _ptr(theta), _ptr(v.contiguous()), _ptr(hv), _ptr(g), _stream()),
               "celeste_hvp")
         self._status("celeste_hvp")
@@ -295,7 +305,7 @@ class Plan:
         import torch
         self._theta(theta)
         src = np.ascontiguousarray(src, np.int32)
-        H = torch.zeros(len(src), 27, 27, dtype=torch.float64, device=theta.device)
+        H = torch.zeros(len(src), self.n_params, self.n_params, dtype=torch.float64, device=theta.device)
         check(lib().celeste_hessian(self.h, _ptr(theta), src.ctypes.data_as(C.POINTER(C.c_int32)), len(src),
                                     _ptr(H), _stream()), "celeste_hessian")
         self._status("celeste_hessian")

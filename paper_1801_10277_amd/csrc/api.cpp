@@ -101,9 +101,10 @@ struct celeste_plan {
     double* d_tile_sums = nullptr;
     double* d_pair_lgamma = nullptr;
     int* d_status = nullptr;
+    double* d_mix = nullptr;     // [2][NMIX][MIXF] colour-prior mixture table, or null
     int* d_counter = nullptr;
     double* d_grad = nullptr;
-    double* d_hess = nullptr;
+    double* d_hess = nullptr;        // [S][npar][npar]
     double* d_grad_trial = nullptr;  // gradient and Hessian at the Newton trial points
     double* d_hess_trial = nullptr;
     uint8_t* d_accepted = nullptr;
@@ -338,10 +339,71 @@ int validate_sky_maps(const celeste_problem_desc* d) {
     return CELESTE_OK;
 }
 
+// Colour-prior mixture table [2][NMIX][MIXF] (weight, log weight, mean, precision, log det)
+// from the problem description: every weight positive and each type's summing to 1 within
+// 1e-9, finite means, covariances symmetric and positive definite (a Cholesky factor with
+// positive pivots, whose columns give the precision).  CELESTE_EINVAL otherwise.
+int mixture_table(const celeste_problem_desc* d, double* tab) {
+    for (int t = 0; t < 2; ++t) {
+        double wsum = 0.0;
+        for (int c = 0; c < NMIX; ++c) {
+            const double w = d->color_mix_w[t][c];
+            if (!(w > 0.0) || !finite(w)) return CELESTE_EINVAL;
+            wsum += w;
+            double* e = tab + (t * NMIX + c) * MIXF;
+            for (int f = 0; f < MIXF; ++f) e[f] = 0.0;
+            e[MX_W] = w;
+            e[MX_LOGW] = std::log(w);
+            const double(&S)[4][4] = d->color_mix_cov[t][c];
+            for (int k = 0; k < 4; ++k) {
+                if (!finite(d->color_mix_mean[t][c][k])) return CELESTE_EINVAL;
+                e[MX_MEAN + k] = d->color_mix_mean[t][c][k];
+                for (int l = 0; l < 4; ++l) {
+                    if (!finite(S[k][l])) return CELESTE_EINVAL;
+                    if (std::fabs(S[k][l] - S[l][k]) > 1e-12 * (std::fabs(S[k][l]) + std::fabs(S[l][k])))
+                        return CELESTE_EINVAL;
+                }
+            }
+            double L[4][4] = {};
+            double logdet = 0.0;
+            for (int j = 0; j < 4; ++j) {
+                double v = S[j][j];
+                for (int k = 0; k < j; ++k) v -= L[j][k] * L[j][k];
+                if (!(v > 0.0)) return CELESTE_EINVAL;
+                L[j][j] = std::sqrt(v);
+                logdet += 2.0 * std::log(L[j][j]);
+                for (int i = j + 1; i < 4; ++i) {
+                    double u = S[i][j];
+                    for (int k = 0; k < j; ++k) u -= L[i][k] * L[j][k];
+                    L[i][j] = u / L[j][j];
+                }
+            }
+            for (int col = 0; col < 4; ++col) {   // S^-1 e_col = L^-T L^-1 e_col
+                double y[4], x[4];
+                for (int i = 0; i < 4; ++i) {
+                    double u = i == col ? 1.0 : 0.0;
+                    for (int k = 0; k < i; ++k) u -= L[i][k] * y[k];
+                    y[i] = u / L[i][i];
+                }
+                for (int i = 3; i >= 0; --i) {
+                    double u = y[i];
+                    for (int k = i + 1; k < 4; ++k) u -= L[k][i] * x[k];
+                    x[i] = u / L[i][i];
+                }
+                for (int i = 0; i < 4; ++i) e[MX_P + 4 * i + col] = x[i];
+            }
+            e[MX_LOGDET] = logdet;
+        }
+        if (!(std::fabs(wsum - 1.0) <= 1e-9)) return CELESTE_EINVAL;
+    }
+    return CELESTE_OK;
+}
+
 int validate_desc(const celeste_problem_desc* d) {
     if (!d || d->n_img <= 0 || d->n_src <= 0 || !d->images || !d->x || !d->patch_ptr || d->n_pix <= 0)
         return CELESTE_EINVAL;
-    if (d->flags & ~(uint32_t)(CELESTE_INCLUDE_KL | CELESTE_INCLUDE_LGAMMA)) return CELESTE_EINVAL;
+    if (d->flags & ~(uint32_t)(CELESTE_INCLUDE_KL | CELESTE_INCLUDE_LGAMMA | CELESTE_COLOR_MIXTURE))
+        return CELESTE_EINVAL;
     for (int n = 0; n < d->n_img; ++n) {
         const celeste_image& im = d->images[n];
         if (im.band < 0 || im.band > 4 || im.H <= 0 || im.W <= 0 || im.pix_offset < 0) return CELESTE_EINVAL;
@@ -385,6 +447,10 @@ int validate_desc(const celeste_problem_desc* d) {
         if (!(d->exp_alpha[j] > 0.0) || !(d->exp_nu[j] > 0.0) || !finite(d->exp_nu[j])) return CELESTE_EINVAL;
     for (int j = 0; j < NDEV; ++j)
         if (!(d->dev_alpha[j] > 0.0) || !(d->dev_nu[j] > 0.0) || !finite(d->dev_nu[j])) return CELESTE_EINVAL;
+    if (d->flags & CELESTE_COLOR_MIXTURE) {
+        double tab[2 * NMIX * MIXF];
+        if (mixture_table(d, tab) != CELESTE_OK) return CELESTE_EINVAL;
+    }
     if (!(d->prior_phi > 0.0 && d->prior_phi < 1.0)) return CELESTE_EINVAL;
     for (int t = 0; t < 2; ++t) {
         if (!finite(d->prior_r[t][0]) || !(d->prior_r[t][1] > 0.0)) return CELESTE_EINVAL;
@@ -592,7 +658,7 @@ int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& 
 
 int validate_theta(celeste_plan* p, const double* theta, const uint8_t* active, const int32_t* d_list, int n,
                    hipStream_t st) {
-    HIPCHK(launch_validate(theta, active, d_list, n, p->n_src, p->d_status, st));
+    HIPCHK(launch_validate(theta, active, d_list, n, p->n_src, p->consts.npar, p->d_status, st));
     return CELESTE_OK;
 }
 
@@ -752,6 +818,7 @@ int newton_run(celeste_plan* p, double* theta, const Sel& src, const Sel& pair, 
     tr.eta_accept = prm->eta_accept;
     tr.radius_max = prm->radius_max;
     tr.gtol = prm->gtol;
+    tr.npar = p->consts.npar;
     tr.status = p->d_status;
     if (n_steps <= 0) return CELESTE_OK;
     // value, gradient and Hessian at the entry point
@@ -839,7 +906,8 @@ void celeste_plan_destroy(celeste_plan* p) {
                     p->d_tile_sums, p->d_status, p->d_counter, p->d_grad, p->d_hess, p->d_theta_trial,
                     p->d_pred, p->d_elbo_cur, p->d_elbo_trial, p->d_radius, p->d_done, p->d_list_src,
                     p->d_list_pair, p->d_list_item, p->d_cls_items, p->d_pair_lgamma, p->d_fg, p->d_gw,
-                    p->d_hw, p->d_kk, p->d_hg, p->d_hc, p->d_grad_trial, p->d_hess_trial, p->d_accepted, p->d_live};
+                    p->d_hw, p->d_kk, p->d_hg, p->d_hc, p->d_grad_trial, p->d_hess_trial, p->d_accepted, p->d_live,
+                    p->d_mix};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -881,6 +949,8 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     std::memcpy(p->consts.prior_r, d->prior_r, sizeof(d->prior_r));
     std::memcpy(p->consts.prior_c, d->prior_c, sizeof(d->prior_c));
     p->consts.flags = d->flags;
+    p->consts.npar = (d->flags & CELESTE_COLOR_MIXTURE) ? NPK : NP;
+    p->consts.mix = nullptr;
     const int nb = d->patch_ptr[d->n_src];
     p->pairs.resize(nb);
     int64_t voff = 0;
@@ -939,9 +1009,9 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     A(dalloc(&p->d_counter, 1, W));
     const size_t S = (size_t)p->n_src;
     A(dalloc(&p->d_grad, S * ROW, W));
-    A(dalloc(&p->d_hess, S * NP * NP, W));
+    A(dalloc(&p->d_hess, S * NPK * NPK, W));
     A(dalloc(&p->d_grad_trial, S * ROW, W));
-    A(dalloc(&p->d_hess_trial, S * NP * NP, W));
+    A(dalloc(&p->d_hess_trial, S * NPK * NPK, W));
     A(dalloc(&p->d_accepted, S, W));
     A(dalloc(&p->d_live, S, W));
     A(dalloc(&p->d_gw, np * NACC, W));
@@ -956,12 +1026,20 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     A(dalloc(&p->d_list_pair, np, W));
     A(dalloc(&p->d_list_item, max_items, W));
     A(dalloc(&p->d_cls_items, max_items, W));
+    if (d->flags & CELESTE_COLOR_MIXTURE) A(dalloc(&p->d_mix, 2 * NMIX * MIXF, W));
     p->cap_list_item = max_items;
     if (r != CELESTE_OK) {
         celeste_plan_destroy(p);
         return r;
     }
     int rc = upload_geometry(p);
+    if (rc == CELESTE_OK && p->d_mix) {
+        double tab[2 * NMIX * MIXF];
+        mixture_table(d, tab);
+        if (hipMemcpy(p->d_mix, tab, sizeof(tab), hipMemcpyHostToDevice) != hipSuccess)
+            rc = hip_fail(hipGetLastError(), "mixture table upload");
+        p->consts.mix = p->d_mix;
+    }
     if (rc == CELESTE_OK) {
         if (hipMemcpy(p->d_images, p->images.data(), p->images.size() * sizeof(celeste_image),
                       hipMemcpyHostToDevice) != hipSuccess ||
@@ -1002,6 +1080,7 @@ int celeste_plan_get_info(const celeste_plan* p, celeste_plan_info* info) {
     info->strip_rows = p->rows;
     info->render_mode = p->render_mode;
     info->n_classes = p->n_class;
+    info->n_params = p->consts.npar;
     info->workspace_bytes = (int64_t)p->workspace;
     return CELESTE_OK;
 }
@@ -1178,7 +1257,8 @@ int celeste_hessian(celeste_plan* p, const double* theta, const int32_t* src, in
     }
     CHK(adjoint(p, si, nullptr, false, BASE_BG, true, st, 0, true));
     CHK(hessian_from_intermediates(p, theta, ss, sp, si, BASE_BG, p->d_hess, st));
-    HIPCHK(hipMemcpyAsync(hess, p->d_hess, (size_t)n * NP * NP * sizeof(double), hipMemcpyDeviceToDevice, st));
+    const size_t np2 = (size_t)p->consts.npar * p->consts.npar;
+    HIPCHK(hipMemcpyAsync(hess, p->d_hess, (size_t)n * np2 * sizeof(double), hipMemcpyDeviceToDevice, st));
     return CELESTE_OK;
 }
 

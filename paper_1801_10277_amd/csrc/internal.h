@@ -14,8 +14,11 @@ constexpr int NEXP = 6;
 constexpr int NGAL_PER_PSF = NDEV + NEXP;                 // 14
 constexpr int NCOMP = NPSF * (1 + NGAL_PER_PSF);           // 45 Gaussians per (source, image)
 constexpr int CST = 10;                                    // fields per component entry
-constexpr int NP = 27;                                     // parameters per source
-constexpr int ROW = 32;                                    // padded row of theta / grad
+constexpr int NP = 27;                                     // parameters the pixel terms depend on
+constexpr int NMIX = 8;                                    // components of a type's colour-prior mixture
+constexpr int NPK = NP + 2 * NMIX;                         // parameters with the mixture responsibilities
+constexpr int ROW = 48;                                    // padded row of theta / grad
+constexpr int MIXF = 24;                                   // fields of one colour-prior mixture component
 constexpr int NCOEF = 4;                                   // per-(source, image) brightness factors
 
 // Fields of one component entry of a (source, image) table.  For the Gaussian
@@ -101,11 +104,16 @@ struct TileDev {              // a tile_h x tile_w render tile and its box list
     int32_t img, r0, c0, list_begin, list_end, pad;
 };
 
+// One component of a type's colour-prior mixture, [2][NMIX][MIXF] in device memory: weight,
+// its log, mean[4], precision P = S^-1 (row-major 4 x 4), log det S, padding.
+enum MixField { MX_W = 0, MX_LOGW, MX_MEAN, MX_P = MX_MEAN + 4, MX_LOGDET = MX_P + 16 };
+
 struct Consts {
     double exp_alpha[NEXP], exp_nu[NEXP], dev_alpha[NDEV], dev_nu[NDEV];
     double prior_phi, prior_r[2][2], prior_c[2][2][4];
+    const double* mix;         // colour-prior mixture table (CELESTE_COLOR_MIXTURE), or null
     uint32_t flags;
-    int32_t pad;
+    int32_t npar;              // parameters per source: NP, or NPK with the mixture
 };
 
 // A subset of sources / boxes / items: entry j is ids[j] if ids is set, else base + j.
@@ -213,7 +221,7 @@ struct FinArgs {
 
 // Kernel launchers (kernels.hip)
 hipError_t launch_validate(const double* theta, const uint8_t* active, const int32_t* list, int n,
-                           int S, int* status, hipStream_t st);
+                           int S, int npar, int* status, hipStream_t st);
 hipError_t launch_prep(const PrepArgs& a, bool tangent, hipStream_t st);
 hipError_t launch_render(const RenderArgs& a, int waves_per_block, hipStream_t st);
 // strips.hip
@@ -285,6 +293,7 @@ struct TrArgs {
     uint8_t* done;             // [S]
     uint8_t* live;             // [S] set by tr_solve: the source takes a step this iteration
     double eta_accept, radius_max, gtol;
+    int32_t npar;              // NP, or NPK with the colour-prior mixture (Hessian rows and columns)
     int* status;
 };
 hipError_t launch_tr_solve(const TrArgs& a, hipStream_t st);

@@ -24,14 +24,29 @@ namespace cel {
 
 // ----------------------------------------------------------------------- validation
 // Domain of a source row: finite; q in (0,1); frac_dev in [0,1]; axis ratio in (0,1];
-// radius > 0; variances > 0.  Branch-free so that the row's loads issue together.
-__device__ inline bool row_ok(const double* __restrict__ p) {
+// radius > 0; variances > 0; with the colour-prior mixture (npar = NPK) every
+// responsibility positive and each type's eight summing to 1 within 1e-9.  Branch-free so
+// that the row's loads issue together.
+__device__ inline bool row_ok(const double* __restrict__ p, int npar) {
     double v[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) v[i] = p[i];
     bool ok = true;
 #pragma unroll
     for (int i = 0; i < NP; ++i) ok &= (bool)isfinite(v[i]);
+    if (npar == NPK) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            double sum = 0.0;
+#pragma unroll
+            for (int d = 0; d < NMIX; ++d) {
+                const double k = p[NP + NMIX * t + d];
+                ok &= k > 0.0 && k <= 1.0;
+                sum += k;
+            }
+            ok &= fabs(sum - 1.0) <= 1e-9;
+        }
+    }
     ok &= v[6] > 0.0 && v[6] < 1.0;
     ok &= v[2] >= 0.0 && v[2] <= 1.0;
     ok &= v[3] > 0.0 && v[3] <= 1.0;
@@ -48,14 +63,14 @@ __device__ inline bool row_ok(const double* __restrict__ p) {
 
 // One thread per listed source; the status word was cleared by the launcher's fill.
 __global__ void __launch_bounds__(256) k_validate(const double* __restrict__ theta, const uint8_t* active,
-                                                  const int32_t* list, int n, int S, int* status) {
+                                                  const int32_t* list, int n, int S, int npar, int* status) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const int s = list ? list[j] : j;
     bool bad;
     if (s < 0 || s >= S) bad = true;
     else if (active && !active[s]) bad = false;
-    else bad = !row_ok(theta + (size_t)s * ROW);
+    else bad = !row_ok(theta + (size_t)s * ROW, npar);
     if (bad) atomicOr(status, CELESTE_EDOMAIN);
 }
 
@@ -192,11 +207,11 @@ __global__ void __launch_bounds__(64) k_finalize(FinArgs a) {
     if (j >= a.srcs.n) return;
     const int s = sel_at(a.srcs, j);
     if (a.active && !a.active[s]) return;
-    T p[NP];
-    for (int i = 0; i < NP; ++i) p[i] = seed<T>(a.theta, a.dir, a.dir_mode, a.dir_unit, s, i);
+    T p[NPK];
+    for (int i = 0; i < NPK; ++i) p[i] = seed<T>(a.theta, a.dir, a.dir_mode, a.dir_unit, s, i);
     const T zero = scalar_traits<T>::make(0.0, 0.0);
-    T g[NP];
-    for (int i = 0; i < NP; ++i) g[i] = zero;
+    T g[NPK];
+    for (int i = 0; i < NPK; ++i) g[i] = zero;
     T val = zero;
     const T* part = reinterpret_cast<const T*>(a.partials);
     // lane l takes the source's boxes l, l + 64, ...; each box's items in order
@@ -223,24 +238,24 @@ __global__ void __launch_bounds__(64) k_finalize(FinArgs a) {
         for (int i = 0; i < NP; ++i) g[i] = wave_sum(g[i]);
     }
     if (a.g.consts.flags & CELESTE_INCLUDE_KL) {
-        T gk[NP];
-        for (int i = 0; i < NP; ++i) gk[i] = zero;
+        T gk[NPK];
+        for (int i = 0; i < NPK; ++i) gk[i] = zero;
         val -= kl_source<T>(p, a.g.consts, gk);
         if (a.deriv)
-            for (int i = 0; i < NP; ++i) g[i] += gk[i];
+            for (int i = 0; i < NPK; ++i) g[i] += gk[i];
     }
     if (lane != 0) return;
     if (a.elbo) a.elbo[s] = value_of(val);
     if (a.deriv && a.grad) {
         double* o = a.grad + (size_t)s * ROW;
-        for (int i = 0; i < NP; ++i) o[i] = value_of(g[i]);
-        for (int i = NP; i < ROW; ++i) o[i] = 0.0;
+        for (int i = 0; i < NPK; ++i) o[i] = value_of(g[i]);
+        for (int i = NPK; i < ROW; ++i) o[i] = 0.0;
     }
     if (a.deriv && a.tangent) {
         double* o = a.tangent + (size_t)(a.tangent_by_list ? j : s) * a.tangent_stride;
-        for (int i = 0; i < NP; ++i) o[i] = tangent_of(g[i]);
+        for (int i = 0; i < NPK; ++i) o[i] = tangent_of(g[i]);
         if (a.tangent_pad)
-            for (int i = NP; i < ROW; ++i) o[i] = 0.0;
+            for (int i = NPK; i < ROW; ++i) o[i] = 0.0;
     }
 }
 
@@ -331,19 +346,21 @@ __global__ void __launch_bounds__(128) k_pair_hess(Sel sel, const PairDev* __res
 
 // Hessian of ELBO_s: column d is the tangent, along parameter d, of the chain rule
 // J^T z applied to the pair gradients z (value gw, tangent hw * (dw / dtheta_d)), plus the
-// KL term.  One thread per (listed source, direction).
+// KL term.  One thread per (listed source, direction); npar (NP, or NPK with the colour-prior
+// mixture, whose responsibilities enter the KL only) rows and columns per source.
 __global__ void __launch_bounds__(128) k_assemble_hessian(Sel srcs, Geometry g, const int32_t* __restrict__ patch_ptr,
                                                           const double* __restrict__ theta,
                                                           const double* __restrict__ gw,
                                                           const double* __restrict__ hw,
                                                           double* __restrict__ hess, const int* status) {
     if (*status) return;
+    const int npar = g.consts.npar;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= srcs.n * NP) return;
-    const int j = t / NP, d = t - j * NP;
+    if (t >= srcs.n * npar) return;
+    const int j = t / npar, d = t - j * npar;
     const int s = sel_at(srcs, j);
-    dual p[NP], gh[NP];
-    for (int i = 0; i < NP; ++i) {
+    dual p[NPK], gh[NPK];
+    for (int i = 0; i < NPK; ++i) {
         p[i] = mkd(theta[(size_t)s * ROW + i], i == d ? 1.0 : 0.0);
         gh[i] = mkd(0.0, 0.0);
     }
@@ -372,8 +389,8 @@ __global__ void __launch_bounds__(128) k_assemble_hessian(Sel srcs, Geometry g, 
         chain_pair<dual>(p, im, z, gh);
     }
     if (g.consts.flags & CELESTE_INCLUDE_KL) kl_source<dual>(p, g.consts, gh);
-    double* o = hess + (size_t)j * NP * NP + (size_t)d * NP;
-    for (int i = 0; i < NP; ++i) o[i] = gh[i].t;
+    double* o = hess + (size_t)j * npar * npar + (size_t)d * npar;
+    for (int i = 0; i < npar; ++i) o[i] = gh[i].t;
 }
 
 // Total ELBO: fixed-order sum of the per-tile pixel sums minus every source's KL, by one
@@ -388,8 +405,8 @@ __global__ void __launch_bounds__(TT_THREADS) k_tile_total(const double* tile_su
     for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) acc += tile_sums[t];
     if (K.flags & CELESTE_INCLUDE_KL) {
         for (int s = threadIdx.x; s < S; s += blockDim.x) {
-            double p[NP], g[NP];
-            for (int i = 0; i < NP; ++i) { p[i] = theta[(size_t)s * ROW + i]; g[i] = 0.0; }
+            double p[NPK], g[NPK];
+            for (int i = 0; i < NPK; ++i) { p[i] = theta[(size_t)s * ROW + i]; g[i] = 0.0; }
             acc -= kl_source<double>(p, K, g);
         }
     }
@@ -419,10 +436,11 @@ __global__ void k_fill_f64_sel(double* p, Sel s, double v) {
 
 // ----------------------------------------------------------------------- launchers
 hipError_t launch_validate(const double* theta, const uint8_t* active, const int32_t* list, int n,
-                           int S, int* status, hipStream_t st) {
+                           int S, int npar, int* status, hipStream_t st) {
     const hipError_t e = launch_fill_int(status, 0, 1, st);
     if (e != hipSuccess || n <= 0) return e;
-    hipLaunchKernelGGL(k_validate, dim3((n + 255) / 256), dim3(256), 0, st, theta, active, list, n, S, status);
+    hipLaunchKernelGGL(k_validate, dim3((n + 255) / 256), dim3(256), 0, st, theta, active, list, n, S, npar,
+                       status);
     return hipGetLastError();
 }
 
@@ -493,7 +511,7 @@ hipError_t launch_assemble_hessian(const Sel& srcs, const Geometry& g, const int
                                    const double* gw, const double* hw, double* hess, const int* status,
                                    hipStream_t st) {
     if (srcs.n <= 0) return hipSuccess;
-    const int n = srcs.n * NP;
+    const int n = srcs.n * g.consts.npar;
     hipLaunchKernelGGL(k_assemble_hessian, dim3((n + 127) / 128), dim3(128), 0, st, srcs, g, patch_ptr, theta, gw,
                        hw, hess, status);
     return hipGetLastError();

@@ -306,7 +306,13 @@ __device__ inline T kl_normal(T m, T v, double m0, double v0) {
     return 0.5 * (log(v0) - log(v) + (v + d * d) / v0 - 1.0);
 }
 
-// KL(q || prior) of one source; subtracts its gradient from g.
+// KL(q || prior) of one source; subtracts its gradient from g.  p and g hold NPK entries
+// (the mixture responsibilities at NP..NPK-1 are read only with the colour-prior mixture).
+// With the mixture (K.mix set), a type's colour term is KL(Cat(kappa) || Cat(w)) +
+// sum_d kappa_d KL(N(c_mu, diag c_var) || N(mu_d, S_d)), where the Gaussian KL is
+// (sum_k P_kk v_k + delta^T P delta - 4 + log det S - sum_k log v_k) / 2, delta = c_mu - mu_d,
+// P = S_d^-1; its derivatives: in kappa_d, log(kappa_d / w_d) + 1 + KL_d; in c_mu,
+// sum_d kappa_d P_d delta_d; in c_var_k, sum_d kappa_d (P_d,kk - 1 / v_k) / 2.
 template <class T>
 __device__ inline T kl_source(const T* p, const Consts& K, T* g) {
     const T q = p[6];
@@ -322,12 +328,53 @@ __device__ inline T kl_source(const T* p, const Consts& K, T* g) {
         T kt = kl_normal(p[base], p[base + 1], m0, v0);
         g[base] -= w * ((p[base] - m0) / v0);
         g[base + 1] -= w * (0.5 * (1.0 / v0 - 1.0 / p[base + 1]));
+        if (K.mix) {
+            const T zero = scalar_traits<T>::make(0.0, 0.0);
+            T gm[4] = {zero, zero, zero, zero}, gv[4] = {zero, zero, zero, zero}, ksum = zero;
+            T logv = zero;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const double cm = K.prior_c[t][0][k], cv = K.prior_c[t][1][k];
-            kt += kl_normal(p[base + 2 + k], p[base + 6 + k], cm, cv);
-            g[base + 2 + k] -= w * ((p[base + 2 + k] - cm) / cv);
-            g[base + 6 + k] -= w * (0.5 * (1.0 / cv - 1.0 / p[base + 6 + k]));
+            for (int k = 0; k < 4; ++k) logv += log(p[base + 6 + k]);
+            for (int d = 0; d < NMIX; ++d) {
+                const double* m = K.mix + (size_t)(t * NMIX + d) * MIXF;
+                const T kd = p[NP + NMIX * t + d];
+                T dl[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dl[k] = p[base + 2 + k] - m[MX_MEAN + k];
+                T quad = zero, tr = zero;
+                T Pd[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    T r = zero;
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) r += m[MX_P + 4 * k + l] * dl[l];
+                    Pd[k] = r;
+                    quad += dl[k] * r;
+                    tr += m[MX_P + 5 * k] * p[base + 6 + k];
+                }
+                const T kln = 0.5 * (tr + quad + (m[MX_LOGDET] - 4.0) - logv);
+                const T lk = log(kd) - m[MX_LOGW];
+                kt += kd * (lk + kln);
+                g[NP + NMIX * t + d] -= w * (lk + 1.0 + kln);
+                ksum += kd;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    gm[k] += kd * Pd[k];
+                    gv[k] += kd * m[MX_P + 5 * k];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                g[base + 2 + k] -= w * gm[k];
+                g[base + 6 + k] -= w * (0.5 * (gv[k] - ksum / p[base + 6 + k]));
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double cm = K.prior_c[t][0][k], cv = K.prior_c[t][1][k];
+                kt += kl_normal(p[base + 2 + k], p[base + 6 + k], cm, cv);
+                g[base + 2 + k] -= w * ((p[base + 2 + k] - cm) / cv);
+                g[base + 6 + k] -= w * (0.5 * (1.0 / cv - 1.0 / p[base + 6 + k]));
+            }
         }
         kl += w * kt;
         dq += (t == 0) ? kt : -kt;

@@ -2,9 +2,12 @@
 // with exact Hessians and a trust region; the paper solves the trust-region subproblem
 // through an eigendecomposition, Section VI-B).  One wave per source:
 //  1. map gradient and Hessian to unconstrained coordinates (logit of q, frac_dev and
-//     axis ratio; log of radius and of every variance; identity otherwise);
-//  2. Householder reduction of the 27x27 model Hessian to tridiagonal form T = Q^T B Q in
-//     LDS, the lanes owning the rows of the reflections;
+//     axis ratio; log of radius and of every variance; identity otherwise; with the
+//     colour-prior mixture, each type's 8 responsibilities through a softmax whose last
+//     logit is fixed at 0, so 27 + 2 x 7 = 41 coordinates: B = J^T (-H) J - sum_i g_i
+//     d2 theta_i / d eta^2 with the Jacobian J of theta(eta));
+//  2. Householder reduction of the model Hessian (27 x 27, or 41 x 41) to tridiagonal
+//     form T = Q^T B Q in LDS, the lanes owning the rows of the reflections;
 //  3. exact subproblem  min g'p + p'Bp/2, |p| <= radius  on T (More and Sorensen's
 //     method; Nocedal & Wright, Alg. 4.3): positive pivots of T's factorisation at mu = 0
 //     make T positive definite and allow the interior Newton step; otherwise the smallest
@@ -25,8 +28,7 @@
 
 namespace cel {
 
-constexpr int LD = 28;   // padded LDS row
-constexpr int NJ = 28;   // rows of the LDS matrices (27 parameters, padded)
+constexpr int NEM = NP + 2 * (NMIX - 1);   // unconstrained coordinates with the mixture: 41
 constexpr int QL_MAX_ITER = 60;   // QL iterations per eigenvalue before giving up
 constexpr double EPS_D = 2.220446049250313e-16;   // 2^-52
 
@@ -86,7 +88,35 @@ __device__ inline double from_unconstrained(int i, double eta) {
     return eta;
 }
 
+// Trial row theta(eta + p) from the unconstrained coordinates and the step (LDS), one lane per
+// entry of the row: the 27 model parameters through their own maps; with the mixture, each
+// type's responsibilities through the softmax of its 7 coordinates and a fixed 0 (shifted by
+// their maximum so that no exponential overflows); zero padding.
+template <int M>
+__device__ inline void write_trial(int t, const double* eta, const double* p, double* trial) {
+    if (t < NP) {
+        trial[t] = from_unconstrained(t, eta[t] + p[t]);
+    } else if (M != NP && t < NPK) {
+        const int ty = (t - NP) / NMIX, d = (t - NP) % NMIX;
+        const int c0 = NP + (NMIX - 1) * ty;
+        double mx = 0.0;
+        for (int e = 0; e < NMIX - 1; ++e) mx = fmax(mx, eta[c0 + e] + p[c0 + e]);
+        double z = exp(-mx);
+        for (int e = 0; e < NMIX - 1; ++e) z += exp(eta[c0 + e] + p[c0 + e] - mx);
+        const double num = d < NMIX - 1 ? exp(eta[c0 + d] + p[c0 + d] - mx) : exp(-mx);
+        trial[t] = num / z;
+    } else if (t < ROW) {
+        trial[t] = 0.0;
+    }
+}
+
+// M = NP (27 parameters) or NEM (43 parameters with the colour-prior mixture, 41
+// unconstrained coordinates); NT parameters in theta, gradient and Hessian.
+template <int M>
 __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
+    constexpr int NT = M == NP ? NP : NPK;
+    constexpr int NJ = M == NP ? 28 : 44;   // rows of the LDS matrices (M, padded)
+    constexpr int LD = M == NP ? 28 : 45;   // padded LDS row
     if (*a.status) return;
     const int j = blockIdx.x;
     const int s = sel_at(a.srcs, j);
@@ -94,12 +124,12 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
     __shared__ double B[NJ][LD];
     __shared__ double Q[NJ][LD];
     __shared__ double vs[NJ], ws[NJ], dd[NJ], ee[NJ];
-    __shared__ double gm[NP], eta[NP], d1[NP], lam[NP], gh[NP], ph[NP], pv[NP];
+    __shared__ double gm[NJ], eta[NJ], d1[NJ], lam[NJ], gh[NJ], ph[NJ], pv[NJ];
     __shared__ double sh_red[64];
     __shared__ int sh_done;
     const double* th = a.theta + (size_t)s * ROW;
     const double* gr = a.grad + (size_t)s * ROW;
-    const double* H = a.hess + (size_t)j * NP * NP;
+    const double* H = a.hess + (size_t)j * NT * NT;
     if (t < NP) {
         double e, p1, p2;
         to_unconstrained(t, th[t], e, p1, p2);
@@ -109,25 +139,110 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         gm[t] = -p1 * gr[t];
         lam[t] = p2 * gr[t];   // diagonal curvature term of the ELBO
     }
-    __syncthreads();
-    for (int idx = t; idx < NJ * NJ; idx += 64) {
-        const int r = idx / NJ, c = idx - r * NJ;
-        double b = 0.0;
-        if (r < NP && c < NP) {
-            const double hs = 0.5 * (H[r * NP + c] + H[c * NP + r]);
-            b = -d1[r] * hs * d1[c];
-            if (c == r) b -= lam[r];
+    if constexpr (M == NP) {
+        __syncthreads();
+        for (int idx = t; idx < NJ * NJ; idx += 64) {
+            const int r = idx / NJ, c = idx - r * NJ;
+            double b = 0.0;
+            if (r < NP && c < NP) {
+                const double hs = 0.5 * (H[r * NP + c] + H[c * NP + r]);
+                b = -d1[r] * hs * d1[c];
+                if (c == r) b -= lam[r];
+            }
+            B[r][c] = b;
+            Q[r][c] = (c == r) ? 1.0 : 0.0;
         }
-        B[r][c] = b;
-        Q[r][c] = (c == r) ? 1.0 : 0.0;
+    } else {
+        // softmax coordinates of the responsibilities: kappa_d = e^{eta_d} / (1 + sum_e e^{eta_e})
+        // (d < 7), kappa_7 = 1 / (1 + ...); J_de = kappa_d (delta_de - kappa_e);
+        // sum_d g_d d2 kappa_d / d eta_e d eta_f = delta_ef (gk_e - S kappa_e) - gk_e kappa_f
+        // - kappa_e gk_f + 2 S kappa_e kappa_f with gk_e = g_e kappa_e, S = sum_d g_d kappa_d
+        __shared__ double kap[2][NMIX], sk[2];
+        __shared__ double G[NPK][LD];   // symmetric H times J
+        if (t < 2 * NMIX) kap[t / NMIX][t % NMIX] = th[NP + t];
+        __syncthreads();
+        if (t < 2) {
+            double S = 0.0;
+            for (int d = 0; d < NMIX; ++d) S += gr[NP + NMIX * t + d] * kap[t][d];
+            sk[t] = S;
+        }
+        if (t >= NP && t < M) {
+            const int ty = (t - NP) / (NMIX - 1), e = (t - NP) % (NMIX - 1);
+            eta[t] = log(kap[ty][e]) - log(kap[ty][NMIX - 1]);
+        }
+        auto jac = [&](int k, int c) -> double {   // d theta_k / d eta_c
+            if (c < NP) return k == c ? d1[c] : 0.0;
+            if (k < NP) return 0.0;
+            const int ty = (c - NP) / (NMIX - 1), e = (c - NP) % (NMIX - 1);
+            const int tk = (k - NP) / NMIX, dk = (k - NP) % NMIX;
+            if (tk != ty) return 0.0;
+            return kap[ty][dk] * ((dk == e ? 1.0 : 0.0) - kap[ty][e]);
+        };
+        __syncthreads();
+        if (t >= NP && t < M) {
+            const int ty = (t - NP) / (NMIX - 1), e = (t - NP) % (NMIX - 1);
+            gm[t] = -kap[ty][e] * (gr[NP + NMIX * ty + e] - sk[ty]);
+        }
+        // G = Hs J, lane k owning row k
+        if (t < NT) {
+            for (int c = 0; c < M; ++c) {
+                double v = 0.0;
+                if (c < NP) {
+                    v = 0.5 * (H[t * NT + c] + H[c * NT + t]) * d1[c];
+                } else {
+                    const int ty = (c - NP) / (NMIX - 1);
+                    for (int d = 0; d < NMIX; ++d) {
+                        const int k2 = NP + NMIX * ty + d;
+                        v += 0.5 * (H[t * NT + k2] + H[k2 * NT + t]) * jac(k2, c);
+                    }
+                }
+                G[t][c] = v;
+            }
+        }
+        __syncthreads();
+        // B = -J^T G - curvature, lane r owning row r
+        for (int c = 0; c < NJ; ++c) {
+            double b = 0.0;
+            if (t < M && c < M) {
+                if (t < NP) {
+                    b = -d1[t] * G[t][c];
+                    if (c == t) b -= lam[t];
+                } else {
+                    const int ty = (t - NP) / (NMIX - 1), e = (t - NP) % (NMIX - 1);
+                    for (int d = 0; d < NMIX; ++d) b -= jac(NP + NMIX * ty + d, t) * G[NP + NMIX * ty + d][c];
+                    if (c >= NP && (c - NP) / (NMIX - 1) == ty) {
+                        const int f = (c - NP) % (NMIX - 1);
+                        const double ke = kap[ty][e], kf = kap[ty][f], S = sk[ty];
+                        const double ge = gr[NP + NMIX * ty + e] * ke, gf = gr[NP + NMIX * ty + f] * kf;
+                        double curv = -ge * kf - ke * gf + 2.0 * S * ke * kf;
+                        if (e == f) curv += ge - S * ke;
+                        b -= curv;
+                    }
+                }
+            }
+            if (t < NJ) {
+                B[t][c] = b;
+                Q[t][c] = (c == t) ? 1.0 : 0.0;
+            }
+        }
+        __syncthreads();
+        // symmetrise (the two halves differ by rounding only)
+        for (int idx = t; idx < M * M; idx += 64) {
+            const int r = idx / M, c = idx - r * M;
+            if (c > r) {
+                const double v = 0.5 * (B[r][c] + B[c][r]);
+                B[r][c] = v;
+                B[c][r] = v;
+            }
+        }
     }
     // stop test on the unconstrained gradient
-    double gmax = (t < NP) ? fabs(gm[t]) : 0.0;
+    double gmax = (t < M) ? fabs(gm[t]) : 0.0;
     sh_red[t] = gmax;
     __syncthreads();
     if (t == 0) {
         double m = 0.0;
-        for (int i = 0; i < NP; ++i) m = fmax(m, sh_red[i]);
+        for (int i = 0; i < M; ++i) m = fmax(m, sh_red[i]);
         sh_done = (a.done[s] || !(m >= a.gtol)) ? 1 : 0;
         if (!(m == m)) sh_done = 1;
         a.live[s] = sh_done ? 0 : 1;
@@ -135,7 +250,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
     __syncthreads();
     double* trial = a.theta_trial + (size_t)s * ROW;
     if (sh_done) {
-        if (t < ROW) trial[t] = (t < NP) ? th[t] : 0.0;
+        if (t < ROW) trial[t] = (t < NT) ? th[t] : 0.0;
         if (t == 0) {
             a.pred[2 * s] = 0.0;
             a.pred[2 * s + 1] = 0.0;
@@ -146,9 +261,9 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
     // ---- Householder reduction B = Q T Q^T, T tridiagonal: diagonal dd, ee[i] couples
     // rows i and i + 1.  Lane i owns row i; the reflector v (zero outside k+1..26) and
     // w = p - (v.p) beta/2 v with p = beta B v go through LDS.
-    for (int k = 0; k + 2 < NP; ++k) {
+    for (int k = 0; k + 2 < M; ++k) {
         const double x0 = B[k + 1][k];
-        const double ci = (t >= k + 2 && t < NP) ? B[t][k] : 0.0;
+        const double ci = (t >= k + 2 && t < M) ? B[t][k] : 0.0;
         const double sigma = wave_sum(ci * ci);
         const double dk = B[k][k];
         if (sigma == 0.0) {   // already tridiagonal in this column (uniform branch)
@@ -169,43 +284,43 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         // full-length loops (v and w vanish outside k+1..26), unrolled so that the LDS
         // reads of a loop are all in flight together
         double pi = 0.0;
-        if (t > k && t < NP) {
+        if (t > k && t < M) {
 #pragma unroll
-            for (int c = 0; c < NP; ++c) pi += B[t][c] * vs[c];
+            for (int c = 0; c < M; ++c) pi += B[t][c] * vs[c];
             pi *= beta;
         }
         const double K = 0.5 * beta * wave_sum(vi * pi);
         const double wi = pi - K * vi;
         if (t < NJ) ws[t] = wi;
         __syncthreads();
-        if (t > k && t < NP) {
+        if (t > k && t < M) {
 #pragma unroll
-            for (int c = 0; c < NP; ++c) B[t][c] -= vi * ws[c] + wi * vs[c];
+            for (int c = 0; c < M; ++c) B[t][c] -= vi * ws[c] + wi * vs[c];
         }
-        if (t < NP) {
+        if (t < M) {
             double q = 0.0;
 #pragma unroll
-            for (int c = 0; c < NP; ++c) q += Q[t][c] * vs[c];
+            for (int c = 0; c < M; ++c) q += Q[t][c] * vs[c];
             q *= beta;
 #pragma unroll
-            for (int c = 0; c < NP; ++c) Q[t][c] -= q * vs[c];
+            for (int c = 0; c < M; ++c) Q[t][c] -= q * vs[c];
         }
         __syncthreads();
     }
-    dd[NP - 2] = B[NP - 2][NP - 2];
-    dd[NP - 1] = B[NP - 1][NP - 1];
-    ee[NP - 2] = B[NP - 1][NP - 2];
-    ee[NP - 1] = 0.0;
+    dd[M - 2] = B[M - 2][M - 2];
+    dd[M - 1] = B[M - 1][M - 1];
+    ee[M - 2] = B[M - 1][M - 2];
+    ee[M - 1] = 0.0;
     __syncthreads();
     // ---- subproblem on the tridiagonal matrix T = Q^T B Q (Moré and Sorensen's method,
     // Nocedal & Wright, Alg. 4.3, with T's factorisations instead of B's): lane i keeps
     // d_i, e_i (e_i couples i and i + 1) and the i-th entries of the vectors; scalar
     // recurrences run in every lane alike on values read with a wave-uniform index.
-    double dv = (t < NP) ? dd[t] : 0.0, ev = (t < NP) ? ee[t] : 0.0;
+    double dv = (t < M) ? dd[t] : 0.0, ev = (t < M) ? ee[t] : 0.0;
     const double R = a.radius[s];
     double gtv = 0.0;   // Q^T g
-    if (t < NP)
-        for (int k = 0; k < NP; ++k) gtv += Q[k][t] * gm[k];
+    if (t < M)
+        for (int k = 0; k < M; ++k) gtv += Q[k][t] * gm[k];
     const double gn = sqrt(wave_sum(gtv * gtv));
     // smallest eigenvalue of T (needed when T is indefinite): Sturm counts at 64 points of
     // the bracket per round
@@ -213,9 +328,9 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         double lo_e, hi_e;
         {
             const double em1 = __shfl(ev, t > 0 ? t - 1 : 0, 64);
-            const double rad = (t < NP) ? fabs(t > 0 ? em1 : 0.0) + fabs(t < NP - 1 ? ev : 0.0) : 0.0;
-            lo_e = wave_min((t < NP) ? dv - rad : INFINITY);
-            hi_e = wave_max((t < NP) ? dv + rad : -INFINITY);
+            const double rad = (t < M) ? fabs(t > 0 ? em1 : 0.0) + fabs(t < M - 1 ? ev : 0.0) : 0.0;
+            lo_e = wave_min((t < M) ? dv - rad : INFINITY);
+            hi_e = wave_max((t < M) ? dv + rad : -INFINITY);
         }
         for (int round = 0; round < 40; ++round) {
             const double w = hi_e - lo_e;
@@ -225,7 +340,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
             double q = lane_get(dv, 0) - x;
             if (q == 0.0) q = -1e-300;
             cnt += q < 0.0;
-            for (int i = 1; i < NP; ++i) {
+            for (int i = 1; i < M; ++i) {
                 const double e1 = lane_get(ev, i - 1);
                 q = lane_get(dv, i) - x - e1 * e1 / q;
                 if (q == 0.0) q = -1e-300;
@@ -248,12 +363,12 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         double cprev = 0.0;
         bool pos = true;
 #pragma unroll
-        for (int i = 0; i < NP; ++i) {
+        for (int i = 0; i < M; ++i) {
             const double em1 = i > 0 ? lane_get(ev, i - 1) : 0.0;
             const double den = lane_get(dv, i) + mu - em1 * cprev;
             pos = pos && den > 0.0;
             const double inv = 1.0 / den;
-            cprev = i < NP - 1 ? lane_get(ev, i) * inv : 0.0;
+            cprev = i < M - 1 ? lane_get(ev, i) * inv : 0.0;
             cpv = t == i ? cprev : cpv;
             idv = t == i ? inv : idv;
         }
@@ -262,14 +377,14 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
     auto subst = [&](double rhs) {
         double rprev = 0.0, rpv = 0.0;
 #pragma unroll
-        for (int i = 0; i < NP; ++i) {
+        for (int i = 0; i < M; ++i) {
             const double em1 = i > 0 ? lane_get(ev, i - 1) : 0.0;
             rprev = (lane_get(rhs, i) - em1 * rprev) * lane_get(idv, i);
             rpv = t == i ? rprev : rpv;
         }
-        double ynext = rprev, yv = t == NP - 1 ? rprev : 0.0;
+        double ynext = rprev, yv = t == M - 1 ? rprev : 0.0;
 #pragma unroll
-        for (int i = NP - 2; i >= 0; --i) {
+        for (int i = M - 2; i >= 0; --i) {
             ynext = lane_get(rpv, i) - lane_get(cpv, i) * ynext;
             yv = t == i ? ynext : yv;
         }
@@ -291,7 +406,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         if (lo0 > 0.0) {
             // nearly the hard case (g almost orthogonal to the lowest eigenvector) goes to
             // the eigenbasis below
-            const double scale = fmax(fabs(lmin_t), wave_max((t < NP) ? fabs(dv) + 2.0 * fabs(ev) : 0.0));
+            const double scale = fmax(fabs(lmin_t), wave_max((t < M) ? fabs(dv) + 2.0 * fabs(ev) : 0.0));
             factor(lo0 + 1e-12 * scale);
             const double yp = subst(-gtv);
             const double n2 = wave_sum(yp * yp);
@@ -321,33 +436,33 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
     }
     if (fast) {
         // predicted increase -(g.p + p.B.p/2) with p = Q y: g.p = gt.y, p.B.p = y.T.y
-        const double ynext = __shfl(yv, t < NP - 1 ? t + 1 : t, 64);
-        const double tyy = (t < NP) ? dv * yv * yv + (t < NP - 1 ? 2.0 * ev * yv * ynext : 0.0) : 0.0;
+        const double ynext = __shfl(yv, t < M - 1 ? t + 1 : t, 64);
+        const double tyy = (t < M) ? dv * yv * yv + (t < M - 1 ? 2.0 * ev * yv * ynext : 0.0) : 0.0;
         const double pr = -(wave_sum(gtv * yv) + 0.5 * wave_sum(tyy));
         const double pn = sqrt(wave_sum(yv * yv));
-        if (t < NP) ph[t] = yv;
+        if (t < M) ph[t] = yv;
         if (t == 0) {
             a.pred[2 * s] = pr;
             a.pred[2 * s + 1] = pn;
         }
         __syncthreads();
-        if (t < NP) {
+        if (t < M) {
             double pp = 0.0;
-            for (int i = 0; i < NP; ++i) pp += Q[t][i] * ph[i];
-            trial[t] = from_unconstrained(t, eta[t] + pp);
-        } else if (t < ROW) {
-            trial[t] = 0.0;
+            for (int i = 0; i < M; ++i) pp += Q[t][i] * ph[i];
+            pv[t] = pp;
         }
+        __syncthreads();
+        write_trial<M>(t, eta, pv, trial);
         return;
     }
     // ---- otherwise the full eigendecomposition: implicit QL on T.  Lane i keeps d_i and e_i in registers;
     // the scalar recurrence runs in every lane alike on values read across lanes with a
     // wave-uniform index, and lane i applies the rotations to row i of Q (in LDS).
     bool converged = true;
-    for (int l = 0; l < NP && converged; ++l) {
+    for (int l = 0; l < M && converged; ++l) {
         for (int iter = 0;; ++iter) {
             int m = l;
-            for (; m < NP - 1; ++m)
+            for (; m < M - 1; ++m)
                 if (fabs(lane_get(ev, m)) <= EPS_D * (fabs(lane_get(dv, m)) + fabs(lane_get(dv, m + 1)))) break;
             if (m == l) break;
             if (iter == QL_MAX_ITER) {
@@ -379,7 +494,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
                 p = sn * r;
                 dv = t == i + 1 ? g + p : dv;
                 g = cs * r - b;
-                if (t < NP) {
+                if (t < M) {
                     const double zi = Q[t][i], zn = Q[t][i + 1];
                     Q[t][i + 1] = sn * zi + cs * zn;
                     Q[t][i] = cs * zi - sn * zn;
@@ -393,7 +508,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
     if (t < NJ) dd[t] = dv;
     __syncthreads();
     if (!converged) {   // no step this iteration: the source stops (not met in practice)
-        if (t < ROW) trial[t] = (t < NP) ? th[t] : 0.0;
+        if (t < ROW) trial[t] = (t < NT) ? th[t] : 0.0;
         if (t == 0) {
             a.pred[2 * s] = 0.0;
             a.pred[2 * s + 1] = 0.0;
@@ -402,10 +517,10 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         }
         return;
     }
-    if (t < NP) {
+    if (t < M) {
         lam[t] = dd[t];
         double g = 0.0;
-        for (int k = 0; k < NP; ++k) g += Q[k][t] * gm[k];
+        for (int k = 0; k < M; ++k) g += Q[k][t] * gm[k];
         gh[t] = g;
     }
     __syncthreads();
@@ -413,7 +528,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
     if (t == 0) {
         double lmin = lam[0], lmax = fabs(lam[0]), gn2 = 0.0;
         int imin = 0;
-        for (int i = 0; i < NP; ++i) {
+        for (int i = 0; i < M; ++i) {
             if (lam[i] < lmin) { lmin = lam[i]; imin = i; }
             lmax = fmax(lmax, fabs(lam[i]));
             gn2 += gh[i] * gh[i];
@@ -422,9 +537,9 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         double mu = 0.0;
         if (lmin > 0.0) {
             double n2 = 0.0;
-            for (int i = 0; i < NP; ++i) n2 += (gh[i] / lam[i]) * (gh[i] / lam[i]);
+            for (int i = 0; i < M; ++i) n2 += (gh[i] / lam[i]) * (gh[i] / lam[i]);
             if (n2 <= R * R) {
-                for (int i = 0; i < NP; ++i) ph[i] = -gh[i] / lam[i];
+                for (int i = 0; i < M; ++i) ph[i] = -gh[i] / lam[i];
                 solved = true;
             }
         }
@@ -433,7 +548,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
             const double tol = 1e-12 * fmax(lmax, 1e-300);
             // hard case: gradient (numerically) orthogonal to the lowest eigenspace
             double gmin2 = 0.0, prest2 = 0.0;
-            for (int i = 0; i < NP; ++i) {
+            for (int i = 0; i < M; ++i) {
                 if (lam[i] <= lmin + tol) gmin2 += gh[i] * gh[i];
                 else {
                     const double v = gh[i] / (lam[i] + lo0);
@@ -441,7 +556,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
                 }
             }
             if (lo0 > 0.0 && gmin2 <= 1e-28 * fmax(gn2, 1e-300) && prest2 <= R * R) {
-                for (int i = 0; i < NP; ++i)
+                for (int i = 0; i < M; ++i)
                     ph[i] = (lam[i] <= lmin + tol) ? 0.0 : -gh[i] / (lam[i] + lo0);
                 ph[imin] = sqrt(fmax(R * R - prest2, 0.0));
                 mu = lo0;
@@ -450,7 +565,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
                 mu = hi;
                 for (int itn = 0; itn < 200; ++itn) {
                     double n2 = 0.0, d3 = 0.0;
-                    for (int i = 0; i < NP; ++i) {
+                    for (int i = 0; i < M; ++i) {
                         const double den = lam[i] + mu;
                         const double v = gh[i] / den;
                         n2 += v * v;
@@ -466,11 +581,11 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
                     if (nmu == mu) break;
                     mu = nmu;
                 }
-                for (int i = 0; i < NP; ++i) ph[i] = -gh[i] / (lam[i] + mu);
+                for (int i = 0; i < M; ++i) ph[i] = -gh[i] / (lam[i] + mu);
             }
         }
         double pr = 0.0, pn = 0.0;
-        for (int i = 0; i < NP; ++i) {
+        for (int i = 0; i < M; ++i) {
             pr -= gh[i] * ph[i] + 0.5 * lam[i] * ph[i] * ph[i];
             pn += ph[i] * ph[i];
         }
@@ -478,14 +593,13 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         a.pred[2 * s + 1] = sqrt(pn);
     }
     __syncthreads();
-    if (t < NP) {
+    if (t < M) {
         double p = 0.0;
-        for (int i = 0; i < NP; ++i) p += Q[t][i] * ph[i];
+        for (int i = 0; i < M; ++i) p += Q[t][i] * ph[i];
         pv[t] = p;
-        trial[t] = from_unconstrained(t, eta[t] + p);
-    } else if (t < ROW) {
-        trial[t] = 0.0;
     }
+    __syncthreads();
+    write_trial<M>(t, eta, pv, trial);
 }
 
 __global__ void __launch_bounds__(128) k_tr_update(TrArgs a) {
@@ -506,7 +620,7 @@ __global__ void __launch_bounds__(128) k_tr_update(TrArgs a) {
     if (finite && rho > a.eta_accept) {
         double* th = a.theta + (size_t)s * ROW;
         const double* tr = a.theta_trial + (size_t)s * ROW;
-        for (int i = 0; i < NP; ++i) th[i] = tr[i];
+        for (int i = 0; i < a.npar; ++i) th[i] = tr[i];
         a.elbo_cur[s] = f1;
         a.accepted[s] = 1;
     }
@@ -517,7 +631,12 @@ __global__ void __launch_bounds__(128) k_tr_update(TrArgs a) {
 
 hipError_t launch_tr_solve(const TrArgs& a, hipStream_t st) {
     if (a.srcs.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tr_solve, dim3(a.srcs.n), dim3(64), 0, st, a);
+    if (a.npar == NPK)
+        hipLaunchKernelGGL(k_tr_solve<NEM>, dim3(a.srcs.n), dim3(64), 0, st, a);
+    else if (a.npar == NP)
+        hipLaunchKernelGGL(k_tr_solve<NP>, dim3(a.srcs.n), dim3(64), 0, st, a);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -527,9 +646,10 @@ __global__ void __launch_bounds__(256) k_tr_adopt(TrArgs a) {
     const int j = blockIdx.x;
     const int s = sel_at(a.srcs, j);
     if (!a.accepted[s]) return;
-    const double* hs = a.hess_trial + (size_t)j * NP * NP;
-    double* hd = a.hess + (size_t)j * NP * NP;
-    for (int i = threadIdx.x; i < NP * NP; i += blockDim.x) hd[i] = hs[i];
+    const int n2 = a.npar * a.npar;
+    const double* hs = a.hess_trial + (size_t)j * n2;
+    double* hd = a.hess + (size_t)j * n2;
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) hd[i] = hs[i];
     if (threadIdx.x < ROW) a.grad[(size_t)s * ROW + threadIdx.x] = a.grad_trial[(size_t)s * ROW + threadIdx.x];
 }
 

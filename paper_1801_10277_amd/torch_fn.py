@@ -79,7 +79,7 @@ class _TotalELBO(torch.autograd.Function):
 
 
 def elbo(theta, plan, mode=B.CELESTE_BATCHED):
-    """Per-source ELBO_s of theta ([S, 32] float64 on the plan's device), each differentiated
+    """Per-source ELBO_s of theta ([S, 48] float64 on the plan's device), each differentiated
     in its own source's parameters only (the other sources held fixed)."""
     return _ELBO.apply(theta, plan, mode)
 

@@ -11,8 +11,8 @@ class StandInPlan:
 
     def __init__(self, S, seed=0):
         g = torch.Generator().manual_seed(seed)
-        self.a = torch.rand(32, generator=g, dtype=torch.float64)
-        self.b = torch.rand(32, generator=g, dtype=torch.float64)
+        self.a = torch.rand(48, generator=g, dtype=torch.float64)
+        self.b = torch.rand(48, generator=g, dtype=torch.float64)
         self.calls = {"elbo_grad": 0, "hvp": 0}
 
     def elbo_grad(self, theta, mode=1):
@@ -32,9 +32,9 @@ class StandInPlan:
 def test_forward_backward_and_double_backward_plumbing():
     from paper_1801_10277_amd import torch_fn
     plan = StandInPlan(4)
-    theta = torch.randn(4, 32, dtype=torch.float64, requires_grad=True)
+    theta = torch.randn(4, 48, dtype=torch.float64, requires_grad=True)
     w = torch.randn(4, dtype=torch.float64)
-    v = torch.randn(4, 32, dtype=torch.float64)
+    v = torch.randn(4, 48, dtype=torch.float64)
     e = torch_fn.elbo(theta, plan)
     (g,) = torch.autograd.grad((w * e).sum(), theta, create_graph=True)
     (h,) = torch.autograd.grad((g * v).sum(), theta)
@@ -53,7 +53,7 @@ def test_total_elbo_plumbing():
     and a second differentiation is refused (the total's Hessian is not formed)."""
     from paper_1801_10277_amd import torch_fn
     plan = StandInPlan(3)
-    theta = torch.randn(3, 32, dtype=torch.float64, requires_grad=True)
+    theta = torch.randn(3, 48, dtype=torch.float64, requires_grad=True)
     t = torch_fn.total_elbo(theta, plan)
     (g,) = torch.autograd.grad(2.5 * t, theta)
     ref = theta.detach().clone().requires_grad_(True)
@@ -108,7 +108,7 @@ def test_gpu_autograd_matches_library(synth):
     plan = B.Plan(f)
     theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda", requires_grad=True)
     w = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64, device="cuda")
-    v = torch.zeros(3, 32, dtype=torch.float64, device="cuda")
+    v = torch.zeros(3, 48, dtype=torch.float64, device="cuda")
     v[:, :27] = torch.randn(3, 27, dtype=torch.float64, device="cuda")
     e = torch_fn.elbo(theta, plan)
     (g,) = torch.autograd.grad((w * e).sum(), theta, create_graph=True)

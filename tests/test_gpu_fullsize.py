@@ -83,7 +83,7 @@ def test_second_order_field_1024src_largest_boxes(B, O, synth):
     say("case second order field_1024src largest", picks)
     H = plan.hessian(theta, picks).cpu().numpy()
     rng = np.random.default_rng(23)
-    v = np.zeros((f.n_src, 32))
+    v = np.zeros((f.n_src, 48))
     v[:, :27] = rng.standard_normal((f.n_src, 27))
     hv, g = plan.hvp(theta, torch.tensor(v, device="cuda"), with_grad=True)
     hv, g = hv.cpu().numpy(), g.cpu().numpy()

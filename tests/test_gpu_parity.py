@@ -102,7 +102,7 @@ def test_plain_equals_batched_region_16src(B, synth):
 def test_hvp_matches_oracle(B, O, synth):
     f = synth.tiny(S=3, n_bands=2, size=17, side=11, seed=33)
     rng = np.random.default_rng(0)
-    v = np.zeros((3, 32))
+    v = np.zeros((3, 48))
     v[:, :27] = rng.standard_normal((3, 27))
     plan = B.Plan(f)
     theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
@@ -185,7 +185,7 @@ def test_second_order_on_multi_item_boxes(B, O, synth, rows):
     H1 = plan.hessian(theta, src).cpu().numpy()
     plan.set_hessian_mode(0)
     rng = np.random.default_rng(rows)
-    v = np.zeros((3, 32))
+    v = np.zeros((3, 48))
     v[:, :27] = rng.standard_normal((3, 27))
     hv, g = plan.hvp(theta, torch.tensor(v, device="cuda"), with_grad=True)
     hv, g = hv.cpu().numpy(), g.cpu().numpy()
@@ -225,7 +225,7 @@ def test_active_mask(B, O, synth, mode):
     act = torch.tensor(active, device="cuda")
     say("case active mask mode", mode)
     e = torch.full((6,), -7.5, dtype=torch.float64, device="cuda")
-    g = torch.full((6, 32), 3.25, dtype=torch.float64, device="cuda")
+    g = torch.full((6, 48), 3.25, dtype=torch.float64, device="cuda")
     plan.elbo_grad(theta, mode=mode, active=act, elbo=e, grad=g)
     e2 = torch.full((6,), 11.0, dtype=torch.float64, device="cuda")
     plan.elbo(theta, mode=mode, active=act, out=e2)
@@ -278,7 +278,7 @@ def test_launch_configurations_agree(B, synth):
         e, g = e.cpu().numpy(), g.cpu().numpy()
         np.testing.assert_allclose(e, e0, rtol=1e-12)
         assert np.all(np.abs(g - g0) <= 1e-11 * gmax)
-        v = np.zeros((5, 32))
+        v = np.zeros((5, 48))
         v[:, :27] = 1.0
         hv = plan.hvp(theta, torch.tensor(v, device="cuda")).cpu().numpy()
         if cfg is LAUNCHES[0]:
@@ -343,7 +343,7 @@ def test_degenerate_parameter_values(B, O, synth):
     plan, theta = check_field(B, O, f, range(4), name="degenerate")
     P = O.Problem(f)
     rng = np.random.default_rng(17)
-    v = np.zeros((4, 32))
+    v = np.zeros((4, 48))
     v[:, :27] = rng.standard_normal((4, 27))
     say("case degenerate hvp / hessian")
     hv = plan.hvp(theta, torch.tensor(v, device="cuda")).cpu().numpy()
@@ -471,7 +471,7 @@ def test_astrometry_and_sky_maps(B, O, synth):
     f.img_origin[1] = [0.6, -0.4]
     plan, theta = check_field(B, O, f, range(3), name="wcs-sky")
     rng = np.random.default_rng(3)
-    v = np.zeros((3, 32))
+    v = np.zeros((3, 48))
     v[:, :27] = rng.standard_normal((3, 27))
     say("case wcs-sky hvp / hessian / total")
     hv = plan.hvp(theta, torch.tensor(v, device="cuda")).cpu().numpy()

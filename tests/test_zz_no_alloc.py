@@ -51,7 +51,7 @@ def test_noalloc_dynamic_queue_and_active_mask(B, synth):
     say("case noalloc dynamic + active")
     for _ in range(2):
         e0 = torch.full((5,), 5.0, dtype=torch.float64, device="cuda")
-        g0 = torch.full((5, 32), 2.0, dtype=torch.float64, device="cuda")
+        g0 = torch.full((5, 48), 2.0, dtype=torch.float64, device="cuda")
         e1, g1 = e0.clone(), g0.clone()
         plan.elbo_grad(theta, active=act, elbo=e0, grad=g0)
         plan.elbo_grad_noalloc(theta, active=act, elbo=e1, grad=g1)
@@ -70,7 +70,7 @@ def test_noalloc_rejects_problems_beyond_the_scratch(B, synth):
     plan.set_launch(strip_rows=4)
     say("case noalloc too large", plan.info()["n_items"], "items")
     e = torch.full((f.n_src,), 3.0, dtype=torch.float64, device="cuda")
-    g = torch.full((f.n_src, 32), 4.0, dtype=torch.float64, device="cuda")
+    g = torch.full((f.n_src, 48), 4.0, dtype=torch.float64, device="cuda")
     with pytest.raises(B.CelesteError) as err:
         plan.elbo_grad_noalloc(theta, elbo=e, grad=g)
     assert err.value.code == B.CELESTE_ESCRATCH
