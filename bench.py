@@ -191,6 +191,7 @@ def run_sweep(args):
     if args.launch:
         apply_launch(plan, args.launch)
     plan.set_hessian_mode(args.hessian_mode)
+    plan.use_graph(not args.no_graph)
     log("plan: %s" % plan.info())
     theta = torch.tensor(f.theta, dtype=torch.float64, device=dev)
     params = B.tr_params(newton_steps=args.newton_steps)
@@ -227,6 +228,7 @@ def run_sweep(args):
                                   "%s, %d Newton steps per batch visit"
                                   % (f.n_src, sched, args.newton_steps),
                       "schedule": args.schedule, "batches_per_sweep": rounds,
+                      "sweep_graph": not args.no_graph,
                       "launch": {k: plan.info()[k] for k in LAUNCH_KEYS}, "hessian_mode": args.hessian_mode,
                       "seconds": dt, "visits_per_evaluation": plan.info()["n_visits"],
                       "elbo_trace": [float(v) for v in trace],
@@ -260,6 +262,8 @@ def main():
     ap.add_argument("--schedule", choices=("colour", "cyclades"), default="colour",
                     help="sweep workload: greedy colouring, or Cyclades sampling (Section IV-D)")
     ap.add_argument("--sample-size", type=int, default=2000, help="Cyclades sample size")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="sweep workload: run the sweeps eagerly instead of replaying a captured sweep graph")
     ap.add_argument("--hessian-mode", type=int, default=0, choices=(0, 1),
                     help="Newton / sweep Hessian rows: 0 closed form (default), 1 tangent passes")
     args = ap.parse_args()

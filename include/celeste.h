@@ -167,8 +167,8 @@ typedef struct celeste_plan celeste_plan;
  * bins boxes into render tiles and work items, and allocates the plan-owned device
  * workspace, sized for every later evaluation, Hessian, Newton and sweep call.  Besides
  * this call only celeste_plan_set_launch (grown tile buffers for smaller tiles),
- * celeste_autotune (its own timing outputs) and celeste_sweep (temporary list buffers
- * when a schedule lists sources more often than once in total) allocate device memory;
+ * celeste_autotune (its own timing outputs) and celeste_sweep (grown list buffers when a
+ * schedule lists sources more often than once in total) allocate device memory;
  * celeste_elbo_grad_noalloc never does.  Synchronous.  *out receives the plan.
  * Returns CELESTE_EINVAL (nothing allocated), CELESTE_ENOMEM or CELESTE_EHIP. */
 int celeste_plan_create(const celeste_problem_desc* desc, celeste_plan** out);
@@ -226,9 +226,10 @@ int celeste_hvp(celeste_plan* plan, const double* theta, const double* v, double
  * second derivatives of Section IV-D: each box's Hessian in its ten intermediates
  * (brightness factors and frac_dev from the gradient pass, position and shape from a
  * closed-form pass, or from tangent-adjoint passes: celeste_plan_set_hessian_mode)
- * pushed through the chain rule and its tangent, plus the KL.  Synchronous: it waits for
- * `stream`, then uploads the source, box and item lists with blocking copies before it
- * queues its kernels on `stream`. */
+ * pushed through the chain rule and its tangent, plus the KL.  Stream-ordered: the source,
+ * box and item lists go up through the plan's pinned staging on `stream` (the host waits
+ * only if the previous list upload of this plan is still being copied; a longer list than
+ * before grows the staging, a pinned host allocation). */
 int celeste_hessian(celeste_plan* plan, const double* theta, const int32_t* src, int n,
                     double* hess, hipStream_t stream);
 
@@ -243,9 +244,8 @@ int celeste_hessian(celeste_plan* plan, const double* theta, const int32_t* src,
  * update - all on the device.
  * theta_inout (device [n_src][48]) is updated in place; radius (device [n_src]) is
  * read and written (initialise with params->radius0); elbo_out (device [n_src] or
- * NULL) receives the final ELBO_s of the listed sources.  Synchronous at entry: it waits
- * for `stream` and uploads the lists with blocking copies; the iterations themselves are
- * queued on `stream` with no further host synchronisation. */
+ * NULL) receives the final ELBO_s of the listed sources.  Stream-ordered, with the list
+ * upload of celeste_hessian; no host synchronisation between iterations. */
 int celeste_newton(celeste_plan* plan, double* theta_inout, const int32_t* src, int n,
                    int n_steps, const celeste_tr_params* params, double* radius,
                    double* elbo_out, hipStream_t stream);
@@ -308,10 +308,13 @@ int celeste_cyclades_batches(int32_t n, const int32_t* adj_ptr, const int32_t* a
  * batch_src), each batch optimised by params->newton_steps Newton trust-region
  * iterations with all other sources fixed.  Batches must be conflict-free
  * (CELESTE_ECONFLICT otherwise, nothing run).  elbo_trace (device [n_sweeps + 1])
- * receives the total ELBO before the first sweep and after each sweep.  Synchronous at
- * entry (it waits for `stream` and uploads every batch's lists once, with blocking copies)
- * and at exit when it allocated temporary list buffers; the sweeps are queued on `stream`
- * with no host synchronisation between batches. */
+ * receives the total ELBO before the first sweep and after each sweep.  Every batch's
+ * lists go up once per call, stream-ordered as in celeste_hessian; when a schedule lists
+ * sources more often than the plan's list buffers hold (each source once), the call waits
+ * for `stream` and grows them (device allocation, kept by the plan).  No host
+ * synchronisation between batches or sweeps.  With celeste_plan_use_graph enabled, one
+ * sweep is captured into a HIP graph per call and replayed n_sweeps times (the same
+ * kernels in the same order: the same results). */
 int celeste_sweep(celeste_plan* plan, double* theta_inout, const int32_t* batch_ptr,
                   const int32_t* batch_src, int n_batches, int n_sweeps,
                   const celeste_tr_params* params, double* elbo_trace, hipStream_t stream);
@@ -334,7 +337,8 @@ int celeste_autotune(celeste_plan* plan, const double* theta, int reps, double* 
                      hipStream_t stream);
 
 /* Capture the batched celeste_elbo_grad sequence for these exact pointers in a HIP
- * graph on first use and replay it afterwards (0 = off, the default). */
+ * graph on first use and replay it afterwards, and run celeste_sweep's sweeps as replays
+ * of a captured sweep (0 = off, the default). */
 int celeste_plan_use_graph(celeste_plan* plan, int enable);
 
 /* Per-phase device time of the batched evaluation (celeste_elbo / celeste_elbo_grad,

@@ -120,7 +120,7 @@ struct celeste_plan {
     int32_t* d_list_src = nullptr;   // [n_src]
     int32_t* d_list_pair = nullptr;  // [n_pairs]
     int32_t* d_list_item = nullptr;  // [cap_items]
-    size_t cap_list_item = 0;
+    size_t cap_list_item = 0, cap_list_src = 0, cap_list_pair = 0;
     // conflict-free classes of boxes (no two boxes of a class share a pixel) and their items
     std::vector<int32_t> pair_class;
     int n_class = 0;
@@ -134,6 +134,18 @@ struct celeste_plan {
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     double phase_ms[4] = {0, 0, 0, 0};
     int64_t phase_calls = 0;
+
+    // pinned host staging of the source / box / item lists, uploaded on the caller's stream;
+    // stage_ev marks the end of the last upload (the staging may be rewritten after it)
+    int32_t* h_stage = nullptr;
+    size_t cap_stage = 0;
+    hipEvent_t stage_ev = nullptr;
+    bool stage_pending = false;
+    // sweep graph: one sweep over a schedule captured once per celeste_sweep call and replayed
+    hipGraphExec_t sweep_exec = nullptr;
+    hipEvent_t sweep_ev = nullptr;   // recorded after the last replay
+    bool sweep_pending = false;
+    double* d_scalar = nullptr;      // total ELBO written by a replayed sweep
 
     // graph cache of the batched elbo_grad sequence
     hipStream_t cap_stream = nullptr;
@@ -750,6 +762,45 @@ int fill_f64(double* d, const Sel& srcs, double v, hipStream_t st) {
     return CELESTE_OK;
 }
 
+// Lists of hs into device buffers (default: the plan's own list buffers, sized for each
+// source once) on `st`, through the plan's pinned staging: no host synchronisation except,
+// when the staging is still being read by the previous upload, a wait for that copy.
+// Growing the staging allocates pinned host memory.
+int upload_lists(celeste_plan* p, const HostScope& hs, hipStream_t st, int32_t* d_src = nullptr,
+                 int32_t* d_pair = nullptr, int32_t* d_item = nullptr) {
+    if (!d_src) {
+        d_src = p->d_list_src;
+        d_pair = p->d_list_pair;
+        d_item = p->d_list_item;
+    }
+    const size_t n = hs.src.size() + hs.pair.size() + hs.item.size();
+    if (p->stage_pending) {
+        HIPCHK(hipEventSynchronize(p->stage_ev));
+        p->stage_pending = false;
+    }
+    if (n > p->cap_stage) {
+        if (p->h_stage) HIPCHK(hipHostFree(p->h_stage));
+        p->h_stage = nullptr;
+        p->cap_stage = 0;
+        HIPCHK(hipHostMalloc((void**)&p->h_stage, std::max<size_t>(n, 1024) * sizeof(int32_t), hipHostMallocDefault));
+        p->cap_stage = std::max<size_t>(n, 1024);
+    }
+    int32_t* h = p->h_stage;
+    std::copy(hs.src.begin(), hs.src.end(), h);
+    std::copy(hs.pair.begin(), hs.pair.end(), h + hs.src.size());
+    std::copy(hs.item.begin(), hs.item.end(), h + hs.src.size() + hs.pair.size());
+    if (!hs.src.empty())
+        HIPCHK(hipMemcpyAsync(d_src, h, hs.src.size() * 4, hipMemcpyHostToDevice, st));
+    if (!hs.pair.empty())
+        HIPCHK(hipMemcpyAsync(d_pair, h + hs.src.size(), hs.pair.size() * 4, hipMemcpyHostToDevice, st));
+    if (!hs.item.empty())
+        HIPCHK(hipMemcpyAsync(d_item, h + hs.src.size() + hs.pair.size(), hs.item.size() * 4, hipMemcpyHostToDevice,
+                              st));
+    HIPCHK(hipEventRecord(p->stage_ev, st));
+    p->stage_pending = true;
+    return CELESTE_OK;
+}
+
 int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& src, const Sel& pair, const Sel& item,
                                int base, double* hess, hipStream_t st, const uint8_t* active) {
     HIPCHK(launch_pair_reduce(pair, p->d_pairs, p->d_partials, p->d_kk, false, 0, p->d_gw, p->d_hw, p->d_status,
@@ -901,13 +952,19 @@ const char* celeste_status_string(int s) {
 void celeste_plan_destroy(celeste_plan* p) {
     if (!p) return;
     drop_graph(p);
+    if (p->sweep_pending && p->sweep_ev) (void)hipEventSynchronize(p->sweep_ev);
+    if (p->sweep_exec) (void)hipGraphExecDestroy(p->sweep_exec);
+    if (p->stage_pending && p->stage_ev) (void)hipEventSynchronize(p->stage_ev);
+    if (p->h_stage) (void)hipHostFree(p->h_stage);
+    if (p->stage_ev) (void)hipEventDestroy(p->stage_ev);
+    if (p->sweep_ev) (void)hipEventDestroy(p->sweep_ev);
     void* bufs[] = {p->d_images, p->d_pairs, p->d_items, p->d_nbr, p->d_tiles, p->d_tile_list, p->d_patch_ptr,
                     p->d_tab1, p->d_coef1, p->d_tab2, p->d_coef2, p->d_partials, p->d_E, p->d_V, p->d_bg,
                     p->d_tile_sums, p->d_status, p->d_counter, p->d_grad, p->d_hess, p->d_theta_trial,
                     p->d_pred, p->d_elbo_cur, p->d_elbo_trial, p->d_radius, p->d_done, p->d_list_src,
                     p->d_list_pair, p->d_list_item, p->d_cls_items, p->d_pair_lgamma, p->d_fg, p->d_gw,
                     p->d_hw, p->d_kk, p->d_hg, p->d_hc, p->d_grad_trial, p->d_hess_trial, p->d_accepted, p->d_live,
-                    p->d_mix};
+                    p->d_mix, p->d_scalar};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -1026,8 +1083,11 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     A(dalloc(&p->d_list_pair, np, W));
     A(dalloc(&p->d_list_item, max_items, W));
     A(dalloc(&p->d_cls_items, max_items, W));
+    A(dalloc(&p->d_scalar, 1, W));
     if (d->flags & CELESTE_COLOR_MIXTURE) A(dalloc(&p->d_mix, 2 * NMIX * MIXF, W));
     p->cap_list_item = max_items;
+    p->cap_list_src = S;
+    p->cap_list_pair = np;
     if (r != CELESTE_OK) {
         celeste_plan_destroy(p);
         return r;
@@ -1049,7 +1109,9 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
                       hipMemcpyHostToDevice) != hipSuccess ||
             hipMemset(p->d_status, 0, sizeof(int)) != hipSuccess ||
             hipMemset(p->d_counter, 0, sizeof(int)) != hipSuccess ||
-            hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&p->stage_ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&p->sweep_ev, hipEventDisableTiming) != hipSuccess)
             rc = hip_fail(hipGetLastError(), "plan upload");
     }
     if (rc == CELESTE_OK && (p->consts.flags & CELESTE_INCLUDE_LGAMMA)) {
@@ -1236,10 +1298,7 @@ int celeste_hessian(celeste_plan* p, const double* theta, const int32_t* src, in
     }
     HostScope hs;
     scope_lists(p, src, n, hs);
-    HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipMemcpy(p->d_list_src, hs.src.data(), hs.src.size() * 4, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(p->d_list_pair, hs.pair.data(), hs.pair.size() * 4, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(p->d_list_item, hs.item.data(), hs.item.size() * 4, hipMemcpyHostToDevice));
+    CHK(upload_lists(p, hs, st));
     const Sel ss{p->d_list_src, 0, (int32_t)hs.src.size()};
     const Sel sp{p->d_list_pair, 0, (int32_t)hs.pair.size()};
     const Sel si{p->d_list_item, 0, (int32_t)hs.item.size()};
@@ -1285,11 +1344,7 @@ int celeste_newton(celeste_plan* p, double* theta, const int32_t* src, int n, in
     }
     HostScope hs;
     scope_lists(p, src, n, hs);
-    HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipMemcpy(p->d_list_src, hs.src.data(), hs.src.size() * 4, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(p->d_list_pair, hs.pair.data(), std::max<size_t>(hs.pair.size(), 1) * 4, hipMemcpyHostToDevice));
-    if (!hs.item.empty())
-        HIPCHK(hipMemcpy(p->d_list_item, hs.item.data(), hs.item.size() * 4, hipMemcpyHostToDevice));
+    CHK(upload_lists(p, hs, st));
     const Sel ss{p->d_list_src, 0, (int32_t)hs.src.size()};
     const Sel sp{p->d_list_pair, 0, (int32_t)hs.pair.size()};
     const Sel si{p->d_list_item, 0, (int32_t)hs.item.size()};
@@ -1499,73 +1554,96 @@ int celeste_sweep(celeste_plan* p, double* theta, const int32_t* batch_ptr, cons
     off_src[n_batches] = (int32_t)hs.src.size();
     off_pair[n_batches] = (int32_t)hs.pair.size();
     off_item[n_batches] = (int32_t)hs.item.size();
-    // list buffers sized for one appearance of each source; grow if a schedule repeats sources
-    HIPCHK(hipStreamSynchronize(st));
+    // list buffers sized for one appearance of each source; grown (plan-owned) if a schedule
+    // repeats sources, after the stream has finished with the old ones
+    if (hs.src.size() > p->cap_list_src || hs.pair.size() > p->cap_list_pair || hs.item.size() > p->cap_list_item) {
+        HIPCHK(hipStreamSynchronize(st));
+        int32_t *ns = nullptr, *np_ = nullptr, *ni = nullptr;
+        const size_t cs = std::max(hs.src.size(), p->cap_list_src), cp = std::max(hs.pair.size(), p->cap_list_pair),
+                     ci = std::max(hs.item.size(), p->cap_list_item);
+        if (hipMalloc((void**)&ns, cs * 4) != hipSuccess || hipMalloc((void**)&np_, cp * 4) != hipSuccess ||
+            hipMalloc((void**)&ni, ci * 4) != hipSuccess) {
+            (void)hipFree(ns);
+            (void)hipFree(np_);
+            (void)hipFree(ni);
+            (void)hipGetLastError();
+            return CELESTE_ENOMEM;
+        }
+        (void)hipFree(p->d_list_src);
+        (void)hipFree(p->d_list_pair);
+        (void)hipFree(p->d_list_item);
+        p->d_list_src = ns;
+        p->d_list_pair = np_;
+        p->d_list_item = ni;
+        p->cap_list_src = cs;
+        p->cap_list_pair = cp;
+        p->cap_list_item = ci;
+    }
+    CHK(upload_lists(p, hs, st));
     int32_t *dl_src = p->d_list_src, *dl_pair = p->d_list_pair, *dl_item = p->d_list_item;
-    std::vector<void*> temp;
-    if (hs.src.size() > (size_t)p->n_src || hs.pair.size() > p->pairs.size() || hs.item.size() > p->cap_list_item) {
-        if (hipMalloc((void**)&dl_src, hs.src.size() * 4) != hipSuccess) return CELESTE_ENOMEM;
-        temp.push_back(dl_src);
-        if (hipMalloc((void**)&dl_pair, std::max<size_t>(hs.pair.size(), 1) * 4) != hipSuccess) return CELESTE_ENOMEM;
-        temp.push_back(dl_pair);
-        if (hipMalloc((void**)&dl_item, std::max<size_t>(hs.item.size(), 1) * 4) != hipSuccess) return CELESTE_ENOMEM;
-        temp.push_back(dl_item);
-    }
-    auto cleanup = [&]() {
-        (void)hipStreamSynchronize(st);
-        for (void* t : temp) (void)hipFree(t);
-    };
-    if (hipMemcpy(dl_src, hs.src.data(), hs.src.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        (!hs.pair.empty() &&
-         hipMemcpy(dl_pair, hs.pair.data(), hs.pair.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
-        (!hs.item.empty() &&
-         hipMemcpy(dl_item, hs.item.data(), hs.item.size() * 4, hipMemcpyHostToDevice) != hipSuccess)) {
-        cleanup();
-        return hip_fail(hipGetLastError(), "sweep list upload");
-    }
-    int rc = CELESTE_OK;
     // With the strip render, the total ELBO leaves every box's own profile values and
     // coefficients current; each batch then takes its background from them, and its boxes
     // are rendered again at their new parameters before the next batch.
     const bool stored = p->render_mode == 2 || p->render_mode == 3;
-    do {
-        rc = celeste_total_elbo(p, theta, elbo_trace, st);
-        if (rc != CELESTE_OK) break;
-        for (int sw = 0; sw < n_sweeps && rc == CELESTE_OK; ++sw) {
-            for (int b = 0; b < n_batches && rc == CELESTE_OK; ++b) {
-                const Sel ss{dl_src + off_src[b], 0, off_src[b + 1] - off_src[b]};
-                const Sel sp{dl_pair + off_pair[b], 0, off_pair[b + 1] - off_pair[b]};
-                const Sel si{dl_item + off_item[b], 0, off_item[b + 1] - off_item[b]};
-                if (ss.n == 0) continue;
-                rc = fill_u8(p->d_done, ss, 0, st);
-                if (rc != CELESTE_OK) break;
-                // fresh trust region for every visit of a batch
-                rc = fill_f64(p->d_radius, ss, prm->radius0, st);
-                if (rc != CELESTE_OK) break;
-                rc = newton_run(p, theta, ss, sp, si, prm->newton_steps, prm, p->d_radius, st, stored);
-                if (rc != CELESTE_OK || !stored) continue;
-                rc = prep(p, theta, sp, false, DIR_NONE, nullptr, 0, st);
-                if (rc == CELESTE_OK &&
-                    launch_strip_fg(si, p->geom(), p->d_tab1, p->d_fg, p->rows, p->persistent_grid(), p->wpb,
-                                    p->d_status, st) != hipSuccess)
-                    rc = hip_fail(hipGetLastError(), "sweep render");
-            }
-            if (rc != CELESTE_OK) break;
-            if (stored) {
-                // every box's stored own values and coefficients are current: the total
-                // needs the gather only, not the strip pass
-                rc = gather(p, true, st);
-                if (rc == CELESTE_OK &&
-                    launch_tile_total(p->d_tile_sums, (int)p->tiles.size(), theta, p->consts, p->n_src,
-                                      elbo_trace + sw + 1, p->d_status, st) != hipSuccess)
-                    rc = hip_fail(hipGetLastError(), "sweep total");
-            } else {
-                rc = celeste_total_elbo(p, theta, elbo_trace + sw + 1, st);
-            }
+    // one sweep over the schedule, then the total ELBO into `total`
+    auto one_sweep = [&](double* total, hipStream_t s) -> int {
+        for (int b = 0; b < n_batches; ++b) {
+            const Sel ss{dl_src + off_src[b], 0, off_src[b + 1] - off_src[b]};
+            const Sel sp{dl_pair + off_pair[b], 0, off_pair[b + 1] - off_pair[b]};
+            const Sel si{dl_item + off_item[b], 0, off_item[b + 1] - off_item[b]};
+            if (ss.n == 0) continue;
+            CHK(fill_u8(p->d_done, ss, 0, s));
+            // fresh trust region for every visit of a batch
+            CHK(fill_f64(p->d_radius, ss, prm->radius0, s));
+            CHK(newton_run(p, theta, ss, sp, si, prm->newton_steps, prm, p->d_radius, s, stored));
+            if (!stored) continue;
+            CHK(prep(p, theta, sp, false, DIR_NONE, nullptr, 0, s));
+            HIPCHK(launch_strip_fg(si, p->geom(), p->d_tab1, p->d_fg, p->rows, p->persistent_grid(), p->wpb,
+                                   p->d_status, s));
         }
-    } while (0);
-    cleanup();
-    return rc;
+        if (!stored) return celeste_total_elbo(p, theta, total, s);
+        // every box's stored own values and coefficients are current: the total needs the
+        // gather only, not the strip pass
+        CHK(gather(p, true, s));
+        HIPCHK(launch_tile_total(p->d_tile_sums, (int)p->tiles.size(), theta, p->consts, p->n_src, total,
+                                 p->d_status, s));
+        return CELESTE_OK;
+    };
+    CHK(celeste_total_elbo(p, theta, elbo_trace, st));
+    if (!p->use_graph || n_sweeps == 0) {
+        for (int sw = 0; sw < n_sweeps; ++sw) CHK(one_sweep(elbo_trace + sw + 1, st));
+        return CELESTE_OK;
+    }
+    // graph mode: the sweep is captured once (its total into the plan's scalar) and replayed
+    // n_sweeps times on `st`, each replay's total copied into the trace
+    if (p->sweep_exec) {
+        if (p->sweep_pending) HIPCHK(hipEventSynchronize(p->sweep_ev));
+        p->sweep_pending = false;
+        (void)hipGraphExecDestroy(p->sweep_exec);
+        p->sweep_exec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = one_sweep(p->d_scalar, p->cap_stream);
+    const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (rc != CELESTE_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "sweep capture");
+    const hipError_t e2 = hipGraphInstantiate(&p->sweep_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        p->sweep_exec = nullptr;
+        return hip_fail(e2, "sweep graph instantiation");
+    }
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+        HIPCHK(hipGraphLaunch(p->sweep_exec, st));
+        HIPCHK(hipMemcpyAsync(elbo_trace + sw + 1, p->d_scalar, sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    HIPCHK(hipEventRecord(p->sweep_ev, st));
+    p->sweep_pending = true;
+    return CELESTE_OK;
 }
 
 int celeste_autotune(celeste_plan* p, const double* theta, int reps, double* best_ms, hipStream_t st) {

@@ -252,3 +252,33 @@ def test_plan_rejects_bad_image_metadata(B, synth):
         B.Plan(h)
     assert e.value.code == B.CELESTE_EINVAL
     B.Plan(f)
+
+
+@pytest.mark.parametrize("schedule", ["colour", "cyclades"])
+def test_sweep_graph_replays_match_eager(B, synth, schedule):
+    """Sweeps replayed from a captured HIP graph (celeste_plan_use_graph) give bitwise the
+    parameters and ELBO trace of the eager sweeps, over several replays in one call and
+    over two calls with unrelated eager work and synchronisations in between."""
+    f = synth.tiny(S=8, n_bands=2, size=33, side=9, seed=73)
+    eager = B.Plan(f)
+    if schedule == "colour":
+        ptr, src = eager.color_batches(seed=3)
+    else:
+        ptr, src, _, _ = eager.cyclades_batches(seed=5, sample_size=5)
+    params = B.tr_params(newton_steps=2)
+    th_e = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+    tr_e = [eager.sweep(th_e, ptr, src, 3, params).clone()]
+    tr_e.append(eager.sweep(th_e, ptr, src, 2, params).clone())
+    graph = B.Plan(f)
+    graph.use_graph(True)
+    th_g = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+    say("case sweep graph", schedule, len(ptr) - 1, "batches")
+    tr_g = [graph.sweep(th_g, ptr, src, 3, params).clone()]
+    torch.cuda.synchronize()
+    x = torch.randn(4096, device="cuda").sum()       # unrelated eager work between calls
+    torch.cuda.synchronize()
+    tr_g.append(graph.sweep(th_g, ptr, src, 2, params).clone())
+    torch.cuda.synchronize()
+    for a, b in zip(tr_e, tr_g):
+        assert torch.equal(a, b), (a, b)
+    assert torch.equal(th_e, th_g)
