@@ -98,8 +98,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(f, theta_gpu_grad, elbo_gpu, seconds):
-    """The oracle as it stands, OpenMP over sources on this host, on a bounded sample."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(f, theta_gpu_grad, elbo_gpu, seconds, seconds_single):
+    """The oracle as it stands on this host, on bounded samples of the same field: OpenMP over
+    sources on the host cores OMP_NUM_THREADS allows, then one thread (the oracle's
+    per-source gradient called source by source), each with the parity of the GPU result on
+    the sources it covered."""
     import numpy as np
     from oracle import oracle as O
     O.build()
@@ -108,21 +122,40 @@ def cpu_baseline(f, theta_gpu_grad, elbo_gpu, seconds):
     batch = max(cores, 8)
     done, visits, t0 = 0, 0, time.perf_counter()
     rel_e, rel_g = 0.0, 0.0
+
+    def check(s, val3, gi):
+        ref = val3[0] + val3[1]
+        return abs(elbo_gpu[s] - ref) / abs(ref), float(np.max(np.abs(theta_gpu_grad[s, :27] - gi)) / np.abs(gi).max())
+
     while time.perf_counter() - t0 < seconds and done < f.n_src:
         srcs = np.arange(done, min(done + batch, f.n_src))
         val, g = O.grad_many(P, srcs)
         b = f.boxes[f.patch_ptr[srcs[0]]:f.patch_ptr[srcs[-1] + 1]]
         visits += int((b[:, 3].astype(np.int64) * b[:, 4]).sum())
         for k, s in enumerate(srcs):
-            ref = val[k, 0] + val[k, 1]
-            rel_e = max(rel_e, abs(elbo_gpu[s] - ref) / abs(ref))
-            gi = g[k]
-            rel_g = max(rel_g, float(np.max(np.abs(theta_gpu_grad[s, :27] - gi)) / np.abs(gi).max()))
+            e_, g_ = check(s, val[k], g[k])
+            rel_e, rel_g = max(rel_e, e_), max(rel_g, g_)
         done = srcs[-1] + 1
     dt = time.perf_counter() - t0
+    # one thread: the last sources of the field, one oracle call each
+    s1, v1, t1 = f.n_src - 1, 0, time.perf_counter()
+    n1 = 0
+    while time.perf_counter() - t1 < seconds_single and s1 >= done:
+        val3, gi, _ = O.source_grad(P, s1)
+        b = f.boxes[f.patch_ptr[s1]:f.patch_ptr[s1 + 1]]
+        v1 += int((b[:, 3].astype(np.int64) * b[:, 4]).sum())
+        e_, g_ = check(s1, val3, gi)
+        rel_e, rel_g = max(rel_e, e_), max(rel_g, g_)
+        s1 -= 1
+        n1 += 1
+    dt1 = time.perf_counter() - t1
     return {"value": visits / dt, "unit": "source-pixel ELBO+grad evals/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": "first %d of %d sources of the same field (%d visits, %.1f s), FP64 dual-number "
-                      "gradient, OpenMP over sources" % (done, f.n_src, visits, dt)}, rel_e, rel_g, done
+                      "gradient, OpenMP over sources on %d threads" % (done, f.n_src, visits, dt, cores),
+            "single_thread": {"value": v1 / dt1 if dt1 > 0 else None, "cores": 1,
+                              "sample": "last %d sources of the field (%d visits, %.1f s), one oracle call "
+                                        "per source" % (n1, v1, dt1)}}, rel_e, rel_g, done + n1
 
 
 def apply_launch(plan, text):
@@ -242,12 +275,13 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds-single", type=float, default=8.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-hvp", action="store_true")
-    ap.add_argument("--tune", action="store_true",
-                    help="autotune the launch first (default: the plan's default launch, which the "
-                         "committed counter profile was taken at)")
+    ap.add_argument("--no-small", action="store_true", help="skip the one- and 16-source configurations")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner and time the plan's default launch")
     ap.add_argument("--sources", type=int, default=2000)
     ap.add_argument("--launch", type=str, default=None,
                     help="fixed launch chunk,waves_per_block,grid,dynamic,strip_rows,render_mode[,tile_h,tile_w] "
@@ -295,13 +329,19 @@ def main():
     elbo = torch.zeros(f.n_src, dtype=torch.float64, device=dev)
     grad = torch.zeros(f.n_src, 48, dtype=torch.float64, device=dev)
 
+    default_launch = {k: info[k] for k in LAUNCH_KEYS}
+    tuned = None
     if args.launch:
         apply_launch(plan, args.launch)
         info = plan.info()
-    elif args.tune:
-        ms = plan.autotune(theta, reps=3)
+    elif not args.no_tune:
+        t_tune = time.perf_counter()
+        ms = plan.autotune(theta, reps=5)
         info = plan.info()
-        log("autotuned: %s (%.3f ms)" % ({k: info[k] for k in LAUNCH_KEYS}, ms))
+        tuned = {"launch": {k: info[k] for k in LAUNCH_KEYS}, "median_ms": round(ms, 4),
+                 "seconds": round(time.perf_counter() - t_tune, 2),
+                 "equals_default": {k: info[k] for k in LAUNCH_KEYS} == default_launch}
+        log("autotuned: %s (%.3f ms)" % (tuned["launch"], ms))
 
     # correctness of this configuration before timing
     plan.check_status = True
@@ -320,6 +360,16 @@ def main():
     ms_step = 1e3 * dt / args.steps
     value = visits * args.steps / dt
     log("batched: %.3f ms/step, %.3e visits/s" % (ms_step, value))
+    # each replay bracketed by HIP events on the launch stream (after the timed region)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for e0, e1 in evs:
+        e0.record()
+        plan.elbo_grad(theta, elbo=elbo, grad=grad)
+        e1.record()
+    torch.cuda.synchronize()
+    replay_ms = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+    median_ms = replay_ms[len(replay_ms) // 2]
+    log("replays (HIP events): median %.4f ms, min %.4f, max %.4f" % (median_ms, replay_ms[0], replay_ms[-1]))
 
     # per-phase device time with HIP events on the launch stream (outside the graph)
     plan.use_graph(False)
@@ -390,12 +440,35 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # the small configurations (one source; 16 sources): plain and batched, eager calls
+    small = {}
+    if not args.no_small:
+        for name, g in (("single_source", synth.single_source()), ("region_16src", synth.region_16src())):
+            sp = B.Plan(g, check_status=False)
+            th = torch.tensor(g.theta, dtype=torch.float64, device=dev)
+            row = {"visits": sp.info()["n_visits"]}
+            for mode, label in ((B.CELESTE_PLAIN, "plain"), (B.CELESTE_BATCHED, "batched")):
+                sp.elbo_grad(th, mode=mode)
+                torch.cuda.synchronize()
+                reps = 20
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    sp.elbo_grad(th, mode=mode)
+                torch.cuda.synchronize()
+                ms = 1e3 * (time.perf_counter() - t0) / reps
+                row[label] = {"ms_per_eval": round(ms, 4), "visits_per_s": row["visits"] / (ms * 1e-3)}
+            small[name] = row
+            log("%s: plain %.3f ms, batched %.3f ms" % (name, row["plain"]["ms_per_eval"],
+                                                        row["batched"]["ms_per_eval"]))
+            del sp
+
     # batched result for the parity sample
     plan.elbo_grad(theta, mode=B.CELESTE_BATCHED, elbo=elbo, grad=grad)
     torch.cuda.synchronize()
     cpu, parity = None, None
     if not args.no_cpu:
-        cpu, rel_e, rel_g, n_checked = cpu_baseline(f, grad.cpu().numpy(), elbo.cpu().numpy(), args.cpu_seconds)
+        cpu, rel_e, rel_g, n_checked = cpu_baseline(f, grad.cpu().numpy(), elbo.cpu().numpy(), args.cpu_seconds,
+                                                    args.cpu_seconds_single)
         parity = {"sources_checked": int(n_checked), "max_rel_err_elbo": rel_e, "max_rel_err_grad": rel_g}
         log("cpu oracle: %.3e visits/s on %d cores" % (cpu["value"], cpu["cores"]))
 
@@ -407,7 +480,10 @@ def main():
                                   % (" with astrometry, sky maps and brightness-sized patches" if args.realistic
                                      else "", f.n_src),
                       "sources": f.n_src, "visits_per_step": visits, "form": "batched",
-                      "launch": {k: info[k] for k in LAUNCH_KEYS},
+                      "launch": {k: info[k] for k in LAUNCH_KEYS}, "autotune": tuned,
+                      "replay_ms_hip_events": {"median": round(median_ms, 4), "min": round(replay_ms[0], 4),
+                                               "max": round(replay_ms[-1], 4), "n": len(replay_ms),
+                                               "visits_per_s_at_median": visits / (median_ms * 1e-3)},
                       "phase_ms": [round(v, 4) for v in phase],
                       "path_flops_per_visit": round((adj_flops + render_flops) / visits, 1),
                       "path_tflops": round(whole, 3),
@@ -417,6 +493,7 @@ def main():
                       "plain": plain,
                       "batched_vs_plain": (value / plain["visits_per_s"]) if plain else None,
                       "hvp_all_sources": hvp,
+                      "small_configs": small or None,
                       "parity_vs_oracle": parity},
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
