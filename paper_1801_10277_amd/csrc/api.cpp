@@ -120,6 +120,8 @@ struct celeste_plan {
     int32_t* d_list_src = nullptr;   // [n_src]
     int32_t* d_list_pair = nullptr;  // [n_pairs]
     int32_t* d_list_item = nullptr;  // [cap_items]
+    int32_t* d_list_npair = nullptr; // [n_pairs] boxes whose stored values a Newton call renders
+    int32_t* d_list_nitem = nullptr; // [max_items] their items
     size_t cap_list_item = 0, cap_list_src = 0, cap_list_pair = 0;
     // conflict-free classes of boxes (no two boxes of a class share a pixel) and their items
     std::vector<int32_t> pair_class;
@@ -146,6 +148,7 @@ struct celeste_plan {
     hipEvent_t sweep_ev = nullptr;   // recorded after the last replay
     bool sweep_pending = false;
     double* d_scalar = nullptr;      // total ELBO written by a replayed sweep
+    double* d_tt_part = nullptr;     // [1024] partial sums of the total ELBO
 
     // graph cache of the batched elbo_grad sequence
     hipStream_t cap_stream = nullptr;
@@ -762,18 +765,13 @@ int fill_f64(double* d, const Sel& srcs, double v, hipStream_t st) {
     return CELESTE_OK;
 }
 
-// Lists of hs into device buffers (default: the plan's own list buffers, sized for each
-// source once) on `st`, through the plan's pinned staging: no host synchronisation except,
-// when the staging is still being read by the previous upload, a wait for that copy.
-// Growing the staging allocates pinned host memory.
-int upload_lists(celeste_plan* p, const HostScope& hs, hipStream_t st, int32_t* d_src = nullptr,
-                 int32_t* d_pair = nullptr, int32_t* d_item = nullptr) {
-    if (!d_src) {
-        d_src = p->d_list_src;
-        d_pair = p->d_list_pair;
-        d_item = p->d_list_item;
-    }
-    const size_t n = hs.src.size() + hs.pair.size() + hs.item.size();
+// Host lists into device buffers on `st`, through the plan's pinned staging: no host
+// synchronisation except, when the staging is still being read by the previous upload, a
+// wait for that copy.  Growing the staging allocates pinned host memory.
+int upload(celeste_plan* p, std::initializer_list<std::pair<const std::vector<int32_t>*, int32_t*>> lists,
+           hipStream_t st) {
+    size_t n = 0;
+    for (const auto& l : lists) n += l.first->size();
     if (p->stage_pending) {
         HIPCHK(hipEventSynchronize(p->stage_ev));
         p->stage_pending = false;
@@ -785,19 +783,71 @@ int upload_lists(celeste_plan* p, const HostScope& hs, hipStream_t st, int32_t* 
         HIPCHK(hipHostMalloc((void**)&p->h_stage, std::max<size_t>(n, 1024) * sizeof(int32_t), hipHostMallocDefault));
         p->cap_stage = std::max<size_t>(n, 1024);
     }
-    int32_t* h = p->h_stage;
-    std::copy(hs.src.begin(), hs.src.end(), h);
-    std::copy(hs.pair.begin(), hs.pair.end(), h + hs.src.size());
-    std::copy(hs.item.begin(), hs.item.end(), h + hs.src.size() + hs.pair.size());
-    if (!hs.src.empty())
-        HIPCHK(hipMemcpyAsync(d_src, h, hs.src.size() * 4, hipMemcpyHostToDevice, st));
-    if (!hs.pair.empty())
-        HIPCHK(hipMemcpyAsync(d_pair, h + hs.src.size(), hs.pair.size() * 4, hipMemcpyHostToDevice, st));
-    if (!hs.item.empty())
-        HIPCHK(hipMemcpyAsync(d_item, h + hs.src.size() + hs.pair.size(), hs.item.size() * 4, hipMemcpyHostToDevice,
-                              st));
+    size_t off = 0;
+    for (const auto& l : lists) {
+        const std::vector<int32_t>& v = *l.first;
+        if (v.empty()) continue;
+        std::copy(v.begin(), v.end(), p->h_stage + off);
+        HIPCHK(hipMemcpyAsync(l.second, p->h_stage + off, v.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        off += v.size();
+    }
     HIPCHK(hipEventRecord(p->stage_ev, st));
     p->stage_pending = true;
+    return CELESTE_OK;
+}
+
+int upload_lists(celeste_plan* p, const HostScope& hs, hipStream_t st) {
+    return upload(p, {{&hs.src, p->d_list_src}, {&hs.pair, p->d_list_pair}, {&hs.item, p->d_list_item}}, st);
+}
+
+// The boxes whose tables, coefficients and stored own profile values a call on the listed
+// boxes reads: the listed boxes and every box of the same image meeting one (whose stored
+// values the listed boxes' backgrounds sum), with their items.
+void neighbour_lists(const celeste_plan* p, const HostScope& hs, std::vector<int32_t>& npair,
+                     std::vector<int32_t>& nitem) {
+    std::vector<char> mark(p->pairs.size(), 0);
+    for (int32_t pi : hs.pair) {
+        mark[pi] = 1;
+        for (int q = p->pairs[pi].nbr_begin; q < p->pairs[pi].nbr_end; ++q) mark[p->nbr[q]] = 1;
+    }
+    npair.clear();
+    nitem.clear();
+    for (size_t q = 0; q < mark.size(); ++q)
+        if (mark[q]) {
+            npair.push_back((int32_t)q);
+            for (int it = p->pairs[q].item_begin; it < p->pairs[q].item_end; ++it) nitem.push_back(it);
+        }
+}
+
+// Lists of hs and, when the stored-value render is used (`stored`), the boxes whose stored
+// own profile values and brightness coefficients the listed boxes' backgrounds read: every
+// box when those are most of the field, else the neighbour boxes only (uploaded with the
+// lists).  *render receives the boxes and items to render.
+int upload_scope(celeste_plan* p, const HostScope& hs, bool stored, Scope* render, hipStream_t st) {
+    std::vector<int32_t> npair, nitem;
+    if (stored) neighbour_lists(p, hs, npair, nitem);
+    const bool restrict_render = stored && 2 * nitem.size() < p->items.size();
+    if (restrict_render)
+        CHK(upload(p, {{&hs.src, p->d_list_src}, {&hs.pair, p->d_list_pair}, {&hs.item, p->d_list_item},
+                       {&npair, p->d_list_npair}, {&nitem, p->d_list_nitem}},
+                   st));
+    else
+        CHK(upload_lists(p, hs, st));
+    *render = scope_all(p);
+    if (restrict_render) {
+        render->pair = Sel{p->d_list_npair, 0, (int32_t)npair.size()};
+        render->item = Sel{p->d_list_nitem, 0, (int32_t)nitem.size()};
+    }
+    return CELESTE_OK;
+}
+
+// Stored own profile values and coefficients of the boxes of `render` (d_fg then no longer
+// holds a full render's values).
+int render_stored(celeste_plan* p, const double* theta, const Scope& render, hipStream_t st) {
+    CHK(prep(p, theta, render.pair, false, DIR_NONE, nullptr, 0, st));
+    HIPCHK(launch_strip_fg(render.item, p->geom(), p->d_tab1, p->d_fg, p->rows, p->persistent_grid(), p->wpb,
+                           p->d_status, st));
+    p->fg_valid = false;
     return CELESTE_OK;
 }
 
@@ -964,7 +1014,7 @@ void celeste_plan_destroy(celeste_plan* p) {
                     p->d_pred, p->d_elbo_cur, p->d_elbo_trial, p->d_radius, p->d_done, p->d_list_src,
                     p->d_list_pair, p->d_list_item, p->d_cls_items, p->d_pair_lgamma, p->d_fg, p->d_gw,
                     p->d_hw, p->d_kk, p->d_hg, p->d_hc, p->d_grad_trial, p->d_hess_trial, p->d_accepted, p->d_live,
-                    p->d_mix, p->d_scalar};
+                    p->d_mix, p->d_scalar, p->d_tt_part, p->d_list_npair, p->d_list_nitem};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -1082,8 +1132,11 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     A(dalloc(&p->d_list_src, S, W));
     A(dalloc(&p->d_list_pair, np, W));
     A(dalloc(&p->d_list_item, max_items, W));
+    A(dalloc(&p->d_list_npair, np, W));
+    A(dalloc(&p->d_list_nitem, max_items, W));
     A(dalloc(&p->d_cls_items, max_items, W));
     A(dalloc(&p->d_scalar, 1, W));
+    A(dalloc(&p->d_tt_part, 1024, W));
     if (d->flags & CELESTE_COLOR_MIXTURE) A(dalloc(&p->d_mix, 2 * NMIX * MIXF, W));
     p->cap_list_item = max_items;
     p->cap_list_src = S;
@@ -1298,20 +1351,21 @@ int celeste_hessian(celeste_plan* p, const double* theta, const int32_t* src, in
     }
     HostScope hs;
     scope_lists(p, src, n, hs);
-    CHK(upload_lists(p, hs, st));
+    const bool stored = p->render_mode == 2 || p->render_mode == 3;
+    Scope rs;
+    CHK(upload_scope(p, hs, stored, &rs, st));
     const Sel ss{p->d_list_src, 0, (int32_t)hs.src.size()};
     const Sel sp{p->d_list_pair, 0, (int32_t)hs.pair.size()};
     const Sel si{p->d_list_item, 0, (int32_t)hs.item.size()};
-    const Scope all = scope_all(p);
     CHK(validate_theta(p, theta, nullptr, nullptr, p->n_src, st));
     // stored per-visit backgrounds, as in a Newton iteration (with the strip render, summed
-    // from every box's stored own values)
-    CHK(prep(p, theta, all.pair, false, DIR_NONE, nullptr, 0, st));
-    if (p->render_mode == 2 || p->render_mode == 3) {
-        HIPCHK(launch_strip_fg(all.item, p->geom(), p->d_tab1, p->d_fg, p->rows, p->persistent_grid(), p->wpb,
-                               p->d_status, st));
+    // from the neighbour boxes' stored own values)
+    if (stored) {
+        CHK(render_stored(p, theta, rs, st));
         CHK(background(p, si, st, true));
     } else {
+        const Scope all = scope_all(p);
+        CHK(prep(p, theta, all.pair, false, DIR_NONE, nullptr, 0, st));
         CHK(background(p, si, st));
     }
     CHK(adjoint(p, si, nullptr, false, BASE_BG, true, st, 0, true));
@@ -1327,7 +1381,8 @@ int celeste_total_elbo(celeste_plan* p, const double* theta, double* out, hipStr
     CHK(validate_theta(p, theta, nullptr, nullptr, p->n_src, st));
     CHK(prep(p, theta, sc.pair, false, DIR_NONE, nullptr, 0, st));
     CHK(render(p, st, true));
-    HIPCHK(launch_tile_total(p->d_tile_sums, (int)p->tiles.size(), theta, p->consts, p->n_src, out, p->d_status, st));
+    HIPCHK(launch_tile_total(p->d_tile_sums, (int)p->tiles.size(), theta, p->consts, p->n_src, p->d_tt_part, out,
+                             p->d_status, st));
     return CELESTE_OK;
 }
 
@@ -1344,23 +1399,18 @@ int celeste_newton(celeste_plan* p, double* theta, const int32_t* src, int n, in
     }
     HostScope hs;
     scope_lists(p, src, n, hs);
-    CHK(upload_lists(p, hs, st));
+    // with the strip render, the own profile values of the boxes the listed visits' backgrounds
+    // read are stored once and the backgrounds are summed from them (cheaper than evaluating
+    // the neighbours' Gaussians per visit)
+    const bool stored = p->render_mode == 2 || p->render_mode == 3;
+    Scope rs;
+    CHK(upload_scope(p, hs, stored && n_steps > 0, &rs, st));
     const Sel ss{p->d_list_src, 0, (int32_t)hs.src.size()};
     const Sel sp{p->d_list_pair, 0, (int32_t)hs.pair.size()};
     const Sel si{p->d_list_item, 0, (int32_t)hs.item.size()};
     CHK(validate_theta(p, theta, nullptr, p->d_list_src, n, st));
     CHK(fill_u8(p->d_done, ss, 0, st));
-    // with the strip render, every box's own profile values are stored once and the listed
-    // visits take their background from them (cheaper than evaluating the neighbours'
-    // Gaussians per visit)
-    const bool stored = p->render_mode == 2 || p->render_mode == 3;
-    if (stored && n_steps > 0) {
-        const Scope all = scope_all(p);
-        CHK(prep(p, theta, all.pair, false, DIR_NONE, nullptr, 0, st));
-        HIPCHK(launch_strip_fg(all.item, p->geom(), p->d_tab1, p->d_fg, p->rows, p->persistent_grid(), p->wpb,
-                               p->d_status, st));
-        p->fg_valid = false;
-    }
+    if (stored && n_steps > 0) CHK(render_stored(p, theta, rs, st));
     CHK(newton_run(p, theta, ss, sp, si, n_steps, prm, radius, st, stored && n_steps > 0));
     if (elbo_out) {
         // final ELBO_s at the returned point
@@ -1605,7 +1655,7 @@ int celeste_sweep(celeste_plan* p, double* theta, const int32_t* batch_ptr, cons
         // every box's stored own values and coefficients are current: the total needs the
         // gather only, not the strip pass
         CHK(gather(p, true, s));
-        HIPCHK(launch_tile_total(p->d_tile_sums, (int)p->tiles.size(), theta, p->consts, p->n_src, total,
+        HIPCHK(launch_tile_total(p->d_tile_sums, (int)p->tiles.size(), theta, p->consts, p->n_src, p->d_tt_part, total,
                                  p->d_status, s));
         return CELESTE_OK;
     };

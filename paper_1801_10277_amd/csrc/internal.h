@@ -246,8 +246,9 @@ hipError_t launch_render_strips(const Sel& items, const Geometry& g, const doubl
                                 double* E, double* V, int strip_rows, int grid, int waves_per_block,
                                 const int* status, hipStream_t st);
 hipError_t launch_finalize(const FinArgs& a, bool tangent, hipStream_t st);
+// Total ELBO from the per-tile sums and every KL; part: device scratch of 1024 doubles.
 hipError_t launch_tile_total(const double* tile_sums, int n_tiles, const double* theta, const Consts& c,
-                             int S, double* out, const int* status, hipStream_t st);
+                             int S, double* part, double* out, const int* status, hipStream_t st);
 hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st);
 hipError_t launch_fill_u8_sel(uint8_t* p, const Sel& s, uint8_t v, hipStream_t st);
 hipError_t launch_fill_f64_sel(double* p, const Sel& s, double v, hipStream_t st);

@@ -393,30 +393,52 @@ __global__ void __launch_bounds__(128) k_assemble_hessian(Sel srcs, Geometry g, 
     for (int i = 0; i < npar; ++i) o[i] = gh[i].t;
 }
 
-// Total ELBO: fixed-order sum of the per-tile pixel sums minus every source's KL, by one
-// work-group of TT_THREADS threads.
-constexpr int TT_THREADS = 1024;
-__global__ void __launch_bounds__(TT_THREADS) k_tile_total(const double* tile_sums, int n_tiles,
-                                                           const double* theta, Consts K, int S,
-                                                           double* out, const int* status) {
-    if (*status) return;
-    __shared__ double red[TT_THREADS];
-    double acc = 0.0;
-    for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) acc += tile_sums[t];
-    if (K.flags & CELESTE_INCLUDE_KL) {
-        for (int s = threadIdx.x; s < S; s += blockDim.x) {
-            double p[NPK], g[NPK];
-            for (int i = 0; i < NPK; ++i) { p[i] = theta[(size_t)s * ROW + i]; g[i] = 0.0; }
-            acc -= kl_source<double>(p, K, g);
-        }
-    }
-    red[threadIdx.x] = acc;
+// Total ELBO: a fixed-order two-level sum.  Block b of k_total_partial sums its contiguous
+// slices of the per-tile pixel sums and of the sources' KL terms (a fixed tree per block) into
+// part[b]; k_total_final sums the TT_BLOCKS partials in block order.  Deterministic, and
+// spread over the chip instead of one work-group.
+constexpr int TT_THREADS = 256;
+constexpr int TT_BLOCKS = 1024;
+
+__device__ inline double block_sum_256(double v, double* red) {
+    red[threadIdx.x] = v;
     __syncthreads();
     for (int w = TT_THREADS / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = red[0];
+    return red[0];
+}
+
+__global__ void __launch_bounds__(TT_THREADS) k_total_partial(const double* __restrict__ tile_sums, int n_tiles,
+                                                              const double* __restrict__ theta, Consts K, int S,
+                                                              double* __restrict__ part, const int* status) {
+    if (*status) return;
+    __shared__ double red[TT_THREADS];
+    const int b = blockIdx.x;
+    const int t0 = (int)((int64_t)n_tiles * b / TT_BLOCKS), t1 = (int)((int64_t)n_tiles * (b + 1) / TT_BLOCKS);
+    double acc = 0.0;
+    for (int t = t0 + threadIdx.x; t < t1; t += TT_THREADS) acc += tile_sums[t];
+    if (K.flags & CELESTE_INCLUDE_KL) {
+        const int s0 = (int)((int64_t)S * b / TT_BLOCKS), s1 = (int)((int64_t)S * (b + 1) / TT_BLOCKS);
+        for (int s = s0 + threadIdx.x; s < s1; s += TT_THREADS) {
+            double p[NPK], g[NPK];
+            for (int i = 0; i < NPK; ++i) { p[i] = theta[(size_t)s * ROW + i]; g[i] = 0.0; }
+            acc -= kl_source<double>(p, K, g);
+        }
+    }
+    const double v = block_sum_256(acc, red);
+    if (threadIdx.x == 0) part[b] = v;
+}
+
+__global__ void __launch_bounds__(TT_THREADS) k_total_final(const double* __restrict__ part, double* out,
+                                                            const int* status) {
+    if (*status) return;
+    __shared__ double red[TT_THREADS];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < TT_BLOCKS; b += TT_THREADS) acc += part[b];
+    const double v = block_sum_256(acc, red);
+    if (threadIdx.x == 0) out[0] = v;
 }
 
 __global__ void k_fill_int(int* p, int v, int n) {
@@ -475,8 +497,10 @@ hipError_t launch_finalize(const FinArgs& a, bool tangent, hipStream_t st) {
 }
 
 hipError_t launch_tile_total(const double* tile_sums, int n_tiles, const double* theta, const Consts& c,
-                             int S, double* out, const int* status, hipStream_t st) {
-    hipLaunchKernelGGL(k_tile_total, dim3(1), dim3(TT_THREADS), 0, st, tile_sums, n_tiles, theta, c, S, out, status);
+                             int S, double* part, double* out, const int* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_total_partial, dim3(TT_BLOCKS), dim3(TT_THREADS), 0, st, tile_sums, n_tiles, theta, c, S,
+                       part, status);
+    hipLaunchKernelGGL(k_total_final, dim3(1), dim3(TT_THREADS), 0, st, part, out, status);
     return hipGetLastError();
 }
 

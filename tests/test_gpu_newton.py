@@ -282,3 +282,26 @@ def test_sweep_graph_replays_match_eager(B, synth, schedule):
     for a, b in zip(tr_e, tr_g):
         assert torch.equal(a, b), (a, b)
     assert torch.equal(th_e, th_g)
+
+
+def test_newton_one_source_equals_its_part_of_a_batch(B, synth):
+    """Newton on one listed source (its backgrounds from the stored values of its neighbour
+    boxes only) gives bitwise the parameters, ELBO and radius that source reaches when every
+    source is listed (each listed source sees the others at their entry values)."""
+    f = synth.tiny(S=10, n_bands=2, size=60, side=11, seed=91)
+    plan = B.Plan(f)
+    th_all = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+    e_all, r_all = plan.newton(th_all, list(range(10)), 3)
+    for s in (0, 4, 9):
+        th = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+        say("case newton one source", s)
+        e1, r1 = plan.newton(th, [s], 3)
+        assert torch.equal(th[s], th_all[s]) and e1[s] == e_all[s] and r1[s] == r_all[s], s
+        others = [t for t in range(10) if t != s]
+        np.testing.assert_array_equal(th.cpu().numpy()[others], f.theta[others])
+        # a Hessian call on a fresh plan (no tables left by an earlier call) for one source
+        # and for all of them
+        fresh = B.Plan(f)
+        H1 = fresh.hessian(th, [s])
+        Ha = B.Plan(f).hessian(th, list(range(10)))
+        assert torch.equal(H1[0], Ha[s]), s
