@@ -52,12 +52,19 @@ __host__ __device__ inline dual value_with_tangent(double base, dual own) { retu
 
 // Unroll factor of the loops over the 42 galaxy Gaussians.  Value arithmetic: two at a
 // time, so that one component's table loads and seed overlap the other's rows (measured
-// best of 1, 2, 3, 6).  Dual (value + tangent) arithmetic keeps one: its kernels already
-// hold 256 VGPRs plus accumulation registers, and the two-at-a-time fused adjoint with
-// neighbour backgrounds at 16-row strips returned wrong tangents (values correct) in a
-// build whose only difference was this factor.
+// best of 1, 2, 3, 6).  Dual (value + tangent) arithmetic keeps one.  At two, the tangent
+// products of the streamed passes (own values recomputed, planes or stored backgrounds)
+// came out bitwise equal to those at one, but the pass that recomputes both the own values
+// and the neighbours' background per strip (stored neighbour values, 16-row strips) returned
+// tangents off by up to a factor of four in the position and shape directions while its
+// values and gradients agreed to 1e-12; the source changes no index or lane assignment with
+// this factor, and the cause in the generated code is not identified (its kernels spill a
+// few hundred bytes per lane at either factor).
 #ifndef CELESTE_GAL_UNROLL
 #define CELESTE_GAL_UNROLL 2
+#endif
+#ifndef CELESTE_DUAL_GAL_UNROLL
+#define CELESTE_DUAL_GAL_UNROLL 1
 #endif
 
 template <class T> struct scalar_traits;
@@ -68,6 +75,6 @@ template <> struct scalar_traits<double> {
 };
 template <> struct scalar_traits<dual> {
     static constexpr int width = 2;
-    static constexpr int gal_unroll = 1;
+    static constexpr int gal_unroll = CELESTE_DUAL_GAL_UNROLL;
     __host__ __device__ static dual make(double v, double t) { return mkd(v, t); }
 };
