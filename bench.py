@@ -47,10 +47,14 @@ N_STAR, N_GAL = 3, 42                   # Gaussians per (source, image): 3 star,
 # pass and its values are stored; the fused adjoint runs the pixel terms and pass B (seed
 # again; per row one FMA and one (star) or two (galaxy) running-sum adds; per strip the
 # moments from the running sums and the fold into the ten intermediates).
+# Pass B takes its table staged in LDS with the offsets from each PSF group's shared centre
+# formed once per group (12 FLOPs), so its seed costs 9 + 2 exps and its fold 11 (star) or
+# 46 (galaxy) FLOPs.
 SEED = 16 + 2 * FEXP_FLOPS
+SEED_B = 9 + 2 * FEXP_FLOPS
 PASS_A_PER_STRIP = (N_STAR + N_GAL) * SEED
 PASS_A_PER_VISIT = N_STAR * 3 + N_GAL * 4
-PASS_B_PER_STRIP = (N_STAR + N_GAL) * SEED + N_STAR * 14 + N_GAL * 53
+PASS_B_PER_STRIP = 3 * 12 + (N_STAR + N_GAL) * SEED_B + N_STAR * 11 + N_GAL * 46
 PASS_B_PER_VISIT = N_STAR * 5 + N_GAL * 6
 PIXEL_PER_VISIT = 40 + FLOG_FLOPS + FRCP_FLOPS
 GATHER_PER_VISIT = 11

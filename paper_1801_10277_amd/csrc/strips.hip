@@ -154,6 +154,118 @@ __device__ __forceinline__ void strip_adjoint(const T* __restrict__ tab, double 
     }
 }
 
+// Pass B of the value-gradient adjoint from a box table staged in LDS.
+// The star component and the 14 galaxy components of one PSF component share their centre
+// (the source position plus that PSF component's offset), so the offsets dx = px - cx,
+// dy = py0 - cy and their products are formed once per group and strip.  With
+// P = [[a, b], [b, d]] and j = py0 + k - cy the row offset from the centre, a component's
+// exponent is LW - (a dx^2 + 2 b dx dy + d dy^2) / 2 and its first row ratio
+// exp(-(b dx + d dy) - d / 2), and every intermediate's contribution is a combination of
+// the raw row moments M_i = sum_k t_k j^i (t_k = row weight x value).  With
+// U = a dx M0 + b M1, U' = b dx M0 + d M1 (the sums of t (P (m - mu))_x and _y),
+// W = a dx M1 + b M2 and W' = b dx M1 + d M2:
+//   position:  wt U, wt U';    frac_dev: sgn M0;
+//   shape xx:  wnu (a (dx U - M0) + b W),   xy: wnu (b (dx U - M0) + d W),
+//   shape yy:  wnu (b dx U' + d (W' - M0)),
+// (the sums of t ((P (m - mu))_x^2 - a), t ((P (m - mu))_x (P (m - mu))_y - b) and
+// t ((P (m - mu))_y^2 - d)).  The moments come from the running sums A, B, C of the strip
+// recurrence through the row-moment identity about a centre c with L - c = e = L + dy:
+// M0 = A, M1 = e A - B, M2 = e^2 A - (2e + 1) B + 2C.  Per galaxy component this takes 29
+// operations after the rows, against about 38 for the same fold about the strip centre with
+// per-lane products of the precision, and the seed 6 instead of 12.
+// Staged table: field-major, [NDF][NCP] (lane c writes component c's fields at stride NCP,
+// no bank conflicts; every lane then reads the same words); stars at slots 0..2, galaxy
+// group g at 4 + 14 g, so that the pairs of the unrolled galaxy loop are 16-byte aligned.
+constexpr int NCP = 46;
+enum DerivedField { D_CX = 0, D_CY, D_LW, D_RDY, D_A, D_B, D_D, D_WT, D_WNU, D_SGN, NDF };
+
+__device__ __forceinline__ int staged_slot(int c) { return c < NPSF ? c : c + 1; }
+
+// One wave writes the staged table of a box into its LDS slot (lane c: component c).
+__device__ __forceinline__ void stage_derived(const double* __restrict__ tab, double* my, int lane) {
+    if (lane < NCOMP) {
+        const double* e = tab + lane * CST;
+        double* o = my + staged_slot(lane);
+        o[D_CX * NCP] = e[F_CX];
+        o[D_CY * NCP] = e[F_CY];
+        o[D_LW * NCP] = e[F_LOGW];
+        o[D_RDY * NCP] = e[F_RDY];
+        o[D_A * NCP] = e[F_PXX];
+        o[D_B * NCP] = e[F_PXY];
+        o[D_D * NCP] = e[F_PYY];
+        o[D_WT * NCP] = e[F_WT];
+        o[D_WNU * NCP] = e[F_WNU];
+        o[D_SGN * NCP] = e[F_SGN];
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void strip_adjoint_staged(const double* __restrict__ lt, double px, double py0,
+                                                     const double* Gs, const double* Gg, double* acc,
+                                                     const double* __restrict__ t2) {
+#pragma unroll 1
+    for (int grp = 0; grp < NPSF; ++grp) {
+        const double* es = lt + grp;
+        const double dx = px - es[D_CX * NCP], dy = py0 - es[D_CY * NCP];
+        const double h2x = -0.5 * (dx * dx), mxy = -(dx * dy), h2y = -0.5 * (dy * dy);
+        const double mdx = -dx, mdyh = -(dy + 0.5);
+        const double ev = (double)L + dy;
+        const double ev2 = ev * ev, e21 = 2.0 * ev + 1.0;
+        {
+            const double a = es[D_A * NCP], b = es[D_B * NCP], d = es[D_D * NCP];
+            double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, es[D_LW * NCP]))), t2);
+            double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
+            const double rdy = es[D_RDY * NCP];
+            double A = 0.0, B = 0.0;
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                A = fma(Gs[k], n, A);
+                B += A;
+                if (k + 1 < L) {
+                    n = n * rt;
+                    rt = rt * rdy;
+                }
+            }
+            const double M1 = fma(ev, A, -B), X1 = dx * A;
+            acc[A_UX] = fma(a, X1, fma(b, M1, acc[A_UX]));
+            acc[A_UY] = fma(b, X1, fma(d, M1, acc[A_UY]));
+        }
+        const double* eg = lt + NPSF + 1 + grp * NGAL_PER_PSF;
+#pragma unroll CELESTE_GAL_UNROLL
+        for (int c = 0; c < NGAL_PER_PSF; ++c) {
+            const double* e = eg + c;
+            const double a = e[D_A * NCP], b = e[D_B * NCP], d = e[D_D * NCP];
+            double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, e[D_LW * NCP]))), t2);
+            double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
+            const double rdy = e[D_RDY * NCP];
+            double A = 0.0, B = 0.0, C = 0.0;
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                A = fma(Gg[k], n, A);
+                B += A;
+                C += B;
+                if (k + 1 < L) {
+                    n = n * rt;
+                    rt = rt * rdy;
+                }
+            }
+            const double M1 = fma(ev, A, -B), M2 = fma(ev2, A, fma(-e21, B, C + C));
+            const double X1 = dx * A, Y1 = dx * M1;
+            const double U = fma(a, X1, b * M1), Up = fma(b, X1, d * M1);
+            const double W = fma(a, Y1, b * M2), Wp = fma(b, Y1, d * M2);
+            const double dU = fma(dx, U, -A), dUp = dx * Up, Wm = Wp - A;
+            const double wt = e[D_WT * NCP], wnu = e[D_WNU * NCP];
+            const double wna = wnu * a, wnb = wnu * b, wnd = wnu * d;
+            acc[A_FDEV] = fma(e[D_SGN * NCP], A, acc[A_FDEV]);
+            acc[A_UX] = fma(wt, U, acc[A_UX]);
+            acc[A_UY] = fma(wt, Up, acc[A_UY]);
+            acc[A_SXX] = fma(wna, dU, fma(wnb, W, acc[A_SXX]));
+            acc[A_SXY] = fma(wnb, dU, fma(wnd, W, acc[A_SXY]));
+            acc[A_SYY] = fma(wnb, dUp, fma(wnd, Wm, acc[A_SYY]));
+        }
+    }
+}
+
 // Pixel term of one row: accumulates the value and d/dk1..k4 and returns the row
 // weights d l / d f_star and d l / d f_gal.
 // (The -log(x!) constant is not added here: each box's sum of it is precomputed once.)
@@ -343,8 +455,10 @@ __global__ void __launch_bounds__(256) k_render_strips(Sel sel, const Item* __re
 // At least two waves per SIMD: the dual-number variants would otherwise take 256 VGPRs
 // plus accumulation registers and run one wave per SIMD; with the bound they spill a few
 // hundred bytes per lane and run 17% faster (the value variants fit without spilling).
+// Three for the value-gradient pass over stored own values (the hot path): it needs 191
+// VGPRs unbounded and 168 with the bound (two registers spilled).
 template <class T, int BASE, bool DERIV, int L, bool FGM, bool KK>
-__global__ void __launch_bounds__(256, 2) k_adjoint_strips(AdjArgs a, const Item* __restrict__ items,
+__global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>::value) ? 3 : 2) k_adjoint_strips(AdjArgs a, const Item* __restrict__ items,
                                                         const PairDev* __restrict__ pairs,
                                                         const celeste_image* __restrict__ images,
                                                         const int32_t* __restrict__ nbr,
@@ -361,13 +475,14 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_strips(AdjArgs a, const Item
     __shared__ double t2[64];
     __shared__ double2 tl[128];
     // The value-gradient pass over stored own values (the hot path) reads each box's table
-    // from LDS, copied by the wave at the start of each item: the per-component loads of the
-    // galaxy loop then wait on LDS instead of missing the scalar cache (38% of the scalar
-    // loads missed with the table read from global memory), and the table leaves the scalar
-    // registers (no spills).
+    // from LDS, staged by the wave at the start of each item in the derived form of
+    // strip_adjoint_staged: the per-component loads of the galaxy loop then wait on LDS
+    // instead of missing the scalar cache (38% of the scalar loads missed with the table read
+    // from global memory), the table leaves the scalar registers (no spills), and the
+    // coefficients every lane shares are formed once per box instead of once per strip.
     constexpr bool LDS_TAB = FGM && DERIV && (BASE == BASE_PLANES || BASE == BASE_FG) &&
                              std::is_same<T, double>::value;
-    __shared__ double ltab[LDS_TAB ? 4 : 1][LDS_TAB ? NCOMP * CST : 1];
+    extern __shared__ double ltab[];   // LDS_TAB: [waves per block][NCOMP][NDF], sized at launch
     fill_log_table(tl);
     fill_exp_table(t2);
     const int lane = threadIdx.x & 63;
@@ -384,9 +499,9 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_strips(AdjArgs a, const Item
             const T* tab = reinterpret_cast<const T*>(tabp) + (size_t)it.pair * NCOMP * CST;
             if constexpr (LDS_TAB) {
                 // the wave's previous item has finished reading its copy (in-order LDS)
-                double* my = ltab[threadIdx.x >> 6];
+                double* my = ltab + (threadIdx.x >> 6) * (NCP * NDF);
                 __builtin_amdgcn_wave_barrier();
-                for (int i = lane; i < NCOMP * CST; i += 64) my[i] = tab[i];
+                stage_derived(reinterpret_cast<const double*>(tab), my, lane);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -453,7 +568,8 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_strips(AdjArgs a, const Item
                         __builtin_amdgcn_sched_barrier(0);
                     }
                     if constexpr (LDS_TAB)
-                        strip_adjoint<T, L>(ltab[threadIdx.x >> 6], px, py0, Gs, Gg, acc, t2);
+                        strip_adjoint_staged<L>(ltab + (threadIdx.x >> 6) * (NCP * NDF), px, py0, Gs, Gg,
+                                                acc, t2);
                     else
                         strip_adjoint<T, L>(tab, px, py0, Gs, Gg, acc, t2);
                     continue;
@@ -1165,7 +1281,10 @@ hipError_t launch_render_strips(const Sel& sel, const Geometry& g, const double*
 template <class T, int BASE, bool DERIV, int L, bool FGM, bool KK>
 static void adjk(const AdjArgs& a, int grid, int wpb, hipStream_t st) {
     const Geometry& g = a.g;
-    hipLaunchKernelGGL((k_adjoint_strips<T, BASE, DERIV, L, FGM, KK>), dim3(grid), dim3(64 * wpb), 0, st, a,
+    constexpr bool lds_tab = FGM && DERIV && (BASE == BASE_PLANES || BASE == BASE_FG) &&
+                             std::is_same<T, double>::value;
+    const size_t lds = lds_tab ? (size_t)wpb * NCP * NDF * sizeof(double) : 0;
+    hipLaunchKernelGGL((k_adjoint_strips<T, BASE, DERIV, L, FGM, KK>), dim3(grid), dim3(64 * wpb), lds, st, a,
                        g.items, g.pairs, g.images, g.nbr, g.x, a.E, a.V, a.bg, a.tab, a.coef, a.tab_val, a.coef_val,
                        a.active, a.fg, a.partials);
 }
