@@ -82,7 +82,7 @@ enum celeste_flags {
                                      sum_d kappa_d KL(N(c_mu, diag c_var) || N(mean_d, cov_d)) */
 };
 
-/* One image: header of a row-major H x W plane of float64 counts inside x. */
+/* One image: header of a row-major H x W plane of float64 counts inside x (H * W < 2^29). */
 typedef struct celeste_image {
     int32_t band;         /* 0..4 = u, g, r, i, z */
     int32_t H, W;
@@ -100,7 +100,8 @@ typedef struct celeste_image {
                              A galaxy's world-frame shape covariance S appears as wcs S wcs^T */
 } celeste_image;
 
-/* A source's patch ("active pixels") in one image: rows r0..r0+h-1, cols c0..c0+w-1. */
+/* A source's patch ("active pixels") in one image: rows r0..r0+h-1, cols c0..c0+w-1
+   (h * w < 2^28). */
 typedef struct celeste_box {
     int32_t img, r0, c0, h, w;
 } celeste_box;

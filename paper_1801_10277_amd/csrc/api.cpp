@@ -422,6 +422,7 @@ int validate_desc(const celeste_problem_desc* d) {
     for (int n = 0; n < d->n_img; ++n) {
         const celeste_image& im = d->images[n];
         if (im.band < 0 || im.band > 4 || im.H <= 0 || im.W <= 0 || im.pix_offset < 0) return CELESTE_EINVAL;
+        if ((int64_t)im.H * im.W >= ((int64_t)1 << 29)) return CELESTE_EINVAL;   // 32-bit byte offsets
         if (im.pix_offset + (int64_t)im.H * im.W > d->n_pix) return CELESTE_EINVAL;
         if (!(im.sky > 0.0) || !finite(im.sky) || !(im.iota > 0.0) || !finite(im.iota)) return CELESTE_EINVAL;
         if (!finite(im.origin_x) || !finite(im.origin_y)) return CELESTE_EINVAL;
@@ -454,6 +455,7 @@ int validate_desc(const celeste_problem_desc* d) {
             const celeste_image& im = d->images[bx.img];
             if (bx.h <= 0 || bx.w <= 0 || bx.r0 < 0 || bx.c0 < 0 || bx.r0 + bx.h > im.H || bx.c0 + bx.w > im.W)
                 return CELESTE_EINVAL;
+            if ((int64_t)bx.h * bx.w >= ((int64_t)1 << 28)) return CELESTE_EINVAL;   // 32-bit byte offsets
             for (int b2 = d->patch_ptr[s]; b2 < b; ++b2)
                 if (d->boxes[b2].img == bx.img) return CELESTE_EINVAL;
         }

@@ -20,31 +20,32 @@ __device__ __forceinline__ double sky_at(const celeste_image& im, int r, int c) 
 constexpr double LOG_2PI = 1.8378770664093454836;
 
 // Table-driven exponential (P. T. P. Tang, "Table-driven implementation of the exponential
-// function in IEEE floating-point arithmetic", ACM TOMS 15(2), 1989), with 64 table
-// entries: x = (64 k + j) ln2/64 + r, |r| <= ln2/128, so e^x = 2^k 2^(j/64) e^r and e^r is
-// the degree-5 Taylor polynomial (truncation r^6/720 < 3.5e-17 relative).  The table
-// t2[j] = 2^(j/64) lives in LDS (fill_exp_table).  Accuracy within a few ulps of the
+// function in IEEE floating-point arithmetic", ACM TOMS 15(2), 1989), with 256 table
+// entries: x = (256 k + j) ln2/256 + r, |r| <= ln2/512, so e^x = 2^k 2^(j/256) e^r and e^r is
+// the degree-4 Taylor polynomial (truncation r^5/120 < 3.8e-17 relative).  The reduction
+// x - n ln2/256 takes ln2/256 in two parts through fused multiply-adds.  The table
+// t2[j] = 2^(j/256) lives in LDS (fill_exp_table).  Accuracy within a few ulps of the
 // correctly rounded result for arguments down to the underflow threshold; arguments must
 // be <= 709 (callers clamp) and not NaN.
-constexpr double INV_LN2_64 = 92.332482616893656877;       // 64 / ln 2
-constexpr double LN2_64_HI = 1.0830424696249145e-02;        // ln 2 / 64, leading part
-constexpr double LN2_64_LO = 3.623510646634843e-19;         // ln 2 / 64 - LN2_64_HI
+constexpr int EXP_TAB = 256;
+constexpr double INV_LN2_256 = 369.32993046757463228;      // 256 / ln 2
+constexpr double LN2_256_HI = 2.7076061740622862743e-03;    // ln 2 / 256 rounded
+constexpr double LN2_256_LO = 9.0587766165871076501e-20;    // ln 2 / 256 - LN2_256_HI
 
 __device__ __forceinline__ void fill_exp_table(double* t2) {
-    for (int j = threadIdx.x; j < 64; j += blockDim.x) t2[j] = exp2((double)j * (1.0 / 64.0));
+    for (int j = threadIdx.x; j < EXP_TAB; j += blockDim.x) t2[j] = exp2((double)j * (1.0 / EXP_TAB));
     __syncthreads();
 }
 
 __device__ __forceinline__ double fexp(double x, const double* __restrict__ t2) {
-    const double n = rint(x * INV_LN2_64);
-    const double r = fma(-n, LN2_64_LO, fma(-n, LN2_64_HI, x));
+    const double n = rint(x * INV_LN2_256);
+    const double r = fma(-n, LN2_256_LO, fma(-n, LN2_256_HI, x));
     const int ni = (int)n;
-    double p = fma(r, 1.0 / 120.0, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
+    double p = fma(r, 1.0 / 24.0, 1.0 / 6.0);
     p = fma(p, r, 0.5);
     p = fma(p, r, 1.0);
     p = fma(p, r, 1.0);
-    return ldexp(t2[ni & 63] * p, ni >> 6);
+    return ldexp(t2[ni & (EXP_TAB - 1)] * p, ni >> 8);
 }
 
 __device__ __forceinline__ dual fexp(dual x, const double* __restrict__ t2) {

@@ -419,7 +419,7 @@ __global__ void __launch_bounds__(256) k_render_strips(Sel sel, const Item* __re
                                                        const double* __restrict__ coef, double* __restrict__ E,
                                                        double* __restrict__ V, const int* status) {
     if (*status) return;
-    __shared__ double t2[64];
+    __shared__ double t2[EXP_TAB];
     fill_exp_table(t2);
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -472,7 +472,7 @@ __global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>:
                                                         const double* __restrict__ fgm,
                                                         double* __restrict__ partials) {
     if (*a.status) return;
-    __shared__ double t2[64];
+    __shared__ double t2[EXP_TAB];
     __shared__ double2 tl[128];
     // The value-gradient pass over stored own values (the hot path) reads each box's table
     // from LDS, staged by the wave at the start of each item in the derived form of
@@ -525,24 +525,37 @@ __global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>:
                     double Eb[L], Vb[L];
                     if constexpr (BASE == BASE_FG)
                         strip_background_fg<L>(p, pairs, nbr, coefv, fgm, im, c, r0, Eb, Vb);
-                    auto row_load = [&](int rr, double& x_, double& e_, double& v_, double& s_, double& g_) {
-                        const size_t gi = (size_t)im.pix_offset + (size_t)(r0 + rr) * im.W + c;
-                        const size_t vi = (size_t)p.visit_off + (size_t)(r0 + rr - p.r0) * p.w + (c - p.c0);
-                        x_ = xs[gi];
+                    // Row addresses as 32-bit byte offsets from wave-uniform bases (the image's
+                    // planes, the box's stored values; plan creation bounds images below 2^29
+                    // pixels and boxes below 2^28 visits): one add and one select per row.
+                    const char* xb = reinterpret_cast<const char*>(xs + im.pix_offset);
+                    const char* eb = reinterpret_cast<const char*>(Ep + im.pix_offset);
+                    const char* vb = reinterpret_cast<const char*>(Vp + im.pix_offset);
+                    const char* fb = reinterpret_cast<const char*>(fgm + 2 * p.visit_off);
+                    const uint32_t W8 = (uint32_t)im.W * 8u, w16 = (uint32_t)p.w * 16u;
+                    const uint32_t go = (uint32_t)(r0 * im.W + c) * 8u;
+                    const uint32_t vo = (uint32_t)((r0 - p.r0) * p.w + (c - p.c0)) * 16u;
+                    // row rr of the strip if `in`, else its top row (a row past the box)
+                    auto row_load = [&](int rr, bool in, double& x_, double& e_, double& v_, double& s_,
+                                        double& g_) {
+                        const uint32_t gr = go + (in ? (uint32_t)rr * W8 : 0u);
+                        const uint32_t vr = vo + (in ? (uint32_t)rr * w16 : 0u);
+                        x_ = *reinterpret_cast<const double*>(xb + gr);
                         if constexpr (BASE == BASE_PLANES) {
-                            e_ = Ep[gi];
-                            v_ = Vp[gi];
+                            e_ = *reinterpret_cast<const double*>(eb + gr);
+                            v_ = *reinterpret_cast<const double*>(vb + gr);
                         }
-                        s_ = fgm[2 * vi];
-                        g_ = fgm[2 * vi + 1];
+                        const double2 sg = *reinterpret_cast<const double2*>(fb + vr);
+                        s_ = sg.x;
+                        g_ = sg.y;
                     };
                     T Gs[L], Gg[L];
                     double cx_, ce_ = 0.0, cv_ = 0.0, cs_, cg_;
-                    row_load(0, cx_, ce_, cv_, cs_, cg_);
+                    row_load(0, true, cx_, ce_, cv_, cs_, cg_);
 #pragma unroll
                     for (int kk = 0; kk < L; ++kk) {
                         double nx_ = 0.0, ne_ = 0.0, nv_ = 0.0, ns_ = 0.0, ng_ = 0.0;
-                        if (kk + 1 < L) row_load(kk + 1 < nrow ? kk + 1 : 0, nx_, ne_, nv_, ns_, ng_);
+                        if (kk + 1 < L) row_load(kk + 1, kk + 1 < nrow, nx_, ne_, nv_, ns_, ng_);
                         T gs = zero, gg = zero;
                         if (kk < nrow && cx_ == cx_) {
                             const T fsk = scalar_traits<T>::make(cs_, 0.0), fgk = scalar_traits<T>::make(cg_, 0.0);
@@ -899,7 +912,7 @@ __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __r
                                                    const double* __restrict__ own, const double* __restrict__ hcp,
                                                    double* __restrict__ hg) {
     if (*a.status) return;
-    __shared__ double t2[64];
+    __shared__ double t2[EXP_TAB];
     fill_exp_table(t2);
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -967,7 +980,7 @@ __global__ void __launch_bounds__(256) k_background_strips(BgArgs a, const Item*
                                                            const double* __restrict__ coefv,
                                                            double* __restrict__ bg) {
     if (*a.status) return;
-    __shared__ double t2[64];
+    __shared__ double t2[EXP_TAB];
     fill_exp_table(t2);
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -1055,7 +1068,7 @@ __global__ void __launch_bounds__(256) k_strip_fg(Sel sel, const Item* __restric
                                                   const PairDev* __restrict__ pairs, const double* __restrict__ tab,
                                                   double* __restrict__ fgm, const int* status) {
     if (*status) return;
-    __shared__ double t2[64];
+    __shared__ double t2[EXP_TAB];
     fill_exp_table(t2);
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -1189,7 +1202,7 @@ __global__ void __launch_bounds__(256) k_gather_planes(RenderArgs a, const TileD
 // for testing them against the host's libm.
 __global__ void __launch_bounds__(256) k_debug_math(int fn, const double* __restrict__ x, double* __restrict__ y,
                                                     int n) {
-    __shared__ double t2[64];
+    __shared__ double t2[EXP_TAB];
     __shared__ double2 tl[128];
     fill_log_table(tl);
     fill_exp_table(t2);
