@@ -29,14 +29,14 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector peak (vendor figure)
 
 # Algorithmic FP64 operations, counted from the formulas the kernels evaluate (add, sub,
 # mul, div = 1 each, FMA = 2).  The strip kernels' own elementary functions: table-driven
-# exp (64/ln2 scaling, two-part reduction, degree-5 polynomial, table product: 16 FLOPs),
+# exp (256/ln2 scaling, two-part reduction, degree-4 polynomial, table product: 14 FLOPs),
 # table-driven log (breakpoint, reduced argument, degree-6 log1p, m ln2 recombination:
 # 20 FLOPs), reciprocal (hardware estimate + two Newton steps: 9 FLOPs).  Elsewhere exp = 27
 # and log = 78, the FP64 operations of one call of the ROCm device library's exp and log on
 # gfx950 (read from this build's ISA).
 EXP_FLOPS = 27
 LOG_FLOPS = 78
-FEXP_FLOPS = 16
+FEXP_FLOPS = 14
 FLOG_FLOPS = 20
 FRCP_FLOPS = 9
 N_STAR, N_GAL = 3, 42                   # Gaussians per (source, image): 3 star, 3 x (8 + 6) galaxy
