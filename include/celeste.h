@@ -70,7 +70,7 @@ enum celeste_status {
 
 enum celeste_mode {
     CELESTE_PLAIN = 0,    /* one launch per source, overlapping sources evaluated on the fly */
-    CELESTE_BATCHED = 1   /* all sources: render pass + one persistent fused adjoint launch */
+    CELESTE_BATCHED = 1   /* all sources: render pass + one grid-stride fused adjoint launch */
 };
 
 enum celeste_flags {
@@ -146,7 +146,7 @@ typedef struct celeste_plan_info {
     int64_t n_nbr;         /* entries of the box-overlap lists used by the plain form */
     int32_t chunk;         /* strips per adjoint work item */
     int32_t waves_per_block;
-    int32_t grid_blocks;   /* persistent grid size of the fused adjoint launch */
+    int32_t grid_blocks;   /* grid size (blocks) of the grid-stride strip and adjoint launches */
     int32_t tile_h, tile_w;
     int32_t dynamic_queue; /* 1: items popped from a device counter; 0: static round robin */
     int32_t strip_rows;    /* pixels per strip: a lane walks one column of a box this many rows */
@@ -321,8 +321,8 @@ int celeste_sweep(celeste_plan* plan, double* theta_inout, const int32_t* batch_
                   const celeste_tr_params* params, double* elbo_trace, hipStream_t stream);
 
 /* Launch configuration: strips per work item (multiple of 64, at most 1024), waves per
- * block (1, 2 or 4), persistent grid size (blocks; 0 = 64 per compute unit), dynamic_queue
- * (0/1), render tile tile_h x tile_w (tile_w divides 64; tile_h * tile_w = 64, 128 or 256),
+ * block (1, 2 or 4), grid size of the grid-stride launches (blocks; 0 = 64 per compute
+ * unit), dynamic_queue (0/1), render tile tile_h x tile_w (tile_w divides 64; tile_h * tile_w = 64, 128 or 256),
  * strip_rows (4, 8 or 16 pixels per strip) and render_mode (see celeste_plan_info).  A new
  * plan starts at chunk 64, 4 waves per block, grid 0, static queue, 16 x 16 tiles, 16-row
  * strips, render mode 2.  Rebuilds work items and render tiles (synchronous).  If grown
@@ -332,7 +332,8 @@ int celeste_plan_set_launch(celeste_plan* plan, int chunk, int waves_per_block, 
                             int dynamic_queue, int tile_h, int tile_w, int strip_rows, int render_mode);
 
 /* Times candidate launch configurations of celeste_elbo_grad (batched) on theta with
- * HIP events (median of `reps` runs each) and keeps the fastest.  Synchronous.
+ * HIP events (median of `reps` runs each) and keeps the fastest (a candidate replaces the
+ * current choice only when at least 1% faster).  Synchronous.
  * best_ms (host, or NULL) receives its time. */
 int celeste_autotune(celeste_plan* plan, const double* theta, int reps, double* best_ms,
                      hipStream_t stream);
