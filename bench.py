@@ -42,19 +42,18 @@ FRCP_FLOPS = 9
 N_STAR, N_GAL = 3, 42                   # Gaussians per (source, image): 3 star, 3 x (8 + 6) galaxy
 
 # Strip algorithm (what runs): per strip of L rows and per Gaussian, the value and the
-# first row ratio at the top row (2 exps + 16 FLOPs), then per row 2 multiplies for the
-# recurrence plus the accumulation.  Pass A (profile values) runs in the render's strip
-# pass and its values are stored; the fused adjoint runs the pixel terms and pass B (seed
-# again; per row one FMA and one (star) or two (galaxy) running-sum adds; per strip the
-# moments from the running sums and the fold into the ten intermediates).
-# Pass B takes its table staged in LDS with the offsets from each PSF group's shared centre
-# formed once per group (12 FLOPs), so its seed costs 9 + 2 exps and its fold 11 (star) or
-# 46 (galaxy) FLOPs.
-SEED = 16 + 2 * FEXP_FLOPS
-SEED_B = 9 + 2 * FEXP_FLOPS
-PASS_A_PER_STRIP = (N_STAR + N_GAL) * SEED
+# first row ratio at the top row, then per row 2 multiplies for the recurrence plus the
+# accumulation.  Both strip passes take the box's table staged in LDS, with the offsets from
+# each PSF group's shared centre formed once per group and strip (12 FLOPs), so a seed costs
+# 9 FLOPs + 2 exps.  Pass A (profile values) runs in the render's strip pass and its values
+# are stored; the fused adjoint runs the pixel terms and pass B (seed again; per row one FMA
+# and one (star) or two (galaxy) running-sum adds; per strip the moments from the running
+# sums and the fold into the ten intermediates: 11 FLOPs per star, 46 per galaxy component).
+SEED = 9 + 2 * FEXP_FLOPS
+GROUPS = 3 * 12
+PASS_A_PER_STRIP = GROUPS + (N_STAR + N_GAL) * SEED
 PASS_A_PER_VISIT = N_STAR * 3 + N_GAL * 4
-PASS_B_PER_STRIP = 3 * 12 + (N_STAR + N_GAL) * SEED_B + N_STAR * 11 + N_GAL * 46
+PASS_B_PER_STRIP = GROUPS + (N_STAR + N_GAL) * SEED + N_STAR * 11 + N_GAL * 46
 PASS_B_PER_VISIT = N_STAR * 5 + N_GAL * 6
 PIXEL_PER_VISIT = 40 + FLOG_FLOPS + FRCP_FLOPS
 GATHER_PER_VISIT = 11
