@@ -269,11 +269,18 @@ __device__ __forceinline__ void strip_adjoint_staged(const double* __restrict__ 
 // Pass A of the render's strip pass from the box table staged in LDS (strip_adjoint_staged's
 // layout): star and galaxy profile values down the strip, the offsets from each PSF group's
 // shared centre formed once per group.
-template <int L>
+// SGN: also fgd[k] = sum of the de Vaucouleurs minus the exponential components (d fg /
+// d frac_dev).
+template <int L, bool SGN = false>
 __device__ __forceinline__ void strip_values_staged(const double* __restrict__ lt, double px, double py0,
-                                                    double* fs, double* fg, const double* __restrict__ t2) {
+                                                    double* fs, double* fg, const double* __restrict__ t2,
+                                                    double* fgd = nullptr) {
 #pragma unroll
     for (int k = 0; k < L; ++k) fs[k] = fg[k] = 0.0;
+    if constexpr (SGN) {
+#pragma unroll
+        for (int k = 0; k < L; ++k) fgd[k] = 0.0;
+    }
 #pragma unroll 1
     for (int grp = 0; grp < NPSF; ++grp) {
         const double* es = lt + grp;
@@ -302,9 +309,11 @@ __device__ __forceinline__ void strip_values_staged(const double* __restrict__ l
             double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, e[D_LW * NCP]))), t2);
             double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
             const double rdy = e[D_RDY * NCP], wt = e[D_WT * NCP];
+            const double sgn = SGN ? e[D_SGN * NCP] : 0.0;
 #pragma unroll
             for (int k = 0; k < L; ++k) {
                 fg[k] = fma(n, wt, fg[k]);
+                if constexpr (SGN) fgd[k] = fma(n, sgn, fgd[k]);
                 if (k + 1 < L) {
                     n = n * rt;
                     rt = rt * rdy;
@@ -528,9 +537,9 @@ __global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>:
     // instead of missing the scalar cache (38% of the scalar loads missed with the table read
     // from global memory), the table leaves the scalar registers (no spills), and the
     // coefficients every lane shares are formed once per box instead of once per strip.
-    constexpr bool LDS_TAB = FGM && DERIV && (BASE == BASE_PLANES || BASE == BASE_FG) &&
-                             std::is_same<T, double>::value;
-    extern __shared__ double ltab[];   // LDS_TAB: [waves per block][NCOMP][NDF], sized at launch
+    constexpr bool LDS_TAB = DERIV && std::is_same<T, double>::value &&
+                             (FGM ? (BASE == BASE_PLANES || BASE == BASE_FG) : (BASE == BASE_PLANES || BASE == BASE_BG));
+    extern __shared__ double ltab[];   // LDS_TAB: [waves per block][NDF][NCP], sized at launch
     fill_log_table(tl);
     fill_exp_table(t2);
     const int lane = threadIdx.x & 63;
@@ -638,7 +647,11 @@ __global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>:
                 if constexpr (DERIV && !FGM && (BASE == BASE_PLANES || BASE == BASE_BG)) {
                     // Own values from pass A, then the pixel rows streamed as above.
                     T fs[L], fg[L], fgd[KK ? L : 1];
-                    strip_values<T, L, KK>(tab, px, py0, fs, fg, t2, fgd);
+                    if constexpr (LDS_TAB)
+                        strip_values_staged<L, KK>(ltab + (threadIdx.x >> 6) * (NCP * NDF), px, py0, fs, fg, t2,
+                                                   fgd);
+                    else
+                        strip_values<T, L, KK>(tab, px, py0, fs, fg, t2, fgd);
                     const double* xs_i = xs + im.pix_offset;
                     auto row_load = [&](int rr, double& x_, double& e_, double& v_) {
                         const size_t gi = (size_t)(r0 + rr) * im.W + c;
@@ -688,7 +701,10 @@ __global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>:
                         cv_ = nv_;
                         __builtin_amdgcn_sched_barrier(0);
                     }
-                    strip_adjoint<T, L>(tab, px, py0, fs, fg, acc, t2);
+                    if constexpr (LDS_TAB)
+                        strip_adjoint_staged<L>(ltab + (threadIdx.x >> 6) * (NCP * NDF), px, py0, fs, fg, acc, t2);
+                    else
+                        strip_adjoint<T, L>(tab, px, py0, fs, fg, acc, t2);
                     continue;
                 }
                 double x[L], Eb[L], Vb[L];
@@ -1352,8 +1368,8 @@ hipError_t launch_render_strips(const Sel& sel, const Geometry& g, const double*
 template <class T, int BASE, bool DERIV, int L, bool FGM, bool KK>
 static void adjk(const AdjArgs& a, int grid, int wpb, hipStream_t st) {
     const Geometry& g = a.g;
-    constexpr bool lds_tab = FGM && DERIV && (BASE == BASE_PLANES || BASE == BASE_FG) &&
-                             std::is_same<T, double>::value;
+    constexpr bool lds_tab = DERIV && std::is_same<T, double>::value &&
+                             (FGM ? (BASE == BASE_PLANES || BASE == BASE_FG) : (BASE == BASE_PLANES || BASE == BASE_BG));
     const size_t lds = lds_tab ? (size_t)wpb * NCP * NDF * sizeof(double) : 0;
     hipLaunchKernelGGL((k_adjoint_strips<T, BASE, DERIV, L, FGM, KK>), dim3(grid), dim3(64 * wpb), lds, st, a,
                        g.items, g.pairs, g.images, g.nbr, g.x, a.E, a.V, a.bg, a.tab, a.coef, a.tab_val, a.coef_val,
