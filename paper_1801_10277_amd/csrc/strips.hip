@@ -818,17 +818,17 @@ __global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>:
 //   + Gs fs_gh + Gg fg_gh,
 // and the entry between g and k_i follows from dE/dk = (fs, fg, 0, 0) and
 // dV/dk = (-2 Es fs, -2 Es fg, fs^2, fg^2).  Entry layout: see HGField.
-// NPX pixels of one column (rows py0, py0 + 1, ...) at once, sharing every table read; a
-// pixel with ok[i] false contributes nothing (its weights are zeroed).
+// The terms Gs fs_gh + Gg fg_gh are summed per strip from row moments (k_hess_second); this
+// function adds, for NPX pixels of one column (rows py0, py0 + 1, ...) at once, sharing every
+// table read, the products of first derivatives and the k-block entries.  A pixel with ok[i]
+// false contributes nothing (its weights are zeroed).
 template <int NPX>
-__device__ __forceinline__ void hess_pixels(const double* __restrict__ tab, const double* __restrict__ hc,
-                                            double px, double py0, const bool* ok, const double* x,
-                                            const double* Eb, const double* Vb, const double* fs,
+__device__ __forceinline__ void hess_pixels(const double* __restrict__ tab, double px, double py0, const bool* ok,
+                                            const double* x, const double* Eb, const double* Vb, const double* fs,
                                             const double* fg, const double* k, double* H,
                                             const double* __restrict__ t2) {
-    // pixel scalars first (own values from the gradient pass), so that the second
-    // derivatives go straight into H with their row weights
-    double Es[NPX], lE[NPX], lV[NPX], lEE[NPX], lEV[NPX], A[NPX], Gs[NPX], Gg[NPX];
+    // pixel scalars first (own values from the gradient pass)
+    double Es[NPX], lE[NPX], lV[NPX], lEE[NPX], lEV[NPX], A[NPX];
 #pragma unroll
     for (int i = 0; i < NPX; ++i) {
         Es[i] = k[C_K1] * fs[i] + k[C_K2] * fg[i];
@@ -843,8 +843,6 @@ __device__ __forceinline__ void hess_pixels(const double* __restrict__ tab, cons
         lEE[i] = -xm * inv2 * (1.0 + 3.0 * r);
         lEV[i] = xm * inv2 * inv;
         A[i] = lE[i] - 2.0 * Es[i] * lV[i];
-        Gs[i] = A[i] * k[C_K1] + 2.0 * lV[i] * (k[C_K3] * fs[i]);
-        Gg[i] = A[i] * k[C_K2] + 2.0 * lV[i] * (k[C_K4] * fg[i]);
     }
     double S[NPX][2];
 #pragma unroll
@@ -859,12 +857,8 @@ __device__ __forceinline__ void hess_pixels(const double* __restrict__ tab, cons
             const double dy = py0 + (double)i - e[F_CY];
             const double zx = a * dx + b * dy, zy = b * dx + d * dy;
             const double n = fexp(e[F_LOGW] - 0.5 * (dx * zx + dy * zy), t2);
-            const double gn = Gs[i] * n;
             S[i][0] += n * zx;
             S[i][1] += n * zy;
-            H[HG_XX] += gn * (zx * zx - a);
-            H[HG_XY] += gn * (zx * zy - b);
-            H[HG_YY] += gn * (zy * zy - d);
         }
     }
     double F[NPX][6];
@@ -879,7 +873,6 @@ __device__ __forceinline__ void hess_pixels(const double* __restrict__ tab, cons
         const double dx = px - e0[F_CX], dy0 = py0 - e0[F_CY];
         for (int j = 0; j < NGAL_PER_PSF; ++j) {
             const double* e = e0 + j * CST;
-            const double* h = hc + (kp * NGAL_PER_PSF + j) * NHC;
             const double a = e[F_PXX], b = e[F_PXY], d = e[F_PYY];
 #pragma unroll
             for (int i = 0; i < NPX; ++i) {
@@ -894,32 +887,6 @@ __device__ __forceinline__ void hess_pixels(const double* __restrict__ tab, cons
                 F[i][3] += vn * Dxx;
                 F[i][4] += vn * Dxy;
                 F[i][5] += vn * Dyy;
-                const double wg = Gg[i] * wn, sg = Gg[i] * sn, vg = Gg[i] * vn;
-                const double sgn = sg * h[HC_NU], vgn = vg * h[HC_NU];
-                H[HG_XX] += wg * Dxx;
-                H[HG_XY] += wg * Dxy;
-                H[HG_YY] += wg * Dyy;
-                H[HG_XF] += sg * zx;
-                H[HG_YF] += sg * zy;
-                const double t1 = Dxx + h[HC_M2A];   // Dxx - 2a
-                const double t2b = Dxy - b;          // Dxy - b
-                const double t3 = Dyy + h[HC_M2D];   // Dyy - 2d
-                const double s2 = Dxy + h[HC_M2B];   // Dxy - 2b
-                H[HG_X_SXX] += vg * (zx * t1);
-                H[HG_X_SXY] += vg * (zx * t2b - a * zy);
-                H[HG_X_SYY] += vg * (zx * Dyy + h[HC_M2B] * zy);
-                H[HG_Y_SXX] += vg * (zy * Dxx + h[HC_M2B] * zx);
-                H[HG_Y_SXY] += vg * (zy * t2b - d * zx);
-                H[HG_Y_SYY] += vg * (zy * t3);
-                H[HG_F_SXX] += sgn * Dxx;
-                H[HG_F_SXY] += sgn * Dxy;
-                H[HG_F_SYY] += sgn * Dyy;
-                H[HG_SXX_SXX] += vgn * (Dxx * (Dxx + h[HC_M4A]) + h[HC_M2AA]);
-                H[HG_SXX_SXY] += vgn * (Dxx * h[HC_M2B] + (Dxy * t1 + h[HC_M2AB]));
-                H[HG_SXX_SYY] += vgn * (Dxy * h[HC_M4B] + (Dxx * Dyy + h[HC_M2BB]));
-                H[HG_SXY_SXY] += vgn * (Dxx * (-d) + (Dyy * (-a) + (Dxy * s2 + h[HC_MQ])));
-                H[HG_SXY_SYY] += vgn * (Dxy * h[HC_M2D] + (Dyy * s2 + h[HC_M2BD]));
-                H[HG_SYY_SYY] += vgn * (Dyy * (Dyy + h[HC_M4D]) + h[HC_M2DD]);
             }
         }
     }
@@ -958,14 +925,264 @@ __device__ __forceinline__ void hess_pixels(const double* __restrict__ tab, cons
 }
 
 
+// ---------------------------------------------- closed-form Hessian: second-derivative terms
+// The second-derivative terms of the geometric block (each pixel's row weight Gs or Gg times a
+// profile's second derivatives in position, frac_dev and shape) are, per Gaussian, the
+// weighted pixel sum of n times a polynomial of degree <= 4 in z = P (m - mu).  Down a strip
+// z is affine in the row: z_k = z_c + (b, d) s_k with z_c its value at the strip centre and
+// s_k = k - (L - 1)/2, so with the strip recurrence for n and the exact centred row moments
+// U_m = sum_k t_k s_k^m (t_k = row weight x value, m <= 4; s_k^m are compile-time constants)
+// the sums N_pq = sum_k t_k zx_k^p zy_k^q follow by applying the maps
+// (X V)_m = zx_c V_m + b V_(m+1) and (Y V)_m = zy_c V_m + d V_(m+1) to U: N_pq = (X^p Y^q U)_0.
+// With the moments about the strip centre, every term of these expansions is bounded by the
+// strip's own values of |z|^4, so no cancellation beyond a small factor arises.  The entries
+// (galaxy component, weights wt, sgn, wnu = wt nu):
+//   XX, XY, YY: wt (N20 - a N00, N11 - b N00, N02 - d N00);   XF, YF: sgn N10, sgn N01;
+//   F_Sxx, F_Sxy, F_Syy: sgn nu times the same three as XX, XY, YY;
+//   X_Sxx: wnu (N30 - 3a N10);   X_Sxy = Y_Sxx: wnu (N21 - 2b N10 - a N01);
+//   X_Syy = Y_Sxy: wnu (N12 - d N10 - 2b N01);   Y_Syy: wnu (N03 - 3d N01);
+//   Sxx_Sxx: wnu nu (N40 - 6a N20 + 3a^2 N00);   Sxx_Sxy: wnu nu (N31 - 3b N20 - 3a N11 + 3ab N00);
+//   Sxx_Syy = Sxy_Sxy: wnu nu (N22 - d N20 - a N02 - 4b N11 + (ad + 2b^2) N00);
+//   Sxy_Syy: wnu nu (N13 - 3d N11 - 3b N02 + 3bd N00);   Syy_Syy: wnu nu (N04 - 6d N02 + 3d^2 N00)
+// (the expansions of the per-pixel formulas of hess_pixels), and for a star (weight Gs):
+// XX, XY, YY: N20 - a N00, N11 - b N00, N02 - d N00.  One pass over the components per strip
+// (two exps per component), against one exp and about 55 operations per pixel and component
+// for the same terms pixel by pixel.
+enum HessStagedField { H_CX = 0, H_CY, H_LW, H_RDY, H_A, H_B, H_D, H_WT, H_WNU, H_SGN, H_NU, NDH };
+
+// One wave writes the staged table of a box (field-major [NDH][NCP], slots as in
+// stage_derived) into its LDS slot; nu from the closed-form constants hc.
+__device__ __forceinline__ void stage_hess(const double* __restrict__ tab, const double* __restrict__ hc,
+                                           double* my, int lane) {
+    if (lane < NCOMP) {
+        const double* e = tab + lane * CST;
+        double* o = my + staged_slot(lane);
+        o[H_CX * NCP] = e[F_CX];
+        o[H_CY * NCP] = e[F_CY];
+        o[H_LW * NCP] = e[F_LOGW];
+        o[H_RDY * NCP] = e[F_RDY];
+        o[H_A * NCP] = e[F_PXX];
+        o[H_B * NCP] = e[F_PXY];
+        o[H_D * NCP] = e[F_PYY];
+        o[H_WT * NCP] = e[F_WT];
+        o[H_WNU * NCP] = e[F_WNU];
+        o[H_SGN * NCP] = e[F_SGN];
+        o[H_NU * NCP] = lane < NPSF ? 0.0 : hc[(lane - NPSF) * NHC + HC_NU];
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void hess_second_strip(const double* __restrict__ lt, double px, double py0,
+                                                  const double* Gs, const double* Gg, double* H,
+                                                  const double* __restrict__ t2) {
+    constexpr double KC = 0.5 * (L - 1);
+#pragma unroll 1
+    for (int grp = 0; grp < NPSF; ++grp) {
+        const double* es = lt + grp;
+        const double dx = px - es[H_CX * NCP], dy = py0 - es[H_CY * NCP];
+        const double h2x = -0.5 * (dx * dx), mxy = -(dx * dy), h2y = -0.5 * (dy * dy);
+        const double mdx = -dx, mdyh = -(dy + 0.5), dyc = dy + KC;
+        {
+            const double a = es[H_A * NCP], b = es[H_B * NCP], d = es[H_D * NCP];
+            double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, es[H_LW * NCP]))), t2);
+            double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
+            const double rdy = es[H_RDY * NCP];
+            double U0 = 0.0, U1 = 0.0, U2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                const double sk = (double)k - KC;
+                const double t = Gs[k] * n;
+                U0 += t;
+                U1 = fma(sk, t, U1);
+                U2 = fma(sk * sk, t, U2);
+                if (k + 1 < L) {
+                    n = n * rt;
+                    rt = rt * rdy;
+                }
+            }
+            const double zx = fma(a, dx, b * dyc), zy = fma(b, dx, d * dyc);
+            const double X10 = fma(zx, U0, b * U1), X11 = fma(zx, U1, b * U2);
+            const double Y10 = fma(zy, U0, d * U1), Y11 = fma(zy, U1, d * U2);
+            const double N20 = fma(zx, X10, b * X11), N11 = fma(zy, X10, d * X11), N02 = fma(zy, Y10, d * Y11);
+            H[HG_XX] += fma(-a, U0, N20);
+            H[HG_XY] += fma(-b, U0, N11);
+            H[HG_YY] += fma(-d, U0, N02);
+        }
+        const double* eg = lt + NPSF + 1 + grp * NGAL_PER_PSF;
+#pragma unroll CELESTE_GAL_UNROLL
+        for (int c = 0; c < NGAL_PER_PSF; ++c) {
+            const double* e = eg + c;
+            const double a = e[H_A * NCP], b = e[H_B * NCP], d = e[H_D * NCP];
+            double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, e[H_LW * NCP]))), t2);
+            double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
+            const double rdy = e[H_RDY * NCP];
+            double U[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                const double sk = (double)k - KC;
+                const double t = Gg[k] * n;
+                U[0] += t;
+                U[1] = fma(sk, t, U[1]);
+                U[2] = fma(sk * sk, t, U[2]);
+                U[3] = fma(sk * sk * sk, t, U[3]);
+                U[4] = fma(sk * sk * sk * sk, t, U[4]);
+                if (k + 1 < L) {
+                    n = n * rt;
+                    rt = rt * rdy;
+                }
+            }
+            const double zx = fma(a, dx, b * dyc), zy = fma(b, dx, d * dyc);
+            // Y^q U for q = 1..4, then X^p on each: N_pq = (X^p Y^q U)_0
+            double Y1[4], Y2[3], Y3[2];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) Y1[m] = fma(zy, U[m], d * U[m + 1]);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) Y2[m] = fma(zy, Y1[m], d * Y1[m + 1]);
+#pragma unroll
+            for (int m = 0; m < 2; ++m) Y3[m] = fma(zy, Y2[m], d * Y2[m + 1]);
+            const double N04 = fma(zy, Y3[0], d * Y3[1]);
+            double X1[4], X2[3], X3[2];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) X1[m] = fma(zx, U[m], b * U[m + 1]);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) X2[m] = fma(zx, X1[m], b * X1[m + 1]);
+#pragma unroll
+            for (int m = 0; m < 2; ++m) X3[m] = fma(zx, X2[m], b * X2[m + 1]);
+            const double N40 = fma(zx, X3[0], b * X3[1]);
+            const double N00 = U[0], N10 = X1[0], N20 = X2[0], N30 = X3[0];
+            const double XY1a = fma(zx, Y1[0], b * Y1[1]), XY1b = fma(zx, Y1[1], b * Y1[2]),
+                         XY1c = fma(zx, Y1[2], b * Y1[3]);
+            const double XXY1a = fma(zx, XY1a, b * XY1b), XXY1b = fma(zx, XY1b, b * XY1c);
+            const double N01 = Y1[0], N11 = XY1a, N21 = XXY1a, N31 = fma(zx, XXY1a, b * XXY1b);
+            const double XY2a = fma(zx, Y2[0], b * Y2[1]), XY2b = fma(zx, Y2[1], b * Y2[2]);
+            const double N02 = Y2[0], N12 = XY2a, N22 = fma(zx, XY2a, b * XY2b);
+            const double N03 = Y3[0], N13 = fma(zx, Y3[0], b * Y3[1]);
+            const double wt = e[H_WT * NCP], sg = e[H_SGN * NCP], wnu = e[H_WNU * NCP], nu = e[H_NU * NCP];
+            const double snu = sg * nu, vnu = wnu * nu;
+            const double e20 = fma(-a, N00, N20), e11 = fma(-b, N00, N11), e02 = fma(-d, N00, N02);
+            H[HG_XX] = fma(wt, e20, H[HG_XX]);
+            H[HG_XY] = fma(wt, e11, H[HG_XY]);
+            H[HG_YY] = fma(wt, e02, H[HG_YY]);
+            H[HG_XF] = fma(sg, N10, H[HG_XF]);
+            H[HG_YF] = fma(sg, N01, H[HG_YF]);
+            H[HG_F_SXX] = fma(snu, e20, H[HG_F_SXX]);
+            H[HG_F_SXY] = fma(snu, e11, H[HG_F_SXY]);
+            H[HG_F_SYY] = fma(snu, e02, H[HG_F_SYY]);
+            const double x1 = fma(-3.0 * a, N10, N30);
+            const double x2 = fma(-2.0 * b, N10, fma(-a, N01, N21));
+            const double x3 = fma(-d, N10, fma(-2.0 * b, N01, N12));
+            const double x4 = fma(-3.0 * d, N01, N03);
+            H[HG_X_SXX] = fma(wnu, x1, H[HG_X_SXX]);
+            H[HG_X_SXY] = fma(wnu, x2, H[HG_X_SXY]);
+            H[HG_Y_SXX] = fma(wnu, x2, H[HG_Y_SXX]);
+            H[HG_X_SYY] = fma(wnu, x3, H[HG_X_SYY]);
+            H[HG_Y_SXY] = fma(wnu, x3, H[HG_Y_SXY]);
+            H[HG_Y_SYY] = fma(wnu, x4, H[HG_Y_SYY]);
+            const double s1 = fma(-6.0 * a, N20, fma(3.0 * (a * a), N00, N40));
+            const double s2 = fma(-3.0 * b, N20, fma(-3.0 * a, N11, fma(3.0 * (a * b), N00, N31)));
+            const double s3 = fma(-d, N20, fma(-a, N02, fma(-4.0 * b, N11, fma(fma(a, d, 2.0 * (b * b)), N00, N22))));
+            const double s4 = fma(-3.0 * d, N11, fma(-3.0 * b, N02, fma(3.0 * (b * d), N00, N13)));
+            const double s5 = fma(-6.0 * d, N02, fma(3.0 * (d * d), N00, N04));
+            H[HG_SXX_SXX] = fma(vnu, s1, H[HG_SXX_SXX]);
+            H[HG_SXX_SXY] = fma(vnu, s2, H[HG_SXX_SXY]);
+            H[HG_SXX_SYY] = fma(vnu, s3, H[HG_SXX_SYY]);
+            H[HG_SXY_SXY] = fma(vnu, s3, H[HG_SXY_SXY]);
+            H[HG_SXY_SYY] = fma(vnu, s4, H[HG_SXY_SYY]);
+            H[HG_SYY_SYY] = fma(vnu, s5, H[HG_SYY_SYY]);
+        }
+    }
+}
+
+// Second-derivative terms of the geometric block, one lane per strip: the row weights Gs, Gg
+// from the stored background and own profile values of each row, then hess_second_strip.
+// Writes hg[item] (geometric entries; the k-block entries zero), to which k_hess_geom then
+// adds the first-derivative products.  Items of sources outside a.active get zeros.
+template <int L>
+__global__ void __launch_bounds__(256, 2) k_hess_second(AdjArgs a, const Item* __restrict__ items,
+                                                     const PairDev* __restrict__ pairs,
+                                                     const celeste_image* __restrict__ images,
+                                                     const double* __restrict__ xs, const double* __restrict__ bg,
+                                                     const double* __restrict__ tabp,
+                                                     const double* __restrict__ coefp,
+                                                     const double* __restrict__ own, const double* __restrict__ hcp,
+                                                     double* __restrict__ hg) {
+    if (*a.status) return;
+    __shared__ double t2[EXP_TAB];
+    extern __shared__ double ltab[];   // [waves per block][NDH][NCP], sized at launch
+    fill_exp_table(t2);
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int nw = gridDim.x * wpb;
+    double* my = ltab + (threadIdx.x >> 6) * (NCP * NDH);
+    int j = a.dynamic ? next_item_s(a.counter, lane) : blockIdx.x * wpb + (threadIdx.x >> 6);
+    while (j < a.items.n) {
+        const int ii = __builtin_amdgcn_readfirstlane(sel_at(a.items, j));
+        const Item it = items[ii];
+        const PairDev p = pairs[it.pair];
+        double* out = hg + (size_t)ii * NHG;
+        if (a.active && !a.active[p.src]) {
+            if (lane < NHG) out[lane] = 0.0;
+            j = a.dynamic ? next_item_s(a.counter, lane) : j + nw;
+            continue;
+        }
+        const celeste_image& im = images[p.img];
+        const double* kp = coefp + (size_t)it.pair * NCOEF;
+        const double k1 = kp[C_K1], k2 = kp[C_K2], k3 = kp[C_K3], k4 = kp[C_K4];
+        __builtin_amdgcn_wave_barrier();
+        stage_hess(tabp + (size_t)it.pair * NCOMP * CST, hcp + (size_t)it.pair * NGAL * NHC, my, lane);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double H[NHG_GEO];
+#pragma unroll
+        for (int f = 0; f < NHG_GEO; ++f) H[f] = 0.0;
+        for (int q = lane; q < it.count; q += 64) {
+            int c, r0, nrow;
+            strip_geometry(p, it.start + q, L, c, r0, nrow);
+            double Gs[L], Gg[L];
+#pragma unroll
+            for (int kk = 0; kk < L; ++kk) {
+                const int r = r0 + (kk < nrow ? kk : 0);   // rows past the box reuse row 0 (weight 0)
+                const double x = xs[(size_t)im.pix_offset + (size_t)r * im.W + c];
+                const size_t vi = (size_t)p.visit_off + (size_t)(r - p.r0) * p.w + (c - p.c0);
+                double gs = 0.0, gg = 0.0;
+                if (kk < nrow && x == x) {
+                    const double fs = own[2 * vi], fgv = own[2 * vi + 1];
+                    const double Es = k1 * fs + k2 * fgv;
+                    const double E = bg[2 * vi] + Es;
+                    const double V = bg[2 * vi + 1] + k3 * (fs * fs) + k4 * (fgv * fgv) - Es * Es;
+                    const double inv = frcp(E);
+                    const double inv2 = inv * inv;
+                    const double lE = x * inv * (1.0 + V * inv2) - 1.0;
+                    const double lV = -0.5 * x * inv2;
+                    const double A = lE - 2.0 * Es * lV;
+                    gs = A * k1 + 2.0 * lV * (k3 * fs);
+                    gg = A * k2 + 2.0 * lV * (k4 * fgv);
+                }
+                Gs[kk] = gs;
+                Gg[kk] = gg;
+            }
+            hess_second_strip<L>(my, (double)c, (double)r0, Gs, Gg, H, t2);
+        }
+#pragma unroll
+        for (int f = 0; f < NHG_GEO; ++f) {
+            const double v = wave_sum(H[f]);
+            if (lane == 0) out[f] = v;
+        }
+        if (lane >= NHG_GEO && lane < NHG) out[lane] = 0.0;
+        j = a.dynamic ? next_item_s(a.counter, lane) : j + nw;
+    }
+}
+
 // One wave per work item.  The item's pixels (stored backgrounds and own profile values of
 // the listed boxes) are cut into runs of HPX rows of one strip; the runs, taken by row
 // index and then by strip, are dealt round-robin to the lanes, so that an item of fewer
-// than 64 strips still fills the wave.  The wave sums the NHG entries into hg[item]; the
-// items of sources outside a.active (when given) get zeros.  Launched with two rows and
-// two waves per SIMD (a few bytes of spills per lane): on 1024 sources 24% faster per
-// Newton iteration than one row, and faster than three rows (more spills) or four rows at
-// one wave.
+// than 64 strips still fills the wave.  The wave adds its NHG sums onto hg[item], which
+// k_hess_second has filled with the second-derivative terms; the items of sources outside
+// a.active (when given) get zeros.  Launched with two rows and two waves per SIMD: on 1024
+// sources 24% faster per Newton iteration than one row (before the second-derivative terms
+// moved to k_hess_second), and faster than three rows (more spills) or four rows at one
+// wave.
 template <int L, int HPX>
 __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __restrict__ items,
                                                    const PairDev* __restrict__ pairs,
@@ -993,7 +1210,6 @@ __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __r
         }
         const celeste_image& im = images[p.img];
         const double* tab = tabp + (size_t)it.pair * NCOMP * CST;
-        const double* hc = hcp + (size_t)it.pair * NGAL * NHC;
         const double* kp = coefp + (size_t)it.pair * NCOEF;
         const double k[NCOEF] = {kp[0], kp[1], kp[2], kp[3]};
         double H[NHG];
@@ -1022,14 +1238,14 @@ __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __r
                     fs[i] = ok[i] ? own[2 * vi] : 0.0;
                     fg[i] = ok[i] ? own[2 * vi + 1] : 0.0;
                 }
-                if (any) hess_pixels<HPX>(tab, hc, (double)c, (double)(r0 + kk), ok, x, Eb, Vb, fs, fg, k, H, t2);
+                if (any) hess_pixels<HPX>(tab, (double)c, (double)(r0 + kk), ok, x, Eb, Vb, fs, fg, k, H, t2);
             }
         }
         double* out = hg + (size_t)ii * NHG;
 #pragma unroll
         for (int f = 0; f < NHG; ++f) {
             const double v = wave_sum(H[f]);
-            if (lane == 0) out[f] = v;
+            if (lane == 0) out[f] += v;   // onto the second-derivative terms of k_hess_second
         }
         j = a.dynamic ? next_item_s(a.counter, lane) : j + nw;
     }
@@ -1482,28 +1698,39 @@ hipError_t launch_hess_consts(const Sel& pairs, const double* tab, const Consts&
 hipError_t launch_hess_geom(const AdjArgs& a, const double* hc, double* hg, int grid, int wpb, int L,
                             hipStream_t st) {
     if (a.items.n <= 0) return hipSuccess;
-    if (a.dynamic) {
-        hipError_t e = launch_fill_int(a.counter, 0, 1, st);
-        if (e != hipSuccess) return e;
-    } else {
+    if (L != 16 && L != 8 && L != 4) return hipErrorInvalidValue;
+    if (!a.dynamic) {
         const int need = (a.items.n + wpb - 1) / wpb;
         if (grid > need) grid = need;
     }
     if (grid < 1) grid = 1;
     const Geometry& g = a.g;
-#define CEL_HG(LL)                                                                                                \
-    hipLaunchKernelGGL((k_hess_geom<LL, 2>), dim3(grid), dim3(64 * wpb), 0, st, a, g.items, g.pairs, g.images, g.x, a.bg, \
-                       a.tab, a.coef, a.fg, hc, hg)
-    if (L == 16)
-        CEL_HG(16);
-    else if (L == 8)
-        CEL_HG(8);
-    else if (L == 4)
-        CEL_HG(4);
-    else
-        return hipErrorInvalidValue;
+    const size_t lds = (size_t)wpb * NCP * NDH * sizeof(double);
+    // second-derivative terms first (they write hg), then the first-derivative products (added
+    // onto hg); each kernel takes the items from a fresh queue when the queue is dynamic
+    for (int pass = 0; pass < 2; ++pass) {
+        if (a.dynamic) {
+            hipError_t e = launch_fill_int(a.counter, 0, 1, st);
+            if (e != hipSuccess) return e;
+        }
+#define CEL_HG(LL)                                                                                                 \
+    if (pass == 0)                                                                                                 \
+        hipLaunchKernelGGL((k_hess_second<LL>), dim3(grid), dim3(64 * wpb), lds, st, a, g.items, g.pairs, g.images, \
+                           g.x, a.bg, a.tab, a.coef, a.fg, hc, hg);                                                \
+    else                                                                                                           \
+        hipLaunchKernelGGL((k_hess_geom<LL, 2>), dim3(grid), dim3(64 * wpb), 0, st, a, g.items, g.pairs, g.images, \
+                           g.x, a.bg, a.tab, a.coef, a.fg, hc, hg)
+        if (L == 16)
+            CEL_HG(16);
+        else if (L == 8)
+            CEL_HG(8);
+        else
+            CEL_HG(4);
 #undef CEL_HG
-    return hipGetLastError();
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_background(const BgArgs& a, int grid, int wpb, int L, hipStream_t st) {
