@@ -818,112 +818,8 @@ __global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>:
 //   + Gs fs_gh + Gg fg_gh,
 // and the entry between g and k_i follows from dE/dk = (fs, fg, 0, 0) and
 // dV/dk = (-2 Es fs, -2 Es fg, fs^2, fg^2).  Entry layout: see HGField.
-// The terms Gs fs_gh + Gg fg_gh are summed per strip from row moments (k_hess_second); this
-// function adds, for NPX pixels of one column (rows py0, py0 + 1, ...) at once, sharing every
-// table read, the products of first derivatives and the k-block entries.  A pixel with ok[i]
-// false contributes nothing (its weights are zeroed).
-template <int NPX>
-__device__ __forceinline__ void hess_pixels(const double* __restrict__ tab, double px, double py0, const bool* ok,
-                                            const double* x, const double* Eb, const double* Vb, const double* fs,
-                                            const double* fg, const double* k, double* H,
-                                            const double* __restrict__ t2) {
-    // pixel scalars first (own values from the gradient pass)
-    double Es[NPX], lE[NPX], lV[NPX], lEE[NPX], lEV[NPX], A[NPX];
-#pragma unroll
-    for (int i = 0; i < NPX; ++i) {
-        Es[i] = k[C_K1] * fs[i] + k[C_K2] * fg[i];
-        const double E = Eb[i] + Es[i];
-        const double V = Vb[i] + k[C_K3] * (fs[i] * fs[i]) + k[C_K4] * (fg[i] * fg[i]) - Es[i] * Es[i];
-        const double inv = frcp(E);
-        const double inv2 = inv * inv;
-        const double r = V * inv2;
-        const double xm = ok[i] ? x[i] : 0.0;
-        lE[i] = ok[i] ? xm * inv * (1.0 + r) - 1.0 : 0.0;
-        lV[i] = -0.5 * xm * inv2;
-        lEE[i] = -xm * inv2 * (1.0 + 3.0 * r);
-        lEV[i] = xm * inv2 * inv;
-        A[i] = lE[i] - 2.0 * Es[i] * lV[i];
-    }
-    double S[NPX][2];
-#pragma unroll
-    for (int i = 0; i < NPX; ++i) S[i][0] = S[i][1] = 0.0;
-#pragma unroll
-    for (int c = 0; c < NPSF; ++c) {
-        const double* e = tab + c * CST;
-        const double a = e[F_PXX], b = e[F_PXY], d = e[F_PYY];
-        const double dx = px - e[F_CX];
-#pragma unroll
-        for (int i = 0; i < NPX; ++i) {
-            const double dy = py0 + (double)i - e[F_CY];
-            const double zx = a * dx + b * dy, zy = b * dx + d * dy;
-            const double n = fexp(e[F_LOGW] - 0.5 * (dx * zx + dy * zy), t2);
-            S[i][0] += n * zx;
-            S[i][1] += n * zy;
-        }
-    }
-    double F[NPX][6];
-#pragma unroll
-    for (int i = 0; i < NPX; ++i)
-#pragma unroll
-        for (int f = 0; f < 6; ++f) F[i][f] = 0.0;
-    // the 14 galaxy components of one PSF component share their mean; each expression below
-    // reads at most one value from the scalar tables per instruction
-    for (int kp = 0; kp < NPSF; ++kp) {
-        const double* e0 = tab + (NPSF + kp * NGAL_PER_PSF) * CST;
-        const double dx = px - e0[F_CX], dy0 = py0 - e0[F_CY];
-        for (int j = 0; j < NGAL_PER_PSF; ++j) {
-            const double* e = e0 + j * CST;
-            const double a = e[F_PXX], b = e[F_PXY], d = e[F_PYY];
-#pragma unroll
-            for (int i = 0; i < NPX; ++i) {
-                const double dy = dy0 + (double)i;
-                const double zx = a * dx + b * dy, zy = b * dx + d * dy;
-                const double n = fexp(e[F_LOGW] - 0.5 * (dx * zx + dy * zy), t2);
-                const double wn = e[F_WT] * n, sn = e[F_SGN] * n, vn = e[F_WNU] * n;
-                const double Dxx = zx * zx - a, Dxy = zx * zy - b, Dyy = zy * zy - d;
-                F[i][0] += wn * zx;
-                F[i][1] += wn * zy;
-                F[i][2] += sn;
-                F[i][3] += vn * Dxx;
-                F[i][4] += vn * Dxy;
-                F[i][5] += vn * Dyy;
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NPX; ++i) {
-        // first-derivative products: E_g, V_g over (ux, uy, frac_dev, Sxx, Sxy, Syy)
-        double Eg[6], Vg[6];
-#pragma unroll
-        for (int g = 0; g < 6; ++g) {
-            const double Sg = g < 2 ? S[i][g] : 0.0;
-            Eg[g] = k[C_K1] * Sg + k[C_K2] * F[i][g];
-            Vg[g] = 2.0 * (k[C_K3] * fs[i]) * Sg + 2.0 * (k[C_K4] * fg[i]) * F[i][g] - 2.0 * Es[i] * Eg[g];
-        }
-        const double lEE2 = lEE[i] - 2.0 * lV[i], lV2 = 2.0 * lV[i];
-#pragma unroll
-        for (int q = 0; q < NHG_GEO; ++q) {
-            const int g = hg_row(q), h = hg_col(q);
-            double v = (lEE2 * Eg[g] + lEV[i] * Vg[g]) * Eg[h] + (lEV[i] * Eg[g]) * Vg[h] +
-                       lV2 * k[C_K4] * F[i][g] * F[i][h];
-            if (g < 2 && h < 2) v += lV2 * k[C_K3] * S[i][g] * S[i][h];
-            H[q] += v;
-        }
-        const double Rc = lEE[i] - 2.0 * lEV[i] * Es[i] - 2.0 * lV[i];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            const int g = q < 2 ? q : q + 1;
-            const double Sg = g < 2 ? S[i][g] : 0.0;
-            const double R = Rc * Eg[g] + lEV[i] * Vg[g];
-            double* o = H + NHG_GEO + 4 * q;
-            o[0] += fs[i] * R + A[i] * Sg;
-            o[1] += fg[i] * R + A[i] * F[i][g];
-            o[2] += lEV[i] * (fs[i] * fs[i]) * Eg[g] + lV2 * fs[i] * Sg;
-            o[3] += lEV[i] * (fg[i] * fg[i]) * Eg[g] + lV2 * fg[i] * F[i][g];
-        }
-    }
-}
-
+// The terms Gs fs_gh + Gg fg_gh are summed per strip from row moments (k_hess_second);
+// k_hess_geom adds the products of first derivatives and the k-block entries.
 
 // ---------------------------------------------- closed-form Hessian: second-derivative terms
 // The second-derivative terms of the geometric block (each pixel's row weight Gs or Gg times a
@@ -1183,7 +1079,12 @@ __global__ void __launch_bounds__(256, 2) k_hess_second(AdjArgs a, const Item* _
 // sources 24% faster per Newton iteration than one row (before the second-derivative terms
 // moved to k_hess_second), and faster than three rows (more spills) or four rows at one
 // wave.
-template <int L, int HPX>
+#ifndef CELESTE_HESS_RUN
+#define CELESTE_HESS_RUN 4
+#endif
+constexpr int HESS_RUN = CELESTE_HESS_RUN;   // rows per run of k_hess_geom
+
+template <int L, int R>
 __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __restrict__ items,
                                                    const PairDev* __restrict__ pairs,
                                                    const celeste_image* __restrict__ images,
@@ -1194,10 +1095,12 @@ __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __r
                                                    double* __restrict__ hg) {
     if (*a.status) return;
     __shared__ double t2[EXP_TAB];
+    extern __shared__ double ltab[];   // [waves per block][NDH][NCP], sized at launch
     fill_exp_table(t2);
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int nw = gridDim.x * wpb;
+    double* my = ltab + (threadIdx.x >> 6) * (NCP * NDH);
     int j = a.dynamic ? next_item_s(a.counter, lane) : blockIdx.x * wpb + (threadIdx.x >> 6);
     while (j < a.items.n) {
         const int ii = __builtin_amdgcn_readfirstlane(sel_at(a.items, j));
@@ -1209,36 +1112,133 @@ __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __r
             continue;
         }
         const celeste_image& im = images[p.img];
-        const double* tab = tabp + (size_t)it.pair * NCOMP * CST;
         const double* kp = coefp + (size_t)it.pair * NCOEF;
         const double k[NCOEF] = {kp[0], kp[1], kp[2], kp[3]};
+        __builtin_amdgcn_wave_barrier();
+        stage_hess(tabp + (size_t)it.pair * NCOMP * CST, hcp + (size_t)it.pair * NGAL * NHC, my, lane);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         double H[NHG];
 #pragma unroll
         for (int f = 0; f < NHG; ++f) H[f] = 0.0;
-        // runs per strip: those of the item's first strip, the longest
-        const int nk = (min(L, p.h - (it.start / p.w) * L) + HPX - 1) / HPX;
+        // runs of R rows per strip: those of the item's first strip, the longest
+        const int nk = (min(L, p.h - (it.start / p.w) * L) + R - 1) / R;
         for (int g = lane; g < it.count * nk; g += 64) {
             const int kr = g / it.count, q = g - kr * it.count;
             int c, r0, nrow;
             strip_geometry(p, it.start + q, L, c, r0, nrow);
-            const int kk = kr * HPX;
-            if (kk < nrow) {
-                bool ok[HPX];
-                double x[HPX], Eb[HPX], Vb[HPX], fs[HPX], fg[HPX];
-                bool any = false;
+            const int kk = kr * R;
+            if (kk >= nrow) continue;
+            const double px = (double)c, py0 = (double)(r0 + kk);
+            // first derivatives of the star and galaxy profiles down the run, summed over the
+            // components: each component's value by the strip recurrence, z affine in the row
+            double S[R][2], F[R][6];
 #pragma unroll
-                for (int i = 0; i < HPX; ++i) {
-                    const int r = r0 + (kk + i < nrow ? kk + i : kk);   // rows past the strip reuse row kk
-                    x[i] = xs[(size_t)im.pix_offset + (size_t)r * im.W + c];
-                    ok[i] = kk + i < nrow && x[i] == x[i];
-                    any = any || ok[i];
-                    const size_t vi = (size_t)p.visit_off + (size_t)(r - p.r0) * p.w + (c - p.c0);
-                    Eb[i] = ok[i] ? bg[2 * vi] : 1.0;
-                    Vb[i] = ok[i] ? bg[2 * vi + 1] : 0.0;
-                    fs[i] = ok[i] ? own[2 * vi] : 0.0;
-                    fg[i] = ok[i] ? own[2 * vi + 1] : 0.0;
+            for (int r = 0; r < R; ++r) {
+                S[r][0] = S[r][1] = 0.0;
+#pragma unroll
+                for (int f = 0; f < 6; ++f) F[r][f] = 0.0;
+            }
+#pragma unroll 1
+            for (int grp = 0; grp < NPSF; ++grp) {
+                const double* es = my + grp;
+                const double dx = px - es[H_CX * NCP], dy = py0 - es[H_CY * NCP];
+                const double h2x = -0.5 * (dx * dx), mxy = -(dx * dy), h2y = -0.5 * (dy * dy);
+                const double mdx = -dx, mdyh = -(dy + 0.5);
+                {
+                    const double a = es[H_A * NCP], b = es[H_B * NCP], d = es[H_D * NCP];
+                    double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, es[H_LW * NCP]))), t2);
+                    double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
+                    const double rdy = es[H_RDY * NCP];
+                    const double zx0 = fma(a, dx, b * dy), zy0 = fma(b, dx, d * dy);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const double zx = fma(b, (double)r, zx0), zy = fma(d, (double)r, zy0);
+                        S[r][0] = fma(n, zx, S[r][0]);
+                        S[r][1] = fma(n, zy, S[r][1]);
+                        if (r + 1 < R) {
+                            n = n * rt;
+                            rt = rt * rdy;
+                        }
+                    }
                 }
-                if (any) hess_pixels<HPX>(tab, (double)c, (double)(r0 + kk), ok, x, Eb, Vb, fs, fg, k, H, t2);
+                const double* eg = my + NPSF + 1 + grp * NGAL_PER_PSF;
+#pragma unroll CELESTE_GAL_UNROLL
+                for (int cc = 0; cc < NGAL_PER_PSF; ++cc) {
+                    const double* e = eg + cc;
+                    const double a = e[H_A * NCP], b = e[H_B * NCP], d = e[H_D * NCP];
+                    double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, e[H_LW * NCP]))), t2);
+                    double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
+                    const double rdy = e[H_RDY * NCP];
+                    const double wt = e[H_WT * NCP], sg = e[H_SGN * NCP], wnu = e[H_WNU * NCP];
+                    const double zx0 = fma(a, dx, b * dy), zy0 = fma(b, dx, d * dy);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const double zx = fma(b, (double)r, zx0), zy = fma(d, (double)r, zy0);
+                        const double wn = wt * n, vn = wnu * n;
+                        F[r][0] = fma(wn, zx, F[r][0]);
+                        F[r][1] = fma(wn, zy, F[r][1]);
+                        F[r][2] = fma(sg, n, F[r][2]);
+                        F[r][3] = fma(vn, fma(zx, zx, -a), F[r][3]);
+                        F[r][4] = fma(vn, fma(zx, zy, -b), F[r][4]);
+                        F[r][5] = fma(vn, fma(zy, zy, -d), F[r][5]);
+                        if (r + 1 < R) {
+                            n = n * rt;
+                            rt = rt * rdy;
+                        }
+                    }
+                }
+            }
+            // products of first derivatives and the k-block entries, row by row (the pixel
+            // scalars from the row's stored background and own values)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int row = kk + r < nrow ? kk + r : kk;   // rows past the strip reuse row kk
+                const size_t gi = (size_t)im.pix_offset + (size_t)(r0 + row) * im.W + c;
+                const double x = xs[gi];
+                if (!(kk + r < nrow && x == x)) continue;
+                const size_t vi = (size_t)p.visit_off + (size_t)(r0 + row - p.r0) * p.w + (c - p.c0);
+                const double fs = own[2 * vi], fg = own[2 * vi + 1];
+                const double Es = k[C_K1] * fs + k[C_K2] * fg;
+                const double E = bg[2 * vi] + Es;
+                const double V = bg[2 * vi + 1] + k[C_K3] * (fs * fs) + k[C_K4] * (fg * fg) - Es * Es;
+                const double inv = frcp(E);
+                const double inv2 = inv * inv;
+                const double rr = V * inv2;
+                const double lE = x * inv * (1.0 + rr) - 1.0;
+                const double lV = -0.5 * x * inv2;
+                const double lEE = -x * inv2 * (1.0 + 3.0 * rr);
+                const double lEV = x * inv2 * inv;
+                const double A = lE - 2.0 * Es * lV;
+                double Eg[6], Vg[6];
+#pragma unroll
+                for (int gg = 0; gg < 6; ++gg) {
+                    const double Sg = gg < 2 ? S[r][gg] : 0.0;
+                    Eg[gg] = k[C_K1] * Sg + k[C_K2] * F[r][gg];
+                    Vg[gg] = 2.0 * (k[C_K3] * fs) * Sg + 2.0 * (k[C_K4] * fg) * F[r][gg] - 2.0 * Es * Eg[gg];
+                }
+                const double lEE2 = lEE - 2.0 * lV, lV2 = 2.0 * lV;
+#pragma unroll
+                for (int qq = 0; qq < NHG_GEO; ++qq) {
+                    const int g1 = hg_row(qq), h1 = hg_col(qq);
+                    double v = (lEE2 * Eg[g1] + lEV * Vg[g1]) * Eg[h1] + (lEV * Eg[g1]) * Vg[h1] +
+                               lV2 * k[C_K4] * F[r][g1] * F[r][h1];
+                    if (g1 < 2 && h1 < 2) v += lV2 * k[C_K3] * S[r][g1] * S[r][h1];
+                    H[qq] += v;
+                }
+                const double Rc = lEE - 2.0 * lEV * Es - 2.0 * lV;
+#pragma unroll
+                for (int qq = 0; qq < 5; ++qq) {
+                    const int g1 = qq < 2 ? qq : qq + 1;
+                    const double Sg = g1 < 2 ? S[r][g1] : 0.0;
+                    const double Rv = Rc * Eg[g1] + lEV * Vg[g1];
+                    double* o = H + NHG_GEO + 4 * qq;
+                    o[0] += fs * Rv + A * Sg;
+                    o[1] += fg * Rv + A * F[r][g1];
+                    o[2] += lEV * (fs * fs) * Eg[g1] + lV2 * fs * Sg;
+                    o[3] += lEV * (fg * fg) * Eg[g1] + lV2 * fg * F[r][g1];
+                }
             }
         }
         double* out = hg + (size_t)ii * NHG;
@@ -1718,8 +1718,8 @@ hipError_t launch_hess_geom(const AdjArgs& a, const double* hc, double* hg, int 
         hipLaunchKernelGGL((k_hess_second<LL>), dim3(grid), dim3(64 * wpb), lds, st, a, g.items, g.pairs, g.images, \
                            g.x, a.bg, a.tab, a.coef, a.fg, hc, hg);                                                \
     else                                                                                                           \
-        hipLaunchKernelGGL((k_hess_geom<LL, 2>), dim3(grid), dim3(64 * wpb), 0, st, a, g.items, g.pairs, g.images, \
-                           g.x, a.bg, a.tab, a.coef, a.fg, hc, hg)
+        hipLaunchKernelGGL((k_hess_geom<LL, (HESS_RUN < LL ? HESS_RUN : LL)>), dim3(grid), dim3(64 * wpb), lds, st,    \
+                           a, g.items, g.pairs, g.images, g.x, a.bg, a.tab, a.coef, a.fg, hc, hg)
         if (L == 16)
             CEL_HG(16);
         else if (L == 8)
