@@ -91,7 +91,7 @@ struct celeste_plan {
     double* d_partials = nullptr;
     double* d_kk = nullptr;          // [cap_items][NKK] brightness-factor Hessian blocks
     double* d_hg = nullptr;          // [cap_items][NHG] closed-form position / shape Hessian blocks
-    double* d_hc = nullptr;          // [n_pairs][NGAL][NHC] constants of the closed-form pass
+    double* d_nu = nullptr;          // [NGAL] nu of each galaxy component (closed-form pass)
     int hess_mode = 0;               // 0: closed-form block pass, 1: tangent passes of the adjoint
     double* d_E = nullptr;
     double* d_V = nullptr;
@@ -872,8 +872,7 @@ int hessian_from_intermediates(celeste_plan* p, const double* theta, const Sel& 
         a.dynamic = p->dynamic;
         a.counter = p->d_counter;
         a.status = p->d_status;
-        HIPCHK(launch_hess_consts(pair, p->d_tab1, p->consts, p->d_hc, p->d_status, st));
-        HIPCHK(launch_hess_geom(a, p->d_hc, p->d_hg, p->launch_grid(), p->wpb, p->rows, st));
+        HIPCHK(launch_hess_geom(a, p->d_nu, p->d_hg, p->launch_grid(), p->wpb, p->rows, st));
         HIPCHK(launch_pair_hess(pair, p->d_pairs, p->d_hg, p->d_hw, p->d_status, st));
         HIPCHK(launch_assemble_hessian(src, p->geom(), p->d_patch_ptr, theta, p->d_gw, p->d_hw, hess, p->d_status,
                                        st));
@@ -1015,7 +1014,7 @@ void celeste_plan_destroy(celeste_plan* p) {
                     p->d_tile_sums, p->d_status, p->d_counter, p->d_grad, p->d_hess, p->d_theta_trial,
                     p->d_pred, p->d_elbo_cur, p->d_elbo_trial, p->d_radius, p->d_done, p->d_list_src,
                     p->d_list_pair, p->d_list_item, p->d_cls_items, p->d_pair_lgamma, p->d_fg, p->d_gw,
-                    p->d_hw, p->d_kk, p->d_hg, p->d_hc, p->d_grad_trial, p->d_hess_trial, p->d_accepted, p->d_live,
+                    p->d_hw, p->d_kk, p->d_hg, p->d_nu, p->d_grad_trial, p->d_hess_trial, p->d_accepted, p->d_live,
                     p->d_mix, p->d_scalar, p->d_tt_part, p->d_list_npair, p->d_list_nitem};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -1107,7 +1106,7 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     A(dalloc(&p->d_partials, max_items * NACC * 2, W));
     A(dalloc(&p->d_kk, max_items * NKK, W));
     A(dalloc(&p->d_hg, max_items * NHG, W));
-    A(dalloc(&p->d_hc, np * NGAL * NHC, W));
+    A(dalloc(&p->d_nu, NGAL, W));
     A(dalloc(&p->d_E, (size_t)p->n_pix, W));
     A(dalloc(&p->d_V, (size_t)p->n_pix, W));
     A(dalloc(&p->d_bg, (size_t)p->n_visits * 2, W));
@@ -1148,6 +1147,15 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
         return r;
     }
     int rc = upload_geometry(p);
+    if (rc == CELESTE_OK) {
+        double nu[NGAL];
+        for (int g = 0; g < NGAL; ++g) {
+            const int jj = g % NGAL_PER_PSF;
+            nu[g] = jj < NDEV ? p->consts.dev_nu[jj] : p->consts.exp_nu[jj - NDEV];
+        }
+        if (hipMemcpy(p->d_nu, nu, sizeof(nu), hipMemcpyHostToDevice) != hipSuccess)
+            rc = hip_fail(hipGetLastError(), "component table upload");
+    }
     if (rc == CELESTE_OK && p->d_mix) {
         double tab[2 * NMIX * MIXF];
         mixture_table(d, tab);

@@ -71,13 +71,6 @@ enum HGField {
     NHG_GEO,
     NHG = NHG_GEO + 20
 };
-// Per galaxy component constants of the closed-form pass (built by k_hess_consts for the
-// listed boxes): nu_j and multiples of the precision P = [[a, b], [b, d]].
-enum HCField {
-    HC_NU = 0, HC_M2A, HC_M2B, HC_M2D, HC_M4A, HC_M4B, HC_M4D,   // nu, -2a, -2b, -2d, -4a, -4b, -4d
-    HC_M2AA, HC_M2AB, HC_M2BB, HC_MQ, HC_M2BD, HC_M2DD,          // -2a^2, -2ab, -2b^2, -(ad + b^2), -2bd, -2d^2
-    NHC = 16
-};
 constexpr int NGAL = NPSF * NGAL_PER_PSF;   // 42 galaxy components per box
 
 __host__ __device__ constexpr int hg_row(int q) {
@@ -229,12 +222,10 @@ hipError_t launch_adjoint(const AdjArgs& a, bool tangent, int base_mode, bool de
                           int waves_per_block, int strip_rows, hipStream_t st);
 hipError_t launch_background(const BgArgs& a, int grid, int waves_per_block, int strip_rows, hipStream_t st);
 // Closed-form geometric block of each listed item's box Hessian into hg[item][NHG]
-// (tables a.tab / a.coef in double, stored backgrounds a.bg, own values a.fg).
-hipError_t launch_hess_geom(const AdjArgs& a, const double* hc, double* hg, int grid, int waves_per_block,
+// (tables a.tab / a.coef in double, stored backgrounds a.bg, own values a.fg; nu[NGAL] the
+// nu of each galaxy component): k_hess_second, then k_hess_geom.
+hipError_t launch_hess_geom(const AdjArgs& a, const double* nu, double* hg, int grid, int waves_per_block,
                             int strip_rows, hipStream_t st);
-// Per galaxy component constants hc[pair][NGAL][NHC] of the listed boxes (double tables).
-hipError_t launch_hess_consts(const Sel& pairs, const double* tab, const Consts& K, double* hc, const int* status,
-                              hipStream_t st);
 hipError_t launch_debug_math(int fn, const double* x, double* y, int n, hipStream_t st);
 hipError_t launch_pair_lgamma(const Geometry& g, int n_pairs, double* out, hipStream_t st);
 hipError_t launch_fill_planes(const celeste_image* images, int n_img, int max_pix, double* E, double* V,

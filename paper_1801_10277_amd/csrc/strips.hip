@@ -847,8 +847,8 @@ __global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>:
 enum HessStagedField { H_CX = 0, H_CY, H_LW, H_RDY, H_A, H_B, H_D, H_WT, H_WNU, H_SGN, H_NU, NDH };
 
 // One wave writes the staged table of a box (field-major [NDH][NCP], slots as in
-// stage_derived) into its LDS slot; nu from the closed-form constants hc.
-__device__ __forceinline__ void stage_hess(const double* __restrict__ tab, const double* __restrict__ hc,
+// stage_derived) into its LDS slot; nu[g]: nu of galaxy component g.
+__device__ __forceinline__ void stage_hess(const double* __restrict__ tab, const double* __restrict__ nu,
                                            double* my, int lane) {
     if (lane < NCOMP) {
         const double* e = tab + lane * CST;
@@ -863,7 +863,7 @@ __device__ __forceinline__ void stage_hess(const double* __restrict__ tab, const
         o[H_WT * NCP] = e[F_WT];
         o[H_WNU * NCP] = e[F_WNU];
         o[H_SGN * NCP] = e[F_SGN];
-        o[H_NU * NCP] = lane < NPSF ? 0.0 : hc[(lane - NPSF) * NHC + HC_NU];
+        o[H_NU * NCP] = lane < NPSF ? 0.0 : nu[lane - NPSF];
     }
 }
 
@@ -1000,7 +1000,7 @@ __global__ void __launch_bounds__(256, 2) k_hess_second(AdjArgs a, const Item* _
                                                      const double* __restrict__ xs, const double* __restrict__ bg,
                                                      const double* __restrict__ tabp,
                                                      const double* __restrict__ coefp,
-                                                     const double* __restrict__ own, const double* __restrict__ hcp,
+                                                     const double* __restrict__ own, const double* __restrict__ nu,
                                                      double* __restrict__ hg) {
     if (*a.status) return;
     __shared__ double t2[EXP_TAB];
@@ -1025,7 +1025,7 @@ __global__ void __launch_bounds__(256, 2) k_hess_second(AdjArgs a, const Item* _
         const double* kp = coefp + (size_t)it.pair * NCOEF;
         const double k1 = kp[C_K1], k2 = kp[C_K2], k3 = kp[C_K3], k4 = kp[C_K4];
         __builtin_amdgcn_wave_barrier();
-        stage_hess(tabp + (size_t)it.pair * NCOMP * CST, hcp + (size_t)it.pair * NGAL * NHC, my, lane);
+        stage_hess(tabp + (size_t)it.pair * NCOMP * CST, nu, my, lane);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1091,7 +1091,7 @@ __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __r
                                                    const double* __restrict__ xs, const double* __restrict__ bg,
                                                    const double* __restrict__ tabp,
                                                    const double* __restrict__ coefp,
-                                                   const double* __restrict__ own, const double* __restrict__ hcp,
+                                                   const double* __restrict__ own, const double* __restrict__ nu,
                                                    double* __restrict__ hg) {
     if (*a.status) return;
     __shared__ double t2[EXP_TAB];
@@ -1115,7 +1115,7 @@ __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __r
         const double* kp = coefp + (size_t)it.pair * NCOEF;
         const double k[NCOEF] = {kp[0], kp[1], kp[2], kp[3]};
         __builtin_amdgcn_wave_barrier();
-        stage_hess(tabp + (size_t)it.pair * NCOMP * CST, hcp + (size_t)it.pair * NGAL * NHC, my, lane);
+        stage_hess(tabp + (size_t)it.pair * NCOMP * CST, nu, my, lane);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1659,43 +1659,7 @@ hipError_t launch_adjoint(const AdjArgs& a, bool tangent, int base, bool deriv, 
 }
 
 
-// One thread per (listed box, galaxy component).
-__global__ void __launch_bounds__(256) k_hess_consts(Sel pairs, const double* __restrict__ tab, Consts K,
-                                                     double* __restrict__ hc, const int* status) {
-    if (*status) return;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= pairs.n * NGAL) return;
-    const int j = t / NGAL, g = t - j * NGAL;
-    const int pi = sel_at(pairs, j);
-    const double* e = tab + ((size_t)pi * NCOMP + NPSF + g) * CST;
-    const double a = e[F_PXX], b = e[F_PXY], d = e[F_PYY];
-    const int jj = g % NGAL_PER_PSF;
-    double* o = hc + ((size_t)pi * NGAL + g) * NHC;
-    o[HC_NU] = jj < NDEV ? K.dev_nu[jj] : K.exp_nu[jj - NDEV];
-    o[HC_M2A] = -2.0 * a;
-    o[HC_M2B] = -2.0 * b;
-    o[HC_M2D] = -2.0 * d;
-    o[HC_M4A] = -4.0 * a;
-    o[HC_M4B] = -4.0 * b;
-    o[HC_M4D] = -4.0 * d;
-    o[HC_M2AA] = -2.0 * (a * a);
-    o[HC_M2AB] = -2.0 * (a * b);
-    o[HC_M2BB] = -2.0 * (b * b);
-    o[HC_MQ] = -(a * d + b * b);
-    o[HC_M2BD] = -2.0 * (b * d);
-    o[HC_M2DD] = -2.0 * (d * d);
-    for (int f = HC_M2DD + 1; f < NHC; ++f) o[f] = 0.0;
-}
-
-hipError_t launch_hess_consts(const Sel& pairs, const double* tab, const Consts& K, double* hc, const int* status,
-                              hipStream_t st) {
-    if (pairs.n <= 0) return hipSuccess;
-    const int n = pairs.n * NGAL;
-    hipLaunchKernelGGL(k_hess_consts, dim3((n + 255) / 256), dim3(256), 0, st, pairs, tab, K, hc, status);
-    return hipGetLastError();
-}
-
-hipError_t launch_hess_geom(const AdjArgs& a, const double* hc, double* hg, int grid, int wpb, int L,
+hipError_t launch_hess_geom(const AdjArgs& a, const double* nu, double* hg, int grid, int wpb, int L,
                             hipStream_t st) {
     if (a.items.n <= 0) return hipSuccess;
     if (L != 16 && L != 8 && L != 4) return hipErrorInvalidValue;
@@ -1716,10 +1680,10 @@ hipError_t launch_hess_geom(const AdjArgs& a, const double* hc, double* hg, int 
 #define CEL_HG(LL)                                                                                                 \
     if (pass == 0)                                                                                                 \
         hipLaunchKernelGGL((k_hess_second<LL>), dim3(grid), dim3(64 * wpb), lds, st, a, g.items, g.pairs, g.images, \
-                           g.x, a.bg, a.tab, a.coef, a.fg, hc, hg);                                                \
+                           g.x, a.bg, a.tab, a.coef, a.fg, nu, hg);                                                \
     else                                                                                                           \
         hipLaunchKernelGGL((k_hess_geom<LL, (HESS_RUN < LL ? HESS_RUN : LL)>), dim3(grid), dim3(64 * wpb), lds, st,    \
-                           a, g.items, g.pairs, g.images, g.x, a.bg, a.tab, a.coef, a.fg, hc, hg)
+                           a, g.items, g.pairs, g.images, g.x, a.bg, a.tab, a.coef, a.fg, nu, hg)
         if (L == 16)
             CEL_HG(16);
         else if (L == 8)
