@@ -49,16 +49,44 @@ N_STAR, N_GAL = 3, 42                   # Gaussians per (source, image): 3 star,
 # are stored; the fused adjoint runs the pixel terms and pass B (seed again; per row one FMA
 # and one (star) or two (galaxy) running-sum adds; per strip the moments from the running
 # sums and the fold into the ten intermediates: 11 FLOPs per star, 46 per galaxy component).
+# The strip kernels leave out of a work item the Gaussians below exp(-50) of their peak on
+# all of its pixels, so the count is taken per evaluated (live) component from the library's
+# own work counts (celeste_work_counts); the zero components that pad an odd group to a pair
+# are overhead, not counted.
 SEED = 9 + 2 * FEXP_FLOPS
-GROUPS = 3 * 12
-PASS_A_PER_STRIP = GROUPS + (N_STAR + N_GAL) * SEED
-PASS_A_PER_VISIT = N_STAR * 3 + N_GAL * 4
-PASS_B_PER_STRIP = GROUPS + (N_STAR + N_GAL) * SEED + N_STAR * 11 + N_GAL * 46
-PASS_B_PER_VISIT = N_STAR * 5 + N_GAL * 6
+GROUP = 12
+PASS_A_STRIP = {"star": SEED, "gal": SEED}
+PASS_A_VISIT = {"star": 3, "gal": 4}
+PASS_B_STRIP = {"star": SEED + 11, "gal": SEED + 46}
+PASS_B_VISIT = {"star": 5, "gal": 6}
 PIXEL_PER_VISIT = 40 + FLOG_FLOPS + FRCP_FLOPS
 GATHER_PER_VISIT = 11
-RENDER_PER_STRIP, RENDER_PER_VISIT = PASS_A_PER_STRIP, PASS_A_PER_VISIT + GATHER_PER_VISIT
-ADJ_PER_STRIP, ADJ_PER_VISIT = PASS_B_PER_STRIP, PASS_B_PER_VISIT + PIXEL_PER_VISIT
+
+
+def pass_flops(wc, per_strip, per_visit):
+    return (wc["group_strips"] * GROUP + wc["star_strips"] * per_strip["star"]
+            + wc["galaxy_strips"] * per_strip["gal"] + wc["star_visits"] * per_visit["star"]
+            + wc["galaxy_visits"] * per_visit["gal"])
+
+
+def full_counts(strips, visits):
+    """Work counts with every Gaussian evaluated on every strip (no culling)."""
+    return {"strips": strips, "visits": visits, "group_strips": 3 * strips, "star_strips": N_STAR * strips,
+            "galaxy_strips": N_GAL * strips, "pad_strips": 0, "star_visits": N_STAR * visits,
+            "galaxy_visits": N_GAL * visits, "pad_visits": 0}
+
+
+def step_flops(wc, render_mode):
+    """(fused adjoint, render) algorithmic FLOPs of one step.  Render modes 2 and 3 store the
+    own values in the render's strip pass; modes 0 and 1 recompute them in the adjoint (their
+    render is counted as the same strip values plus the plane accumulation)."""
+    visits = wc["visits"]
+    a = pass_flops(wc, PASS_A_STRIP, PASS_A_VISIT)
+    b = pass_flops(wc, PASS_B_STRIP, PASS_B_VISIT) + visits * PIXEL_PER_VISIT
+    if render_mode in (2, 3):
+        return b, a + visits * GATHER_PER_VISIT
+    return a + b, a + visits * GATHER_PER_VISIT
+
 
 # Direct evaluation of the same quantities (one exp per Gaussian per visit), for context.
 GAUSS_VALUE = 13 + EXP_FLOPS
@@ -396,8 +424,13 @@ def main():
     adj_ms = phase[2]
     L = info["strip_rows"]
     strips = strip_count(f, L)
-    adj_flops = strips * ADJ_PER_STRIP + visits * ADJ_PER_VISIT
-    render_flops = strips * RENDER_PER_STRIP + visits * RENDER_PER_VISIT
+    wc = plan.work_counts(theta)
+    assert wc["strips"] == strips and wc["visits"] == visits, (wc, strips, visits)
+    adj_flops, render_flops = step_flops(wc, info["render_mode"])
+    adj_full, render_full = step_flops(full_counts(strips, visits), info["render_mode"])
+    live_per_strip = (wc["star_strips"] + wc["galaxy_strips"]) / strips
+    log("live Gaussians per strip %.2f of 45 (+%.2f zero pads); adjoint %.3e FLOPs per launch (%.3e without culling)"
+        % (live_per_strip, wc["pad_strips"] / strips, adj_flops, adj_full))
     achieved = adj_flops / (adj_ms * 1e-3) / 1e12
     launch_str = "%d,%d,%d,%d,%d,%d" % (info["chunk"], info["waves_per_block"], info["grid_blocks"],
                                         info["dynamic_queue"], info["strip_rows"], info["render_mode"])
@@ -412,6 +445,8 @@ def main():
                 "counted_fp64_tflops": None if counted is None else round(counted / (adj_ms * 1e-3) / 1e12, 3),
                 "kernel": "k_adjoint_strips<double, planes, grad, L=%d> (fused own-source forward + adjoint)" % L,
                 "flops_per_launch": adj_flops, "flops_per_visit": round(adj_flops / visits, 1),
+                "live_gaussians_per_strip": round(live_per_strip, 3),
+                "flops_per_launch_without_culling": adj_full,
                 "visits_per_launch": visits, "strips_per_launch": strips, "avg_launch_ms": round(adj_ms, 4)}
     whole = (adj_flops + render_flops) / visits * value / 1e12
     direct_equiv = (DIRECT_ADJ_PER_VISIT + DIRECT_RENDER_PER_VISIT) * value / 1e12

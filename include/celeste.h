@@ -191,7 +191,10 @@ int celeste_elbo(celeste_plan* plan, const double* theta, const uint8_t* active,
  * (Section III model) plus the KL's closed-form gradient.  No per-pixel tape: with
  * render modes 0 and 1 the fused adjoint recomputes each visit's own profile values; with
  * modes 2 (the default) and 3 the render stores them (16 B per visit in plan memory) and
- * the adjoint reads them back instead of evaluating the 45 Gaussians a second time. */
+ * the adjoint reads them back instead of evaluating the 45 Gaussians a second time.  The
+ * strip kernels leave out of a work item every Gaussian that stays below exp(-50) of its
+ * own peak on all of the item's pixels (celeste_work_counts): a change far below the
+ * rounding of any pixel's expected count, which holds the sky. */
 int celeste_elbo_grad(celeste_plan* plan, const double* theta, const uint8_t* active, int mode,
                       double* elbo, double* grad, hipStream_t stream);
 
@@ -250,6 +253,18 @@ int celeste_hessian(celeste_plan* plan, const double* theta, const int32_t* src,
 int celeste_newton(celeste_plan* plan, double* theta_inout, const int32_t* src, int n,
                    int n_steps, const celeste_tr_params* params, double* radius,
                    double* elbo_out, hipStream_t stream);
+
+/* Work of the batched path's strip passes at theta (device [n_src][48]) under the
+ * component culling of the strip kernels (a Gaussian whose quadratic form exceeds 100 on
+ * every pixel of a work item, i.e. below exp(-50) of its own peak there, is left out of
+ * that item's strips), for FLOP counts: counts (host int64[9]) = strips, visits, PSF groups
+ * evaluated x strips, live star components x strips, live galaxy components x strips,
+ * zero-component pads x strips (an odd number of live galaxy components in a group is
+ * padded to a pair), then live stars, live galaxy components and pads x visits, all
+ * summed over the work items of the current launch configuration.  Builds the tables,
+ * counts with the kernels' own test and synchronises the stream; CELESTE_EDOMAIN if theta
+ * leaves the parameter domain. */
+int celeste_work_counts(celeste_plan* plan, const double* theta, int64_t* counts, hipStream_t stream);
 
 /* Total ELBO of the field (each covered pixel counted once, minus every KL) into
  * out[0] (device). */
@@ -359,7 +374,7 @@ const char* celeste_last_hip_error(void);
 
 /* Diagnostic: the elementary functions of the strip kernels applied elementwise to device
  * arrays of n, for comparison with a reference libm.  fn = CELESTE_FN_EXP: table-driven
- * exp (Tang's method: 64-entry 2^(j/64) table, |r| <= ln2/128, degree-5 polynomial),
+ * exp (Tang's method: 256-entry 2^(j/256) table, |r| <= ln2/512, degree-4 polynomial),
  * x[i] <= 709 and not NaN; CELESTE_FN_LOG: table-driven log (Tang's method: 128 breakpoints
  * in [1/2, 1), degree-6 log1p), finite x[i] > 0; CELESTE_FN_RCP: 1/x by the hardware estimate
  * and two Newton steps, x[i] finite with a normal reciprocal.  Other fn: CELESTE_EINVAL. */

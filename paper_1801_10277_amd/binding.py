@@ -31,7 +31,8 @@ EXPORTS = ["celeste_plan_create", "celeste_plan_destroy", "celeste_plan_get_info
            "celeste_color_batches", "celeste_sweep", "celeste_plan_set_launch", "celeste_autotune",
            "celeste_plan_use_graph", "celeste_plan_profile", "celeste_plan_status", "celeste_last_hip_error",
            "celeste_status_string", "celeste_version", "celeste_debug_math", "celeste_conflict_graph",
-           "celeste_cyclades_batches", "celeste_plan_set_hessian_mode", "celeste_elbo_grad_noalloc"]
+           "celeste_cyclades_batches", "celeste_plan_set_hessian_mode", "celeste_elbo_grad_noalloc",
+           "celeste_work_counts"]
 
 
 class celeste_image(C.Structure):
@@ -96,6 +97,7 @@ def lib():
     L.celeste_hessian.argtypes = [vp, dp, ip, C.c_int, dp, vp]
     L.celeste_newton.argtypes = [vp, dp, ip, C.c_int, C.c_int, C.POINTER(celeste_tr_params), dp, dp, vp]
     L.celeste_total_elbo.argtypes = [vp, dp, dp, vp]
+    L.celeste_work_counts.argtypes = [vp, dp, C.POINTER(C.c_int64), vp]
     L.celeste_color_batches.argtypes = [vp, C.c_uint64, ip, ip, ip]
     L.celeste_sweep.argtypes = [vp, dp, ip, ip, C.c_int, C.c_int, C.POINTER(celeste_tr_params), dp, vp]
     L.celeste_plan_set_hessian_mode.argtypes = [vp, C.c_int]
@@ -332,6 +334,16 @@ class Plan:
         check(lib().celeste_total_elbo(self.h, _ptr(theta), _ptr(out), _stream()), "celeste_total_elbo")
         self._status("celeste_total_elbo")
         return out
+
+    WORK_KEYS = ("strips", "visits", "group_strips", "star_strips", "galaxy_strips", "pad_strips",
+                 "star_visits", "galaxy_visits", "pad_visits")
+
+    def work_counts(self, theta):
+        """Work of the strip passes at theta under the component culling (dict of
+        WORK_KEYS); synchronises the stream."""
+        out = (C.c_int64 * len(self.WORK_KEYS))()
+        check(lib().celeste_work_counts(self.h, _ptr(self._theta(theta)), out, _stream()), "celeste_work_counts")
+        return dict(zip(self.WORK_KEYS, (int(v) for v in out)))
 
     def color_batches(self, seed=0):
         ptr = np.zeros(self.S + 1, np.int32)

@@ -103,6 +103,7 @@ struct celeste_plan {
     int* d_status = nullptr;
     double* d_mix = nullptr;     // [2][NMIX][MIXF] colour-prior mixture table, or null
     int* d_counter = nullptr;
+    unsigned long long* d_wcount = nullptr;   // [NLIVE_COUNTS] celeste_work_counts
     double* d_grad = nullptr;
     double* d_hess = nullptr;        // [S][npar][npar]
     double* d_grad_trial = nullptr;  // gradient and Hessian at the Newton trial points
@@ -1015,7 +1016,7 @@ void celeste_plan_destroy(celeste_plan* p) {
                     p->d_pred, p->d_elbo_cur, p->d_elbo_trial, p->d_radius, p->d_done, p->d_list_src,
                     p->d_list_pair, p->d_list_item, p->d_cls_items, p->d_pair_lgamma, p->d_fg, p->d_gw,
                     p->d_hw, p->d_kk, p->d_hg, p->d_nu, p->d_grad_trial, p->d_hess_trial, p->d_accepted, p->d_live,
-                    p->d_mix, p->d_scalar, p->d_tt_part, p->d_list_npair, p->d_list_nitem};
+                    p->d_mix, p->d_scalar, p->d_tt_part, p->d_list_npair, p->d_list_nitem, p->d_wcount};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -1115,6 +1116,7 @@ int celeste_plan_create(const celeste_problem_desc* d, celeste_plan** out) {
     A(dalloc(&p->d_pair_lgamma, np, W));
     A(dalloc(&p->d_status, 1, W));
     A(dalloc(&p->d_counter, 1, W));
+    A(dalloc(&p->d_wcount, NLIVE_COUNTS, W));
     const size_t S = (size_t)p->n_src;
     A(dalloc(&p->d_grad, S * ROW, W));
     A(dalloc(&p->d_hess, S * NPK * NPK, W));
@@ -1382,6 +1384,25 @@ int celeste_hessian(celeste_plan* p, const double* theta, const int32_t* src, in
     CHK(hessian_from_intermediates(p, theta, ss, sp, si, BASE_BG, p->d_hess, st));
     const size_t np2 = (size_t)p->consts.npar * p->consts.npar;
     HIPCHK(hipMemcpyAsync(hess, p->d_hess, (size_t)n * np2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return CELESTE_OK;
+}
+
+int celeste_work_counts(celeste_plan* p, const double* theta, int64_t* counts, hipStream_t st) {
+    if (!p || !theta || !counts) return CELESTE_EINVAL;
+    const Scope sc = scope_all(p);
+    CHK(validate_theta(p, theta, nullptr, nullptr, p->n_src, st));
+    CHK(prep(p, theta, sc.pair, false, DIR_NONE, nullptr, 0, st));
+    HIPCHK(launch_live_counts(sc.item, p->geom(), p->d_tab1, p->rows, p->d_wcount, p->d_status, st));
+    unsigned long long h[NLIVE_COUNTS];
+    HIPCHK(hipMemcpyAsync(h, p->d_wcount, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int status = 0;
+    HIPCHK(hipMemcpy(&status, p->d_status, sizeof(int), hipMemcpyDeviceToHost));
+    if (status) {
+        HIPCHK(hipMemset(p->d_status, 0, sizeof(int)));
+        return status;
+    }
+    for (int i = 0; i < NLIVE_COUNTS; ++i) counts[i] = (int64_t)h[i];
     return CELESTE_OK;
 }
 

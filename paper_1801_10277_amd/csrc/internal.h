@@ -241,6 +241,13 @@ hipError_t launch_finalize(const FinArgs& a, bool tangent, hipStream_t st);
 hipError_t launch_tile_total(const double* tile_sums, int n_tiles, const double* theta, const Consts& c,
                              int S, double* part, double* out, const int* status, hipStream_t st);
 hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st);
+// Work counts of the strip passes under the component culling (k_live_counts): strips,
+// visits, evaluated PSF groups, live stars, live galaxy components and zero-component pads,
+// the last four per strip and per visit.
+constexpr int NLIVE_COUNTS = 9;
+hipError_t launch_live_counts(const Sel& sel, const Geometry& g, const double* tab, int L,
+                              unsigned long long* out, const int* status, hipStream_t st);
+
 hipError_t launch_fill_u8_sel(uint8_t* p, const Sel& s, uint8_t v, hipStream_t st);
 hipError_t launch_fill_f64_sel(double* p, const Sel& s, double v, hipStream_t st);
 

@@ -181,7 +181,9 @@ enum DerivedField { D_CX = 0, D_CY, D_LW, D_RDY, D_A, D_B, D_D, D_WT, D_WNU, D_S
 
 __device__ __forceinline__ int staged_slot(int c) { return c < NPSF ? c : c + 1; }
 
-// One wave writes the staged table of a box into its LDS slot (lane c: component c).
+// One wave writes the staged table of a box into its LDS slot (lane c: component c).  Lane
+// NCOMP fills the spare slot NPSF with a component that is zero everywhere (log weight -1000,
+// flat, every weight 0): the loops over the live components below pair an odd one with it.
 __device__ __forceinline__ void stage_derived(const double* __restrict__ tab, double* my, int lane) {
     if (lane < NCOMP) {
         const double* e = tab + lane * CST;
@@ -196,22 +198,129 @@ __device__ __forceinline__ void stage_derived(const double* __restrict__ tab, do
         o[D_WT * NCP] = e[F_WT];
         o[D_WNU * NCP] = e[F_WNU];
         o[D_SGN * NCP] = e[F_SGN];
+    } else if (lane == NCOMP) {
+        double* o = my + NPSF;
+        o[D_CX * NCP] = 0.0;
+        o[D_CY * NCP] = 0.0;
+        o[D_LW * NCP] = -1000.0;   // exp underflows to exactly 0
+        o[D_RDY * NCP] = 1.0;
+        o[D_A * NCP] = 0.0;
+        o[D_B * NCP] = 0.0;
+        o[D_D * NCP] = 0.0;
+        o[D_WT * NCP] = 0.0;
+        o[D_WNU * NCP] = 0.0;
+        o[D_SGN * NCP] = 0.0;
     }
 }
 
+// Components that are negligible on every pixel of a work item are left out of its strips.
+// The item's strips cover at most three rectangles of its box: the rest of its first band,
+// whole bands, the start of its last band.  For P = [[a, b], [b, d]] positive definite,
+// minimising the quadratic form over one coordinate gives
+// (x, y) P (x, y)^T >= x^2 det P / d  and  >= y^2 det P / a,
+// so a component whose form exceeds CULL_Q on each rectangle by one of these bounds stays
+// below exp(-CULL_Q / 2) (< 2e-22) of its own peak on the whole item: far below the
+// rounding of any pixel's expected count, which holds the sky.  Returns the live
+// components as a wave-uniform bit set (bit c: table component c); lane c tests component c.
+constexpr double CULL_Q = 100.0;
+
+__device__ __forceinline__ uint64_t item_live(const double* __restrict__ tab, const PairDev& p, const Item& it,
+                                              int L, int lane) {
+    bool cull = false;
+    if (lane < NCOMP) {
+        const double* e = tab + lane * CST;
+        const double cx = e[F_CX], cy = e[F_CY], a = e[F_PXX], b = e[F_PXY], d = e[F_PYY];
+        const double det = fma(a, d, -(b * b));
+        const double qa = CULL_Q * a, qd = CULL_Q * d;
+        // > 0 if the form exceeds CULL_Q on columns ca..cb, rows ra..rb of the box
+        auto far = [&](int ca, int cb, int ra, int rb) {
+            const double x0 = (double)(p.c0 + ca) - cx, x1 = (double)(p.c0 + cb) - cx;
+            const double y0 = (double)(p.r0 + ra) - cy, y1 = (double)(p.r0 + rb) - cy;
+            const double ux = fmax(fmax(x0, -x1), 0.0), uy = fmax(fmax(y0, -y1), 0.0);
+            return fmax(fma(ux * ux, det, -qd), fma(uy * uy, det, -qa));
+        };
+        const int s0 = it.start, s1 = it.start + it.count - 1;
+        const int rb0 = s0 / p.w, rb1 = s1 / p.w;
+        double m = far(s0 - rb0 * p.w, rb1 > rb0 ? p.w - 1 : s1 - rb0 * p.w, rb0 * L, min(rb0 * L + L, p.h) - 1);
+        if (rb1 > rb0) {
+            m = fmin(m, far(0, s1 - rb1 * p.w, rb1 * L, min(rb1 * L + L, p.h) - 1));
+            if (rb1 > rb0 + 1) m = fmin(m, far(0, p.w - 1, (rb0 + 1) * L, rb1 * L - 1));
+        }
+        cull = a > 0.0 && det > 0.0 && m > 0.0 && cx - cx == 0.0 && cy - cy == 0.0;
+    }
+    return ~__builtin_amdgcn_ballot_w64(cull) & ((1ull << NCOMP) - 1);
+}
+
+// Staged slots of the live galaxy components of PSF group grp, two at a time (an odd last
+// one paired with the zero component in slot NPSF).
+template <class F>
+__device__ __forceinline__ void for_live_pairs(uint64_t live, int grp, F&& f) {
+    uint32_t gm = (uint32_t)(live >> (NPSF + grp * NGAL_PER_PSF)) & ((1u << NGAL_PER_PSF) - 1);
+    const int base = NPSF + 1 + grp * NGAL_PER_PSF;
+    while (gm) {
+        const int s0 = base + __builtin_ctz(gm);
+        gm &= gm - 1;
+        int s1 = NPSF;
+        if (gm) {
+            s1 = base + __builtin_ctz(gm);
+            gm &= gm - 1;
+        }
+        f(s0, s1);
+    }
+}
+
+// One galaxy component's rows and fold (strip_adjoint_staged), in its PSF group's frame.
+template <int L>
+__device__ __forceinline__ void gal_adjoint_staged(const double* __restrict__ e, const double* Gg, double dx,
+                                                   double h2x, double mxy, double h2y, double mdx, double mdyh,
+                                                   double ev, double ev2, double e21, double* acc,
+                                                   const double* __restrict__ t2) {
+    const double a = e[D_A * NCP], b = e[D_B * NCP], d = e[D_D * NCP];
+    double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, e[D_LW * NCP]))), t2);
+    double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
+    const double rdy = e[D_RDY * NCP];
+    double A = 0.0, B = 0.0, C = 0.0;
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        A = fma(Gg[k], n, A);
+        B += A;
+        C += B;
+        if (k + 1 < L) {
+            n = n * rt;
+            rt = rt * rdy;
+        }
+    }
+    const double M1 = fma(ev, A, -B), M2 = fma(ev2, A, fma(-e21, B, C + C));
+    const double X1 = dx * A, Y1 = dx * M1;
+    const double U = fma(a, X1, b * M1), Up = fma(b, X1, d * M1);
+    const double W = fma(a, Y1, b * M2), Wp = fma(b, Y1, d * M2);
+    const double dU = fma(dx, U, -A), dUp = dx * Up, Wm = Wp - A;
+    const double wt = e[D_WT * NCP], wnu = e[D_WNU * NCP];
+    const double wna = wnu * a, wnb = wnu * b, wnd = wnu * d;
+    acc[A_FDEV] = fma(e[D_SGN * NCP], A, acc[A_FDEV]);
+    acc[A_UX] = fma(wt, U, acc[A_UX]);
+    acc[A_UY] = fma(wt, Up, acc[A_UY]);
+    acc[A_SXX] = fma(wna, dU, fma(wnb, W, acc[A_SXX]));
+    acc[A_SXY] = fma(wnb, dU, fma(wnd, W, acc[A_SXY]));
+    acc[A_SYY] = fma(wnb, dUp, fma(wnd, Wm, acc[A_SYY]));
+}
+
+// live: the components to evaluate (item_live); the others are skipped.
 template <int L>
 __device__ __forceinline__ void strip_adjoint_staged(const double* __restrict__ lt, double px, double py0,
                                                      const double* Gs, const double* Gg, double* acc,
-                                                     const double* __restrict__ t2) {
+                                                     const double* __restrict__ t2, uint64_t live) {
 #pragma unroll 1
     for (int grp = 0; grp < NPSF; ++grp) {
+        const bool star = (live >> grp) & 1;
+        if (!star && !((live >> (NPSF + grp * NGAL_PER_PSF)) & ((1u << NGAL_PER_PSF) - 1))) continue;
         const double* es = lt + grp;
         const double dx = px - es[D_CX * NCP], dy = py0 - es[D_CY * NCP];
         const double h2x = -0.5 * (dx * dx), mxy = -(dx * dy), h2y = -0.5 * (dy * dy);
         const double mdx = -dx, mdyh = -(dy + 0.5);
         const double ev = (double)L + dy;
         const double ev2 = ev * ev, e21 = 2.0 * ev + 1.0;
-        {
+        if (star) {
             const double a = es[D_A * NCP], b = es[D_B * NCP], d = es[D_D * NCP];
             double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, es[D_LW * NCP]))), t2);
             double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
@@ -230,39 +339,10 @@ __device__ __forceinline__ void strip_adjoint_staged(const double* __restrict__ 
             acc[A_UX] = fma(a, X1, fma(b, M1, acc[A_UX]));
             acc[A_UY] = fma(b, X1, fma(d, M1, acc[A_UY]));
         }
-        const double* eg = lt + NPSF + 1 + grp * NGAL_PER_PSF;
-#pragma unroll CELESTE_GAL_UNROLL
-        for (int c = 0; c < NGAL_PER_PSF; ++c) {
-            const double* e = eg + c;
-            const double a = e[D_A * NCP], b = e[D_B * NCP], d = e[D_D * NCP];
-            double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, e[D_LW * NCP]))), t2);
-            double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
-            const double rdy = e[D_RDY * NCP];
-            double A = 0.0, B = 0.0, C = 0.0;
-#pragma unroll
-            for (int k = 0; k < L; ++k) {
-                A = fma(Gg[k], n, A);
-                B += A;
-                C += B;
-                if (k + 1 < L) {
-                    n = n * rt;
-                    rt = rt * rdy;
-                }
-            }
-            const double M1 = fma(ev, A, -B), M2 = fma(ev2, A, fma(-e21, B, C + C));
-            const double X1 = dx * A, Y1 = dx * M1;
-            const double U = fma(a, X1, b * M1), Up = fma(b, X1, d * M1);
-            const double W = fma(a, Y1, b * M2), Wp = fma(b, Y1, d * M2);
-            const double dU = fma(dx, U, -A), dUp = dx * Up, Wm = Wp - A;
-            const double wt = e[D_WT * NCP], wnu = e[D_WNU * NCP];
-            const double wna = wnu * a, wnb = wnu * b, wnd = wnu * d;
-            acc[A_FDEV] = fma(e[D_SGN * NCP], A, acc[A_FDEV]);
-            acc[A_UX] = fma(wt, U, acc[A_UX]);
-            acc[A_UY] = fma(wt, Up, acc[A_UY]);
-            acc[A_SXX] = fma(wna, dU, fma(wnb, W, acc[A_SXX]));
-            acc[A_SXY] = fma(wnb, dU, fma(wnd, W, acc[A_SXY]));
-            acc[A_SYY] = fma(wnb, dUp, fma(wnd, Wm, acc[A_SYY]));
-        }
+        for_live_pairs(live, grp, [&](int s0, int s1) {
+            gal_adjoint_staged<L>(lt + s0, Gg, dx, h2x, mxy, h2y, mdx, mdyh, ev, ev2, e21, acc, t2);
+            gal_adjoint_staged<L>(lt + s1, Gg, dx, h2x, mxy, h2y, mdx, mdyh, ev, ev2, e21, acc, t2);
+        });
     }
 }
 
@@ -271,10 +351,30 @@ __device__ __forceinline__ void strip_adjoint_staged(const double* __restrict__ 
 // shared centre formed once per group.
 // SGN: also fgd[k] = sum of the de Vaucouleurs minus the exponential components (d fg /
 // d frac_dev).
+template <int L, bool SGN>
+__device__ __forceinline__ void gal_values_staged(const double* __restrict__ e, double h2x, double mxy, double h2y,
+                                                  double mdx, double mdyh, double* fg, double* fgd,
+                                                  const double* __restrict__ t2) {
+    const double a = e[D_A * NCP], b = e[D_B * NCP], d = e[D_D * NCP];
+    double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, e[D_LW * NCP]))), t2);
+    double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
+    const double rdy = e[D_RDY * NCP], wt = e[D_WT * NCP];
+    const double sgn = SGN ? e[D_SGN * NCP] : 0.0;
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        fg[k] = fma(n, wt, fg[k]);
+        if constexpr (SGN) fgd[k] = fma(n, sgn, fgd[k]);
+        if (k + 1 < L) {
+            n = n * rt;
+            rt = rt * rdy;
+        }
+    }
+}
+
 template <int L, bool SGN = false>
 __device__ __forceinline__ void strip_values_staged(const double* __restrict__ lt, double px, double py0,
                                                     double* fs, double* fg, const double* __restrict__ t2,
-                                                    double* fgd = nullptr) {
+                                                    uint64_t live, double* fgd = nullptr) {
 #pragma unroll
     for (int k = 0; k < L; ++k) fs[k] = fg[k] = 0.0;
     if constexpr (SGN) {
@@ -283,11 +383,13 @@ __device__ __forceinline__ void strip_values_staged(const double* __restrict__ l
     }
 #pragma unroll 1
     for (int grp = 0; grp < NPSF; ++grp) {
+        const bool star = (live >> grp) & 1;
+        if (!star && !((live >> (NPSF + grp * NGAL_PER_PSF)) & ((1u << NGAL_PER_PSF) - 1))) continue;
         const double* es = lt + grp;
         const double dx = px - es[D_CX * NCP], dy = py0 - es[D_CY * NCP];
         const double h2x = -0.5 * (dx * dx), mxy = -(dx * dy), h2y = -0.5 * (dy * dy);
         const double mdx = -dx, mdyh = -(dy + 0.5);
-        {
+        if (star) {
             const double a = es[D_A * NCP], b = es[D_B * NCP], d = es[D_D * NCP];
             double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, es[D_LW * NCP]))), t2);
             double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
@@ -301,25 +403,10 @@ __device__ __forceinline__ void strip_values_staged(const double* __restrict__ l
                 }
             }
         }
-        const double* eg = lt + NPSF + 1 + grp * NGAL_PER_PSF;
-#pragma unroll CELESTE_GAL_UNROLL
-        for (int c = 0; c < NGAL_PER_PSF; ++c) {
-            const double* e = eg + c;
-            const double a = e[D_A * NCP], b = e[D_B * NCP], d = e[D_D * NCP];
-            double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, e[D_LW * NCP]))), t2);
-            double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
-            const double rdy = e[D_RDY * NCP], wt = e[D_WT * NCP];
-            const double sgn = SGN ? e[D_SGN * NCP] : 0.0;
-#pragma unroll
-            for (int k = 0; k < L; ++k) {
-                fg[k] = fma(n, wt, fg[k]);
-                if constexpr (SGN) fgd[k] = fma(n, sgn, fgd[k]);
-                if (k + 1 < L) {
-                    n = n * rt;
-                    rt = rt * rdy;
-                }
-            }
-        }
+        for_live_pairs(live, grp, [&](int s0, int s1) {
+            gal_values_staged<L, SGN>(lt + s0, h2x, mxy, h2y, mdx, mdyh, fg, fgd, t2);
+            gal_values_staged<L, SGN>(lt + s1, h2x, mxy, h2y, mdx, mdyh, fg, fgd, t2);
+        });
     }
 }
 
@@ -447,10 +534,12 @@ __device__ __forceinline__ void strip_background_fg(const PairDev& p, const Pair
     }
 }
 
+// The next item of the dynamic queue for the whole wave (called with every lane active, so
+// the first active lane is lane 0); wave-uniform, so the item loop stays scalar.
 __device__ inline int next_item_s(int* counter, int lane) {
     int v = 0;
     if (lane == 0) v = atomicAdd(counter, 1);
-    return __shfl(v, 0, 64);
+    return __builtin_amdgcn_readfirstlane(v);
 }
 
 // ----------------------------------------------------------------------- planes
@@ -554,11 +643,13 @@ __global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>:
         if (!active || active[p.src]) {
             const celeste_image& im = images[p.img];
             const T* tab = reinterpret_cast<const T*>(tabp) + (size_t)it.pair * NCOMP * CST;
+            uint64_t live = 0;
             if constexpr (LDS_TAB) {
                 // the wave's previous item has finished reading its copy (in-order LDS)
                 double* my = ltab + (threadIdx.x >> 6) * (NCP * NDF);
                 __builtin_amdgcn_wave_barrier();
                 stage_derived(reinterpret_cast<const double*>(tab), my, lane);
+                live = item_live(reinterpret_cast<const double*>(tab), p, it, L, lane);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -639,7 +730,7 @@ __global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>:
                     }
                     if constexpr (LDS_TAB)
                         strip_adjoint_staged<L>(ltab + (threadIdx.x >> 6) * (NCP * NDF), px, py0, Gs, Gg,
-                                                acc, t2);
+                                                acc, t2, live);
                     else
                         strip_adjoint<T, L>(tab, px, py0, Gs, Gg, acc, t2);
                     continue;
@@ -649,7 +740,7 @@ __global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>:
                     T fs[L], fg[L], fgd[KK ? L : 1];
                     if constexpr (LDS_TAB)
                         strip_values_staged<L, KK>(ltab + (threadIdx.x >> 6) * (NCP * NDF), px, py0, fs, fg, t2,
-                                                   fgd);
+                                                   live, fgd);
                     else
                         strip_values<T, L, KK>(tab, px, py0, fs, fg, t2, fgd);
                     const double* xs_i = xs + im.pix_offset;
@@ -702,7 +793,8 @@ __global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>:
                         __builtin_amdgcn_sched_barrier(0);
                     }
                     if constexpr (LDS_TAB)
-                        strip_adjoint_staged<L>(ltab + (threadIdx.x >> 6) * (NCP * NDF), px, py0, fs, fg, acc, t2);
+                        strip_adjoint_staged<L>(ltab + (threadIdx.x >> 6) * (NCP * NDF), px, py0, fs, fg, acc, t2,
+                                                live);
                     else
                         strip_adjoint<T, L>(tab, px, py0, fs, fg, acc, t2);
                     continue;
@@ -1365,6 +1457,7 @@ __global__ void __launch_bounds__(256) k_strip_fg(Sel sel, const Item* __restric
         const double* tb = tab + (size_t)it.pair * NCOMP * CST;
         __builtin_amdgcn_wave_barrier();
         stage_derived(tb, my, lane);
+        const uint64_t live = item_live(tb, p, it, L, lane);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1372,7 +1465,7 @@ __global__ void __launch_bounds__(256) k_strip_fg(Sel sel, const Item* __restric
             int c, r0, nrow;
             strip_geometry(p, it.start + q, L, c, r0, nrow);
             double fs[L], fg[L];
-            strip_values_staged<L>(my, (double)c, (double)r0, fs, fg, t2);
+            strip_values_staged<L>(my, (double)c, (double)r0, fs, fg, t2, live);
 #pragma unroll
             for (int k = 0; k < L; ++k) {
                 if (k >= nrow) break;
@@ -1380,6 +1473,49 @@ __global__ void __launch_bounds__(256) k_strip_fg(Sel sel, const Item* __restric
                 fgm[2 * vi] = fs[k];
                 fgm[2 * vi + 1] = fg[k];
             }
+        }
+    }
+}
+
+// Work of the strip passes under the component culling, for the FLOP count of a launch:
+// one wave per item, each lane testing its component as the strip kernels do (item_live).
+// out[0] strips, [1] visits, [2] PSF groups evaluated x strips, [3] live stars x strips,
+// [4] live galaxy components x strips, [5] zero-component pads x strips, [6] live stars x
+// visits, [7] live galaxy components x visits, [8] pads x visits (all summed over items).
+__global__ void __launch_bounds__(64) k_live_counts(Sel sel, const Item* __restrict__ items,
+                                                    const PairDev* __restrict__ pairs,
+                                                    const double* __restrict__ tab, int L,
+                                                    unsigned long long* __restrict__ out, const int* status) {
+    if (*status) return;
+    const int lane = threadIdx.x;
+    for (int j = blockIdx.x; j < sel.n; j += gridDim.x) {
+        const int ii = __builtin_amdgcn_readfirstlane(sel_at(sel, j));
+        const Item it = items[ii];
+        const PairDev p = pairs[it.pair];
+        const uint64_t live = item_live(tab + (size_t)it.pair * NCOMP * CST, p, it, L, lane);
+        long long v = 0;   // visits of the item's strips
+        for (int q = lane; q < it.count; q += 64) v += min(L, p.h - ((it.start + q) / p.w) * L);
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) {
+            long long groups = 0, stars = 0, gal = 0, pads = 0;
+            for (int g = 0; g < NPSF; ++g) {
+                const uint32_t gm = (uint32_t)(live >> (NPSF + g * NGAL_PER_PSF)) & ((1u << NGAL_PER_PSF) - 1);
+                const int st = (int)((live >> g) & 1), ng = __builtin_popcount(gm);
+                groups += (st || ng) ? 1 : 0;
+                stars += st;
+                gal += ng;
+                pads += ng & 1;
+            }
+            const unsigned long long n = (unsigned long long)it.count, vv = (unsigned long long)v;
+            atomicAdd(out + 0, n);
+            atomicAdd(out + 1, vv);
+            atomicAdd(out + 2, n * groups);
+            atomicAdd(out + 3, n * stars);
+            atomicAdd(out + 4, n * gal);
+            atomicAdd(out + 5, n * pads);
+            atomicAdd(out + 6, vv * stars);
+            atomicAdd(out + 7, vv * gal);
+            atomicAdd(out + 8, vv * pads);
         }
     }
 }
@@ -1537,6 +1673,15 @@ hipError_t launch_strip_fg(const Sel& sel, const Geometry& g, const double* tab,
         hipLaunchKernelGGL(k_strip_fg<16>, dim3(grid), dim3(64 * wpb), (size_t)wpb * NCP * NDF * sizeof(double), st, sel, g.items, g.pairs, tab, fg, status);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_live_counts(const Sel& sel, const Geometry& g, const double* tab, int L,
+                              unsigned long long* out, const int* status, hipStream_t st) {
+    hipError_t e = hipMemsetAsync(out, 0, NLIVE_COUNTS * sizeof(unsigned long long), st);
+    if (e != hipSuccess || sel.n <= 0) return e;
+    const int grid = sel.n < 65536 ? sel.n : 65536;
+    hipLaunchKernelGGL(k_live_counts, dim3(grid), dim3(64), 0, st, sel, g.items, g.pairs, tab, L, out, status);
     return hipGetLastError();
 }
 
