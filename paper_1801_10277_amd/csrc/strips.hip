@@ -956,21 +956,29 @@ __device__ __forceinline__ void stage_hess(const double* __restrict__ tab, const
         o[H_WNU * NCP] = e[F_WNU];
         o[H_SGN * NCP] = e[F_SGN];
         o[H_NU * NCP] = lane < NPSF ? 0.0 : nu[lane - NPSF];
+    } else if (lane == NCOMP) {   // the zero component (stage_derived)
+        double* o = my + NPSF;
+#pragma unroll
+        for (int f = 0; f < NDH; ++f) o[f * NCP] = 0.0;
+        o[H_LW * NCP] = -1000.0;
+        o[H_RDY * NCP] = 1.0;
     }
 }
 
 template <int L>
 __device__ __forceinline__ void hess_second_strip(const double* __restrict__ lt, double px, double py0,
                                                   const double* Gs, const double* Gg, double* H,
-                                                  const double* __restrict__ t2) {
+                                                  const double* __restrict__ t2, uint64_t live) {
     constexpr double KC = 0.5 * (L - 1);
 #pragma unroll 1
     for (int grp = 0; grp < NPSF; ++grp) {
+        const bool star = (live >> grp) & 1;
+        if (!star && !((live >> (NPSF + grp * NGAL_PER_PSF)) & ((1u << NGAL_PER_PSF) - 1))) continue;
         const double* es = lt + grp;
         const double dx = px - es[H_CX * NCP], dy = py0 - es[H_CY * NCP];
         const double h2x = -0.5 * (dx * dx), mxy = -(dx * dy), h2y = -0.5 * (dy * dy);
         const double mdx = -dx, mdyh = -(dy + 0.5), dyc = dy + KC;
-        {
+        if (star) {
             const double a = es[H_A * NCP], b = es[H_B * NCP], d = es[H_D * NCP];
             double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, es[H_LW * NCP]))), t2);
             double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
@@ -996,10 +1004,7 @@ __device__ __forceinline__ void hess_second_strip(const double* __restrict__ lt,
             H[HG_XY] += fma(-b, U0, N11);
             H[HG_YY] += fma(-d, U0, N02);
         }
-        const double* eg = lt + NPSF + 1 + grp * NGAL_PER_PSF;
-#pragma unroll CELESTE_GAL_UNROLL
-        for (int c = 0; c < NGAL_PER_PSF; ++c) {
-            const double* e = eg + c;
+        auto gal = [&](const double* __restrict__ e) {
             const double a = e[H_A * NCP], b = e[H_B * NCP], d = e[H_D * NCP];
             double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, e[H_LW * NCP]))), t2);
             double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
@@ -1077,7 +1082,11 @@ __device__ __forceinline__ void hess_second_strip(const double* __restrict__ lt,
             H[HG_SXY_SXY] = fma(vnu, s3, H[HG_SXY_SXY]);
             H[HG_SXY_SYY] = fma(vnu, s4, H[HG_SXY_SYY]);
             H[HG_SYY_SYY] = fma(vnu, s5, H[HG_SYY_SYY]);
-        }
+        };
+        for_live_pairs(live, grp, [&](int s0, int s1) {
+            gal(lt + s0);
+            gal(lt + s1);
+        });
     }
 }
 
@@ -1118,6 +1127,7 @@ __global__ void __launch_bounds__(256, 2) k_hess_second(AdjArgs a, const Item* _
         const double k1 = kp[C_K1], k2 = kp[C_K2], k3 = kp[C_K3], k4 = kp[C_K4];
         __builtin_amdgcn_wave_barrier();
         stage_hess(tabp + (size_t)it.pair * NCOMP * CST, nu, my, lane);
+        const uint64_t live = item_live(tabp + (size_t)it.pair * NCOMP * CST, p, it, L, lane);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1150,7 +1160,7 @@ __global__ void __launch_bounds__(256, 2) k_hess_second(AdjArgs a, const Item* _
                 Gs[kk] = gs;
                 Gg[kk] = gg;
             }
-            hess_second_strip<L>(my, (double)c, (double)r0, Gs, Gg, H, t2);
+            hess_second_strip<L>(my, (double)c, (double)r0, Gs, Gg, H, t2, live);
         }
 #pragma unroll
         for (int f = 0; f < NHG_GEO; ++f) {
@@ -1208,6 +1218,7 @@ __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __r
         const double k[NCOEF] = {kp[0], kp[1], kp[2], kp[3]};
         __builtin_amdgcn_wave_barrier();
         stage_hess(tabp + (size_t)it.pair * NCOMP * CST, nu, my, lane);
+        const uint64_t live = item_live(tabp + (size_t)it.pair * NCOMP * CST, p, it, L, lane);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1234,11 +1245,13 @@ __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __r
             }
 #pragma unroll 1
             for (int grp = 0; grp < NPSF; ++grp) {
+                const bool star = (live >> grp) & 1;
+                if (!star && !((live >> (NPSF + grp * NGAL_PER_PSF)) & ((1u << NGAL_PER_PSF) - 1))) continue;
                 const double* es = my + grp;
                 const double dx = px - es[H_CX * NCP], dy = py0 - es[H_CY * NCP];
                 const double h2x = -0.5 * (dx * dx), mxy = -(dx * dy), h2y = -0.5 * (dy * dy);
                 const double mdx = -dx, mdyh = -(dy + 0.5);
-                {
+                if (star) {
                     const double a = es[H_A * NCP], b = es[H_B * NCP], d = es[H_D * NCP];
                     double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, es[H_LW * NCP]))), t2);
                     double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
@@ -1255,10 +1268,7 @@ __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __r
                         }
                     }
                 }
-                const double* eg = my + NPSF + 1 + grp * NGAL_PER_PSF;
-#pragma unroll CELESTE_GAL_UNROLL
-                for (int cc = 0; cc < NGAL_PER_PSF; ++cc) {
-                    const double* e = eg + cc;
+                auto gal = [&](const double* __restrict__ e) {
                     const double a = e[H_A * NCP], b = e[H_B * NCP], d = e[H_D * NCP];
                     double n = fexp(fma(a, h2x, fma(b, mxy, fma(d, h2y, e[H_LW * NCP]))), t2);
                     double rt = fexp(clamp_arg(fma(b, mdx, d * mdyh)), t2);
@@ -1280,7 +1290,11 @@ __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __r
                             rt = rt * rdy;
                         }
                     }
-                }
+                };
+                for_live_pairs(live, grp, [&](int s0, int s1) {
+                    gal(my + s0);
+                    gal(my + s1);
+                });
             }
             // products of first derivatives and the k-block entries, row by row (the pixel
             // scalars from the row's stored background and own values)
