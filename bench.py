@@ -97,9 +97,11 @@ DIRECT_RENDER_PER_VISIT = N_STAR * (GAUSS_VALUE + 1) + N_GAL * (GAUSS_VALUE + 2)
 ADJOINT_BYTES_PER_VISIT = {0: 24, 1: 24, 2: 40, 3: 40}
 
 
-def measured_profile(kernel_launch):
+def measured_profile(decomposition):
     """The committed rocprofv3 counter summary of the fused adjoint, if it was taken on the
-    current kernel sources and launch; else None."""
+    current kernel sources and the same work decomposition (strips per work item, strip
+    rows, render mode: these fix what each wave reads; the launch shape does not); else
+    None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "fused_adjoint_sdss_field_2000src.json")
     if not os.path.exists(path):
@@ -110,7 +112,7 @@ def measured_profile(kernel_launch):
     for fn in ("strips.hip", "model.h", "internal.h", "dual.h"):
         with open(os.path.join(ROOT, "paper_1801_10277_amd", "csrc", fn), "rb") as fh:
             h.update(fh.read())
-    if prof.get("source_sha256") != h.hexdigest() or prof.get("launch") != kernel_launch:
+    if prof.get("source_sha256") != h.hexdigest() or prof.get("decomposition") != decomposition:
         return None
     return prof
 
@@ -432,10 +434,10 @@ def main():
     log("live Gaussians per strip %.2f of 45 (+%.2f zero pads); adjoint %.3e FLOPs per launch (%.3e without culling)"
         % (live_per_strip, wc["pad_strips"] / strips, adj_flops, adj_full))
     achieved = adj_flops / (adj_ms * 1e-3) / 1e12
-    launch_str = "%d,%d,%d,%d,%d,%d" % (info["chunk"], info["waves_per_block"], info["grid_blocks"],
-                                        info["dynamic_queue"], info["strip_rows"], info["render_mode"])
+    decomposition = "chunk %d, strip rows %d, render mode %d" % (info["chunk"], info["strip_rows"],
+                                                                  info["render_mode"])
     # the committed counter profile was taken on the default field only
-    prof = None if (args.realistic or f.n_src != 2000) else measured_profile(launch_str)
+    prof = None if (args.realistic or f.n_src != 2000) else measured_profile(decomposition)
     traffic = None if prof is None else prof["bytes_per_launch"]
     counted = None if prof is None else prof["counters"][prof["kernel"]].get("fp64_flops_counted")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -1791,11 +1791,18 @@ int celeste_autotune(celeste_plan* p, const double* theta, int reps, double* bes
     mode_rows();
     Cfg c = best;
     for (int ch : {64, 128, 256, 512, 1024}) { c = best; c.chunk = ch; trial(c); }
-    for (int w : {1, 2, 4}) { c = best; c.wpb = w; trial(c); }
-    for (int g : {p->n_cu, 4 * p->n_cu, 16 * p->n_cu, 64 * p->n_cu, 128 * p->n_cu}) {
-        c = best;
-        c.grid = g;
-        trial(c);
+    // waves per block and grid jointly: the cost of a work item varies with the Gaussians
+    // it culls, and a block holds its slots until its slowest wave ends, so smaller blocks
+    // pay off most with one item per wave (the largest grid, clipped to the item count)
+    {
+        const Cfg start = best;
+        for (int w : {1, 2, 4})
+            for (int g : {p->n_cu, 4 * p->n_cu, 16 * p->n_cu, 64 * p->n_cu, 128 * p->n_cu, 1 << 20}) {
+                c = start;
+                c.wpb = w;
+                c.grid = g;
+                if (c.wpb != start.wpb || c.grid != start.grid) trial(c);
+            }
     }
     for (int d : {0, 1}) { c = best; c.dyn = d; trial(c); }
     if (best.rmode == 1 || best.rmode == 2) {

@@ -1502,6 +1502,7 @@ __global__ void __launch_bounds__(64) k_live_counts(Sel sel, const Item* __restr
                                                     unsigned long long* __restrict__ out, const int* status) {
     if (*status) return;
     const int lane = threadIdx.x;
+    unsigned long long sum[NLIVE_COUNTS] = {};   // this wave's items (lane 0)
     for (int j = blockIdx.x; j < sel.n; j += gridDim.x) {
         const int ii = __builtin_amdgcn_readfirstlane(sel_at(sel, j));
         const Item it = items[ii];
@@ -1510,28 +1511,28 @@ __global__ void __launch_bounds__(64) k_live_counts(Sel sel, const Item* __restr
         long long v = 0;   // visits of the item's strips
         for (int q = lane; q < it.count; q += 64) v += min(L, p.h - ((it.start + q) / p.w) * L);
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) {
-            long long groups = 0, stars = 0, gal = 0, pads = 0;
-            for (int g = 0; g < NPSF; ++g) {
-                const uint32_t gm = (uint32_t)(live >> (NPSF + g * NGAL_PER_PSF)) & ((1u << NGAL_PER_PSF) - 1);
-                const int st = (int)((live >> g) & 1), ng = __builtin_popcount(gm);
-                groups += (st || ng) ? 1 : 0;
-                stars += st;
-                gal += ng;
-                pads += ng & 1;
-            }
-            const unsigned long long n = (unsigned long long)it.count, vv = (unsigned long long)v;
-            atomicAdd(out + 0, n);
-            atomicAdd(out + 1, vv);
-            atomicAdd(out + 2, n * groups);
-            atomicAdd(out + 3, n * stars);
-            atomicAdd(out + 4, n * gal);
-            atomicAdd(out + 5, n * pads);
-            atomicAdd(out + 6, vv * stars);
-            atomicAdd(out + 7, vv * gal);
-            atomicAdd(out + 8, vv * pads);
+        unsigned long long groups = 0, stars = 0, gal = 0, pads = 0;
+        for (int g = 0; g < NPSF; ++g) {
+            const uint32_t gm = (uint32_t)(live >> (NPSF + g * NGAL_PER_PSF)) & ((1u << NGAL_PER_PSF) - 1);
+            const int st = (int)((live >> g) & 1), ng = __builtin_popcount(gm);
+            groups += (st || ng) ? 1 : 0;
+            stars += st;
+            gal += ng;
+            pads += ng & 1;
         }
+        const unsigned long long n = (unsigned long long)it.count, vv = (unsigned long long)v;
+        sum[0] += n;
+        sum[1] += vv;
+        sum[2] += n * groups;
+        sum[3] += n * stars;
+        sum[4] += n * gal;
+        sum[5] += n * pads;
+        sum[6] += vv * stars;
+        sum[7] += vv * gal;
+        sum[8] += vv * pads;
     }
+    if (lane == 0)
+        for (int f = 0; f < NLIVE_COUNTS; ++f) atomicAdd(out + f, sum[f]);
 }
 
 // Render pass 2: E and V of every pixel of a tile, summing the stored own values of the
@@ -1694,7 +1695,7 @@ hipError_t launch_live_counts(const Sel& sel, const Geometry& g, const double* t
                               unsigned long long* out, const int* status, hipStream_t st) {
     hipError_t e = hipMemsetAsync(out, 0, NLIVE_COUNTS * sizeof(unsigned long long), st);
     if (e != hipSuccess || sel.n <= 0) return e;
-    const int grid = sel.n < 65536 ? sel.n : 65536;
+    const int grid = sel.n < 1024 ? sel.n : 1024;
     hipLaunchKernelGGL(k_live_counts, dim3(grid), dim3(64), 0, st, sel, g.items, g.pairs, tab, L, out, status);
     return hipGetLastError();
 }
@@ -1806,10 +1807,9 @@ hipError_t launch_adjoint(const AdjArgs& a, bool tangent, int base, bool deriv, 
     if (a.dynamic) {
         hipError_t e = launch_fill_int(a.counter, 0, 1, st);
         if (e != hipSuccess) return e;
-    } else {
-        const int need = (a.items.n + wpb - 1) / wpb;
-        if (grid > need) grid = need;
     }
+    const int need = (a.items.n + wpb - 1) / wpb;   // never more waves than items
+    if (grid > need) grid = need;
     if (grid < 1) grid = 1;
     const hipError_t e = tangent ? adjs_B<dual>(a, base, deriv, grid, wpb, L, st)
                                  : adjs_B<double>(a, base, deriv, grid, wpb, L, st);
@@ -1822,10 +1822,8 @@ hipError_t launch_hess_geom(const AdjArgs& a, const double* nu, double* hg, int 
                             hipStream_t st) {
     if (a.items.n <= 0) return hipSuccess;
     if (L != 16 && L != 8 && L != 4) return hipErrorInvalidValue;
-    if (!a.dynamic) {
-        const int need = (a.items.n + wpb - 1) / wpb;
-        if (grid > need) grid = need;
-    }
+    const int need = (a.items.n + wpb - 1) / wpb;   // never more waves than items
+    if (grid > need) grid = need;
     if (grid < 1) grid = 1;
     const Geometry& g = a.g;
     const size_t lds = (size_t)wpb * NCP * NDH * sizeof(double);
