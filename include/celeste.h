@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define CELESTE_ABI_VERSION 6
+#define CELESTE_ABI_VERSION 7
 
 enum celeste_status {
     CELESTE_OK = 0,

@@ -32,6 +32,6 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), n
     assert set(declared()) == set(binding.EXPORTS)
     lib.celeste_version.restype = ctypes.c_int
-    assert lib.celeste_version() == 6
+    assert lib.celeste_version() == 7
     lib.celeste_status_string.restype = ctypes.c_char_p
     assert lib.celeste_status_string(-2) == b"batch members share pixels"
