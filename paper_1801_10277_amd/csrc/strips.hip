@@ -1094,8 +1094,11 @@ __device__ __forceinline__ void hess_second_strip(const double* __restrict__ lt,
 // from the stored background and own profile values of each row, then hess_second_strip.
 // Writes hg[item] (geometric entries; the k-block entries zero), to which k_hess_geom then
 // adds the first-derivative products.  Items of sources outside a.active get zeros.
+// Three waves per SIMD (168 VGPRs, some spilled) rather than two (197 VGPRs): the waves wait
+// on each strip's row loads, and the third wave hides more of it (Newton iterations on 1024
+// sources 1.5% faster).
 template <int L>
-__global__ void __launch_bounds__(256, 2) k_hess_second(AdjArgs a, const Item* __restrict__ items,
+__global__ void __launch_bounds__(256, 3) k_hess_second(AdjArgs a, const Item* __restrict__ items,
                                                      const PairDev* __restrict__ pairs,
                                                      const celeste_image* __restrict__ images,
                                                      const double* __restrict__ xs, const double* __restrict__ bg,
