@@ -47,9 +47,11 @@ __device__ __forceinline__ void strip_seed(const T* e, double px, double py0, T&
 // Pass A: star and galaxy profile values down the strip.
 // SGN: also fgd[k] = sum of the de Vaucouleurs minus the exponential components (d fg /
 // d frac_dev).
-template <class T, int L, bool SGN = false>
+// live (with CULL): the components to evaluate (item_live); the others are skipped.
+template <class T, int L, bool SGN = false, bool CULL = false>
 __device__ __forceinline__ void strip_values(const T* __restrict__ tab, double px, double py0, T* fs, T* fg,
-                                             const double* __restrict__ t2, T* fgd = nullptr) {
+                                             const double* __restrict__ t2, T* fgd = nullptr,
+                                             uint64_t live = ~0ull) {
     const T zero = scalar_traits<T>::make(0.0, 0.0);
 #pragma unroll
     for (int k = 0; k < L; ++k) fs[k] = fg[k] = zero;
@@ -59,6 +61,7 @@ __device__ __forceinline__ void strip_values(const T* __restrict__ tab, double p
     }
 #pragma unroll
     for (int c = 0; c < NPSF; ++c) {
+        if (CULL && !((live >> c) & 1)) continue;
         const T* e = tab + c * CST;
         T n, rt, pdx0, pdy0;
         strip_seed(e, px, py0, n, rt, pdx0, pdy0, t2);
@@ -74,6 +77,7 @@ __device__ __forceinline__ void strip_values(const T* __restrict__ tab, double p
     }
 #pragma unroll scalar_traits<T>::gal_unroll
     for (int c = NPSF; c < NCOMP; ++c) {
+        if (CULL && !((live >> c) & 1)) continue;
         const T* e = tab + c * CST;
         T n, rt, pdx0, pdy0;
         strip_seed(e, px, py0, n, rt, pdx0, pdy0, t2);
@@ -92,9 +96,10 @@ __device__ __forceinline__ void strip_values(const T* __restrict__ tab, double p
 
 // Pass B: d/d(position, frac_dev, shape covariance) accumulated with per-row weights
 // Gs (star) and Gg (galaxy).
-template <class T, int L>
+template <class T, int L, bool CULL = false>
 __device__ __forceinline__ void strip_adjoint(const T* __restrict__ tab, double px, double py0, const T* Gs,
-                                              const T* Gg, T* acc, const double* __restrict__ t2) {
+                                              const T* Gg, T* acc, const double* __restrict__ t2,
+                                              uint64_t live = ~0ull) {
     // Row moments by repeated running sums: with t_k = G_k value_k and u = L - k,
     //   A = sum t,  B = sum_k (sum_{i<=k} t_i) = sum t u,  C = sum_k (B after row k) = sum t u(u+1)/2,
     // so about the strip centre KC = (L-1)/2 (h = KC + 1 = (L+1)/2):
@@ -105,6 +110,7 @@ __device__ __forceinline__ void strip_adjoint(const T* __restrict__ tab, double 
     const T zero = scalar_traits<T>::make(0.0, 0.0);
 #pragma unroll
     for (int c = 0; c < NPSF; ++c) {
+        if (CULL && !((live >> c) & 1)) continue;
         const T* e = tab + c * CST;
         T n, rt, pdx0, pdy0;
         strip_seed(e, px, py0, n, rt, pdx0, pdy0, t2);
@@ -126,6 +132,7 @@ __device__ __forceinline__ void strip_adjoint(const T* __restrict__ tab, double 
     }
 #pragma unroll scalar_traits<T>::gal_unroll
     for (int c = NPSF; c < NCOMP; ++c) {
+        if (CULL && !((live >> c) & 1)) continue;
         const T* e = tab + c * CST;
         T n, rt, pdx0, pdy0;
         strip_seed(e, px, py0, n, rt, pdx0, pdy0, t2);
@@ -224,12 +231,14 @@ __device__ __forceinline__ void stage_derived(const double* __restrict__ tab, do
 // components as a wave-uniform bit set (bit c: table component c); lane c tests component c.
 constexpr double CULL_Q = 100.0;
 
-__device__ __forceinline__ uint64_t item_live(const double* __restrict__ tab, const PairDev& p, const Item& it,
-                                              int L, int lane) {
+template <class T>
+__device__ __forceinline__ uint64_t item_live(const T* __restrict__ tab, const PairDev& p, const Item& it, int L,
+                                              int lane) {
     bool cull = false;
     if (lane < NCOMP) {
-        const double* e = tab + lane * CST;
-        const double cx = e[F_CX], cy = e[F_CY], a = e[F_PXX], b = e[F_PXY], d = e[F_PYY];
+        const T* e = tab + lane * CST;
+        const double cx = value_of(e[F_CX]), cy = value_of(e[F_CY]), a = value_of(e[F_PXX]),
+                     b = value_of(e[F_PXY]), d = value_of(e[F_PYY]);
         const double det = fma(a, d, -(b * b));
         const double qa = CULL_Q * a, qd = CULL_Q * d;
         // > 0 if the form exceeds CULL_Q on columns ca..cb, rows ra..rb of the box
@@ -643,7 +652,10 @@ __global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>:
         if (!active || active[p.src]) {
             const celeste_image& im = images[p.img];
             const T* tab = reinterpret_cast<const T*>(tabp) + (size_t)it.pair * NCOMP * CST;
+            // dual passes (HVP, Hessian tangents) read the table directly; they cull too
+            constexpr bool CULL_T = !LDS_TAB && std::is_same<T, dual>::value;
             uint64_t live = 0;
+            if constexpr (CULL_T) live = item_live(tab, p, it, L, lane);
             if constexpr (LDS_TAB) {
                 // the wave's previous item has finished reading its copy (in-order LDS)
                 double* my = ltab + (threadIdx.x >> 6) * (NCP * NDF);
@@ -742,7 +754,7 @@ __global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>:
                         strip_values_staged<L, KK>(ltab + (threadIdx.x >> 6) * (NCP * NDF), px, py0, fs, fg, t2,
                                                    live, fgd);
                     else
-                        strip_values<T, L, KK>(tab, px, py0, fs, fg, t2, fgd);
+                        strip_values<T, L, KK, CULL_T>(tab, px, py0, fs, fg, t2, fgd, live);
                     const double* xs_i = xs + im.pix_offset;
                     auto row_load = [&](int rr, double& x_, double& e_, double& v_) {
                         const size_t gi = (size_t)(r0 + rr) * im.W + c;
@@ -796,7 +808,7 @@ __global__ void __launch_bounds__(256, (FGM && DERIV && std::is_same<T, double>:
                         strip_adjoint_staged<L>(ltab + (threadIdx.x >> 6) * (NCP * NDF), px, py0, fs, fg, acc, t2,
                                                 live);
                     else
-                        strip_adjoint<T, L>(tab, px, py0, fs, fg, acc, t2);
+                        strip_adjoint<T, L, CULL_T>(tab, px, py0, fs, fg, acc, t2, live);
                     continue;
                 }
                 double x[L], Eb[L], Vb[L];
