@@ -8,9 +8,9 @@
 //                 covers each pixel, in box order (deterministic, no atomics), and
 //                 optionally the pixel terms of covered pixels (total ELBO).
 //  * the fused adjoint and the strip render live in strips.hip.
-//  * k_finalize:  one wave per source: each lane sums one box's items in order and applies
-//                 the chain rule to the 27 parameters; a fixed butterfly sums the lanes, then
-//                 the KL term is added.
+//  * k_finalize:  eight lanes per source, eight sources per wave: each lane sums one box's
+//                 items in order and applies the chain rule to the 27 parameters; a fixed
+//                 butterfly over the eight lanes sums the boxes, then the KL term is added.
 // Table entries are addressed with wave-uniform indices so the compiler serves them
 // through scalar loads; pixel data is read coalesced along box rows.
 #include <hip/hip_runtime.h>
@@ -199,14 +199,25 @@ __global__ void __launch_bounds__(256) k_render(RenderArgs a, const TileDev* __r
 }
 
 // ----------------------------------------------------------------------- finalize
+// Sum over the FIN_LANES lanes of a lane group (fixed butterfly: every lane of the group
+// ends with the same sum).
+constexpr int FIN_LANES = 8;
+__device__ inline double group_sum(double v) {
+#pragma unroll
+    for (int o = FIN_LANES / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline dual group_sum(dual v) { return mkd(group_sum(v.v), group_sum(v.t)); }
+
 template <class T>
 __global__ void __launch_bounds__(64) k_finalize(FinArgs a) {
     if (*a.status) return;
-    const int j = blockIdx.x;
-    const int lane = threadIdx.x;
-    if (j >= a.srcs.n) return;
-    const int s = sel_at(a.srcs, j);
-    if (a.active && !a.active[s]) return;
+    const int lane = threadIdx.x & (FIN_LANES - 1);
+    const int j = blockIdx.x * (64 / FIN_LANES) + threadIdx.x / FIN_LANES;
+    // every lane takes part in the butterflies; groups past the list or inactive write nothing
+    const bool listed = j < a.srcs.n;
+    const int s = listed ? sel_at(a.srcs, j) : sel_at(a.srcs, 0);
+    const bool act = listed && (!a.active || a.active[s]);
     T p[NPK];
     for (int i = 0; i < NPK; ++i) p[i] = seed<T>(a.theta, a.dir, a.dir_mode, a.dir_unit, s, i);
     const T zero = scalar_traits<T>::make(0.0, 0.0);
@@ -214,8 +225,9 @@ __global__ void __launch_bounds__(64) k_finalize(FinArgs a) {
     for (int i = 0; i < NPK; ++i) g[i] = zero;
     T val = zero;
     const T* part = reinterpret_cast<const T*>(a.partials);
-    // lane l takes the source's boxes l, l + 64, ...; each box's items in order
-    for (int pi = a.patch_ptr[s] + lane; pi < a.patch_ptr[s + 1]; pi += 64) {
+    // lane l of the group takes the source's boxes l, l + FIN_LANES, ...; each box's items in order
+    const int pe = act ? a.patch_ptr[s + 1] : 0;
+    for (int pi = a.patch_ptr[s] + lane; pi < pe; pi += FIN_LANES) {
         const PairDev pd = a.g.pairs[pi];
         T z[NACC];
         for (int f = 0; f < NACC; ++f) z[f] = zero;
@@ -231,11 +243,10 @@ __global__ void __launch_bounds__(64) k_finalize(FinArgs a) {
         if (a.pair_lgamma) val = val - a.pair_lgamma[pi];
         if (a.deriv) chain_pair<T>(p, a.g.images[pd.img], z, g);
     }
-    // fixed-order butterfly: every lane ends with the same sums
-    val = wave_sum(val);
+    val = group_sum(val);
     if (a.deriv) {
 #pragma unroll
-        for (int i = 0; i < NP; ++i) g[i] = wave_sum(g[i]);
+        for (int i = 0; i < NP; ++i) g[i] = group_sum(g[i]);
     }
     if (a.g.consts.flags & CELESTE_INCLUDE_KL) {
         T gk[NPK];
@@ -244,7 +255,7 @@ __global__ void __launch_bounds__(64) k_finalize(FinArgs a) {
         if (a.deriv)
             for (int i = 0; i < NPK; ++i) g[i] += gk[i];
     }
-    if (lane != 0) return;
+    if (lane != 0 || !act) return;
     if (a.elbo) a.elbo[s] = value_of(val);
     if (a.deriv && a.grad) {
         double* o = a.grad + (size_t)s * ROW;
@@ -490,7 +501,7 @@ hipError_t launch_render(const RenderArgs& a, int wpb, hipStream_t st) {
 
 hipError_t launch_finalize(const FinArgs& a, bool tangent, hipStream_t st) {
     if (a.srcs.n <= 0) return hipSuccess;
-    const dim3 grid(a.srcs.n);
+    const dim3 grid((a.srcs.n + 64 / FIN_LANES - 1) / (64 / FIN_LANES));
     if (tangent) hipLaunchKernelGGL(k_finalize<dual>, grid, dim3(64), 0, st, a);
     else hipLaunchKernelGGL(k_finalize<double>, grid, dim3(64), 0, st, a);
     return hipGetLastError();
