@@ -7,7 +7,8 @@
 //     logit is fixed at 0, so 27 + 2 x 7 = 41 coordinates: B = J^T (-H) J - sum_i g_i
 //     d2 theta_i / d eta^2 with the Jacobian J of theta(eta));
 //  2. Householder reduction of the model Hessian (27 x 27, or 41 x 41) to tridiagonal
-//     form T = Q^T B Q in LDS, the lanes owning the rows of the reflections;
+//     form T = Q^T B Q in LDS, the lanes owning the rows of the reflections; Q is kept as
+//     its reflectors (Q^T g and Q p are applied reflector by reflector), never formed;
 //  3. exact subproblem  min g'p + p'Bp/2, |p| <= radius  on T (More and Sorensen's
 //     method; Nocedal & Wright, Alg. 4.3): positive pivots of T's factorisation at mu = 0
 //     make T positive definite and allow the interior Newton step; otherwise the smallest
@@ -121,9 +122,9 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
     const int j = blockIdx.x;
     const int s = sel_at(a.srcs, j);
     const int t = threadIdx.x;
-    __shared__ double B[NJ][LD];
-    __shared__ double Q[NJ][LD];
-    __shared__ double vs[NJ], ws[NJ], dd[NJ], ee[NJ];
+    __shared__ double B[NJ][LD];   // the model Hessian; later the eigenvectors Z of T (QL path)
+    __shared__ double Q[NJ][LD];   // row k: the k-th Householder reflector v_k
+    __shared__ double vs[NJ], ws[NJ], dd[NJ], ee[NJ], bh[NJ];
     __shared__ double gm[NJ], eta[NJ], d1[NJ], lam[NJ], gh[NJ], ph[NJ], pv[NJ];
     __shared__ double sh_red[64];
     __shared__ int sh_done;
@@ -150,7 +151,6 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
                 if (c == r) b -= lam[r];
             }
             B[r][c] = b;
-            Q[r][c] = (c == r) ? 1.0 : 0.0;
         }
     } else {
         // softmax coordinates of the responsibilities: kappa_d = e^{eta_d} / (1 + sum_e e^{eta_e})
@@ -220,10 +220,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
                     }
                 }
             }
-            if (t < NJ) {
-                B[t][c] = b;
-                Q[t][c] = (c == t) ? 1.0 : 0.0;
-            }
+            if (t < NJ) B[t][c] = b;
         }
         __syncthreads();
         // symmetrise (the two halves differ by rounding only)
@@ -259,8 +256,9 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         return;
     }
     // ---- Householder reduction B = Q T Q^T, T tridiagonal: diagonal dd, ee[i] couples
-    // rows i and i + 1.  Lane i owns row i; the reflector v (zero outside k+1..26) and
-    // w = p - (v.p) beta/2 v with p = beta B v go through LDS.
+    // rows i and i + 1, Q = H_0 H_1 ... with H_k = I - bh[k] v_k v_k^T.  Lane i owns row i;
+    // the reflector v (zero outside k+1..26) and w = p - (v.p) beta/2 v with p = beta B v go
+    // through LDS; v_k is kept in row k of Q.
     for (int k = 0; k + 2 < M; ++k) {
         const double x0 = B[k + 1][k];
         const double ci = (t >= k + 2 && t < M) ? B[t][k] : 0.0;
@@ -269,6 +267,8 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         if (sigma == 0.0) {   // already tridiagonal in this column (uniform branch)
             dd[k] = dk;
             ee[k] = x0;
+            bh[k] = 0.0;   // H_k = I
+            if (t < NJ) Q[k][t] = 0.0;
             __syncthreads();
             continue;
         }
@@ -277,9 +277,13 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         const double v0 = x0 - alpha;
         const double beta = 2.0 / (v0 * v0 + sigma);
         const double vi = (t == k + 1) ? v0 : ci;
-        if (t < NJ) vs[t] = vi;
+        if (t < NJ) {
+            vs[t] = vi;
+            Q[k][t] = vi;
+        }
         dd[k] = dk;
         ee[k] = alpha;
+        bh[k] = beta;
         __syncthreads();
         // full-length loops (v and w vanish outside k+1..26), unrolled so that the LDS
         // reads of a loop are all in flight together
@@ -297,14 +301,6 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
 #pragma unroll
             for (int c = 0; c < M; ++c) B[t][c] -= vi * ws[c] + wi * vs[c];
         }
-        if (t < M) {
-            double q = 0.0;
-#pragma unroll
-            for (int c = 0; c < M; ++c) q += Q[t][c] * vs[c];
-            q *= beta;
-#pragma unroll
-            for (int c = 0; c < M; ++c) Q[t][c] -= q * vs[c];
-        }
         __syncthreads();
     }
     dd[M - 2] = B[M - 2][M - 2];
@@ -318,9 +314,17 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
     // recurrences run in every lane alike on values read with a wave-uniform index.
     double dv = (t < M) ? dd[t] : 0.0, ev = (t < M) ? ee[t] : 0.0;
     const double R = a.radius[s];
-    double gtv = 0.0;   // Q^T g
-    if (t < M)
-        for (int k = 0; k < M; ++k) gtv += Q[k][t] * gm[k];
+    // x <- Q^T x (transpose) or Q x for the vector whose entry i lane i holds: the
+    // reflectors one by one (every lane takes part in the wave sums)
+    auto apply_q = [&](double x, bool transpose) {
+        for (int j = 0; j + 2 < M; ++j) {
+            const int k = transpose ? j : M - 3 - j;
+            const double vk = (t < M) ? Q[k][t] : 0.0;
+            x -= bh[k] * wave_sum(vk * x) * vk;
+        }
+        return x;
+    };
+    const double gtv = apply_q((t < M) ? gm[t] : 0.0, true);   // Q^T g
     const double gn = sqrt(wave_sum(gtv * gtv));
     // smallest eigenvalue of T (needed when T is indefinite): Sturm counts at 64 points of
     // the bracket per round
@@ -440,24 +444,26 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         const double tyy = (t < M) ? dv * yv * yv + (t < M - 1 ? 2.0 * ev * yv * ynext : 0.0) : 0.0;
         const double pr = -(wave_sum(gtv * yv) + 0.5 * wave_sum(tyy));
         const double pn = sqrt(wave_sum(yv * yv));
-        if (t < M) ph[t] = yv;
         if (t == 0) {
             a.pred[2 * s] = pr;
             a.pred[2 * s + 1] = pn;
         }
-        __syncthreads();
-        if (t < M) {
-            double pp = 0.0;
-            for (int i = 0; i < M; ++i) pp += Q[t][i] * ph[i];
-            pv[t] = pp;
-        }
+        const double pq = apply_q(yv, false);   // p = Q y
+        if (t < M) pv[t] = pq;
         __syncthreads();
         write_trial<M>(t, eta, pv, trial);
         return;
     }
     // ---- otherwise the full eigendecomposition: implicit QL on T.  Lane i keeps d_i and e_i in registers;
     // the scalar recurrence runs in every lane alike on values read across lanes with a
-    // wave-uniform index, and lane i applies the rotations to row i of Q (in LDS).
+    // wave-uniform index, and lane i applies the rotations to row i of the eigenvector
+    // matrix Z of T (in LDS, where B was; the eigenvectors of the model Hessian are Q Z).
+    for (int idx = t; idx < NJ * NJ; idx += 64) {
+        const int r = idx / NJ, c = idx - r * NJ;
+        B[r][c] = (c == r) ? 1.0 : 0.0;
+    }
+    if (t < NJ) vs[t] = gtv;
+    __syncthreads();
     bool converged = true;
     for (int l = 0; l < M && converged; ++l) {
         for (int iter = 0;; ++iter) {
@@ -495,9 +501,9 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
                 dv = t == i + 1 ? g + p : dv;
                 g = cs * r - b;
                 if (t < M) {
-                    const double zi = Q[t][i], zn = Q[t][i + 1];
-                    Q[t][i + 1] = sn * zi + cs * zn;
-                    Q[t][i] = cs * zi - sn * zn;
+                    const double zi = B[t][i], zn = B[t][i + 1];
+                    B[t][i + 1] = sn * zi + cs * zn;
+                    B[t][i] = cs * zi - sn * zn;
                 }
             }
             if (deflated) continue;
@@ -519,8 +525,8 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
     }
     if (t < M) {
         lam[t] = dd[t];
-        double g = 0.0;
-        for (int k = 0; k < M; ++k) g += Q[k][t] * gm[k];
+        double g = 0.0;   // (Q Z)^T g = Z^T (Q^T g)
+        for (int k = 0; k < M; ++k) g += B[k][t] * vs[k];
         gh[t] = g;
     }
     __syncthreads();
@@ -593,11 +599,11 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         a.pred[2 * s + 1] = sqrt(pn);
     }
     __syncthreads();
-    if (t < M) {
-        double p = 0.0;
-        for (int i = 0; i < M; ++i) p += Q[t][i] * ph[i];
-        pv[t] = p;
-    }
+    double zp = 0.0;   // Z ph, then p = Q (Z ph)
+    if (t < M)
+        for (int i = 0; i < M; ++i) zp += B[t][i] * ph[i];
+    const double pq = apply_q(zp, false);
+    if (t < M) pv[t] = pq;
     __syncthreads();
     write_trial<M>(t, eta, pv, trial);
 }
