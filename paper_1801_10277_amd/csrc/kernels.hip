@@ -75,17 +75,42 @@ __global__ void __launch_bounds__(256) k_validate(const double* __restrict__ the
 }
 
 // ----------------------------------------------------------------------- prep
-// One wave per box: the box's intermediates are computed by every lane (wave-uniform), then
-// lane c writes table entry c and lane NCOMP the four brightness coefficients.
+// One wave per box, four boxes per block.  The boxes' intermediates (brightness factors,
+// shape, PSF terms) are computed first by lanes 0..3 of the first wave, one box per lane,
+// and passed through LDS (one wave pass for the block's four boxes instead of four);
+// then lane c of each wave writes table entry c of its box and lane NCOMP the four
+// brightness coefficients.
 template <class T>
 __global__ void __launch_bounds__(256) k_prep(PrepArgs a) {
     if (*a.status) return;
     // the box's table is staged in LDS and written out contiguously by the whole wave
     constexpr int TW = NCOMP * CST * scalar_traits<T>::width;   // doubles per table
     __shared__ double stage[4][TW];
+    __shared__ T wsh[4][NW];
     const int wave = threadIdx.x >> 6;
-    const int j = blockIdx.x * (blockDim.x >> 6) + wave;
     const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    if (threadIdx.x < wpb) {   // box of wave threadIdx.x
+        const int jb = blockIdx.x * wpb + threadIdx.x;
+        if (jb < a.pairs.n) {
+            const PairDev pd = a.g.pairs[sel_at(a.pairs, jb)];
+            const celeste_image& im = a.g.images[pd.img];
+            T* w = wsh[threadIdx.x];
+            if (a.dir_mode == DIR_W) {
+                // tangent along one of the box's intermediates
+                double p[NP], wd[NW];
+                for (int i = 0; i < NP; ++i) p[i] = a.theta[(size_t)pd.src * ROW + i];
+                pair_w<double>(p, im, wd);
+                for (int i = 0; i < NW; ++i) w[i] = scalar_traits<T>::make(wd[i], i == a.dir_unit ? 1.0 : 0.0);
+            } else {
+                T p[NP];
+                for (int i = 0; i < NP; ++i) p[i] = seed<T>(a.theta, a.dir, a.dir_mode, a.dir_unit, pd.src, i);
+                pair_w<T>(p, im, w);
+            }
+        }
+    }
+    __syncthreads();
+    const int j = blockIdx.x * wpb + wave;
     const bool valid = j < a.pairs.n;
     const int pi = valid ? sel_at(a.pairs, j) : 0;
     if (valid) {
@@ -93,17 +118,7 @@ __global__ void __launch_bounds__(256) k_prep(PrepArgs a) {
         const celeste_image& im = a.g.images[pd.img];
         T* coef = reinterpret_cast<T*>(a.coef) + (size_t)pi * NCOEF;
         T w[NW];
-        if (a.dir_mode == DIR_W) {
-            // tangent along one of the box's intermediates
-            double p[NP], wd[NW];
-            for (int i = 0; i < NP; ++i) p[i] = a.theta[(size_t)pd.src * ROW + i];
-            pair_w<double>(p, im, wd);
-            for (int i = 0; i < NW; ++i) w[i] = scalar_traits<T>::make(wd[i], i == a.dir_unit ? 1.0 : 0.0);
-        } else {
-            T p[NP];
-            for (int i = 0; i < NP; ++i) p[i] = seed<T>(a.theta, a.dir, a.dir_mode, a.dir_unit, pd.src, i);
-            pair_w<T>(p, im, w);
-        }
+        for (int i = 0; i < NW; ++i) w[i] = wsh[wave][i];
         if (lane < NCOMP) {
             build_comp_from_w<T>(w, im, a.g.consts, lane, reinterpret_cast<T*>(stage[wave]) + lane * CST);
         } else if (lane == NCOMP) {
