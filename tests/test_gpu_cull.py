@@ -50,7 +50,7 @@ def wide_boxes(synth):
 
 
 @pytest.mark.parametrize("rows", [16, 8])
-def test_culled_elbo_grad_and_hessian_match_oracle(B, O, synth, rows):
+def test_culled_elbo_grad_hessian_and_hvp_match_oracle(B, O, synth, rows):
     f = wide_boxes(synth)
     theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
     plan = B.Plan(f)
@@ -76,6 +76,15 @@ def test_culled_elbo_grad_and_hessian_match_oracle(B, O, synth, rows):
     for s in range(f.n_src):
         Href, Habs = O.source_hessian(P, s, with_abs=True)
         hessian_within(H[s], Href, Habs, "rows %d hessian s=%d" % (rows, s))
+    # the dual-number passes cull too (one component at a time)
+    v = np.random.default_rng(7 + rows).standard_normal(f.theta.shape)
+    hv, g2 = plan.hvp(theta, torch.tensor(v, dtype=torch.float64, device="cuda"), with_grad=True)
+    hv, g2 = hv.cpu().numpy(), g2.cpu().numpy()
+    for s in range(f.n_src):
+        ref, habs = O.source_hvp(P, s, v[s])
+        within(hv[s, :27], ref, habs, "rows %d hvp s=%d" % (rows, s))
+        _, gref, gabs = O.source_grad(P, s)
+        within(g2[s, :27], gref, gabs, "rows %d hvp-grad s=%d" % (rows, s))
 
 
 def test_work_counts_on_the_2000_source_field(B, synth):
