@@ -391,4 +391,28 @@ __device__ inline double wave_sum(double v) {
 }
 __device__ inline dual wave_sum(dual v) { return mkd(wave_sum(v.v), wave_sum(v.t)); }
 
+// Wave sums of N values at once, each by the butterfly of wave_sum (so bitwise the same
+// sums): the N shuffles of a step are issued together and their latencies overlap, where
+// N calls of wave_sum would wait on each in turn.
+template <int N>
+__device__ inline void wave_sums(double* v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        double t[N];
+#pragma unroll
+        for (int f = 0; f < N; ++f) t[f] = __shfl_xor(v[f], o, 64);
+#pragma unroll
+        for (int f = 0; f < N; ++f) v[f] += t[f];
+    }
+}
+// v[lane] in lanes below N (zero above): N wave-uniform values spread over the lanes, so
+// that one coalesced store by lanes 0..N-1 writes them all
+template <int N>
+__device__ inline double lane_pick(const double* v, int lane) {
+    double m = 0.0;
+#pragma unroll
+    for (int f = 0; f < N; ++f) m = lane == f ? v[f] : m;
+    return m;
+}
+
 }  // namespace cel

@@ -1362,12 +1362,12 @@ __global__ void __launch_bounds__(256, 2) k_hess_geom(AdjArgs a, const Item* __r
                 }
             }
         }
-        double* out = hg + (size_t)ii * NHG;
-#pragma unroll
-        for (int f = 0; f < NHG; ++f) {
-            const double v = wave_sum(H[f]);
-            if (lane == 0) out[f] += v;   // onto the second-derivative terms of k_hess_second
-        }
+        // the item's sums side by side (one sum at a time, each shuffle and lane 0's
+        // read-modify-write would wait in turn); lane f adds sum f onto the
+        // second-derivative terms of k_hess_second
+        wave_sums<NHG>(H);
+        const double hv = lane_pick<NHG>(H, lane);
+        if (lane < NHG) hg[(size_t)ii * NHG + lane] += hv;
         j = a.dynamic ? next_item_s(a.counter, lane) : j + nw;
     }
 }
