@@ -33,7 +33,7 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector peak (vendor figure)
 # table-driven log (breakpoint, reduced argument, degree-6 log1p, m ln2 recombination:
 # 20 FLOPs), reciprocal (hardware estimate + two Newton steps: 9 FLOPs).  Elsewhere exp = 27
 # and log = 78, the FP64 operations of one call of the ROCm device library's exp and log on
-# gfx950 (read from this build's ISA).
+# gfx950 (counted in the compiled gfx950 ISA).
 EXP_FLOPS = 27
 LOG_FLOPS = 78
 FEXP_FLOPS = 14
@@ -345,7 +345,7 @@ def main():
                     help="Newton / sweep Hessian rows: 0 closed form (default), 1 tangent passes")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.workload == "newton":
