@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
     __shared__ double B[NJ][LD];   // the model Hessian; later the eigenvectors Z of T (QL path)
     __shared__ double Q[NJ][LD];   // row k: the k-th Householder reflector v_k
     __shared__ double vs[NJ], ws[NJ], dd[NJ], ee[NJ], bh[NJ];
-    __shared__ double gm[NJ], eta[NJ], d1[NJ], lam[NJ], gh[NJ], ph[NJ], pv[NJ];
+    __shared__ double gm[NJ], eta[NJ], d1[NJ], lam[NJ], ph[NJ], pv[NJ];
     __shared__ double sh_red[64];
     __shared__ int sh_done;
     const double* th = a.theta + (size_t)s * ROW;
@@ -467,9 +467,12 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
     bool converged = true;
     for (int l = 0; l < M && converged; ++l) {
         for (int iter = 0;; ++iter) {
-            int m = l;
-            for (; m < M - 1; ++m)
-                if (fabs(lane_get(ev, m)) <= EPS_D * (fabs(lane_get(dv, m)) + fabs(lane_get(dv, m + 1)))) break;
+            // m: the first index from l on whose e_m is negligible against its neighbours
+            // (M - 1 if none), every lane testing its own e at once
+            const double dn = __shfl(dv, t < 63 ? t + 1 : t, 64);
+            const bool small = t < M - 1 && fabs(ev) <= EPS_D * (fabs(dv) + fabs(dn));
+            const unsigned long long sm = __ballot(small) & (~0ull << l);
+            const int m = sm ? __ffsll((long long)sm) - 1 : M - 1;
             if (m == l) break;
             if (iter == QL_MAX_ITER) {
                 converged = false;
@@ -481,10 +484,27 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
             g = lane_get(dv, m) - dl + el / (g + copysign(r, g));
             double sn = 1.0, cs = 1.0, p = 0.0;
             bool deflated = false;
+            // row t of Z: entry zpos, rotated but not yet stored, is carried in zc
+            int zpos = m;
+            double zc = (t < M) ? B[t][m] : 0.0;
             for (int i = m - 1; i >= l; --i) {
                 const double ei = lane_get(ev, i);
                 const double f = sn * ei, b = cs * ei;
-                r = hypot(f, g);
+                // r = hypot(f, g) and 1 / r: the reciprocal square root of f^2 + g^2 (hardware
+                // estimate, two Newton steps) where the squares stay far from overflow and
+                // underflow; hypot and a division elsewhere
+                const double q2 = fma(f, f, g * g);
+                double rinv = 0.0;
+                if (q2 > 0x1p-1000 && q2 < 0x1p+1000) {
+                    double y = __builtin_amdgcn_rsq(q2);
+                    y = fma(y, 0.5 * fma(-q2 * y, y, 1.0), y);
+                    y = fma(y, 0.5 * fma(-q2 * y, y, 1.0), y);
+                    rinv = y;
+                    r = q2 * y;
+                } else {
+                    r = hypot(f, g);
+                    if (r != 0.0) rinv = 1.0 / r;
+                }
                 ev = t == i + 1 ? r : ev;
                 if (r == 0.0) {   // underflow: the matrix splits here
                     dv = t == i + 1 ? dv - p : dv;
@@ -492,7 +512,6 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
                     deflated = true;
                     break;
                 }
-                const double rinv = 1.0 / r;
                 sn = f * rinv;
                 cs = g * rinv;
                 g = lane_get(dv, i + 1) - p;
@@ -501,11 +520,13 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
                 dv = t == i + 1 ? g + p : dv;
                 g = cs * r - b;
                 if (t < M) {
-                    const double zi = B[t][i], zn = B[t][i + 1];
-                    B[t][i + 1] = sn * zi + cs * zn;
-                    B[t][i] = cs * zi - sn * zn;
+                    const double zi = B[t][i];
+                    B[t][i + 1] = sn * zi + cs * zc;
+                    zc = cs * zi - sn * zc;
                 }
+                zpos = i;
             }
+            if (t < M) B[t][zpos] = zc;
             if (deflated) continue;
             dv = t == l ? dv - p : dv;
             ev = t == l ? g : (t == m ? 0.0 : ev);
@@ -523,81 +544,64 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
         }
         return;
     }
-    if (t < M) {
-        lam[t] = dd[t];
-        double g = 0.0;   // (Q Z)^T g = Z^T (Q^T g)
-        for (int k = 0; k < M; ++k) g += B[k][t] * vs[k];
-        gh[t] = g;
+    // ---- subproblem in the eigenbasis: lane i holds lambda_i and entry i of (Q Z)^T g; the
+    // sums over the eigenvalues are wave sums (equal in every lane, so every lane takes the
+    // same branches)
+    const double lamv = (t < M) ? dv : 0.0;
+    double ghv = 0.0;   // (Q Z)^T g = Z^T (Q^T g)
+    if (t < M)
+        for (int k = 0; k < M; ++k) ghv += B[k][t] * vs[k];
+    const double lmin = wave_min((t < M) ? lamv : INFINITY);
+    const double lmax = wave_max((t < M) ? fabs(lamv) : 0.0);
+    const int imin = __ffsll((long long)__ballot(t < M && lamv == lmin)) - 1;   // its first lane
+    const double gn2 = wave_sum(ghv * ghv);
+    double phv = 0.0;
+    bool solved = false;
+    if (lmin > 0.0) {
+        const double q = (t < M) ? ghv / lamv : 0.0;
+        if (wave_sum(q * q) <= R * R) {
+            phv = -q;
+            solved = true;
+        }
     }
-    __syncthreads();
-    // ---- subproblem in the eigenbasis (lane 0)
-    if (t == 0) {
-        double lmin = lam[0], lmax = fabs(lam[0]), gn2 = 0.0;
-        int imin = 0;
-        for (int i = 0; i < M; ++i) {
-            if (lam[i] < lmin) { lmin = lam[i]; imin = i; }
-            lmax = fmax(lmax, fabs(lam[i]));
-            gn2 += gh[i] * gh[i];
-        }
-        bool solved = false;
-        double mu = 0.0;
-        if (lmin > 0.0) {
-            double n2 = 0.0;
-            for (int i = 0; i < M; ++i) n2 += (gh[i] / lam[i]) * (gh[i] / lam[i]);
-            if (n2 <= R * R) {
-                for (int i = 0; i < M; ++i) ph[i] = -gh[i] / lam[i];
-                solved = true;
+    if (!solved) {
+        const double lo0 = fmax(0.0, -lmin);
+        const double tol = 1e-12 * fmax(lmax, 1e-300);
+        // hard case: gradient (numerically) orthogonal to the lowest eigenspace
+        const bool low = t < M && lamv <= lmin + tol;
+        const double vr = (t < M && !low) ? ghv / (lamv + lo0) : 0.0;
+        const double gmin2 = wave_sum(low ? ghv * ghv : 0.0), prest2 = wave_sum(vr * vr);
+        if (lo0 > 0.0 && gmin2 <= 1e-28 * fmax(gn2, 1e-300) && prest2 <= R * R) {
+            phv = (t == imin) ? sqrt(fmax(R * R - prest2, 0.0)) : -vr;
+        } else {
+            double lo = lo0, hi = lo0 + sqrt(gn2) / R + 1e-300;
+            double mu = hi;
+            for (int itn = 0; itn < 200; ++itn) {
+                const double den = lamv + mu;
+                const double v = (t < M) ? ghv / den : 0.0;
+                const double n2 = wave_sum(v * v), d3 = wave_sum((t < M) ? v * v / den : 0.0);
+                const double nrm = sqrt(n2);
+                if (fabs(nrm - R) <= 1e-13 * R) break;
+                if (nrm > R) lo = mu;
+                else hi = mu;
+                // Newton step on 1/R - 1/|p(mu)|
+                double nmu = mu + (nrm - R) / R * (n2 / d3);
+                if (!(nmu > lo && nmu < hi)) nmu = 0.5 * (lo + hi);
+                if (nmu == mu) break;
+                mu = nmu;
             }
+            phv = (t < M) ? -ghv / (lamv + mu) : 0.0;
         }
-        if (!solved) {
-            const double lo0 = fmax(0.0, -lmin);
-            const double tol = 1e-12 * fmax(lmax, 1e-300);
-            // hard case: gradient (numerically) orthogonal to the lowest eigenspace
-            double gmin2 = 0.0, prest2 = 0.0;
-            for (int i = 0; i < M; ++i) {
-                if (lam[i] <= lmin + tol) gmin2 += gh[i] * gh[i];
-                else {
-                    const double v = gh[i] / (lam[i] + lo0);
-                    prest2 += v * v;
-                }
-            }
-            if (lo0 > 0.0 && gmin2 <= 1e-28 * fmax(gn2, 1e-300) && prest2 <= R * R) {
-                for (int i = 0; i < M; ++i)
-                    ph[i] = (lam[i] <= lmin + tol) ? 0.0 : -gh[i] / (lam[i] + lo0);
-                ph[imin] = sqrt(fmax(R * R - prest2, 0.0));
-                mu = lo0;
-            } else {
-                double lo = lo0, hi = lo0 + sqrt(gn2) / R + 1e-300;
-                mu = hi;
-                for (int itn = 0; itn < 200; ++itn) {
-                    double n2 = 0.0, d3 = 0.0;
-                    for (int i = 0; i < M; ++i) {
-                        const double den = lam[i] + mu;
-                        const double v = gh[i] / den;
-                        n2 += v * v;
-                        d3 += v * v / den;
-                    }
-                    const double nrm = sqrt(n2);
-                    if (fabs(nrm - R) <= 1e-13 * R) break;
-                    if (nrm > R) lo = mu;
-                    else hi = mu;
-                    // Newton step on 1/R - 1/|p(mu)|
-                    double nmu = mu + (nrm - R) / R * (n2 / d3);
-                    if (!(nmu > lo && nmu < hi)) nmu = 0.5 * (lo + hi);
-                    if (nmu == mu) break;
-                    mu = nmu;
-                }
-                for (int i = 0; i < M; ++i) ph[i] = -gh[i] / (lam[i] + mu);
-            }
-        }
-        double pr = 0.0, pn = 0.0;
-        for (int i = 0; i < M; ++i) {
-            pr -= gh[i] * ph[i] + 0.5 * lam[i] * ph[i] * ph[i];
-            pn += ph[i] * ph[i];
-        }
-        a.pred[2 * s] = pr;
-        a.pred[2 * s + 1] = sqrt(pn);
     }
+    {
+        const double pr = -wave_sum(ghv * phv + 0.5 * lamv * phv * phv);
+        const double pn = wave_sum(phv * phv);
+        if (t == 0) {
+            a.pred[2 * s] = pr;
+            a.pred[2 * s + 1] = sqrt(pn);
+        }
+    }
+    if (t < M) ph[t] = phv;
     __syncthreads();
     double zp = 0.0;   // Z ph, then p = Q (Z ph)
     if (t < M)
