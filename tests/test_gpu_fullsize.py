@@ -71,6 +71,36 @@ def test_newton_field_1024src_full_size_sampled(B, N, synth):
         assert radius[s] == R
 
 
+def test_newton_steps_through_the_ql_path_field_1024src(B, N, synth):
+    """Ten Newton steps of all 1024 sources, one call per step with the radii carried over.
+    On this field the trust-region solve of sources 392 and 660 at step 7, 660 at step 8 and
+    404 at step 9 takes its QL eigendecomposition (the fallback when T's factorisations
+    find the gradient nearly orthogonal to the lowest eigenvector; a build that marks the
+    path showed which), every other solve here the factorisations of T.  Those steps
+    against the oracle's step from the device's previous state: within the derived one-step
+    bound, the same ELBO and the same next radius."""
+    f = synth.field_1024src()
+    plan = B.Plan(f)
+    theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+    src = np.arange(f.n_src, dtype=np.int32)
+    rad = np.ones(f.n_src)
+    checks = {7: [392, 660], 8: [660], 9: [404]}
+    for k in range(1, 10):
+        prev = theta.cpu().numpy().copy()
+        elbo, radius = plan.newton(theta, src, 1, radius=torch.tensor(rad, device="cuda"))
+        th, elbo, radius = theta.cpu().numpy(), elbo.cpu().numpy(), radius.cpu().numpy()
+        for s in checks.get(k, []):
+            g, j = neighbourhood(f, s, theta=prev)
+            say("case newton QL path: step", k, "source", s, "neighbourhood", g.n_src)
+            bound, row, fend, R = newton_step_bound(N, g, g.theta, j, rad[s])
+            diff = np.abs(th[s, :27] - row)
+            say("    max |diff| / bound %.3g" % (diff / np.maximum(bound, 1e-300)).max())
+            assert np.all(diff <= bound), (k, s, (diff / np.maximum(bound, 1e-300)).max())
+            np.testing.assert_allclose(elbo[s], fend, rtol=1e-9)
+            assert radius[s] == R
+        rad = radius.copy()
+
+
 def test_second_order_field_1024src_largest_boxes(B, O, synth):
     """Dense Hessians (celeste_hessian of the listed sources on the full plan) and the
     Hessian-vector product of every source (celeste_hvp) on the 1024-source field, for the
