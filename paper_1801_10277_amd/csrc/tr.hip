@@ -399,9 +399,16 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
     // positive pivots at mu = 0: T is positive definite (the smallest eigenvalue is
     // positive), so try the interior Newton step and bracket the secular equation from 0
     const bool pd = factor(0.0);
+    // a start for the secular equation left of its root, where |p(mu)| > R and Newton's
+    // iteration on 1 / |p(mu)| (concave) rises to the root without overshooting it:
+    // mu = 0 or the point just above the pole probed below, whichever applies with a finite
+    // norm (else the iteration starts from the bracket's upper end)
+    double mu_left = -1.0;
     if (pd) {
         yv = subst(-gtv);
-        fast = wave_sum(yv * yv) <= R * R;
+        const double n2 = wave_sum(yv * yv);
+        fast = n2 <= R * R;
+        if (n2 < INFINITY) mu_left = 0.0;
     }
     if (!fast) {
         const double lmin_t = pd ? 0.0 : smallest_eigenvalue();
@@ -415,10 +422,11 @@ __global__ void __launch_bounds__(64) k_tr_solve(TrArgs a) {
             const double yp = subst(-gtv);
             const double n2 = wave_sum(yp * yp);
             hard = n2 < R * R;   // (an overflowing norm is the opposite of the hard case)
+            if (!hard && n2 < INFINITY) mu_left = lo0 + 1e-12 * scale;
         }
         if (!hard) {
             double lo = lo0, hi = lo0 + gn / R + 1e-300;
-            double mu = hi;
+            double mu = (mu_left >= lo0 && mu_left < hi) ? mu_left : hi;
             for (int itn = 0; itn < 200; ++itn) {
                 factor(mu);
                 yv = subst(-gtv);
