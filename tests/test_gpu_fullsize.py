@@ -101,6 +101,33 @@ def test_newton_steps_through_the_ql_path_field_1024src(B, N, synth):
         rad = radius.copy()
 
 
+def test_mixture_newton_steps_through_the_ql_path_field_1024src(B, N, synth):
+    """As above with the colour-prior mixture (43 parameters, 41 unconstrained coordinates,
+    k_tr_solve<43>): the solves of sources 677 and 699 at step 6 and 297 at step 8 take the
+    QL path.  Those steps against the oracle's step from the device's previous state."""
+    f = synth.with_color_mixture(synth.field_1024src(), seed=3)
+    plan = B.Plan(f)
+    theta = torch.tensor(f.theta, dtype=torch.float64, device="cuda")
+    src = np.arange(f.n_src, dtype=np.int32)
+    rad = np.ones(f.n_src)
+    checks = {6: [677, 699], 8: [297]}
+    for k in range(1, 9):
+        prev = theta.cpu().numpy().copy()
+        elbo, radius = plan.newton(theta, src, 1, radius=torch.tensor(rad, device="cuda"))
+        th, elbo, radius = theta.cpu().numpy(), elbo.cpu().numpy(), radius.cpu().numpy()
+        for s in checks.get(k, []):
+            g, j = neighbourhood(f, s, theta=prev)
+            say("case mixture newton QL path: step", k, "source", s, "neighbourhood", g.n_src)
+            bound, row, fend, R = newton_step_bound(N, g, g.theta, j, rad[s])
+            assert len(row) == 43
+            diff = np.abs(th[s, :43] - row)
+            say("    max |diff| / bound %.3g" % (diff / np.maximum(bound, 1e-300)).max())
+            assert np.all(diff <= bound), (k, s, (diff / np.maximum(bound, 1e-300)).max())
+            np.testing.assert_allclose(elbo[s], fend, rtol=1e-9)
+            assert radius[s] == R
+        rad = radius.copy()
+
+
 def test_second_order_field_1024src_largest_boxes(B, O, synth):
     """Dense Hessians (celeste_hessian of the listed sources on the full plan) and the
     Hessian-vector product of every source (celeste_hvp) on the 1024-source field, for the
